@@ -1,0 +1,272 @@
+/*
+ * Oracle for the FRKC2 superstep: plain CPU FP64 stage loops.
+ *
+ * TEST INFRASTRUCTURE. Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark load this library. It shares no code with the GPU
+ * library; the two meet only in the seeded inputs and in the stepsizes each
+ * computes on its own.
+ *
+ * Method: O'Sullivan, "Factorized Runge-Kutta-Chebyshev Methods",
+ * arXiv:1702.03818, Sec. 3 ("FRKC2 schemes"): a superstep of length T is the
+ * ordered sequence of L = s forward Euler steps W^{l+1} = W^l + T a_l f(W^l),
+ * W^0 = w^n, w^{n+1} = W^L, with complex a_l, so the stages are complex.
+ * The caller passes tau_l = T a_l. The result kept is Re W^L.
+ *
+ * f is the semi-discrete diffusion operator of Sec. 1 (w' = f(t, w) with a
+ * Jacobian whose eigenvalues lie near the negative real axis), here on a
+ * uniform grid of spacing h, cell-centred, x fastest:
+ *   op 0 (Laplace):    f = d sum_faces (W_nb - W_c) / h^2
+ *   op 1 (var. coef.): f = sum_faces D_f (W_nb - W_c) / h^2, D_f = (D_c + D_nb)/2
+ *   op 2 (porous):     f = sum_faces Q_f (W_nb - W_c) / h^2, Q_f = (W_c^2 + W_nb^2)/2
+ *                      (div(u^2 grad u); u^2 is holomorphic, so it is applied
+ *                      to the complex stage values unchanged)
+ * Boundaries: periodic (wrap), or Dirichlet zero (ghost W = 0 and, for op 1,
+ * ghost D equal to the cell's own D, so the boundary face carries D_c).
+ *
+ * Evaluation order (fixed; the GPU library evaluates the same expressions in
+ * the same order, so results agree to the last bit):
+ *   faces in the order x-, x+, y-, y+, z-, z+;
+ *   acc_r = acc_r + Df*(Wr_nb - Wr_c), acc_i likewise (op 2:
+ *   acc_r = acc_r + (Dr*dr - Di*di), acc_i = acc_i + (Dr*di + Di*dr));
+ *   f = acc*inv_h2 with inv_h2 = 1/(h*h);
+ *   Wr = Wr + (tr*fr - ti*fi), Wi = Wi + (tr*fi + ti*fr).
+ * Built with -ffp-contract=off, so no multiply-add is fused.
+ *
+ * The adjoint runs the transposed stages in reverse order. Because A is
+ * symmetric, the adjoint of W <- W + tau A W is lam <- lam + conj(tau) A lam
+ * for lam = dJ/dWr + i dJ/dWi; the derivative with respect to a face
+ * diffusivity is -Re(tau conj(lam_nb - lam_c) (W_nb - W_c))/h^2, with
+ * lam = lam^{l+1} and W = W^l, split half to each cell of an interior face
+ * and fully to the cell of a Dirichlet boundary face.
+ */
+#include <stdlib.h>
+#include <string.h>
+
+enum { BC_PERIODIC = 0, BC_DIRICHLET0 = 1 };
+enum { OP_LAPLACE = 0, OP_VARCOEF = 1, OP_POROUS2 = 2 };
+
+typedef struct {
+    int ndim;
+    long n[3];
+    int bc, op;
+    double inv_h2, d_const;
+} grid_t;
+
+static long npts(const grid_t *g) { return g->n[0] * g->n[1] * g->n[2]; }
+
+/* Index of the neighbour of point (i[0], i[1], i[2]) across face f
+ * (f = 2*dim + side, side 0 = minus, 1 = plus), or -1 for a Dirichlet ghost. */
+static long neighbour(const grid_t *g, const long i[3], int f)
+{
+    long j[3] = {i[0], i[1], i[2]};
+    int d = f / 2;
+    j[d] += (f % 2) ? 1 : -1;
+    if (j[d] < 0 || j[d] >= g->n[d]) {
+        if (g->bc == BC_DIRICHLET0) return -1;
+        j[d] = (j[d] + g->n[d]) % g->n[d];
+    }
+    return j[0] + g->n[0] * (j[1] + g->n[1] * j[2]);
+}
+
+static void coords(const grid_t *g, long p, long i[3])
+{
+    i[0] = p % g->n[0];
+    i[1] = (p / g->n[0]) % g->n[1];
+    i[2] = p / (g->n[0] * g->n[1]);
+}
+
+/* F = f(W) for complex W = (wr, wi), all points. */
+static void apply_op(const grid_t *g, const double *D, const double *wr, const double *wi,
+                     double *fr, double *fi)
+{
+    long N = npts(g);
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < N; ++p) {
+        long i[3];
+        coords(g, p, i);
+        double acc_r = 0.0, acc_i = 0.0;
+        for (int f = 0; f < 2 * g->ndim; ++f) {
+            long q = neighbour(g, i, f);
+            double nr = (q < 0) ? 0.0 : wr[q];
+            double ni = (q < 0) ? 0.0 : wi[q];
+            double dr = nr - wr[p];
+            double di = ni - wi[p];
+            if (g->op == OP_POROUS2) {
+                double qr_c = wr[p] * wr[p] - wi[p] * wi[p];
+                double qi_c = 2.0 * (wr[p] * wi[p]);
+                double qr_n = nr * nr - ni * ni;
+                double qi_n = 2.0 * (nr * ni);
+                double Dr = 0.5 * (qr_c + qr_n);
+                double Di = 0.5 * (qi_c + qi_n);
+                acc_r = acc_r + (Dr * dr - Di * di);
+                acc_i = acc_i + (Dr * di + Di * dr);
+            } else {
+                double Df;
+                if (g->op == OP_LAPLACE) {
+                    Df = g->d_const;
+                } else {
+                    double Dn = (q < 0) ? D[p] : D[q];
+                    Df = 0.5 * (D[p] + Dn);
+                }
+                acc_r = acc_r + Df * dr;
+                acc_i = acc_i + Df * di;
+            }
+        }
+        fr[p] = acc_r * g->inv_h2;
+        fi[p] = acc_i * g->inv_h2;
+    }
+}
+
+static int make_grid(grid_t *g, int ndim, const long *n, int bc, int op, double inv_h2,
+                     double d_const)
+{
+    if (ndim < 1 || ndim > 3) return -1;
+    g->ndim = ndim;
+    for (int d = 0; d < 3; ++d) g->n[d] = (d < ndim) ? n[d] : 1;
+    for (int d = 0; d < 3; ++d) if (g->n[d] < 1) return -1;
+    g->bc = bc;
+    g->op = op;
+    g->inv_h2 = inv_h2;
+    g->d_const = d_const;
+    return 0;
+}
+
+/*
+ * One superstep: W^0 = (w, 0); W^{l+1} = W^l + tau_l f(W^l), l = 0..s-1;
+ * w <- Re W^s. If wi_out is not NULL it receives Im W^s.
+ * If store is not NULL it receives W^0..W^{s-1} as s blocks of 2N doubles
+ * (real part, then imaginary part).
+ */
+int oracle_superstep(int ndim, const long *n, int bc, int op, double inv_h2, double d_const,
+                     const double *D, int s, const double *tau_re, const double *tau_im,
+                     double *w, double *wi_out, double *store)
+{
+    grid_t g;
+    if (make_grid(&g, ndim, n, bc, op, inv_h2, d_const)) return -1;
+    long N = npts(&g);
+    double *wr = malloc(sizeof(double) * N), *wi = malloc(sizeof(double) * N);
+    double *fr = malloc(sizeof(double) * N), *fi = malloc(sizeof(double) * N);
+    if (!wr || !wi || !fr || !fi) { free(wr); free(wi); free(fr); free(fi); return -2; }
+    memcpy(wr, w, sizeof(double) * N);
+    memset(wi, 0, sizeof(double) * N);
+    for (int l = 0; l < s; ++l) {
+        if (store) {
+            memcpy(store + (size_t)2 * N * l, wr, sizeof(double) * N);
+            memcpy(store + (size_t)2 * N * l + N, wi, sizeof(double) * N);
+        }
+        apply_op(&g, D, wr, wi, fr, fi);
+        double tr = tau_re[l], ti = tau_im[l];
+#pragma omp parallel for schedule(static)
+        for (long p = 0; p < N; ++p) {
+            double nr = wr[p] + (tr * fr[p] - ti * fi[p]);
+            double ni = wi[p] + (tr * fi[p] + ti * fr[p]);
+            wr[p] = nr;
+            wi[p] = ni;
+        }
+    }
+    memcpy(w, wr, sizeof(double) * N);
+    if (wi_out) memcpy(wi_out, wi, sizeof(double) * N);
+    free(wr); free(wi); free(fr); free(fi);
+    return 0;
+}
+
+/*
+ * Adjoint of one superstep (ops 0 and 1). Given w_n, the stepsizes and
+ * lam_next = dJ/dw^{n+1}, writes lam_n = dJ/dw^n and adds D * dJ/dD to
+ * grad_logD (op 1 only; grad_logD may be NULL for op 0).
+ */
+int oracle_adjoint(int ndim, const long *n, int bc, int op, double inv_h2, double d_const,
+                   const double *D, int s, const double *tau_re, const double *tau_im,
+                   const double *w_n, const double *lam_next, double *lam_n, double *grad_logD)
+{
+    grid_t g;
+    if (op == OP_POROUS2) return -1;
+    if (make_grid(&g, ndim, n, bc, op, inv_h2, d_const)) return -1;
+    long N = npts(&g);
+    double *store = malloc(sizeof(double) * 2 * N * (size_t)s);
+    double *w = malloc(sizeof(double) * N);
+    double *lr = malloc(sizeof(double) * N), *li = malloc(sizeof(double) * N);
+    double *gr = malloc(sizeof(double) * N), *gi = malloc(sizeof(double) * N);
+    double *gD = calloc(N, sizeof(double));
+    if (!store || !w || !lr || !li || !gr || !gi || !gD) {
+        free(store); free(w); free(lr); free(li); free(gr); free(gi); free(gD);
+        return -2;
+    }
+    memcpy(w, w_n, sizeof(double) * N);
+    oracle_superstep(ndim, n, bc, op, inv_h2, d_const, D, s, tau_re, tau_im, w, NULL, store);
+    memcpy(lr, lam_next, sizeof(double) * N);
+    memset(li, 0, sizeof(double) * N);
+    for (int l = s - 1; l >= 0; --l) {
+        const double *Wr = store + (size_t)2 * N * l, *Wi = Wr + N;
+        double tr = tau_re[l], ti = tau_im[l];
+        if (op == OP_VARCOEF) {
+#pragma omp parallel for schedule(static)
+            for (long p = 0; p < N; ++p) {
+                long i[3];
+                coords(&g, p, i);
+                double gsum = 0.0;
+                for (int f = 0; f < 2 * ndim; ++f) {
+                    long q = neighbour(&g, i, f);
+                    double dWr = ((q < 0) ? 0.0 : Wr[q]) - Wr[p];
+                    double dWi = ((q < 0) ? 0.0 : Wi[q]) - Wi[p];
+                    double dLr = ((q < 0) ? 0.0 : lr[q]) - lr[p];
+                    double dLi = ((q < 0) ? 0.0 : li[q]) - li[p];
+                    double pr = dLr * dWr + dLi * dWi;
+                    double pi = dLr * dWi - dLi * dWr;
+                    double e = tr * pr - ti * pi;
+                    double wgt = (q < 0) ? 1.0 : 0.5;
+                    gsum = gsum + wgt * e;
+                }
+                gD[p] = gD[p] - gsum * inv_h2;
+            }
+        }
+        apply_op(&g, D, lr, li, gr, gi);
+#pragma omp parallel for schedule(static)
+        for (long p = 0; p < N; ++p) {
+            double nr = lr[p] + (tr * gr[p] + ti * gi[p]);
+            double ni = li[p] + (tr * gi[p] - ti * gr[p]);
+            lr[p] = nr;
+            li[p] = ni;
+        }
+    }
+    memcpy(lam_n, lr, sizeof(double) * N);
+    if (op == OP_VARCOEF && grad_logD) {
+        for (long p = 0; p < N; ++p) grad_logD[p] = grad_logD[p] + D[p] * gD[p];
+    }
+    free(store); free(w); free(lr); free(li); free(gr); free(gi); free(gD);
+    return 0;
+}
+
+/*
+ * Gershgorin bound on the spectral radius of the Jacobian of f at real w:
+ * rho = (2*inv_h2) * max_c sum_faces D_f, with D_f of the operator (op 2: the
+ * face value (w_c^2 + w_nb^2)/2 of the current state).
+ */
+double oracle_rho_bound(int ndim, const long *n, int bc, int op, double inv_h2, double d_const,
+                        const double *D, const double *w)
+{
+    grid_t g;
+    if (make_grid(&g, ndim, n, bc, op, inv_h2, d_const)) return -1.0;
+    long N = npts(&g);
+    double m = 0.0;
+    for (long p = 0; p < N; ++p) {
+        long i[3];
+        coords(&g, p, i);
+        double sum = 0.0;
+        for (int f = 0; f < 2 * ndim; ++f) {
+            long q = neighbour(&g, i, f);
+            double Df;
+            if (op == OP_LAPLACE) {
+                Df = d_const;
+            } else if (op == OP_VARCOEF) {
+                Df = 0.5 * (D[p] + ((q < 0) ? D[p] : D[q]));
+            } else {
+                double un = (q < 0) ? 0.0 : w[q];
+                Df = 0.5 * (w[p] * w[p] + un * un);
+            }
+            sum = sum + Df;
+        }
+        if (sum > m) m = sum;
+    }
+    return (2.0 * inv_h2) * m;
+}

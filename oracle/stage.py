@@ -1,0 +1,135 @@
+"""ctypes wrapper of the plain C stage-loop oracle (stage.c).
+
+TEST INFRASTRUCTURE: imported only by the tests, the smoke check and the
+CPU-baseline leg of the benchmark.
+
+The wrapper only marshals arrays. The stepsizes tau_l = T a_l are formed here
+in FP64 from the oracle's own coefficients, and T itself is either given or,
+for the adaptive choice, (cfl * betabar) / rho with rho the Gershgorin bound of
+the current state (the stability requirement T rho <= betabar of Sec. 2;
+cfl < 1 is a safety factor, a proposed reading: the paper leaves the choice of
+T to the user of its stepsize table).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from .coeffs import frkc2_coeffs
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile stage.c with gcc (FP64, no contraction, OpenMP over points)."""
+    os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                               "-fPIC", "-shared", "-o", tmp,
+                               os.path.join(_HERE, "stage.c")])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lp = ctypes.POINTER(ctypes.c_long)
+        common = [ctypes.c_int, lp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                  dp, ctypes.c_int, dp, dp]
+        lib.oracle_superstep.argtypes = common + [dp, dp, dp]
+        lib.oracle_superstep.restype = ctypes.c_int
+        lib.oracle_adjoint.argtypes = common + [dp, dp, dp, dp]
+        lib.oracle_adjoint.restype = ctypes.c_int
+        lib.oracle_rho_bound.argtypes = [ctypes.c_int, lp, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_double, ctypes.c_double, dp, dp]
+        lib.oracle_rho_bound.restype = ctypes.c_double
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _grid_args(prob):
+    n = (ctypes.c_long * 3)(*[int(v) for v in prob.n])
+    inv_h2 = 1.0 / (prob.h * prob.h)
+    return n, inv_h2
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+
+
+def superstep(prob, w, tau_re, tau_im, D=None, want_imag=False):
+    """One superstep from real w with stepsizes tau (execution order). Returns Re W^s (and Im W^s)."""
+    lib = _load()
+    n, inv_h2 = _grid_args(prob)
+    wr = _f64(w).copy()
+    wi = np.empty_like(wr) if want_imag else None
+    Dd = _f64(D if D is not None else prob.D) if (prob.D is not None or D is not None) else None
+    tr, ti = _f64(tau_re), _f64(tau_im)
+    rc = lib.oracle_superstep(prob.ndim, n, prob.bc, prob.op, inv_h2, prob.d_const, _dp(Dd),
+                              len(tr), _dp(tr), _dp(ti), _dp(wr), _dp(wi), None)
+    if rc != 0:
+        raise RuntimeError("oracle_superstep failed (%d)" % rc)
+    return (wr, wi) if want_imag else wr
+
+
+def rho_bound(prob, w=None, D=None) -> float:
+    lib = _load()
+    n, inv_h2 = _grid_args(prob)
+    Dd = D if D is not None else prob.D
+    Dd = _f64(Dd) if Dd is not None else None
+    ww = _f64(w) if w is not None else None
+    return lib.oracle_rho_bound(prob.ndim, n, prob.bc, prob.op, inv_h2, prob.d_const,
+                                _dp(Dd), _dp(ww))
+
+
+def run(prob, s, nsteps, T=None, cfl=None, nu=0.01, w=None, coeffs=None):
+    """nsteps supersteps of s stages; fixed T, or T = (cfl*betabar)/rho(w_n) per superstep.
+
+    Returns (w, list of T used).
+    """
+    c = coeffs if coeffs is not None else frkc2_coeffs(s, nu)
+    cur = _f64(prob.w0 if w is None else w).copy()
+    Ts = []
+    for _ in range(nsteps):
+        if cfl is not None:
+            Tn = (cfl * c.beta_bar) / rho_bound(prob, cur)
+        else:
+            Tn = float(T)
+        Ts.append(Tn)
+        cur = superstep(prob, cur, Tn * c.a_re, Tn * c.a_im)
+    return cur, Ts
+
+
+def adjoint(prob, w_n, lam_next, tau_re, tau_im, grad_logD=None, D=None):
+    """Adjoint of one superstep: returns lam_n and grad_logD (accumulated in place)."""
+    lib = _load()
+    n, inv_h2 = _grid_args(prob)
+    Dd = D if D is not None else prob.D
+    Dd = _f64(Dd) if Dd is not None else None
+    wn = _f64(w_n)
+    ln = _f64(lam_next)
+    out = np.empty_like(wn)
+    g = grad_logD if grad_logD is not None else np.zeros_like(wn)
+    tr, ti = _f64(tau_re), _f64(tau_im)
+    rc = lib.oracle_adjoint(prob.ndim, n, prob.bc, prob.op, inv_h2, prob.d_const, _dp(Dd),
+                            len(tr), _dp(tr), _dp(ti), _dp(wn), _dp(ln), _dp(out), _dp(g))
+    if rc != 0:
+        raise RuntimeError("oracle_adjoint failed (%d)" % rc)
+    return out, g
