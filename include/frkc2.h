@@ -1,0 +1,219 @@
+/*
+ * frkc2.h -- C ABI of libfrkc2, the FRKC2 superstep on AMD MI355X (gfx950).
+ *
+ * Method: S. O'Sullivan, "Factorized Runge-Kutta-Chebyshev Methods",
+ * arXiv:1702.03818. A superstep of length T advances w' = f(w) (Sec. 1, the
+ * semi-discrete system with a Jacobian whose eigenvalues lie near the
+ * negative real axis) by L = s ordered forward Euler steps with complex
+ * stepsizes (Sec. 3, the Euler-step equation of the FRKC2 scheme):
+ *     W^0 = w^n,  W^{l+1} = W^l + T a_l f(W^l),  w^{n+1} = Re W^L.
+ * The a_l come from the roots of the damped second-order FRKC stability
+ * polynomial (Sec. 2 and Sec. 2.1) in the internal-stability order of
+ * Sec. 2.2. f is a diffusion operator on a uniform grid, fused into the
+ * GPU kernels (ops below). Everything is FP64.
+ *
+ * Conventions for every entry point:
+ *  - Arrays are flat, x fastest: index = x + n[0]*(y + n[1]*z).
+ *  - "device" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are ordinary host memory owned by the caller. The library
+ *    never frees caller memory and allocates no device memory in any call
+ *    except the batched graph (see frkc2_step_batched) and its own small
+ *    host-side caches.
+ *  - Work is enqueued on the caller's stream `st` (0 = null stream). Calls
+ *    that return a host value synchronise that stream; others are
+ *    asynchronous unless stated.
+ *  - Arguments are validated before any HIP call. A negative return value is
+ *    an error (frkc2_status); frkc2_last_error() then describes it. A GPU
+ *    fault of an earlier asynchronous call surfaces as FRKC2_EHIP at the next
+ *    call that synchronises.
+ *  - Floating point: the kernels evaluate each grid point's arithmetic in one
+ *    fixed order without fused multiply-adds, so results do not depend on
+ *    tiling, temporal blocking or launch shape.
+ */
+#ifndef FRKC2_H
+#define FRKC2_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FRKC2_OK = 0,
+    FRKC2_WQBOUND = 1,      /* coefficients: no n <= 64 met Q <= 10 L^2; lowest-Q order kept */
+    FRKC2_EINVAL = -1,      /* invalid argument */
+    FRKC2_ENOMEM = -2,      /* workspace too small, or a host allocation failed */
+    FRKC2_EHIP = -3,        /* HIP runtime error (including earlier asynchronous faults) */
+    FRKC2_EUNSTABLE = -4,   /* T * rho > betabar: the superstep would leave the stability interval */
+    FRKC2_ENONFINITE = -5,  /* a norm or bound came out NaN or infinite */
+    FRKC2_ETIMEOUT = -6     /* batched: a bounded dependency wait expired (results invalid) */
+} frkc2_status;
+
+typedef enum { FRKC2_BC_PERIODIC = 0, FRKC2_BC_DIRICHLET0 = 1 } frkc2_bc;
+
+/*
+ * Diffusion operators f (cell-centred, faces in the order x-, x+, y-, y+, z-, z+):
+ *  LAPLACE  f = d_const * sum_f (W_nb - W_c) / h^2
+ *  VARCOEF  f = sum_f D_f (W_nb - W_c) / h^2,  D_f = (D_c + D_nb)/2
+ *  POROUS2  f = div(u^2 grad u): sum_f Q_f (W_nb - W_c) / h^2 with
+ *           Q_f = (W_c^2 + W_nb^2)/2, evaluated on the complex stage values
+ *           (the continuation of u^2 is holomorphic, as the complex Euler
+ *           steps of Sec. 3 require).
+ * Dirichlet-zero boundaries use a ghost value W = 0 and, for VARCOEF, a ghost
+ * diffusivity equal to the boundary cell's own D.
+ */
+typedef enum { FRKC2_OP_LAPLACE = 0, FRKC2_OP_VARCOEF = 1, FRKC2_OP_POROUS2 = 2 } frkc2_op;
+
+typedef struct {
+    int ndim;          /* 1, 2 or 3 */
+    int n[3];          /* points per dimension, x first; unused dimensions = 1 */
+    double h;          /* grid spacing (all dimensions); the stencil uses 1/(h*h) */
+    int bc;            /* frkc2_bc */
+    int op;            /* frkc2_op */
+    double d_const;    /* diffusivity of FRKC2_OP_LAPLACE (ignored otherwise) */
+} frkc2_grid;
+
+typedef struct {
+    double beta;         /* real extent of the damped polynomial: |R(x)| <= 1 on [-beta, 0] */
+    double beta_bar;     /* (1 - n C) beta, C = 1e-4: the usable extent, T rho <= beta_bar */
+    double q_realised;   /* max over x in [-beta, 0] and stage runs j..k of prod |1 + a_l x| */
+    double mu_re, mu_im; /* damping parameter of the first root group */
+    int n_shrink;        /* n of Sec. 2.2 */
+    int q_bound_met;     /* q_realised <= 10 L^2 */
+} frkc2_coeff_info;
+
+typedef struct {
+    double T_last;       /* superstep length of the last superstep */
+    double rho_last;     /* Gershgorin bound used for it (0 when not computed) */
+    double im_ratio;     /* ||Im W^L||_2 / ||W^L||_2 of the last superstep */
+    int supersteps;      /* supersteps completed */
+} frkc2_step_stats;
+
+/* Workspace flags for frkc2_workspace_bytes. */
+#define FRKC2_WS_STEP    0
+#define FRKC2_WS_ADJOINT 1
+
+/*
+ * frkc2_coeffs -- the s ordered stepsizes a_l (Sec. 2, 2.1, 2.2).
+ *   s       even, 2 <= s <= 514 (the range of the paper's table, M <= 257, Sec. 3.1)
+ *   nu      damping, 0 <= nu < 1 (Sec. 2.1: nu = nu0/N)
+ *   a_re, a_im  host arrays of length s, caller-owned; receive a_l in execution order
+ *               (may be NULL to query info only)
+ *   info    host, may be NULL
+ * Host only, no GPU use; results are cached per (s, nu). Returns FRKC2_OK,
+ * FRKC2_WQBOUND (usable, flagged) or FRKC2_EINVAL.
+ */
+int frkc2_coeffs(int s, double nu, double *a_re, double *a_im, frkc2_coeff_info *info);
+
+/*
+ * frkc2_workspace_bytes -- device workspace needed by the calls below for grid g.
+ *   FRKC2_WS_STEP: frkc2_step and frkc2_rho_bound (two complex state buffers
+ *   plus reduction scratch); FRKC2_WS_ADJOINT: frkc2_step_adjoint (s stored
+ *   complex stages, two complex adjoint buffers, one real gradient buffer).
+ * Returns 0 for an invalid grid.
+ */
+size_t frkc2_workspace_bytes(const frkc2_grid *g, int s, int flags);
+
+/*
+ * frkc2_rho_bound -- Gershgorin bound on the spectral radius of the Jacobian
+ * of f at the real state w: rho = (2/h^2) * max_c sum_f D_f (POROUS2: the face
+ * value (w_c^2 + w_nb^2)/2). This is the rho of the stability requirement
+ * T rho <= beta_bar (Sec. 2: |R(T lambda)| <= 1).
+ *   w   device, N doubles (read for POROUS2 only; may be NULL otherwise)
+ *   D   device, N doubles (VARCOEF only; NULL otherwise)
+ *   rho host, receives the bound. Synchronises st.
+ */
+int frkc2_rho_bound(const frkc2_grid *g, const double *w, const double *D, double *rho,
+                    void *ws, size_t ws_bytes, hipStream_t st);
+
+/*
+ * frkc2_step -- nsteps FRKC2 supersteps of s stages (Sec. 3, Euler-step equation).
+ *   w       device, N doubles, in/out: w^n on entry, w^{n+nsteps} on return
+ *   D       device, N doubles (VARCOEF only; NULL otherwise)
+ *   T, cfl  exactly one is positive. T > 0: fixed superstep length.
+ *           cfl > 0: before each superstep T = (cfl * beta_bar) / rho(w^n).
+ *   s, nu   as for frkc2_coeffs
+ *   ws      device workspace of at least frkc2_workspace_bytes(g, s, FRKC2_WS_STEP)
+ *   stats   host, may be NULL; when given, the call synchronises st and fills it
+ * Before the first superstep (and before every superstep for POROUS2) rho is
+ * computed and the call fails with FRKC2_EUNSTABLE if T * rho > beta_bar;
+ * those checks synchronise st. Otherwise asynchronous.
+ */
+int frkc2_step(const frkc2_grid *g, double *w, const double *D, double T, double cfl, int s,
+               double nu, int nsteps, void *ws, size_t ws_bytes, hipStream_t st,
+               frkc2_step_stats *stats);
+
+/*
+ * frkc2_step_adjoint -- reverse-mode derivative of one superstep (VARCOEF or LAPLACE).
+ * With w^{n+1} = S(w^n; D) the superstep from w_n with fixed T:
+ *   lam_next  device, N doubles: dJ/dw^{n+1}
+ *   lam_n     device, N doubles, out: dJ/dw^n = S^T lam_next
+ *   grad_logD device, N doubles, accumulated (+=): D * dJ/dD for this superstep
+ *             (VARCOEF; may be NULL for LAPLACE)
+ * The forward stages are recomputed from w_n and stored in ws (s complex
+ * stages), then the transposed stages run in reverse order:
+ * lam <- lam + conj(tau_l) A lam (A is symmetric), with the face-diffusivity
+ * derivative -Re(tau_l conj(lam_nb - lam_c)(W_nb - W_c))/h^2 of each stage
+ * accumulated per cell. Asynchronous.
+ */
+int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const double *D, double T, int s,
+                       double nu, const double *lam_next, double *lam_n, double *grad_logD,
+                       void *ws, size_t ws_bytes, hipStream_t st);
+
+/*
+ * frkc2_step_batched -- one superstep for each of nprob independent problems
+ * in a single persistent kernel launch (VARCOEF or LAPLACE, 2D or 3D).
+ *   grids  host array of nprob grids
+ *   w      host array of nprob device pointers (in/out states)
+ *   D      host array of nprob device pointers (NULL entries for LAPLACE)
+ *   T      host array of nprob superstep lengths
+ *   s      host array of nprob even stage counts (2..514)
+ *   ws     device workspace of at least frkc2_batched_workspace_bytes(...)
+ * The first call for a given problem set uploads the work descriptors and
+ * stepsize tables into ws and captures the launch into a HIP graph, which
+ * later calls with identical arguments replay. Asynchronous. A dependency
+ * wait that exceeds its bound sets a flag; the next call (or
+ * frkc2_batched_status) reports FRKC2_ETIMEOUT.
+ */
+size_t frkc2_batched_workspace_bytes(int nprob, const frkc2_grid *grids, const int *s);
+int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *const *w,
+                       const double *const *D, const double *T, const int *s, double nu,
+                       void *ws, size_t ws_bytes, hipStream_t st);
+int frkc2_batched_status(void *ws, hipStream_t st);   /* synchronises st */
+
+/*
+ * frkc2_reduce -- deterministic FP64 reductions over n elements (device x, y).
+ *   op 0: sum x_i^2    1: sum x_i    2: max x_i^2    3: sum (x_i - y_i)^2
+ *      4: sum x_i y_i
+ *   result host, synchronises st. ws needs 8 KiB.
+ */
+#define FRKC2_RED_SUMSQ 0
+#define FRKC2_RED_SUM 1
+#define FRKC2_RED_MAXSQ 2
+#define FRKC2_RED_SUMSQDIFF 3
+#define FRKC2_RED_DOT 4
+int frkc2_reduce(int op, const double *x, const double *y, size_t n, double *result,
+                 void *ws, size_t ws_bytes, hipStream_t st);
+
+/*
+ * frkc2_set_option -- tuning knobs (process-wide): FRKC2_OPT_TBLOCK sets the
+ * temporal block depth k (stages per HBM pass) of the plain 3D/2D kernels;
+ * 0 restores automatic choice. Results are identical for every k.
+ */
+#define FRKC2_OPT_TBLOCK 1
+#define FRKC2_OPT_XCD_REMAP 2
+int frkc2_set_option(int key, int value);
+
+/* Thread-local description of the last error. */
+const char *frkc2_last_error(void);
+
+/* Library version string. */
+const char *frkc2_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FRKC2_H */

@@ -1,0 +1,439 @@
+// Host orchestration and C ABI of libfrkc2 (declarations and contracts in
+// include/frkc2.h).
+//
+// A superstep (O'Sullivan, arXiv:1702.03818, Sec. 3) is s stage launches on
+// the caller's stream: the first reads the real state w, the last writes Re W^L
+// back into w, the ones between ping-pong two complex workspace buffers. The
+// stepsizes tau_l = T a_l are formed here in FP64 and passed by value. The
+// stability requirement T rho <= betabar (Sec. 2, |R| <= 1 on the spectrum)
+// is checked against a Gershgorin bound computed on the GPU.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace frkc2 {
+
+namespace {
+thread_local char g_err[512] = "";
+int g_tblock = 0;
+int g_xcd_remap = 1;
+
+constexpr size_t kAlign = 256;
+constexpr size_t kScratch = 64 * 1024;   // reduction partials + stepsize table
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int hip_fail(hipError_t e, const char *what)
+{
+    set_error("%s: HIP error %d (%s)", what, (int)e, hipGetErrorString(e));
+    return FRKC2_EHIP;
+}
+
+#define HIP_TRY(expr, what)                                   \
+    do {                                                      \
+        hipError_t e_ = (hipError_t)(expr);                   \
+        if (e_ != hipSuccess) return hip_fail(e_, what);      \
+    } while (0)
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+}  // namespace
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+bool make_kgrid(const frkc2_grid *g, KGrid &k)
+{
+    if (!g) {
+        set_error("grid is NULL");
+        return false;
+    }
+    if (g->ndim < 1 || g->ndim > 3) {
+        set_error("ndim must be 1, 2 or 3 (got %d)", g->ndim);
+        return false;
+    }
+    for (int d = 0; d < 3; ++d) {
+        const int n = g->n[d];
+        if (d < g->ndim ? n < 1 : n != 1) {
+            set_error("n[%d] = %d invalid (used dimensions >= 1, unused = 1)", d, n);
+            return false;
+        }
+    }
+    if (!(g->h > 0.0) || !std::isfinite(g->h)) {
+        set_error("h must be positive and finite");
+        return false;
+    }
+    if (g->bc != FRKC2_BC_PERIODIC && g->bc != FRKC2_BC_DIRICHLET0) {
+        set_error("unknown boundary condition %d", g->bc);
+        return false;
+    }
+    if (g->op != FRKC2_OP_LAPLACE && g->op != FRKC2_OP_VARCOEF && g->op != FRKC2_OP_POROUS2) {
+        set_error("unknown operator %d", g->op);
+        return false;
+    }
+    if (g->op == FRKC2_OP_LAPLACE && !(g->d_const >= 0.0 && std::isfinite(g->d_const))) {
+        set_error("d_const must be finite and non-negative");
+        return false;
+    }
+    const long long N = (long long)g->n[0] * g->n[1] * g->n[2];
+    if (N > (1LL << 34)) {
+        set_error("grid too large");
+        return false;
+    }
+    k.ndim = g->ndim;
+    k.bc = g->bc;
+    k.op = g->op;
+    k.inv_h2 = 1.0 / (g->h * g->h);
+    k.d_const = g->d_const;
+    if (g->ndim == 1) { k.nx = g->n[0]; k.ny = 1; k.nz = 1; }
+    else if (g->ndim == 2) { k.nx = g->n[0]; k.ny = 1; k.nz = g->n[1]; }
+    else { k.nx = g->n[0]; k.ny = g->n[1]; k.nz = g->n[2]; }
+    return true;
+}
+
+namespace {
+
+struct StepLayout {
+    size_t bufA, bufB, scratch, total;
+};
+
+StepLayout step_layout(long long N)
+{
+    StepLayout L;
+    const size_t cbytes = align_up((size_t)N * 16);
+    L.bufA = 0;
+    L.bufB = cbytes;
+    L.scratch = 2 * cbytes;
+    L.total = L.scratch + kScratch;
+    return L;
+}
+
+struct AdjLayout {
+    size_t store, lamA, lamB, gD, scratch, total;
+};
+
+AdjLayout adj_layout(long long N, int s)
+{
+    AdjLayout L;
+    const size_t cbytes = align_up((size_t)N * 16);
+    L.store = 0;
+    L.lamA = (size_t)s * cbytes;
+    L.lamB = L.lamA + cbytes;
+    L.gD = L.lamB + cbytes;
+    L.scratch = L.gD + align_up((size_t)N * 8);
+    L.total = L.scratch + kScratch;
+    return L;
+}
+
+// Gershgorin bound (2/h^2) max_c sum_f D_f; synchronises st.
+int rho_bound_impl(const KGrid &kg, const double *w, const double *D, double *partials,
+                   double *rho, hipStream_t st)
+{
+    double m;
+    if (kg.op == FRKC2_OP_LAPLACE) {
+        double sum = 0.0;
+        for (int f = 0; f < 2 * kg.ndim; ++f) sum = sum + kg.d_const;
+        m = sum;
+    } else {
+        HIP_TRY(launch_rho(kg, w, D, partials, st), "rho bound launch");
+        HIP_TRY(hipMemcpyAsync(&m, partials + kReduceBlocks, sizeof(double), hipMemcpyDeviceToHost,
+                               st),
+                "rho bound copy");
+        HIP_TRY(hipStreamSynchronize(st), "rho bound");
+    }
+    *rho = (2.0 * kg.inv_h2) * m;
+    if (!std::isfinite(*rho)) {
+        set_error("Gershgorin bound is not finite");
+        return FRKC2_ENONFINITE;
+    }
+    return FRKC2_OK;
+}
+
+bool check_s_nu(int s, double nu)
+{
+    if (s < 2 || s > kMaxStages || (s % 2) != 0) {
+        set_error("s must be even with 2 <= s <= 514 (got %d)", s);
+        return false;
+    }
+    if (!(nu >= 0.0 && nu < 1.0)) {
+        set_error("nu must lie in [0, 1) (got %g)", nu);
+        return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+int get_tblock() { return g_tblock; }
+int get_xcd_remap() { return g_xcd_remap; }
+
+}  // namespace frkc2
+
+using namespace frkc2;
+
+extern "C" const char *frkc2_last_error(void) { return g_err; }
+
+extern "C" const char *frkc2_version(void) { return "frkc2-mi355x 0.1 (gfx950, fp64)"; }
+
+extern "C" int frkc2_set_option(int key, int value)
+{
+    if (key == FRKC2_OPT_TBLOCK) {
+        if (value < 0 || value > kMaxTBlock) {
+            set_error("temporal block depth must lie in [0, %d]", kMaxTBlock);
+            return FRKC2_EINVAL;
+        }
+        g_tblock = value;
+        return FRKC2_OK;
+    }
+    if (key == FRKC2_OPT_XCD_REMAP) {
+        g_xcd_remap = value ? 1 : 0;
+        return FRKC2_OK;
+    }
+    set_error("unknown option %d", key);
+    return FRKC2_EINVAL;
+}
+
+extern "C" size_t frkc2_workspace_bytes(const frkc2_grid *g, int s, int flags)
+{
+    KGrid kg;
+    if (!make_kgrid(g, kg)) return 0;
+    if (flags == FRKC2_WS_ADJOINT) {
+        if (s < 2 || s > kMaxStages || (s % 2)) return 0;
+        return adj_layout(kg.npts(), s).total;
+    }
+    return step_layout(kg.npts()).total;
+}
+
+extern "C" int frkc2_rho_bound(const frkc2_grid *g, const double *w, const double *D, double *rho,
+                               void *ws, size_t ws_bytes, hipStream_t st)
+{
+    KGrid kg;
+    if (!make_kgrid(g, kg)) return FRKC2_EINVAL;
+    if (!rho) {
+        set_error("rho is NULL");
+        return FRKC2_EINVAL;
+    }
+    if (kg.op == FRKC2_OP_VARCOEF && !D) {
+        set_error("VARCOEF needs D");
+        return FRKC2_EINVAL;
+    }
+    if (kg.op == FRKC2_OP_POROUS2 && !w) {
+        set_error("POROUS2 needs w");
+        return FRKC2_EINVAL;
+    }
+    if (kg.op != FRKC2_OP_LAPLACE && (!ws || ws_bytes < kScratch || !aligned16(ws))) {
+        set_error("workspace needs at least %zu bytes, 16-byte aligned", kScratch);
+        return FRKC2_ENOMEM;
+    }
+    return rho_bound_impl(kg, w, D, static_cast<double *>(ws), rho, st);
+}
+
+extern "C" int frkc2_step(const frkc2_grid *g, double *w, const double *D, double T, double cfl,
+                          int s, double nu, int nsteps, void *ws, size_t ws_bytes, hipStream_t st,
+                          frkc2_step_stats *stats)
+{
+    KGrid kg;
+    if (!make_kgrid(g, kg)) return FRKC2_EINVAL;
+    if (!w) {
+        set_error("w is NULL");
+        return FRKC2_EINVAL;
+    }
+    if (kg.op == FRKC2_OP_VARCOEF && !D) {
+        set_error("VARCOEF needs D");
+        return FRKC2_EINVAL;
+    }
+    if (!check_s_nu(s, nu)) return FRKC2_EINVAL;
+    if (nsteps < 0) {
+        set_error("nsteps must be >= 0");
+        return FRKC2_EINVAL;
+    }
+    const bool fixedT = T > 0.0 && std::isfinite(T);
+    const bool adaptive = cfl > 0.0 && std::isfinite(cfl);
+    if (fixedT == adaptive || (!(T >= 0.0) || !(cfl >= 0.0))) {
+        set_error("exactly one of T and cfl must be positive and finite (T=%g, cfl=%g)", T, cfl);
+        return FRKC2_EINVAL;
+    }
+    const long long N = kg.npts();
+    const StepLayout L = step_layout(N);
+    if (!ws || ws_bytes < L.total || !aligned16(ws)) {
+        set_error("workspace needs %zu bytes (got %zu), 16-byte aligned", L.total, ws_bytes);
+        return FRKC2_ENOMEM;
+    }
+    const double *are, *aim;
+    frkc2_coeff_info info;
+    int crc = coeffs_cached(s, nu, &are, &aim, &info);
+    if (crc < 0) return crc;
+    char *base = static_cast<char *>(ws);
+    double *buf[2] = {reinterpret_cast<double *>(base + L.bufA),
+                      reinterpret_cast<double *>(base + L.bufB)};
+    double *partials = reinterpret_cast<double *>(base + L.scratch);
+    double *tau_dev = partials + 2 * (kReduceBlocks + 8);
+
+    double rho = 0.0, Tn = T;
+    static thread_local std::vector<double> tau_host;
+    for (int step = 0; step < nsteps; ++step) {
+        if (step == 0 || kg.op == FRKC2_OP_POROUS2) {
+            int rc = rho_bound_impl(kg, w, D, partials, &rho, st);
+            if (rc < 0) return rc;
+            if (adaptive) {
+                if (!(rho > 0.0)) {
+                    set_error("adaptive T needs a positive Gershgorin bound (got %g)", rho);
+                    return FRKC2_ENONFINITE;
+                }
+                Tn = (cfl * info.beta_bar) / rho;
+            }
+            if (Tn * rho > info.beta_bar) {
+                set_error("T*rho = %g exceeds beta_bar = %g", Tn * rho, info.beta_bar);
+                return FRKC2_EUNSTABLE;
+            }
+        }
+        const bool last_step = (step == nsteps - 1);
+        const bool want_stats = stats && last_step;
+        if (stage1d_lds_fits(kg) && !want_stats) {
+            tau_host.resize(2 * (size_t)s);
+            for (int l = 0; l < s; ++l) {
+                tau_host[2 * l] = Tn * are[l];
+                tau_host[2 * l + 1] = Tn * aim[l];
+            }
+            HIP_TRY(hipMemcpyAsync(tau_dev, tau_host.data(), sizeof(double) * 2 * s,
+                                   hipMemcpyHostToDevice, st),
+                    "stepsize upload");
+            HIP_TRY(launch_stage1d_lds(kg, w, w, D, tau_dev, s, 1, st), "1D stage launch");
+            continue;
+        }
+        for (int l = 0; l < s; ++l) {
+            PassArgs pa{};
+            pa.k = 1;
+            pa.D = D;
+            if (l == 0) pa.in_re = w;
+            else pa.in_c = buf[(l - 1) & 1];
+            if (l == s - 1 && !want_stats) pa.out_re = w;
+            else pa.out_c = buf[l & 1];
+            pa.tr[0] = Tn * are[l];
+            pa.ti[0] = Tn * aim[l];
+            HIP_TRY(launch_pass(kg, pa, g_tblock, st), "stage launch");
+        }
+        if (want_stats) {
+            HIP_TRY(launch_finalize(kg, buf[(s - 1) & 1], w, partials, st), "finalize launch");
+            double sums[2];
+            HIP_TRY(hipMemcpyAsync(sums, partials + 2 * kReduceBlocks, sizeof(sums),
+                                   hipMemcpyDeviceToHost, st),
+                    "stats copy");
+            HIP_TRY(hipStreamSynchronize(st), "stats");
+            stats->im_ratio = sums[1] > 0.0 ? std::sqrt(sums[0] / sums[1]) : 0.0;
+        }
+    }
+    if (stats) {
+        stats->T_last = Tn;
+        stats->rho_last = rho;
+        stats->supersteps = nsteps;
+        if (nsteps == 0) stats->im_ratio = 0.0;
+        HIP_TRY(hipStreamSynchronize(st), "step");
+    }
+    return crc;
+}
+
+extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const double *D,
+                                  double T, int s, double nu, const double *lam_next,
+                                  double *lam_n, double *grad_logD, void *ws, size_t ws_bytes,
+                                  hipStream_t st)
+{
+    KGrid kg;
+    if (!make_kgrid(g, kg)) return FRKC2_EINVAL;
+    if (kg.op == FRKC2_OP_POROUS2) {
+        set_error("the adjoint supports the linear operators (LAPLACE, VARCOEF)");
+        return FRKC2_EINVAL;
+    }
+    if (!w_n || !lam_next || !lam_n || (kg.op == FRKC2_OP_VARCOEF && !D)) {
+        set_error("w_n, lam_next, lam_n (and D for VARCOEF) must be non-NULL");
+        return FRKC2_EINVAL;
+    }
+    if (!check_s_nu(s, nu)) return FRKC2_EINVAL;
+    if (!(T > 0.0) || !std::isfinite(T)) {
+        set_error("T must be positive and finite");
+        return FRKC2_EINVAL;
+    }
+    const long long N = kg.npts();
+    const AdjLayout L = adj_layout(N, s);
+    if (!ws || ws_bytes < L.total || !aligned16(ws)) {
+        set_error("adjoint workspace needs %zu bytes (got %zu), 16-byte aligned", L.total,
+                  ws_bytes);
+        return FRKC2_ENOMEM;
+    }
+    const double *are, *aim;
+    int crc = coeffs_cached(s, nu, &are, &aim, nullptr);
+    if (crc < 0) return crc;
+    char *base = static_cast<char *>(ws);
+    const size_t cbytes = align_up((size_t)N * 16);
+    auto S = [&](int l) { return reinterpret_cast<double *>(base + L.store + (size_t)l * cbytes); };
+    double *lam[2] = {reinterpret_cast<double *>(base + L.lamA),
+                      reinterpret_cast<double *>(base + L.lamB)};
+    double *gD = reinterpret_cast<double *>(base + L.gD);
+
+    // forward recompute, storing W^0 .. W^{s-1}
+    HIP_TRY(launch_real_to_complex(N, w_n, S(0), st), "adjoint: W^0");
+    for (int l = 0; l + 1 < s; ++l) {
+        PassArgs pa{};
+        pa.k = 1;
+        pa.D = D;
+        pa.in_c = S(l);
+        pa.out_c = S(l + 1);
+        pa.tr[0] = T * are[l];
+        pa.ti[0] = T * aim[l];
+        HIP_TRY(launch_pass(kg, pa, 0, st), "adjoint: forward stage");
+    }
+    const bool vc = kg.op == FRKC2_OP_VARCOEF;
+    if (vc) HIP_TRY(launch_zero(N, gD, st), "adjoint: zero gD");
+    for (int r = 0; r < s; ++r) {
+        const int l = s - 1 - r;
+        AdjArgs a{};
+        if (r == 0) a.lam_in_re = lam_next;
+        else a.lam_in_c = lam[(r - 1) & 1];
+        if (r == s - 1) a.lam_out_re = lam_n;
+        else a.lam_out_c = lam[r & 1];
+        a.W = S(l);
+        a.D = D;
+        a.gD = vc ? gD : nullptr;
+        a.tr = T * are[l];
+        a.ti = T * aim[l];
+        HIP_TRY(launch_adjoint_stage(kg, a, st), "adjoint stage");
+    }
+    if (vc && grad_logD) HIP_TRY(launch_grad_finish(N, D, gD, grad_logD, st), "adjoint: gradient");
+    return crc;
+}
+
+extern "C" int frkc2_reduce(int op, const double *x, const double *y, size_t n, double *result,
+                            void *ws, size_t ws_bytes, hipStream_t st)
+{
+    if (op < FRKC2_RED_SUMSQ || op > FRKC2_RED_DOT) {
+        set_error("unknown reduction %d", op);
+        return FRKC2_EINVAL;
+    }
+    if (!x || !result || ((op == FRKC2_RED_SUMSQDIFF || op == FRKC2_RED_DOT) && !y)) {
+        set_error("reduction operands must be non-NULL");
+        return FRKC2_EINVAL;
+    }
+    const size_t need = sizeof(double) * (kReduceBlocks + 8);
+    if (!ws || ws_bytes < need || !aligned16(ws)) {
+        set_error("reduction workspace needs %zu bytes", need);
+        return FRKC2_ENOMEM;
+    }
+    double *partials = static_cast<double *>(ws);
+    HIP_TRY(launch_reduce(op, x, y, (long long)n, partials, st), "reduce launch");
+    HIP_TRY(hipMemcpyAsync(result, partials + kReduceBlocks, sizeof(double), hipMemcpyDeviceToHost,
+                           st),
+            "reduce copy");
+    HIP_TRY(hipStreamSynchronize(st), "reduce");
+    return FRKC2_OK;
+}

@@ -1,0 +1,310 @@
+// FRKC2 stepsizes on the host: roots of the damped second-order FRKC
+// polynomial in the internal-stability order.
+//
+// O'Sullivan, arXiv:1702.03818:
+//  * Sec. 2: the N = 2 FRKC polynomial is d0 + 2 d1 C_M(z) + 2 d2 C_2M(z)
+//    (L = 2M) and a_l = 1 / (M^2 alpha_M (1 - zeta_l)) from its roots.
+//    Maximising the real extent under the order conditions R'(0) = R''(0) = 1
+//    gives d1 = 0 and alpha_M = (4 - 1/M^2)/3, so the roots solve
+//    C_L(zeta) = -(2L^2 + 1)/(L^2 - 1):
+//        zeta_j = cos(theta_j), theta_j = (pi (2j+1) + i eta)/L,
+//        eta = arccosh((2L^2 + 1)/(L^2 - 1)),  M^2 alpha_M = (L^2 - 1)/3.
+//  * Sec. 2.1: damping nu replaces a_l by
+//        (1 - mu) / ((1 - nu) M^2 alpha_M ((1 - zeta_l) + 2 mu zeta_l)),
+//    one mu for the M roots with C_M(zeta) = +i sinh(eta/2) (odd j) and its
+//    conjugate for the others, fixed by Newton-Raphson on R'(0) = R''(0) = 1.
+//  * Sec. 2.2: greedy ordering that keeps the estimate Qbar small on L
+//    samples of [-betabar, 0], betabar = (1 - nC) beta, C = 1e-4, with n
+//    increased until the realised Q is at most 10 L^2.
+//
+// Precision: roots and damping in IEEE binary128 (libquadmath), rounded once
+// to FP64; the real extent is located by bisection on doubles with a
+// binary128 test |R| <= 1; the ordering runs in FP64 log-magnitudes.
+#include <quadmath.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+
+namespace frkc2 {
+namespace {
+
+typedef __float128 q_t;
+
+struct qc {   // binary128 complex with the few operations the construction needs
+    q_t re, im;
+};
+inline qc operator+(qc a, qc b) { return {a.re + b.re, a.im + b.im}; }
+inline qc operator-(qc a, qc b) { return {a.re - b.re, a.im - b.im}; }
+inline qc operator*(qc a, qc b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+inline qc operator*(q_t a, qc b) { return {a * b.re, a * b.im}; }
+inline qc operator/(qc a, qc b)
+{
+    q_t d = b.re * b.re + b.im * b.im;
+    return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
+const double kShrinkC = 1e-4;
+const int kShrinkMax = 64;
+const double kTieRel = 1e-12;
+
+// Odd-j roots zeta_j and 1 - zeta_j = 2 sin^2(theta_j/2) (no cancellation).
+void first_group_roots(int L, std::vector<qc> &zeta, std::vector<qc> &one_minus)
+{
+    q_t L2 = (q_t)L * (q_t)L;
+    q_t eta = acoshq((2 * L2 + 1) / (L2 - 1));
+    q_t v = eta / L;
+    zeta.clear();
+    one_minus.clear();
+    for (int j = 1; j < L; j += 2) {
+        q_t u = M_PIq * (2 * j + 1) / L;
+        qc z = {cosq(u) * coshq(v), -sinq(u) * sinhq(v)};
+        qc sh = {sinq(u / 2) * coshq(v / 2), cosq(u / 2) * sinhq(v / 2)};
+        qc om = (q_t)2 * (sh * sh);
+        zeta.push_back(z);
+        one_minus.push_back(om);
+    }
+}
+
+// Newton-Raphson for mu (Sec. 2.1); returns the first-group stepsizes.
+std::vector<qc> damp(int L, double nu, qc &mu_out)
+{
+    std::vector<qc> z, om;
+    first_group_roots(L, z, om);
+    const size_t M = z.size();
+    q_t K = (q_t)3 / (((q_t)1 - (q_t)nu) * ((q_t)L * (q_t)L - 1));
+    qc mu = {0, 0};
+    std::vector<qc> a(M), da(M);
+    for (int it = 0; it < 100; ++it) {
+        qc F = {0, 0}, G = {0, 0}, Fp = {0, 0}, Gp = {0, 0};
+        for (size_t i = 0; i < M; ++i) {
+            qc den = om[i] + (q_t)2 * (mu * z[i]);
+            qc one = {1, 0};
+            a[i] = K * ((one - mu) / den);
+            da[i] = ((q_t)-1 * K) * ((one + z[i]) / (den * den));
+            F = F + a[i];
+            G = G + a[i] * a[i];
+            Fp = Fp + da[i];
+            Gp = Gp + (q_t)2 * (a[i] * da[i]);
+        }
+        // equations 2 Re F = 1, 2 Re G = 0; d Re H/d Re mu = Re H', d Re H/d Im mu = -Im H'
+        q_t e1 = 2 * F.re - 1, e2 = 2 * G.re;
+        q_t j11 = 2 * Fp.re, j12 = -2 * Fp.im, j21 = 2 * Gp.re, j22 = -2 * Gp.im;
+        q_t det = j11 * j22 - j12 * j21;
+        q_t dp = (e1 * j22 - j12 * e2) / det;
+        q_t dq = (j11 * e2 - j21 * e1) / det;
+        mu.re -= dp;
+        mu.im -= dq;
+        if (fabsq(dp) + fabsq(dq) <= 1e-30Q) break;
+    }
+    for (size_t i = 0; i < M; ++i) {
+        qc one = {1, 0};
+        a[i] = K * ((one - mu) / (om[i] + (q_t)2 * (mu * z[i])));
+    }
+    mu_out = mu;
+    return a;
+}
+
+// sum over the first group of log|1 + a x| (|R(x)| = exp(2 * this) for real x)
+double log_abs_half(const std::vector<double> &ar, const std::vector<double> &ai, double x)
+{
+    double s = 0.0;
+    for (size_t i = 0; i < ar.size(); ++i) s += std::log(std::hypot(1.0 + ar[i] * x, ai[i] * x));
+    return s;
+}
+
+bool stable_q(const std::vector<double> &ar, const std::vector<double> &ai, double b)
+{
+    q_t x = -(q_t)b, p = 1;
+    for (size_t i = 0; i < ar.size(); ++i) {
+        q_t re = 1 + (q_t)ar[i] * x, im = (q_t)ai[i] * x;
+        p *= re * re + im * im;
+    }
+    return p <= 1 + 1e-20Q;
+}
+
+// Largest double b with |R(-x)| <= 1 on [0, b]: scan dense where C_L
+// oscillates fastest (8 samples per half period in z, then past z = -1), then
+// bisect on doubles with the binary128 test.
+double real_extent(const std::vector<double> &ar, const std::vector<double> &ai, int L)
+{
+    double beta0 = 2.0 * (double)(L * L - 1) / 3.0;
+    std::vector<double> xs;
+    for (int k = 1; k <= 8 * L; ++k) {
+        double zk = std::cos((double)k * M_PI / (double)(8 * L));
+        xs.push_back((zk - 1.0) * (beta0 / 2.0));
+    }
+    for (int j = 1; j <= 40; ++j) xs.push_back(-beta0 * (1.0 + 1e-3 * j));
+    size_t i = 0;
+    for (; i < xs.size(); ++i)
+        if (2.0 * log_abs_half(ar, ai, xs[i]) > 1e-12) break;
+    if (i == xs.size()) return -1.0;
+    double lo = (i == 0) ? 0.0 : -xs[i - 1];
+    double hi = -xs[i];
+    for (;;) {
+        double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        if (stable_q(ar, ai, mid)) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Greedy order of the first group on Qbar (Sec. 2.2). Returns indices.
+std::vector<int> greedy(const std::vector<double> &ar, const std::vector<double> &ai,
+                        double beta_bar, int L)
+{
+    const int M = (int)ar.size();
+    std::vector<double> lv((size_t)M * L);
+    for (int k = 1; k <= L; ++k) {
+        double x = -(beta_bar * (double)k) / (double)L;
+        for (int j = 0; j < M; ++j)
+            lv[(size_t)j * L + (k - 1)] = std::log(std::hypot(1.0 + ar[j] * x, ai[j] * x));
+    }
+    std::vector<double> placed(L, 0.0), rest(L);
+    std::vector<int> S(M), order;
+    for (int j = 0; j < M; ++j) S[j] = j;
+    std::vector<double> score;
+    for (int step = 0; step < M; ++step) {
+        std::fill(rest.begin(), rest.end(), 0.0);
+        for (int c : S)
+            for (int k = 0; k < L; ++k) rest[k] += lv[(size_t)c * L + k];
+        score.assign(S.size(), 0.0);
+        double m = INFINITY;
+        for (size_t ci = 0; ci < S.size(); ++ci) {
+            const double *v = &lv[(size_t)S[ci] * L];
+            double sc = 0.0;
+            for (int k = 0; k < L; ++k) {
+                double pre = placed[k] + v[k], suf = rest[k] - v[k];
+                sc += std::exp(pre > suf ? pre : suf);
+            }
+            score[ci] = sc;
+            if (sc < m) m = sc;
+        }
+        size_t pick = 0;
+        while (!(score[pick] <= m * (1.0 + kTieRel))) ++pick;
+        int c = S[pick];
+        S.erase(S.begin() + pick);
+        order.push_back(c);
+        for (int k = 0; k < L; ++k) placed[k] += lv[(size_t)c * L + k];
+    }
+    return order;
+}
+
+// Realised Q: max over x on max(4000, 10 L) points of [-beta, 0] of the best
+// contiguous run of log|1 + a_l x| (Kadane).
+double realised_q(const std::vector<std::complex<double>> &seq, double beta, int L)
+{
+    int G = std::max(4000, 10 * L);
+    double step = (0.0 - (-beta)) / (double)(G - 1);
+    double best = -INFINITY;
+    for (int g = 0; g < G; ++g) {
+        double x = (g == G - 1) ? 0.0 : -beta + (double)g * step;
+        double cur = 0.0, bx = -INFINITY;
+        for (size_t l = 0; l < seq.size(); ++l) {
+            double t = std::log(std::abs(1.0 + seq[l] * x));
+            cur = std::max(t, cur + t);
+            bx = std::max(bx, cur);
+        }
+        best = std::max(best, bx);
+    }
+    return std::exp(best);
+}
+
+struct Entry {
+    std::vector<double> re, im;
+    frkc2_coeff_info info;
+    int status;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, double>, Entry> g_cache;
+
+Entry compute(int s, double nu)
+{
+    const int L = s;
+    Entry e;
+    qc mu;
+    std::vector<qc> aq = damp(L, nu, mu);
+    std::vector<double> ar(aq.size()), ai(aq.size());
+    for (size_t i = 0; i < aq.size(); ++i) {
+        ar[i] = (double)aq[i].re;
+        ai[i] = (double)aq[i].im;
+    }
+    double beta = real_extent(ar, ai, L);
+    double bound = 10.0 * (double)L * (double)L;
+    double best_q = INFINITY, best_bb = 0.0;
+    int best_n = 0;
+    std::vector<std::complex<double>> best_seq;
+    for (int n = 1; n <= kShrinkMax; ++n) {
+        double beta_bar = (1.0 - n * kShrinkC) * beta;
+        std::vector<int> ord = greedy(ar, ai, beta_bar, L);
+        std::vector<std::complex<double>> seq;
+        for (int j : ord) seq.emplace_back(ar[j], ai[j]);
+        for (int j : ord) seq.emplace_back(ar[j], -ai[j]);
+        double q = realised_q(seq, beta, L);
+        if (q < best_q) {
+            best_q = q;
+            best_n = n;
+            best_bb = beta_bar;
+            best_seq = seq;
+        }
+        if (q <= bound) break;
+    }
+    for (auto &c : best_seq) {
+        e.re.push_back(c.real());
+        e.im.push_back(c.imag());
+    }
+    e.info.beta = beta;
+    e.info.beta_bar = best_bb;
+    e.info.q_realised = best_q;
+    e.info.mu_re = (double)mu.re;
+    e.info.mu_im = (double)mu.im;
+    e.info.n_shrink = best_n;
+    e.info.q_bound_met = best_q <= bound;
+    e.status = e.info.q_bound_met ? FRKC2_OK : FRKC2_WQBOUND;
+    return e;
+}
+
+}  // namespace
+
+int coeffs_cached(int s, double nu, const double **re, const double **im, frkc2_coeff_info *info)
+{
+    if (s < 2 || s > kMaxStages || (s % 2) != 0) {
+        set_error("frkc2_coeffs: s must be even with 2 <= s <= 514 (got %d)", s);
+        return FRKC2_EINVAL;
+    }
+    if (!(nu >= 0.0 && nu < 1.0)) {
+        set_error("frkc2_coeffs: nu must lie in [0, 1) (got %g)", nu);
+        return FRKC2_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_pair(s, nu);
+    auto it = g_cache.find(key);
+    if (it == g_cache.end()) it = g_cache.emplace(key, compute(s, nu)).first;
+    if (it->second.info.beta <= 0.0) {
+        set_error("frkc2_coeffs: no end of the stability interval found for s=%d", s);
+        return FRKC2_EINVAL;
+    }
+    if (re) *re = it->second.re.data();
+    if (im) *im = it->second.im.data();
+    if (info) *info = it->second.info;
+    return it->second.status;
+}
+
+}  // namespace frkc2
+
+extern "C" int frkc2_coeffs(int s, double nu, double *a_re, double *a_im, frkc2_coeff_info *info)
+{
+    const double *re = nullptr, *im = nullptr;
+    int rc = frkc2::coeffs_cached(s, nu, &re, &im, info);
+    if (rc < 0) return rc;
+    if (a_re) std::memcpy(a_re, re, sizeof(double) * (size_t)s);
+    if (a_im) std::memcpy(a_im, im, sizeof(double) * (size_t)s);
+    return rc;
+}

@@ -1,0 +1,106 @@
+// Device helpers shared by the stage, adjoint and batched kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace frkc2 {
+namespace dev {
+
+enum { LAP = FRKC2_OP_LAPLACE, VAR = FRKC2_OP_VARCOEF, POR = FRKC2_OP_POROUS2 };
+enum { PER = FRKC2_BC_PERIODIC, DIR = FRKC2_BC_DIRICHLET0 };
+
+struct Dims {
+    int nx, ny, nz;
+};
+
+__device__ __forceinline__ int xcd_remap(int bid, int nb)
+{
+    // Dispatch places block b on XCD b % 8. Give XCD i the logical blocks
+    // [i*per, (i+1)*per) so that tiles sharing halos share an L2.
+    const int per = nb >> 3;
+    if (bid >= (per << 3)) return bid;
+    return (bid & 7) * per + (bid >> 3);
+}
+
+__device__ __forceinline__ int wrap(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Flat index of (gx, gy, gz) after applying the boundary condition; -1 for a
+// Dirichlet ghost outside the grid.
+template <int BC>
+__device__ __forceinline__ long long bc_index(const Dims &d, int gx, int gy, int gz)
+{
+    if (BC == PER) {
+        gx = wrap(gx, d.nx);
+        gy = wrap(gy, d.ny);
+        gz = wrap(gz, d.nz);
+    } else if (gx < 0 || gx >= d.nx || gy < 0 || gy >= d.ny || gz < 0 || gz >= d.nz) {
+        return -1;
+    }
+    return gx + (long long)d.nx * (gy + (long long)d.ny * gz);
+}
+
+// Complex value at (gx, gy, gz); a real input is read as (w, 0); a Dirichlet
+// ghost is 0.
+template <int BC, bool IN_REAL>
+__device__ __forceinline__ double2 load_c(const Dims &d, const double *re, const double2 *c,
+                                          int gx, int gy, int gz)
+{
+    const long long i = bc_index<BC>(d, gx, gy, gz);
+    if (i < 0) return make_double2(0.0, 0.0);
+    if (IN_REAL) return make_double2(re[i], 0.0);
+    return c[i];
+}
+
+// Real value at (gx, gy, gz); 0 for a Dirichlet ghost (a ghost face takes the
+// boundary cell's own diffusivity, so this value is never used).
+template <int BC>
+__device__ __forceinline__ double load_r(const Dims &d, const double *v, int gx, int gy, int gz)
+{
+    const long long i = bc_index<BC>(d, gx, gy, gz);
+    return i < 0 ? 0.0 : v[i];
+}
+
+// One face of the flux sum of the diffusion operator, in the fixed order the
+// library and its CPU check share. nb: neighbour value (0 for a Dirichlet
+// ghost); dc, dn: cell and neighbour diffusivity; ghost selects D_f = D_c,
+// which equals (D_c + D_c)/2 bit for bit.
+template <int OP>
+__device__ __forceinline__ void face(double &acc_r, double &acc_i, double2 c, double2 nb,
+                                     double dc, double dn, bool ghost, double qr_c, double qi_c,
+                                     double d_const)
+{
+    const double dr = nb.x - c.x;
+    const double di = nb.y - c.y;
+    if (OP == POR) {
+        const double qr_n = nb.x * nb.x - nb.y * nb.y;
+        const double qi_n = 2.0 * (nb.x * nb.y);
+        const double Dr = 0.5 * (qr_c + qr_n);
+        const double Di = 0.5 * (qi_c + qi_n);
+        acc_r = acc_r + (Dr * dr - Di * di);
+        acc_i = acc_i + (Dr * di + Di * dr);
+    } else {
+        double Df;
+        if (OP == LAP) Df = d_const;
+        else Df = ghost ? dc : 0.5 * (dc + dn);
+        acc_r = acc_r + Df * dr;
+        acc_i = acc_i + Df * di;
+    }
+}
+
+// Forward Euler update W + tau f with f = acc * inv_h2.
+__device__ __forceinline__ double2 euler(double2 c, double acc_r, double acc_i, double inv_h2,
+                                         double tr, double ti)
+{
+    const double fr = acc_r * inv_h2;
+    const double fi = acc_i * inv_h2;
+    return make_double2(c.x + (tr * fr - ti * fi), c.y + (tr * fi + ti * fr));
+}
+
+}  // namespace dev
+}  // namespace frkc2

@@ -1,0 +1,95 @@
+// Internal declarations shared by the host and kernel translation units of
+// libfrkc2. Not part of the public ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/frkc2.h"
+
+namespace frkc2 {
+
+constexpr int kMaxStages = 514;     // M <= 257 (the paper's table range)
+constexpr int kMaxTBlock = 8;       // stages fused into one HBM pass
+
+void set_error(const char *fmt, ...);
+
+// Cached ordered stepsizes (host pointers valid for the process lifetime).
+int coeffs_cached(int s, double nu, const double **re, const double **im, frkc2_coeff_info *info);
+
+// Grid description as the kernels see it. For ndim = 1 and 2 the last used
+// dimension is the "march" dimension: (nx, ny, nz) = (n0, 1, 1) in 1D,
+// (n0, 1, n1) in 2D and (n0, n1, n2) in 3D, so that index = x + nx*(y + ny*z)
+// equals the public flat index in every case.
+struct KGrid {
+    int ndim, nx, ny, nz;
+    int bc, op;
+    double inv_h2, d_const;
+    long long npts() const { return (long long)nx * ny * nz; }
+};
+
+bool make_kgrid(const frkc2_grid *g, KGrid &k);
+
+// One pass of k consecutive stages over the whole grid.
+struct PassArgs {
+    const double *in_re;        // real input (first pass) or nullptr
+    const double *in_c;         // complex input, interleaved (re, im), or nullptr
+    double *out_re;             // real output (last pass) or nullptr
+    double *out_c;              // complex output, interleaved, or nullptr
+    const double *D;            // diffusivity (VARCOEF) or nullptr
+    double tr[kMaxTBlock];      // tau_l = T a_l of the pass's stages
+    double ti[kMaxTBlock];
+    int k;                      // stages in this pass
+};
+
+// Launchers (stage.hip). Return hipError_t as int.
+int launch_pass(const KGrid &g, const PassArgs &a, int tblock_hint, hipStream_t st);
+int launch_stage1d_lds(const KGrid &g, const double *w_in, double *w_out, const double *D,
+                       const double *tau, int s, int nsteps, hipStream_t st);
+bool stage1d_lds_fits(const KGrid &g);
+int launch_finalize(const KGrid &g, const double *in_c, double *out_re, double *partials,
+                    hipStream_t st);
+int launch_real_to_complex(long long n, const double *in, double *out_c, hipStream_t st);
+int launch_zero(long long n, double *p, hipStream_t st);   // fill kernel (graph-safe)
+
+// Reductions (reduce.hip). partials must hold kReduceBlocks doubles + 2.
+constexpr int kReduceBlocks = 512;
+int launch_reduce(int op, const double *x, const double *y, long long n, double *partials,
+                  hipStream_t st);
+int launch_rho(const KGrid &g, const double *w, const double *D, double *partials, hipStream_t st);
+
+// Adjoint (adjoint.hip).
+struct AdjArgs {
+    const double *lam_in_re;    // real lambda (first reverse stage) or nullptr
+    const double *lam_in_c;     // complex lambda^{l+1}
+    double *lam_out_re;         // real lambda^0 (last reverse stage) or nullptr
+    double *lam_out_c;          // complex lambda^l
+    const double *W;            // stored complex stage W^l
+    const double *D;
+    double *gD;                 // per-cell dJ/dD accumulator (VARCOEF) or nullptr
+    double tr, ti;
+};
+int launch_adjoint_stage(const KGrid &g, const AdjArgs &a, hipStream_t st);
+int launch_grad_finish(long long n, const double *D, const double *gD, double *grad_logD,
+                       hipStream_t st);
+
+// Batched persistent kernel (batched.hip).
+struct BatchProblem {           // one problem's descriptor in device memory
+    double *w;                  // caller state (real)
+    const double *D;
+    double *bufA, *bufB;        // complex ping-pong buffers in the workspace
+    const double *tau;          // 2*s doubles (re, im interleaved)
+    int nx, ny, nz, ndim, bc, op;
+    int s, ntiles, first_item;
+    double inv_h2, d_const;
+};
+struct BatchItem {              // one (problem, stage, tile) unit of work
+    int prob, stage, tile, pad;
+};
+int launch_batched(const BatchProblem *probs, const BatchItem *items, int nitems,
+                   unsigned int *counters, unsigned int *queue_head, int *error_flag,
+                   int nprob, int grid, hipStream_t st);
+int batched_tile_shape(int ndim, int *bx, int *by, int *bz);
+int batched_max_grid();
+
+}  // namespace frkc2

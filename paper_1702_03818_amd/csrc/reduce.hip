@@ -1,0 +1,182 @@
+// Deterministic FP64 reductions for norms, the loss and the Gershgorin bound.
+//
+// First pass: a fixed grid of kReduceBlocks workgroups strides over the
+// input; each thread accumulates in a fixed order, the wavefront folds its 64
+// lanes with cross-lane shuffles, the waves of a workgroup combine through
+// LDS, and each workgroup writes one partial. Second pass: one workgroup folds
+// the partials in index order. The grid is fixed, so the summation order (and
+// the result) does not depend on the device or the run.
+//
+// The Gershgorin bound (stability requirement T rho <= betabar of Sec. 2,
+// |R(T lambda)| <= 1 on the spectrum) is rho = (2/h^2) max_c sum_f D_f with the
+// operator's own face diffusivity, faces in the order x-, x+, y-, y+, z-, z+.
+// A maximum is exact in any order.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace frkc2 {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+enum { R_SUMSQ = FRKC2_RED_SUMSQ, R_SUM = FRKC2_RED_SUM, R_MAXSQ = FRKC2_RED_MAXSQ,
+       R_SQDIFF = FRKC2_RED_SUMSQDIFF, R_DOT = FRKC2_RED_DOT, R_MAX = 100 };
+
+template <int OP>
+__device__ __forceinline__ double combine(double a, double b)
+{
+    if (OP == R_MAXSQ || OP == R_MAX) return a > b ? a : b;
+    return a + b;
+}
+
+template <int OP>
+__device__ __forceinline__ double block_reduce(double v)
+{
+    __shared__ double s[kWaves];
+    for (int off = 32; off > 0; off >>= 1) v = combine<OP>(v, __shfl_xor(v, off, 64));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) s[wave] = v;
+    __syncthreads();
+    double r = s[0];
+    for (int i = 1; i < kWaves; ++i) r = combine<OP>(r, s[i]);
+    return r;
+}
+
+template <int OP>
+__global__ __launch_bounds__(kThreads) void reduce_pass1(const double *x, const double *y,
+                                                         long long n, double *partials)
+{
+    double acc = 0.0;
+    for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kThreads) {
+        const double v = x[i];
+        double t;
+        if (OP == R_SUMSQ || OP == R_MAXSQ) t = v * v;
+        else if (OP == R_SUM) t = v;
+        else if (OP == R_SQDIFF) {
+            const double d = v - y[i];
+            t = d * d;
+        } else if (OP == R_DOT) t = v * y[i];
+        else t = v;
+        acc = combine<OP>(acc, t);
+    }
+    const double r = block_reduce<OP>(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+template <int OP>
+__global__ __launch_bounds__(kThreads) void reduce_pass2(double *partials, int nb)
+{
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kThreads) acc = combine<OP>(acc, partials[i]);
+    const double r = block_reduce<OP>(acc);
+    if (threadIdx.x == 0) partials[nb] = r;
+}
+
+// per-cell sum of face diffusivities, then max
+template <int OP, int BC, int NDIM>
+__global__ __launch_bounds__(kThreads) void rho_pass1(const double *w, const double *D, int nx,
+                                                      int ny, int nz, double d_const,
+                                                      double *partials)
+{
+    const long long n = (long long)nx * ny * nz;
+    double m = 0.0;
+    for (long long p = blockIdx.x * (long long)kThreads + threadIdx.x; p < n;
+         p += (long long)gridDim.x * kThreads) {
+        const int x = (int)(p % nx);
+        const int y = (int)((p / nx) % ny);
+        const int z = (int)(p / ((long long)nx * ny));
+        double sum = 0.0;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int d = f >> 1;
+            if (NDIM == 1 && d > 0) continue;
+            if (NDIM == 2 && d == 1) continue;   // 2D grids march in z
+            int j[3] = {x, y, z};
+            const int nd[3] = {nx, ny, nz};
+            j[d] += (f & 1) ? 1 : -1;
+            bool ghost = false;
+            if (j[d] < 0 || j[d] >= nd[d]) {
+                if (BC == FRKC2_BC_DIRICHLET0) ghost = true;
+                else j[d] = (j[d] + nd[d]) % nd[d];
+            }
+            const long long q = ghost ? p : j[0] + (long long)nx * (j[1] + (long long)ny * j[2]);
+            double Df;
+            if (OP == FRKC2_OP_LAPLACE) {
+                Df = d_const;
+            } else if (OP == FRKC2_OP_VARCOEF) {
+                Df = 0.5 * (D[p] + (ghost ? D[p] : D[q]));
+            } else {
+                const double un = ghost ? 0.0 : w[q];
+                Df = 0.5 * (w[p] * w[p] + un * un);
+            }
+            sum = sum + Df;
+        }
+        m = m > sum ? m : sum;
+    }
+    const double r = block_reduce<R_MAX>(m);
+    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+template <int OP>
+int launch_red(const double *x, const double *y, long long n, double *partials, hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_pass1<OP>, dim3(kReduceBlocks), dim3(kThreads), 0, st, x, y, n,
+                       partials);
+    hipLaunchKernelGGL(reduce_pass2<OP>, dim3(1), dim3(kThreads), 0, st, partials,
+                       kReduceBlocks);
+    return (int)hipGetLastError();
+}
+
+template <int OP, int BC>
+int launch_rho_t(const KGrid &g, const double *w, const double *D, double *partials,
+                 hipStream_t st)
+{
+    dim3 grid(kReduceBlocks), block(kThreads);
+    if (g.ndim == 3)
+        hipLaunchKernelGGL((rho_pass1<OP, BC, 3>), grid, block, 0, st, w, D, g.nx, g.ny, g.nz,
+                           g.d_const, partials);
+    else if (g.ndim == 2)
+        hipLaunchKernelGGL((rho_pass1<OP, BC, 2>), grid, block, 0, st, w, D, g.nx, g.ny, g.nz,
+                           g.d_const, partials);
+    else
+        hipLaunchKernelGGL((rho_pass1<OP, BC, 1>), grid, block, 0, st, w, D, g.nx, g.ny, g.nz,
+                           g.d_const, partials);
+    hipLaunchKernelGGL(reduce_pass2<R_MAX>, dim3(1), dim3(kThreads), 0, st, partials,
+                       kReduceBlocks);
+    return (int)hipGetLastError();
+}
+
+template <int OP>
+int launch_rho_bc(const KGrid &g, const double *w, const double *D, double *partials,
+                  hipStream_t st)
+{
+    if (g.bc == FRKC2_BC_PERIODIC) return launch_rho_t<OP, FRKC2_BC_PERIODIC>(g, w, D, partials, st);
+    return launch_rho_t<OP, FRKC2_BC_DIRICHLET0>(g, w, D, partials, st);
+}
+
+}  // namespace
+
+int launch_reduce(int op, const double *x, const double *y, long long n, double *partials,
+                  hipStream_t st)
+{
+    switch (op) {
+    case R_SUMSQ: return launch_red<R_SUMSQ>(x, y, n, partials, st);
+    case R_SUM: return launch_red<R_SUM>(x, y, n, partials, st);
+    case R_MAXSQ: return launch_red<R_MAXSQ>(x, y, n, partials, st);
+    case R_SQDIFF: return launch_red<R_SQDIFF>(x, y, n, partials, st);
+    case R_DOT: return launch_red<R_DOT>(x, y, n, partials, st);
+    default: return (int)hipErrorInvalidValue;
+    }
+}
+
+int launch_rho(const KGrid &g, const double *w, const double *D, double *partials, hipStream_t st)
+{
+    if (g.op == FRKC2_OP_LAPLACE) return launch_rho_bc<FRKC2_OP_LAPLACE>(g, w, D, partials, st);
+    if (g.op == FRKC2_OP_VARCOEF) return launch_rho_bc<FRKC2_OP_VARCOEF>(g, w, D, partials, st);
+    return launch_rho_bc<FRKC2_OP_POROUS2>(g, w, D, partials, st);
+}
+
+}  // namespace frkc2

@@ -1,0 +1,443 @@
+// FRKC2 stage kernels for gfx950: one forward Euler step with a complex
+// stepsize, W <- W + tau f(W) (O'Sullivan, arXiv:1702.03818, Sec. 3, the
+// Euler-step equation of the FRKC2 scheme), with the diffusion operator f
+// fused into the update.
+//
+// Data layout in HBM: the real state w and the diffusivity D are the
+// caller's flat FP64 arrays (x fastest); complex stage values live in
+// workspace buffers as interleaved (re, im) pairs, 16 B per point, so one
+// 128-bit load or store moves a whole complex value.
+//
+// plane_stage: a workgroup owns a BX x BY tile of the (x, y) plane and marches
+// through a chunk of z planes. The z-neighbours of a point stay in registers
+// (planes z-1, z, z+1 of the thread's own column); the x/y neighbours come
+// from an LDS copy of plane z with a one-cell halo, double-buffered so one
+// barrier per plane suffices; the halo of the next plane is prefetched into
+// registers while the current plane is computed. Every input value is read
+// from HBM once per pass except the tile halos, which are shared through L2:
+// the block index is remapped so that each XCD receives a contiguous range of
+// tiles (round-robin dispatch would scatter neighbouring tiles over all eight
+// L2 caches). 2D grids march along their second dimension with BY = 1; 1D
+// grids use a single plane.
+//
+// Arithmetic order (identical in every kernel and in the CPU check):
+// faces x-, x+, y-, y+, z-, z+; acc = acc + Df*(W_nb - W_c) per face
+// (POROUS2: acc_r = acc_r + (Dr*dr - Di*di), acc_i = acc_i + (Dr*di + Di*dr));
+// f = acc*inv_h2; W_r + (tr*f_r - ti*f_i), W_i + (tr*f_i + ti*f_r). The library
+// is compiled with -ffp-contract=off, so nothing is fused and the result is
+// independent of the tile shape.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace frkc2 {
+namespace {
+
+using namespace dev;
+
+struct PlaneArgs {
+    const double *in_re;
+    const double2 *in_c;
+    double *out_re;
+    double2 *out_c;
+    const double *D;
+    int nx, ny, nz;
+    int zchunk, ntx, nty;
+    double inv_h2, d_const, tr, ti;
+};
+
+template <int BC, bool IN_REAL>
+__device__ __forceinline__ double2 load_w(const PlaneArgs &a, int gx, int gy, int gz)
+{
+    return load_c<BC, IN_REAL>(Dims{a.nx, a.ny, a.nz}, a.in_re, a.in_c, gx, gy, gz);
+}
+
+template <int BC>
+__device__ __forceinline__ double load_d(const PlaneArgs &a, int gx, int gy, int gz)
+{
+    return load_r<BC>(Dims{a.nx, a.ny, a.nz}, a.D, gx, gy, gz);
+}
+
+template <int OP, int BC, int NDIM, int BX, int BY, bool IN_REAL, bool OUT_REAL>
+__global__ __launch_bounds__(BX *BY) void plane_stage(PlaneArgs a)
+{
+    constexpr int SX = BX + 2;
+    constexpr int SY = (NDIM == 3) ? BY + 2 : 1;   // 1D/2D tiles need only the x halo
+    constexpr int NT = BX * BY;
+    constexpr int NH = 2 * BY + (NDIM == 3 ? 2 * BX : 0);   // halo cells per plane
+    static_assert(NH <= NT, "one halo cell per thread at most");
+    __shared__ double2 sW[2][SY * SX];
+    __shared__ double sD[2][(OP == VAR) ? SY * SX : 1];
+
+    const int tid = threadIdx.x;
+    const int tx = tid % BX, ty = tid / BX;
+    int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = lb % a.ntx;
+    lb /= a.ntx;
+    const int by = lb % a.nty;
+    const int bz = lb / a.nty;
+    const int x0 = bx * BX, y0 = by * BY;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool active = x < a.nx && y < a.ny;
+    const int z0 = bz * a.zchunk;
+    const int z1 = min(z0 + a.zchunk, a.nz);
+
+    // this thread's halo cell (if any), as plane-local (hx, hy)
+    int hx = 0, hy = 0;
+    const bool has_halo = tid < NH;
+    if (has_halo) {
+        if (tid < 2 * BY) {
+            hy = tid % BY;
+            hx = (tid < BY) ? -1 : BX;
+        } else {
+            const int hh = tid - 2 * BY;
+            hx = hh % BX;
+            hy = (hh < BX) ? -1 : BY;
+        }
+    }
+    const int hslot = (NDIM == 3 ? (hy + 1) * SX : 0) + (hx + 1);
+    const int oslot = (NDIM == 3 ? (ty + 1) * SX : 0) + (tx + 1);
+
+    // own column: planes z-1, z, z+1 (ghost or wrapped at the domain ends)
+    double2 Wm = load_w<BC, IN_REAL>(a, x, y, z0 - 1);
+    double2 Wc = load_w<BC, IN_REAL>(a, x, y, z0);
+    double2 Wp = load_w<BC, IN_REAL>(a, x, y, z0 + 1);
+    double Dm = 0.0, Dc = 0.0, Dp = 0.0;
+    if (OP == VAR) {
+        Dm = load_d<BC>(a, x, y, z0 - 1);
+        Dc = load_d<BC>(a, x, y, z0);
+        Dp = load_d<BC>(a, x, y, z0 + 1);
+    }
+    double2 hW = make_double2(0.0, 0.0);
+    double hD = 0.0;
+    if (has_halo) {
+        hW = load_w<BC, IN_REAL>(a, x0 + hx, y0 + hy, z0);
+        if (OP == VAR) hD = load_d<BC>(a, x0 + hx, y0 + hy, z0);
+    }
+
+    for (int z = z0; z < z1; ++z) {
+        const int b = z & 1;
+        sW[b][oslot] = Wc;
+        if (OP == VAR) sD[b][oslot] = Dc;
+        if (has_halo) {
+            sW[b][hslot] = hW;
+            if (OP == VAR) sD[b][hslot] = hD;
+        }
+        __syncthreads();
+        // prefetch the next plane's halo cell
+        if (has_halo && z + 1 < z1) {
+            hW = load_w<BC, IN_REAL>(a, x0 + hx, y0 + hy, z + 1);
+            if (OP == VAR) hD = load_d<BC>(a, x0 + hx, y0 + hy, z + 1);
+        }
+        if (active) {
+            const double2 c = Wc;
+            double qr_c = 0.0, qi_c = 0.0;
+            if (OP == POR) {
+                qr_c = c.x * c.x - c.y * c.y;
+                qi_c = 2.0 * (c.x * c.y);
+            }
+            double acc_r = 0.0, acc_i = 0.0;
+            const bool dir = (BC == DIR);
+            face<OP>(acc_r, acc_i, c, sW[b][oslot - 1], Dc, (OP == VAR) ? sD[b][oslot - 1] : 0.0,
+                     dir && x == 0, qr_c, qi_c, a.d_const);
+            face<OP>(acc_r, acc_i, c, sW[b][oslot + 1], Dc, (OP == VAR) ? sD[b][oslot + 1] : 0.0,
+                     dir && x == a.nx - 1, qr_c, qi_c, a.d_const);
+            if (NDIM == 3) {
+                face<OP>(acc_r, acc_i, c, sW[b][oslot - SX], Dc,
+                         (OP == VAR) ? sD[b][oslot - SX] : 0.0, dir && y == 0, qr_c, qi_c,
+                         a.d_const);
+                face<OP>(acc_r, acc_i, c, sW[b][oslot + SX], Dc,
+                         (OP == VAR) ? sD[b][oslot + SX] : 0.0, dir && y == a.ny - 1, qr_c, qi_c,
+                         a.d_const);
+            }
+            if (NDIM >= 2) {
+                face<OP>(acc_r, acc_i, c, Wm, Dc, Dm, dir && z == 0, qr_c, qi_c, a.d_const);
+                face<OP>(acc_r, acc_i, c, Wp, Dc, Dp, dir && z == a.nz - 1, qr_c, qi_c,
+                         a.d_const);
+            }
+            const double2 nv = euler(c, acc_r, acc_i, a.inv_h2, a.tr, a.ti);
+            const long long i = x + (long long)a.nx * (y + (long long)a.ny * z);
+            if (OUT_REAL) a.out_re[i] = nv.x;
+            else a.out_c[i] = nv;
+        }
+        Wm = Wc;
+        Wc = Wp;
+        if (OP == VAR) {
+            Dm = Dc;
+            Dc = Dp;
+        }
+        if (z + 1 < z1) {
+            Wp = load_w<BC, IN_REAL>(a, x, y, z + 2);
+            if (OP == VAR) Dp = load_d<BC>(a, x, y, z + 2);
+        }
+    }
+}
+
+// Whole 1D grid resident in LDS: every stage of every superstep in one
+// launch, two barriers per stage. Used when the grid fits (small 1D cases).
+constexpr int k1dThreads = 1024;
+constexpr int k1dMaxPts = 4096;
+constexpr int k1dPerThread = k1dMaxPts / k1dThreads;
+
+template <int OP, int BC>
+__global__ __launch_bounds__(k1dThreads) void stage1d_lds(const double *w_in, double *w_out,
+                                                          const double *D, const double2 *tau,
+                                                          int n, int s, int nsteps,
+                                                          double inv_h2, double d_const)
+{
+    extern __shared__ double2 s1[];
+    double2 *sW = s1;
+    double *sD = reinterpret_cast<double *>(s1 + n);
+    const int tid = threadIdx.x;
+    for (int i = tid; i < n; i += k1dThreads) {
+        sW[i] = make_double2(w_in[i], 0.0);
+        if (OP == VAR) sD[i] = D[i];
+    }
+    __syncthreads();
+    for (int step = 0; step < nsteps; ++step) {
+        for (int l = 0; l < s; ++l) {
+            const double tr = tau[l].x, ti = tau[l].y;
+            const bool last = (l == s - 1);
+            double2 nv[k1dPerThread];
+#pragma unroll
+            for (int p = 0; p < k1dPerThread; ++p) {
+                const int i = tid + p * k1dThreads;
+                if (i >= n) break;
+                const double2 c = sW[i];
+                double qr_c = 0.0, qi_c = 0.0;
+                if (OP == POR) {
+                    qr_c = c.x * c.x - c.y * c.y;
+                    qi_c = 2.0 * (c.x * c.y);
+                }
+                const bool gl = (BC == DIR) && i == 0;
+                const bool gr = (BC == DIR) && i == n - 1;
+                const int il = (i == 0) ? n - 1 : i - 1;
+                const int ir = (i == n - 1) ? 0 : i + 1;
+                const double2 wl = gl ? make_double2(0.0, 0.0) : sW[il];
+                const double2 wr = gr ? make_double2(0.0, 0.0) : sW[ir];
+                const double dc = (OP == VAR) ? sD[i] : 0.0;
+                double acc_r = 0.0, acc_i = 0.0;
+                face<OP>(acc_r, acc_i, c, wl, dc, (OP == VAR) ? sD[il] : 0.0, gl, qr_c, qi_c,
+                         d_const);
+                face<OP>(acc_r, acc_i, c, wr, dc, (OP == VAR) ? sD[ir] : 0.0, gr, qr_c, qi_c,
+                         d_const);
+                const double2 u = euler(c, acc_r, acc_i, inv_h2, tr, ti);
+                // a superstep keeps Re W^L; the next one starts from a real state
+                nv[p] = make_double2(u.x, last ? 0.0 : u.y);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < k1dPerThread; ++p) {
+                const int i = tid + p * k1dThreads;
+                if (i >= n) break;
+                sW[i] = nv[p];
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < n; i += k1dThreads) w_out[i] = sW[i].x;
+}
+
+// w = Re W and per-block partial sums of (Im W)^2 and |W|^2.
+constexpr int kFinThreads = 256;
+__global__ __launch_bounds__(kFinThreads) void finalize_kernel(const double2 *in, double *out,
+                                                               long long n, double *partials)
+{
+    __shared__ double s_im[kFinThreads], s_all[kFinThreads];
+    double im2 = 0.0, all2 = 0.0;
+    for (long long i = blockIdx.x * (long long)kFinThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kFinThreads) {
+        const double2 v = in[i];
+        out[i] = v.x;
+        im2 = im2 + v.y * v.y;
+        all2 = all2 + (v.x * v.x + v.y * v.y);
+    }
+    s_im[threadIdx.x] = im2;
+    s_all[threadIdx.x] = all2;
+    __syncthreads();
+    for (int w = kFinThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s_im[threadIdx.x] = s_im[threadIdx.x] + s_im[threadIdx.x + w];
+            s_all[threadIdx.x] = s_all[threadIdx.x] + s_all[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = s_im[0];
+        partials[2 * blockIdx.x + 1] = s_all[0];
+    }
+}
+
+__global__ void finalize_sum(double *partials, int nb)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int i = 0; i < nb; ++i) {
+            a = a + partials[2 * i];
+            b = b + partials[2 * i + 1];
+        }
+        partials[2 * nb] = a;
+        partials[2 * nb + 1] = b;
+    }
+}
+
+__global__ void real_to_complex(const double *in, double2 *out, long long n)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        out[i] = make_double2(in[i], 0.0);
+}
+
+// ---- launch ----
+
+template <int BX, int BY>
+struct TileCfg {
+    static constexpr int bx = BX, by = BY;
+};
+
+int choose_zchunk(long long tiles_xy, int nz)
+{
+    // aim for >= 2048 workgroups (8 per CU on 256 CUs) with chunks of >= 8 planes
+    int zc = nz;
+    while (zc > 8 && tiles_xy * ((nz + zc - 1) / zc) < 2048) zc = (zc + 1) / 2;
+    return zc;
+}
+
+template <int OP, int BC, int NDIM, int BX, int BY>
+int launch_plane_t(const PlaneArgs &pa0, bool in_real, bool out_real, hipStream_t st)
+{
+    PlaneArgs pa = pa0;
+    pa.ntx = (pa.nx + BX - 1) / BX;
+    pa.nty = (pa.ny + BY - 1) / BY;
+    pa.zchunk = choose_zchunk((long long)pa.ntx * pa.nty, pa.nz);
+    const long long nzc = (pa.nz + pa.zchunk - 1) / pa.zchunk;
+    const long long nblk = (long long)pa.ntx * pa.nty * nzc;
+    if (nblk > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+    dim3 grid((unsigned)nblk), block(BX * BY);
+    if (in_real && out_real)
+        hipLaunchKernelGGL((plane_stage<OP, BC, NDIM, BX, BY, true, true>), grid, block, 0, st, pa);
+    else if (in_real)
+        hipLaunchKernelGGL((plane_stage<OP, BC, NDIM, BX, BY, true, false>), grid, block, 0, st, pa);
+    else if (out_real)
+        hipLaunchKernelGGL((plane_stage<OP, BC, NDIM, BX, BY, false, true>), grid, block, 0, st, pa);
+    else
+        hipLaunchKernelGGL((plane_stage<OP, BC, NDIM, BX, BY, false, false>), grid, block, 0, st, pa);
+    return (int)hipGetLastError();
+}
+
+template <int OP, int BC>
+int launch_plane_dim(const KGrid &g, const PlaneArgs &pa, bool ir, bool orl, hipStream_t st)
+{
+    if (g.ndim == 3) return launch_plane_t<OP, BC, 3, 64, 4>(pa, ir, orl, st);
+    if (g.ndim == 2) return launch_plane_t<OP, BC, 2, 256, 1>(pa, ir, orl, st);
+    return launch_plane_t<OP, BC, 1, 256, 1>(pa, ir, orl, st);
+}
+
+template <int OP>
+int launch_plane_bc(const KGrid &g, const PlaneArgs &pa, bool ir, bool orl, hipStream_t st)
+{
+    if (g.bc == PER) return launch_plane_dim<OP, PER>(g, pa, ir, orl, st);
+    return launch_plane_dim<OP, DIR>(g, pa, ir, orl, st);
+}
+
+}  // namespace
+
+int launch_pass(const KGrid &g, const PassArgs &a, int /*tblock_hint*/, hipStream_t st)
+{
+    // one stage per pass (k = 1)
+    if (a.k != 1) return (int)hipErrorInvalidValue;
+    PlaneArgs pa{};
+    pa.in_re = a.in_re;
+    pa.in_c = reinterpret_cast<const double2 *>(a.in_c);
+    pa.out_re = a.out_re;
+    pa.out_c = reinterpret_cast<double2 *>(a.out_c);
+    pa.D = a.D;
+    pa.nx = g.nx;
+    pa.ny = g.ny;
+    pa.nz = g.nz;
+    pa.inv_h2 = g.inv_h2;
+    pa.d_const = g.d_const;
+    pa.tr = a.tr[0];
+    pa.ti = a.ti[0];
+    const bool ir = a.in_re != nullptr, orl = a.out_re != nullptr;
+    if (g.op == LAP) return launch_plane_bc<LAP>(g, pa, ir, orl, st);
+    if (g.op == VAR) return launch_plane_bc<VAR>(g, pa, ir, orl, st);
+    return launch_plane_bc<POR>(g, pa, ir, orl, st);
+}
+
+bool stage1d_lds_fits(const KGrid &g) { return g.ndim == 1 && g.nx <= k1dMaxPts; }
+
+namespace {
+template <int OP, int BC>
+int launch_1d_t(const KGrid &g, const double *w_in, double *w_out, const double *D,
+                const double *tau, int s, int nsteps, hipStream_t st)
+{
+    const size_t shm = (size_t)g.nx * (sizeof(double2) + sizeof(double));
+    auto kern = stage1d_lds<OP, BC>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL(kern, dim3(1), dim3(k1dThreads), shm, st, w_in, w_out, D,
+                       reinterpret_cast<const double2 *>(tau), g.nx, s, nsteps, g.inv_h2,
+                       g.d_const);
+    return (int)hipGetLastError();
+}
+template <int OP>
+int launch_1d_bc(const KGrid &g, const double *w_in, double *w_out, const double *D,
+                 const double *tau, int s, int nsteps, hipStream_t st)
+{
+    if (g.bc == PER) return launch_1d_t<OP, PER>(g, w_in, w_out, D, tau, s, nsteps, st);
+    return launch_1d_t<OP, DIR>(g, w_in, w_out, D, tau, s, nsteps, st);
+}
+}  // namespace
+
+int launch_stage1d_lds(const KGrid &g, const double *w_in, double *w_out, const double *D,
+                       const double *tau, int s, int nsteps, hipStream_t st)
+{
+    if (!stage1d_lds_fits(g)) return (int)hipErrorInvalidValue;
+    if (g.op == LAP) return launch_1d_bc<LAP>(g, w_in, w_out, D, tau, s, nsteps, st);
+    if (g.op == VAR) return launch_1d_bc<VAR>(g, w_in, w_out, D, tau, s, nsteps, st);
+    return launch_1d_bc<POR>(g, w_in, w_out, D, tau, s, nsteps, st);
+}
+
+int launch_finalize(const KGrid &g, const double *in_c, double *out_re, double *partials,
+                    hipStream_t st)
+{
+    const long long n = g.npts();
+    hipLaunchKernelGGL(finalize_kernel, dim3(kReduceBlocks), dim3(kFinThreads), 0, st,
+                       reinterpret_cast<const double2 *>(in_c), out_re, n, partials);
+    hipLaunchKernelGGL(finalize_sum, dim3(1), dim3(64), 0, st, partials, kReduceBlocks);
+    return (int)hipGetLastError();
+}
+
+int launch_real_to_complex(long long n, const double *in, double *out_c, hipStream_t st)
+{
+    long long blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(real_to_complex, dim3((unsigned)blocks), dim3(256), 0, st, in,
+                       reinterpret_cast<double2 *>(out_c), n);
+    return (int)hipGetLastError();
+}
+
+}  // namespace frkc2
+
+namespace frkc2 {
+namespace {
+__global__ void zero_kernel(double *p, long long n)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+}  // namespace
+
+int launch_zero(long long n, double *p, hipStream_t st)
+{
+    long long blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+    return (int)hipGetLastError();
+}
+}  // namespace frkc2

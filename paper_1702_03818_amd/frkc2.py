@@ -1,0 +1,281 @@
+"""Python binding of libfrkc2 (the C ABI in include/frkc2.h).
+
+Argument marshalling only: every step of the superstep runs in the library's
+HIP kernels. Tensors are torch float64 CUDA (HIP) tensors, contiguous; the
+binding passes their device pointers, the current torch stream, and a device
+workspace it allocates through torch (cached per device and size).
+
+The functions keep the C names. Grids are anything with the attributes
+ndim, n (nx, ny, nz), h, bc, op and d_const (a workloads.Problem works) or a
+dict with those keys.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfrkc2.so")
+
+FRKC2_OK = 0
+FRKC2_WQBOUND = 1
+STATUS_NAMES = {0: "OK", 1: "WQBOUND", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP",
+                -4: "EUNSTABLE", -5: "ENONFINITE", -6: "ETIMEOUT"}
+WS_STEP = 0
+WS_ADJOINT = 1
+RED_SUMSQ, RED_SUM, RED_MAXSQ, RED_SUMSQDIFF, RED_DOT = 0, 1, 2, 3, 4
+OPT_TBLOCK = 1
+OPT_XCD_REMAP = 2
+
+
+class Frkc2Error(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (STATUS_NAMES.get(status, "?"), status, msg))
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double),
+                ("bc", ctypes.c_int), ("op", ctypes.c_int), ("d_const", ctypes.c_double)]
+
+
+class CoeffInfo(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("beta_bar", ctypes.c_double),
+                ("q_realised", ctypes.c_double), ("mu_re", ctypes.c_double),
+                ("mu_im", ctypes.c_double), ("n_shrink", ctypes.c_int),
+                ("q_bound_met", ctypes.c_int)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("T_last", ctypes.c_double), ("rho_last", ctypes.c_double),
+                ("im_ratio", ctypes.c_double), ("supersteps", ctypes.c_int)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "frkc2_coeffs": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, _DP, _DP, ctypes.POINTER(CoeffInfo)]),
+    "frkc2_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), ctypes.c_int, ctypes.c_int]),
+    "frkc2_rho_bound": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, _DP, _VP, ctypes.c_size_t, _VP]),
+    "frkc2_step": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_int, ctypes.c_double, ctypes.c_int, _VP, ctypes.c_size_t,
+                                  _VP, ctypes.POINTER(StepStats)]),
+    "frkc2_step_adjoint": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, ctypes.c_double,
+                                          ctypes.c_int, ctypes.c_double, _VP, _VP, _VP, _VP,
+                                          ctypes.c_size_t, _VP]),
+    "frkc2_batched_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.POINTER(Grid),
+                                                        ctypes.POINTER(ctypes.c_int)]),
+    "frkc2_step_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Grid),
+                                          ctypes.POINTER(_VP), ctypes.POINTER(_VP), _DP,
+                                          ctypes.POINTER(ctypes.c_int), ctypes.c_double, _VP,
+                                          ctypes.c_size_t, _VP]),
+    "frkc2_batched_status": (ctypes.c_int, [_VP, _VP]),
+    "frkc2_reduce": (ctypes.c_int, [ctypes.c_int, _VP, _VP, ctypes.c_size_t, _DP, _VP,
+                                    ctypes.c_size_t, _VP]),
+    "frkc2_set_option": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    "frkc2_last_error": (ctypes.c_char_p, []),
+    "frkc2_version": (ctypes.c_char_p, []),
+}
+
+
+def load():
+    """Load libfrkc2.so (built in-tree). Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libfrkc2.so is not built: run `python -m paper_1702_03818_amd.build` "
+                               "(or __graft_entry__.build()) first")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc):
+    if rc < 0:
+        raise Frkc2Error(rc, load().frkc2_last_error().decode())
+    return rc
+
+
+def make_grid(g) -> Grid:
+    if isinstance(g, Grid):
+        return g
+    get = (lambda k: g[k]) if isinstance(g, dict) else (lambda k: getattr(g, k))
+    n = list(get("n")) + [1] * (3 - len(get("n")))
+    return Grid(int(get("ndim")), (ctypes.c_int * 3)(*[int(v) for v in n[:3]]), float(get("h")),
+                int(get("bc")), int(get("op")), float(get("d_const")))
+
+
+# ---- device plumbing (torch) ----
+
+_ws_cache = {}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 GPU tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def workspace(nbytes: int, device=None, key="default"):
+    """A cached uint8 device buffer of at least nbytes (grown on demand)."""
+    torch = _torch()
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    k = (dev.index, key)
+    buf = _ws_cache.get(k)
+    if buf is None or buf.numel() < nbytes:
+        _ws_cache.pop(k, None)
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=dev)
+        _ws_cache[k] = buf
+    return buf
+
+
+def release_workspaces():
+    _ws_cache.clear()
+
+
+# ---- the ABI ----
+
+def frkc2_coeffs(s: int, nu: float = 0.01):
+    """Returns (a_re, a_im, info dict, status). Host only."""
+    lib = load()
+    re = np.zeros(s)
+    im = np.zeros(s)
+    info = CoeffInfo()
+    rc = _check(lib.frkc2_coeffs(int(s), float(nu), re.ctypes.data_as(_DP), im.ctypes.data_as(_DP),
+                                 ctypes.byref(info)))
+    d = {f: getattr(info, f) for f, _ in CoeffInfo._fields_}
+    return re, im, d, rc
+
+
+def frkc2_workspace_bytes(grid, s: int, flags: int = WS_STEP) -> int:
+    g = make_grid(grid)
+    return int(load().frkc2_workspace_bytes(ctypes.byref(g), int(s), int(flags)))
+
+
+def frkc2_rho_bound(grid, w=None, D=None, stream=None) -> float:
+    lib = load()
+    g = make_grid(grid)
+    ws = workspace(64 * 1024)
+    rho = ctypes.c_double()
+    _check(lib.frkc2_rho_bound(ctypes.byref(g), _ptr(w), _ptr(D), ctypes.byref(rho),
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    return rho.value
+
+
+def frkc2_step(grid, w, D=None, T=0.0, cfl=0.0, s=16, nu=0.01, nsteps=1, stream=None,
+               stats=False, ws=None):
+    """nsteps supersteps in place on w. Returns the stats dict if stats=True, else the status."""
+    lib = load()
+    g = make_grid(grid)
+    need = lib.frkc2_workspace_bytes(ctypes.byref(g), int(s), WS_STEP)
+    if need == 0:
+        _check(-1)
+    buf = ws if ws is not None else workspace(need)
+    st = StepStats() if stats else None
+    rc = _check(lib.frkc2_step(ctypes.byref(g), _ptr(w), _ptr(D), float(T), float(cfl), int(s),
+                               float(nu), int(nsteps), ctypes.c_void_p(buf.data_ptr()),
+                               buf.numel(), _stream_ptr(stream),
+                               ctypes.byref(st) if st is not None else None))
+    if stats:
+        return {f: getattr(st, f) for f, _ in StepStats._fields_}
+    return rc
+
+
+def frkc2_step_adjoint(grid, w_n, D, T, s, lam_next, lam_n, grad_logD=None, nu=0.01,
+                       stream=None, ws=None):
+    lib = load()
+    g = make_grid(grid)
+    need = lib.frkc2_workspace_bytes(ctypes.byref(g), int(s), WS_ADJOINT)
+    if need == 0:
+        _check(-1)
+    buf = ws if ws is not None else workspace(need, key="adjoint")
+    return _check(lib.frkc2_step_adjoint(ctypes.byref(g), _ptr(w_n), _ptr(D), float(T), int(s),
+                                         float(nu), _ptr(lam_next), _ptr(lam_n), _ptr(grad_logD),
+                                         ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                         _stream_ptr(stream)))
+
+
+def frkc2_batched_workspace_bytes(grids, s_list) -> int:
+    lib = load()
+    n = len(grids)
+    garr = (Grid * n)(*[make_grid(g) for g in grids])
+    sarr = (ctypes.c_int * n)(*[int(v) for v in s_list])
+    return int(lib.frkc2_batched_workspace_bytes(n, garr, sarr))
+
+
+class BatchedArgs:
+    """Marshalled arguments of one problem set (kept alive across graph replays)."""
+
+    def __init__(self, grids, ws_list, D_list, T_list, s_list):
+        n = len(grids)
+        self.n = n
+        self.grids = (Grid * n)(*[make_grid(g) for g in grids])
+        self.w = (_VP * n)(*[_ptr(t) for t in ws_list])
+        self.D = (_VP * n)(*[_ptr(t) if t is not None else None for t in D_list])
+        self.T = (ctypes.c_double * n)(*[float(v) for v in T_list])
+        self.s = (ctypes.c_int * n)(*[int(v) for v in s_list])
+        self.tensors = (list(ws_list), list(D_list))
+
+
+def frkc2_step_batched(args: BatchedArgs, nu=0.01, stream=None, ws=None):
+    lib = load()
+    need = lib.frkc2_batched_workspace_bytes(args.n, args.grids, args.s)
+    if need == 0:
+        _check(-1)
+    buf = ws if ws is not None else workspace(need, key="batched")
+    return _check(lib.frkc2_step_batched(args.n, args.grids, args.w, args.D, args.T, args.s,
+                                         float(nu), ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                         _stream_ptr(stream)))
+
+
+def frkc2_batched_status(ws, stream=None):
+    return _check(load().frkc2_batched_status(ctypes.c_void_p(ws.data_ptr()), _stream_ptr(stream)))
+
+
+def frkc2_reduce(op: int, x, y=None, stream=None) -> float:
+    lib = load()
+    ws = workspace(64 * 1024)
+    out = ctypes.c_double()
+    _check(lib.frkc2_reduce(int(op), _ptr(x), _ptr(y), x.numel(), ctypes.byref(out),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    return out.value
+
+
+def frkc2_set_option(key: int, value: int):
+    return _check(load().frkc2_set_option(int(key), int(value)))
+
+
+def frkc2_last_error() -> str:
+    return load().frkc2_last_error().decode()
+
+
+def frkc2_version() -> str:
+    return load().frkc2_version().decode()

@@ -1,0 +1,143 @@
+"""CPU tests of the C-ABI library: loading, exported symbols, host-side
+stepsizes against the oracle, and argument validation (which runs before any
+HIP call, so no GPU is needed)."""
+import ctypes
+import re
+
+import numpy as np
+import pytest
+
+from oracle.coeffs import frkc2_coeffs as oracle_coeffs
+from paper_1702_03818_amd import frkc2 as F
+from paper_1702_03818_amd import workloads as wl
+
+HEADER = "include/frkc2.h"
+
+
+def header_functions():
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = open(os.path.join(root, HEADER)).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(frkc2_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    lib = F.load()
+    names = header_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(F.exported_symbols())
+
+
+def test_version():
+    assert "gfx950" in F.frkc2_version()
+
+
+@pytest.mark.parametrize("s", [2, 4, 6, 8, 10, 16, 20, 32, 50, 64, 100, 128, 200, 256, 400, 514])
+def test_coeffs_bitwise_equal_to_oracle(s):
+    """Library (binary128 host code) and oracle (50-digit mpmath) round to the same doubles and
+    pick the same stage order; beta, betabar and n agree exactly, Q to rounding."""
+    re_, im_, info, rc = F.frkc2_coeffs(s, 0.01)
+    o = oracle_coeffs(s, 0.01)
+    assert np.array_equal(re_, o.a_re)
+    assert np.array_equal(im_, o.a_im)
+    assert info["beta"] == o.beta
+    assert info["beta_bar"] == o.beta_bar
+    assert info["n_shrink"] == o.n_shrink
+    assert abs(info["q_realised"] / o.q_realised - 1) < 1e-12
+    assert bool(info["q_bound_met"]) == o.q_bound_met
+    assert rc == (F.FRKC2_OK if o.q_bound_met else F.FRKC2_WQBOUND)
+    assert complex(info["mu_re"], info["mu_im"]) == o.mu
+
+
+@pytest.mark.parametrize("nu", [0.0, 0.05, 0.3])
+def test_coeffs_other_damping(nu):
+    for s in (8, 64):
+        re_, im_, info, _ = F.frkc2_coeffs(s, nu)
+        o = oracle_coeffs(s, nu)
+        assert np.array_equal(re_, o.a_re) and np.array_equal(im_, o.a_im)
+        assert info["beta"] == o.beta
+
+
+@pytest.mark.parametrize("s,nu", [(0, 0.01), (3, 0.01), (516, 0.01), (8, -0.1), (8, 1.0),
+                                  (8, float("nan"))])
+def test_coeffs_rejects(s, nu):
+    with pytest.raises(F.Frkc2Error) as e:
+        F.frkc2_coeffs(s, nu)
+    assert e.value.status == -1
+
+
+def grid(**kw):
+    d = dict(ndim=3, n=(8, 8, 8), h=0.1, bc=1, op=1, d_const=1.0)
+    d.update(kw)
+    return F.make_grid(d)
+
+
+@pytest.mark.parametrize("kw", [dict(ndim=0), dict(ndim=4), dict(n=(0, 8, 8)), dict(ndim=2, n=(8, 8, 8)),
+                                dict(h=0.0), dict(h=float("inf")), dict(bc=7), dict(op=9),
+                                dict(op=0, d_const=-1.0)])
+def test_workspace_bytes_invalid_grid(kw):
+    g = grid(**kw)
+    assert F.load().frkc2_workspace_bytes(ctypes.byref(g), 16, F.WS_STEP) == 0
+
+
+def test_workspace_bytes_sizes():
+    lib = F.load()
+    g = grid(n=(256, 256, 256))
+    N = 256 ** 3
+    step = lib.frkc2_workspace_bytes(ctypes.byref(g), 100, F.WS_STEP)
+    adj = lib.frkc2_workspace_bytes(ctypes.byref(g), 64, F.WS_ADJOINT)
+    assert 32 * N <= step < 32 * N + (1 << 20)
+    assert (64 + 2) * 16 * N + 8 * N <= adj < (64 + 2) * 16 * N + 8 * N + (1 << 20)
+
+
+def _step(g, w=1, D=1, T=1e-3, cfl=0.0, s=16, nu=0.01, nsteps=1, ws=1, ws_bytes=1 << 40):
+    lib = F.load()
+    p = lambda v: ctypes.c_void_p(4096 * 16) if v else None  # never dereferenced: validation fails first
+    return lib.frkc2_step(ctypes.byref(g), p(w), p(D), T, cfl, s, nu, nsteps, p(ws), ws_bytes, None,
+                          None)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(w=0), -1), (dict(D=0), -1), (dict(s=7), -1), (dict(s=600), -1), (dict(nu=1.5), -1),
+    (dict(nsteps=-1), -1), (dict(T=0.0), -1), (dict(T=1e-3, cfl=0.5), -1),
+    (dict(T=float("nan")), -1), (dict(T=-1.0), -1), (dict(ws=0), -2), (dict(ws_bytes=100), -2),
+])
+def test_step_validation(kw, expect):
+    g = grid()
+    assert _step(g, **kw) == expect
+    assert F.frkc2_last_error()
+
+
+def test_adjoint_rejects_nonlinear_operator():
+    lib = F.load()
+    g = grid(op=2)
+    p = ctypes.c_void_p(4096)
+    rc = lib.frkc2_step_adjoint(ctypes.byref(g), p, None, 1e-3, 16, 0.01, p, p, None, p, 1 << 40,
+                                None)
+    assert rc == -1
+
+
+def test_reduce_validation():
+    lib = F.load()
+    out = ctypes.c_double()
+    assert lib.frkc2_reduce(9, ctypes.c_void_p(4096), None, 10, ctypes.byref(out),
+                            ctypes.c_void_p(4096), 1 << 20, None) == -1
+    assert lib.frkc2_reduce(3, ctypes.c_void_p(4096), None, 10, ctypes.byref(out),
+                            ctypes.c_void_p(4096), 1 << 20, None) == -1
+    assert lib.frkc2_reduce(0, ctypes.c_void_p(4096), None, 10, ctypes.byref(out),
+                            ctypes.c_void_p(4096), 8, None) == -2
+
+
+def test_set_option_validation():
+    assert F.load().frkc2_set_option(F.OPT_TBLOCK, 99) == -1
+    assert F.load().frkc2_set_option(12345, 1) == -1
+    assert F.frkc2_set_option(F.OPT_TBLOCK, 0) == 0
+
+
+def test_grid_from_problem():
+    p = wl.heat1d()
+    g = F.make_grid(p)
+    assert g.ndim == 1 and list(g.n) == [1024, 1, 1] and g.h == p.h
