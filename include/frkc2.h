@@ -164,24 +164,30 @@ int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const double *D, 
 
 /*
  * frkc2_step_batched -- one superstep for each of nprob independent problems
- * in a single persistent kernel launch (VARCOEF or LAPLACE, 2D or 3D).
+ * (VARCOEF or LAPLACE, 2D or 3D, each with its own grid, T and s) in a single
+ * HIP graph launch: one kernel per stage level l, covering stage l of every
+ * problem with s > l.
  *   grids  host array of nprob grids
- *   w      host array of nprob device pointers (in/out states)
+ *   w      host array of nprob device pointers (in/out states, real)
  *   D      host array of nprob device pointers (NULL entries for LAPLACE)
  *   T      host array of nprob superstep lengths
  *   s      host array of nprob even stage counts (2..514)
- *   ws     device workspace of at least frkc2_batched_workspace_bytes(...)
- * The first call for a given problem set uploads the work descriptors and
- * stepsize tables into ws and captures the launch into a HIP graph, which
- * later calls with identical arguments replay. Asynchronous. A dependency
- * wait that exceeds its bound sets a flag; the next call (or
- * frkc2_batched_status) reports FRKC2_ETIMEOUT.
+ *   ws     device workspace of at least frkc2_batched_workspace_bytes(...),
+ *          256-byte aligned; it holds the work tables and two complex
+ *          buffers per problem and must not be shared by concurrent calls
+ * The first call for a given set of arguments uploads the work tables into
+ * ws (synchronising st) and captures the graph; later calls with identical
+ * arguments only replay it (asynchronous). The graph stays cached for ws
+ * until frkc2_batched_release(ws). Each problem's result is bit-identical to
+ * frkc2_step on it. frkc2_batched_status synchronises st and reports any
+ * HIP error of the replays.
  */
 size_t frkc2_batched_workspace_bytes(int nprob, const frkc2_grid *grids, const int *s);
 int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *const *w,
                        const double *const *D, const double *T, const int *s, double nu,
                        void *ws, size_t ws_bytes, hipStream_t st);
 int frkc2_batched_status(void *ws, hipStream_t st);   /* synchronises st */
+int frkc2_batched_release(void *ws);                  /* frees the graph cached for ws */
 
 /*
  * frkc2_reduce -- deterministic FP64 reductions over n elements (device x, y).
@@ -198,12 +204,17 @@ int frkc2_reduce(int op, const double *x, const double *y, size_t n, double *res
                  void *ws, size_t ws_bytes, hipStream_t st);
 
 /*
- * frkc2_set_option -- tuning knobs (process-wide): FRKC2_OPT_TBLOCK sets the
- * temporal block depth k (stages per HBM pass) of the plain 3D/2D kernels;
- * 0 restores automatic choice. Results are identical for every k.
+ * frkc2_set_option -- tuning knobs (process-wide, not thread-safe to change
+ * while other threads call the library):
+ *   FRKC2_OPT_TBLOCK  stages fused per HBM pass of frkc2_step: 1, or 2 and 3
+ *                     (3D), 2, 3, 4, 6 and 8 (2D); 0 = automatic
+ *   FRKC2_OPT_TILE    3D tile shape of the fused passes: 0 = 64x16, 1 = 64x32 (k = 2)
+ *   FRKC2_OPT_XCD_REMAP  reserved (1)
+ * Results are identical, bit for bit, for every setting.
  */
 #define FRKC2_OPT_TBLOCK 1
 #define FRKC2_OPT_XCD_REMAP 2
+#define FRKC2_OPT_TILE 3
 int frkc2_set_option(int key, int value);
 
 /* Thread-local description of the last error. */

@@ -270,3 +270,16 @@ double oracle_rho_bound(int ndim, const long *n, int bc, int op, double inv_h2, 
     }
     return (2.0 * inv_h2) * m;
 }
+
+/* Threads the OpenMP loops above use (1 when built without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -54,6 +54,8 @@ def _load():
         lib.oracle_rho_bound.argtypes = [ctypes.c_int, lp, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_double, ctypes.c_double, dp, dp]
         lib.oracle_rho_bound.restype = ctypes.c_double
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -72,6 +74,11 @@ def _grid_args(prob):
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(_load().oracle_threads())
 
 
 def superstep(prob, w, tau_re, tau_im, D=None, want_imag=False):

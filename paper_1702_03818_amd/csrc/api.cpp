@@ -22,6 +22,7 @@ namespace frkc2 {
 namespace {
 thread_local char g_err[512] = "";
 int g_tblock = 0;
+int g_tile = 0;
 int g_xcd_remap = 1;
 
 constexpr size_t kAlign = 256;
@@ -160,6 +161,58 @@ int rho_bound_impl(const KGrid &kg, const double *w, const double *D, double *pa
     return FRKC2_OK;
 }
 
+// Stages fused per HBM pass: the option if set, else the measured best for
+// the grid's dimension (2D rows have little halo overhead, 3D tiles more).
+int pass_depth(const KGrid &kg)
+{
+    int k = g_tblock;
+    if (k == 0) k = (kg.ndim == 3) ? 2 : (kg.ndim == 2 ? 4 : 1);
+    if (k >= 2 && !tblock_supported(kg, k)) k = 1;
+    return k;
+}
+
+// One superstep of s stages from the real state w: passes of k fused stages,
+// the remainder as single stages. The first pass reads w, the last writes
+// Re W^L to w (or, with last_complex, the complex W^L to a buffer, returned).
+int run_superstep(const KGrid &kg, double *w, const double *D, double Tn, const double *are,
+                  const double *aim, int s, bool last_complex, double *const buf[2],
+                  const double **last_out, hipStream_t st)
+{
+    const int k = pass_depth(kg);
+    int l = 0, pass = 0;
+    const double *in = nullptr;
+    while (l < s) {
+        int kk = (k >= 2 && s - l >= k) ? k : 1;
+        // A fused pass reads its input around each tile and chunk (halo), so it
+        // must not write into the array it reads: the pass that starts from w
+        // may not also be the one that writes w back.
+        if (l == 0 && kk == s) {
+            kk = s - 1;
+            while (kk >= 2 && !tblock_supported(kg, kk)) --kk;
+        }
+        PassArgs pa{};
+        pa.k = kk;
+        pa.D = D;
+        if (l == 0) pa.in_re = w;
+        else pa.in_c = in;
+        const bool last = (l + kk == s);
+        double *out = buf[pass & 1];
+        if (last && !last_complex) pa.out_re = w;
+        else pa.out_c = out;
+        for (int i = 0; i < kk; ++i) {
+            pa.tr[i] = Tn * are[l + i];
+            pa.ti[i] = Tn * aim[l + i];
+        }
+        const int rc = (kk == 1) ? launch_pass(kg, pa, 1, st) : launch_tblock(kg, pa, g_tile, st);
+        if (rc != 0) return rc;
+        in = out;
+        l += kk;
+        ++pass;
+    }
+    if (last_out) *last_out = in;
+    return 0;
+}
+
 bool check_s_nu(int s, double nu)
 {
     if (s < 2 || s > kMaxStages || (s % 2) != 0) {
@@ -194,6 +247,14 @@ extern "C" int frkc2_set_option(int key, int value)
             return FRKC2_EINVAL;
         }
         g_tblock = value;
+        return FRKC2_OK;
+    }
+    if (key == FRKC2_OPT_TILE) {
+        if (value < 0 || value > 2) {
+            set_error("tile shape must be 0, 1 or 2");
+            return FRKC2_EINVAL;
+        }
+        g_tile = value;
         return FRKC2_OK;
     }
     if (key == FRKC2_OPT_XCD_REMAP) {
@@ -312,20 +373,11 @@ extern "C" int frkc2_step(const frkc2_grid *g, double *w, const double *D, doubl
             HIP_TRY(launch_stage1d_lds(kg, w, w, D, tau_dev, s, 1, st), "1D stage launch");
             continue;
         }
-        for (int l = 0; l < s; ++l) {
-            PassArgs pa{};
-            pa.k = 1;
-            pa.D = D;
-            if (l == 0) pa.in_re = w;
-            else pa.in_c = buf[(l - 1) & 1];
-            if (l == s - 1 && !want_stats) pa.out_re = w;
-            else pa.out_c = buf[l & 1];
-            pa.tr[0] = Tn * are[l];
-            pa.ti[0] = Tn * aim[l];
-            HIP_TRY(launch_pass(kg, pa, g_tblock, st), "stage launch");
-        }
+        const double *last_out = nullptr;
+        HIP_TRY(run_superstep(kg, w, D, Tn, are, aim, s, want_stats, buf, &last_out, st),
+                "stage launch");
         if (want_stats) {
-            HIP_TRY(launch_finalize(kg, buf[(s - 1) & 1], w, partials, st), "finalize launch");
+            HIP_TRY(launch_finalize(kg, last_out, w, partials, st), "finalize launch");
             double sums[2];
             HIP_TRY(hipMemcpyAsync(sums, partials + 2 * kReduceBlocks, sizeof(sums),
                                    hipMemcpyDeviceToHost, st),

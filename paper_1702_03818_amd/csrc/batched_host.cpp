@@ -1,0 +1,275 @@
+// Host side of frkc2_step_batched: validation, work tables, workspace layout
+// and the cached HIP graph (one kernel node per stage level).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+namespace frkc2 {
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t probs, chunk_prefix, tau, bufs, total;
+    std::vector<size_t> buf_off;   // per problem (caller's order): offset of buffer A
+};
+
+bool validate(int nprob, const frkc2_grid *grids, const int *s, std::vector<KGrid> &kg)
+{
+    if (nprob < 1 || !grids || !s) {
+        set_error("batched: need nprob >= 1 and non-NULL grids and s");
+        return false;
+    }
+    kg.resize(nprob);
+    for (int i = 0; i < nprob; ++i) {
+        if (!make_kgrid(&grids[i], kg[i])) return false;
+        if (kg[i].ndim < 2 || kg[i].op == FRKC2_OP_POROUS2) {
+            set_error("batched: problem %d must be 2D or 3D with a linear operator", i);
+            return false;
+        }
+        if (s[i] < 2 || s[i] > kMaxStages || (s[i] % 2)) {
+            set_error("batched: problem %d has invalid s = %d", i, s[i]);
+            return false;
+        }
+    }
+    return true;
+}
+
+Layout layout(int nprob, const std::vector<KGrid> &kg, const int *s)
+{
+    Layout L;
+    const size_t sum_s = std::accumulate(s, s + nprob, (size_t)0);
+    size_t o = 0;
+    L.probs = o; o = align_up(o + sizeof(BatchProblem) * nprob);
+    L.chunk_prefix = o; o = align_up(o + sizeof(long long) * (nprob + 1));
+    L.tau = o; o = align_up(o + sizeof(double) * 2 * sum_s);
+    L.bufs = o;
+    L.buf_off.resize(nprob);
+    for (int i = 0; i < nprob; ++i) {
+        L.buf_off[i] = o;
+        o = align_up(o + 2 * align_up((size_t)kg[i].npts() * 16));
+    }
+    L.total = o;
+    return L;
+}
+
+struct GraphEntry {
+    std::vector<unsigned char> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<BatchProblem> probs;   // host copies of the uploaded tables
+    std::vector<long long> chunk_prefix;
+    std::vector<double> tau;
+};
+
+std::mutex g_mu;
+std::map<void *, GraphEntry> g_graphs;
+hipStream_t g_capture = nullptr;
+
+void append(std::vector<unsigned char> &k, const void *p, size_t n)
+{
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    k.insert(k.end(), c, c + n);
+}
+
+int hip_err(hipError_t e, const char *what)
+{
+    set_error("batched: %s: HIP error %d (%s)", what, (int)e, hipGetErrorString(e));
+    return FRKC2_EHIP;
+}
+
+void drop(GraphEntry &E)
+{
+    if (E.exec) hipGraphExecDestroy(E.exec);
+    if (E.graph) hipGraphDestroy(E.graph);
+    E.exec = nullptr;
+    E.graph = nullptr;
+    E.key.clear();
+}
+
+}  // namespace
+}  // namespace frkc2
+
+using namespace frkc2;
+
+extern "C" size_t frkc2_batched_workspace_bytes(int nprob, const frkc2_grid *grids, const int *s)
+{
+    std::vector<KGrid> kg;
+    if (!validate(nprob, grids, s, kg)) return 0;
+    return layout(nprob, kg, s).total;
+}
+
+extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *const *w,
+                                  const double *const *D, const double *T, const int *s,
+                                  double nu, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    std::vector<KGrid> kg;
+    if (!validate(nprob, grids, s, kg)) return FRKC2_EINVAL;
+    if (!w || !D || !T) {
+        set_error("batched: w, D and T arrays must be non-NULL");
+        return FRKC2_EINVAL;
+    }
+    if (!(nu >= 0.0 && nu < 1.0)) {
+        set_error("batched: nu must lie in [0, 1)");
+        return FRKC2_EINVAL;
+    }
+    for (int i = 0; i < nprob; ++i) {
+        if (!w[i] || (kg[i].op == FRKC2_OP_VARCOEF && !D[i])) {
+            set_error("batched: problem %d lacks w or D", i);
+            return FRKC2_EINVAL;
+        }
+        if (!(T[i] > 0.0) || !std::isfinite(T[i])) {
+            set_error("batched: problem %d has invalid T", i);
+            return FRKC2_EINVAL;
+        }
+    }
+    const Layout L = layout(nprob, kg, s);
+    if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) {
+        set_error("batched: workspace needs %zu bytes (got %zu), 256-byte aligned", L.total,
+                  ws_bytes);
+        return FRKC2_ENOMEM;
+    }
+    std::vector<unsigned char> key;
+    append(key, &nprob, sizeof(nprob));
+    append(key, grids, sizeof(frkc2_grid) * nprob);
+    append(key, w, sizeof(double *) * nprob);
+    append(key, D, sizeof(double *) * nprob);
+    append(key, T, sizeof(double) * nprob);
+    append(key, s, sizeof(int) * nprob);
+    append(key, &nu, sizeof(nu));
+    append(key, &ws_bytes, sizeof(ws_bytes));
+
+    std::lock_guard<std::mutex> lk(g_mu);
+    GraphEntry &E = g_graphs[ws];
+    if (E.exec && E.key == key) {
+        hipError_t e = hipGraphLaunch(E.exec, st);
+        return e == hipSuccess ? FRKC2_OK : hip_err(e, "graph launch");
+    }
+    drop(E);
+    // ---- work tables (problems sorted by decreasing s, stable) ----
+    char *base = static_cast<char *>(ws);
+    std::vector<int> order(nprob);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return s[a] > s[b]; });
+    const int max_s = s[order[0]];
+    const long long chunk = batched_chunk_points();
+    E.probs.assign(nprob, BatchProblem{});
+    E.chunk_prefix.assign(nprob + 1, 0);
+    E.tau.clear();
+    for (int j = 0; j < nprob; ++j) {
+        const int i = order[j];
+        const double *are, *aim;
+        int crc = coeffs_cached(s[i], nu, &are, &aim, nullptr);
+        if (crc < 0) return crc;
+        const size_t toff = E.tau.size();
+        for (int l = 0; l < s[i]; ++l) {
+            E.tau.push_back(T[i] * are[l]);
+            E.tau.push_back(T[i] * aim[l]);
+        }
+        BatchProblem &P = E.probs[j];
+        P.w = w[i];
+        P.D = D[i];
+        P.bufA = reinterpret_cast<double *>(base + L.buf_off[i]);
+        P.bufB = reinterpret_cast<double *>(base + L.buf_off[i] + align_up((size_t)kg[i].npts() * 16));
+        P.tau = reinterpret_cast<const double *>(base + L.tau) + toff;
+        P.nx = kg[i].nx;
+        P.ny = kg[i].ny;
+        P.nz = kg[i].nz;
+        P.ndim = kg[i].ndim;
+        P.bc = kg[i].bc;
+        P.op = kg[i].op;
+        P.s = s[i];
+        P.ntiles = (int)((kg[i].npts() + chunk - 1) / chunk);
+        P.inv_h2 = kg[i].inv_h2;
+        P.d_const = kg[i].d_const;
+        E.chunk_prefix[j + 1] = E.chunk_prefix[j] + P.ntiles;
+    }
+    hipError_t e;
+    e = hipMemcpyAsync(base + L.probs, E.probs.data(), sizeof(BatchProblem) * nprob,
+                       hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + L.chunk_prefix, E.chunk_prefix.data(),
+                           sizeof(long long) * (nprob + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + L.tau, E.tau.data(), sizeof(double) * E.tau.size(),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_err(e, "table upload");
+
+    // ---- capture one kernel per stage level ----
+    if (!g_capture) {
+        e = hipStreamCreate(&g_capture);
+        if (e != hipSuccess) return hip_err(e, "capture stream");
+    }
+    const int grid_max = batched_grid_size();
+    if (grid_max <= 0) return hip_err(hipErrorInvalidValue, "occupancy query");
+    e = hipStreamBeginCapture(g_capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_err(e, "begin capture");
+    int lrc = 0;
+    int active = nprob;
+    for (int l = 0; l < max_s && lrc == 0; ++l) {
+        while (active > 0 && E.probs[active - 1].s <= l) --active;
+        const long long items = E.chunk_prefix[active];
+        long long grid = std::min<long long>(grid_max, (items + 7) / 8 * 8);
+        if (grid < 1) grid = 1;
+        lrc = launch_batched_level(reinterpret_cast<const BatchProblem *>(base + L.probs),
+                                   reinterpret_cast<const long long *>(base + L.chunk_prefix),
+                                   items, active, l, (int)grid, g_capture);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(g_capture, &graph);
+    if (lrc != 0) {
+        if (graph) hipGraphDestroy(graph);
+        return hip_err((hipError_t)lrc, "capture launch");
+    }
+    if (e2 != hipSuccess) return hip_err(e2, "end capture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(graph);
+        return hip_err(e, "instantiate");
+    }
+    E.graph = graph;
+    E.exec = exec;
+    E.key = key;
+    e = hipGraphLaunch(E.exec, st);
+    return e == hipSuccess ? FRKC2_OK : hip_err(e, "graph launch");
+}
+
+extern "C" int frkc2_batched_status(void *ws, hipStream_t st)
+{
+    if (!ws) {
+        set_error("batched: workspace is NULL");
+        return FRKC2_EINVAL;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_graphs.find(ws);
+        if (it == g_graphs.end() || !it->second.exec) {
+            set_error("batched: no batched launch recorded for this workspace");
+            return FRKC2_EINVAL;
+        }
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_err(e, "status");
+    return FRKC2_OK;
+}
+
+extern "C" int frkc2_batched_release(void *ws)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_graphs.find(ws);
+    if (it == g_graphs.end()) return FRKC2_OK;
+    drop(it->second);
+    g_graphs.erase(it);
+    return FRKC2_OK;
+}

@@ -66,6 +66,50 @@ __device__ __forceinline__ double load_r(const Dims &d, const double *v, int gx,
     return i < 0 ? 0.0 : v[i];
 }
 
+// Branch-free versions for software pipelining: the load is always issued
+// (at a clamped in-range address) and a Dirichlet ghost is selected to 0
+// afterwards, so no control flow separates a prefetch from its use and the
+// compiler can keep several loads in flight across barriers.
+template <int BC>
+__device__ __forceinline__ long long bc_index_nb(const Dims &d, int gx, int gy, int gz, bool &ghost)
+{
+    if (BC == PER) {
+        ghost = false;
+        gx = wrap(gx, d.nx);
+        gy = wrap(gy, d.ny);
+        gz = wrap(gz, d.nz);
+    } else {
+        ghost = (gx < 0) | (gx >= d.nx) | (gy < 0) | (gy >= d.ny) | (gz < 0) | (gz >= d.nz);
+        gx = min(max(gx, 0), d.nx - 1);
+        gy = min(max(gy, 0), d.ny - 1);
+        gz = min(max(gz, 0), d.nz - 1);
+    }
+    return gx + (long long)d.nx * (gy + (long long)d.ny * gz);
+}
+
+template <int BC, bool IN_REAL>
+__device__ __forceinline__ double2 load_c_nb(const Dims &d, const double *re, const double2 *c,
+                                             int gx, int gy, int gz)
+{
+    bool ghost;
+    const long long i = bc_index_nb<BC>(d, gx, gy, gz, ghost);
+    double2 v;
+    if (IN_REAL) v = make_double2(re[i], 0.0);
+    else v = c[i];
+    v.x = ghost ? 0.0 : v.x;
+    v.y = ghost ? 0.0 : v.y;
+    return v;
+}
+
+template <int BC>
+__device__ __forceinline__ double load_r_nb(const Dims &d, const double *v, int gx, int gy, int gz)
+{
+    bool ghost;
+    const long long i = bc_index_nb<BC>(d, gx, gy, gz, ghost);
+    const double r = v[i];
+    return ghost ? 0.0 : r;
+}
+
 // One face of the flux sum of the diffusion operator, in the fixed order the
 // library and its CPU check share. nb: neighbour value (0 for a Dirichlet
 // ghost); dc, dn: cell and neighbour diffusivity; ghost selects D_f = D_c,

@@ -52,6 +52,10 @@ int launch_finalize(const KGrid &g, const double *in_c, double *out_re, double *
 int launch_real_to_complex(long long n, const double *in, double *out_c, hipStream_t st);
 int launch_zero(long long n, double *p, hipStream_t st);   // fill kernel (graph-safe)
 
+// Temporally blocked passes (tblock.hip): p.k stages in one HBM pass.
+bool tblock_supported(const KGrid &g, int k);
+int launch_tblock(const KGrid &g, const PassArgs &p, int shape, hipStream_t st);
+
 // Reductions (reduce.hip). partials must hold kReduceBlocks doubles + 2.
 constexpr int kReduceBlocks = 512;
 int launch_reduce(int op, const double *x, const double *y, long long n, double *partials,
@@ -80,16 +84,12 @@ struct BatchProblem {           // one problem's descriptor in device memory
     double *bufA, *bufB;        // complex ping-pong buffers in the workspace
     const double *tau;          // 2*s doubles (re, im interleaved)
     int nx, ny, nz, ndim, bc, op;
-    int s, ntiles, first_item;
+    int s, ntiles;              // stages, work chunks per stage
     double inv_h2, d_const;
 };
-struct BatchItem {              // one (problem, stage, tile) unit of work
-    int prob, stage, tile, pad;
-};
-int launch_batched(const BatchProblem *probs, const BatchItem *items, int nitems,
-                   unsigned int *counters, unsigned int *queue_head, int *error_flag,
-                   int nprob, int grid, hipStream_t st);
-int batched_tile_shape(int ndim, int *bx, int *by, int *bz);
-int batched_max_grid();
+int batched_chunk_points();
+int batched_grid_size();
+int launch_batched_level(const BatchProblem *probs, const long long *chunk_prefix, long long items,
+                         int active, int level, int grid, hipStream_t st);
 
 }  // namespace frkc2

@@ -98,37 +98,62 @@ __global__ __launch_bounds__(BX *BY) void plane_stage(PlaneArgs a)
     const int hslot = (NDIM == 3 ? (hy + 1) * SX : 0) + (hx + 1);
     const int oslot = (NDIM == 3 ? (ty + 1) * SX : 0) + (tx + 1);
 
-    // own column: planes z-1, z, z+1 (ghost or wrapped at the domain ends)
-    double2 Wm = load_w<BC, IN_REAL>(a, x, y, z0 - 1);
-    double2 Wc = load_w<BC, IN_REAL>(a, x, y, z0);
-    double2 Wp = load_w<BC, IN_REAL>(a, x, y, z0 + 1);
-    double Dm = 0.0, Dc = 0.0, Dp = 0.0;
-    if (OP == VAR) {
-        Dm = load_d<BC>(a, x, y, z0 - 1);
-        Dc = load_d<BC>(a, x, y, z0);
-        Dp = load_d<BC>(a, x, y, z0 + 1);
-    }
-    double2 hW = make_double2(0.0, 0.0);
-    double hD = 0.0;
-    if (has_halo) {
-        hW = load_w<BC, IN_REAL>(a, x0 + hx, y0 + hy, z0);
-        if (OP == VAR) hD = load_d<BC>(a, x0 + hx, y0 + hy, z0);
-    }
+    // Own column: planes z-1, z, z+1 in use and z+2 in flight; halo cell of
+    // plane z in use and of z+1 in flight. All loads are branch-free (a
+    // thread without a halo cell re-reads its own point), so the prefetches
+    // stay outstanding across the barrier.
+    const Dims dm{a.nx, a.ny, a.nz};
+    const int hgx = has_halo ? x0 + hx : x, hgy = has_halo ? y0 + hy : y;
+    // Raw loads at clamped (or wrapped) addresses; a Dirichlet ghost is zeroed
+    // only where the value is consumed, so nothing waits for a prefetch early.
+    auto LW = [&](int gx, int gy, int gz) {
+        bool g;
+        const long long i = bc_index_nb<BC>(dm, gx, gy, gz, g);
+        return IN_REAL ? make_double2(a.in_re[i], 0.0) : a.in_c[i];
+    };
+    auto LD = [&](int gx, int gy, int gz) {
+        bool g;
+        const long long i = bc_index_nb<BC>(dm, gx, gy, gz, g);
+        return (OP == VAR) ? a.D[i] : 0.0;   // ghost D is never used
+    };
+    const bool dirichlet = (BC == DIR);
+    const bool own_out = dirichlet && !(x < a.nx && y < a.ny);
+    const bool halo_out = dirichlet && !(hgx >= 0 && hgx < a.nx && hgy >= 0 && hgy < a.ny);
+    auto keep = [&](double2 v, bool ghost) {
+        v.x = ghost ? 0.0 : v.x;
+        v.y = ghost ? 0.0 : v.y;
+        return v;
+    };
+    auto zout = [&](int p) { return dirichlet && (p < 0 || p >= a.nz); };
+    // Plane p of the own column sits in ring slot (p - z0 + 1) & 3 and the
+    // halo cell of plane p in slot (p - z0) & 1. The z loop is unrolled by
+    // four, so every slot index is a compile-time constant: a new plane is
+    // loaded straight into the slot it will be used from, and no register
+    // copy has to wait for a load in flight.
+    double2 Wr[4] = {LW(x, y, z0 - 1), LW(x, y, z0), LW(x, y, z0 + 1), LW(x, y, z0 + 2)};
+    double Dr[4] = {LD(x, y, z0 - 1), LD(x, y, z0), LD(x, y, z0 + 1), LD(x, y, z0 + 2)};
+    double2 hWr[2] = {LW(hgx, hgy, z0), LW(hgx, hgy, z0 + 1)};
+    double hDr[2] = {LD(hgx, hgy, z0), LD(hgx, hgy, z0 + 1)};
 
-    for (int z = z0; z < z1; ++z) {
+    for (int zb = z0; zb < z1; zb += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int z = zb + u;
+        if (z >= z1) break;
+        const double2 Wm = keep(Wr[u & 3], own_out || zout(z - 1));
+        const double2 Wc = keep(Wr[(u + 1) & 3], own_out || zout(z));
+        const double2 Wp = keep(Wr[(u + 2) & 3], own_out || zout(z + 1));
+        const double Dm = Dr[u & 3], Dc = Dr[(u + 1) & 3], Dp = Dr[(u + 2) & 3];
         const int b = z & 1;
         sW[b][oslot] = Wc;
         if (OP == VAR) sD[b][oslot] = Dc;
         if (has_halo) {
-            sW[b][hslot] = hW;
-            if (OP == VAR) sD[b][hslot] = hD;
+            sW[b][hslot] = keep(hWr[u & 1], halo_out || zout(z));
+            if (OP == VAR) sD[b][hslot] = hDr[u & 1];
         }
         __syncthreads();
-        // prefetch the next plane's halo cell
-        if (has_halo && z + 1 < z1) {
-            hW = load_w<BC, IN_REAL>(a, x0 + hx, y0 + hy, z + 1);
-            if (OP == VAR) hD = load_d<BC>(a, x0 + hx, y0 + hy, z + 1);
-        }
+        hWr[u & 1] = LW(hgx, hgy, z + 2);
+        hDr[u & 1] = LD(hgx, hgy, z + 2);
         if (active) {
             const double2 c = Wc;
             double qr_c = 0.0, qi_c = 0.0;
@@ -160,16 +185,9 @@ __global__ __launch_bounds__(BX *BY) void plane_stage(PlaneArgs a)
             if (OUT_REAL) a.out_re[i] = nv.x;
             else a.out_c[i] = nv;
         }
-        Wm = Wc;
-        Wc = Wp;
-        if (OP == VAR) {
-            Dm = Dc;
-            Dc = Dp;
-        }
-        if (z + 1 < z1) {
-            Wp = load_w<BC, IN_REAL>(a, x, y, z + 2);
-            if (OP == VAR) Dp = load_d<BC>(a, x, y, z + 2);
-        }
+        Wr[u & 3] = LW(x, y, z + 3);   // the slot of plane z-1
+        Dr[u & 3] = LD(x, y, z + 3);
+    }
     }
 }
 

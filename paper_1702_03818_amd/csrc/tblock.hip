@@ -1,0 +1,336 @@
+// Temporally blocked FRKC2 stages: K consecutive Euler stages
+// W <- W + tau_l f(W) (O'Sullivan, arXiv:1702.03818, Sec. 3, Euler-step
+// equation) in one HBM pass.
+//
+// The stages of a superstep are strictly sequential, but stage l+1 at a
+// point only needs stage l within one cell of it, so K stages of a tile can
+// be computed from the tile's input extended by a K-cell halo. Each
+// workgroup owns an extended tile of BXE x BYE columns (3D; 2D tiles are one
+// row of BXE) and marches through a chunk of z planes with a software
+// pipeline: at time step t it has level 0 (the pass input) of plane t and
+// computes level m (the state after m stages of the pass) at plane t - m for
+// m = 1..K. Level m at plane p needs level m-1 at planes p-1, p, p+1 of the
+// same column, which the thread keeps in registers, and level m-1 at the x/y
+// neighbours of plane p, which sit in LDS (one plane per level, written in
+// the previous time step). The diffusivity planes t-K-1 .. t-1 live in an LDS
+// ring. Two barriers per time step separate the LDS reads from the writes.
+//
+// Level 0 is prefetched one time step ahead into a four-slot register ring;
+// the time loop is unrolled by four so the slot indices are compile-time
+// constants and a load in flight is never copied (a copy would have to wait
+// for it). Dirichlet ghosts are zeroed where a value is used, not where it is
+// loaded, for the same reason.
+//
+// Only level K inside the inner (BXE-2K) x (BYE-2K) region is written back;
+// the ring of halo columns is recomputed by the neighbouring tile (their
+// input is read twice, mostly through L2). HBM traffic per pass is the input
+// (16 B complex or 8 B real, plus 8 B of D) and the output (16 B or 8 B), so
+// per stage it drops roughly by K.
+//
+// Every value is computed with the same per-point arithmetic, in the same
+// order, as the one-stage kernel (faces x-, x+, y-, y+, z-, z+; no fused
+// multiply-adds), so the results are identical to the last bit.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace frkc2 {
+namespace {
+
+using namespace dev;
+
+struct TbArgs {
+    const double *in_re;
+    const double2 *in_c;
+    double *out_re;
+    double2 *out_c;
+    const double *D;
+    int nx, ny, nz;
+    int zchunk, ntx, nty;
+    double inv_h2, d_const;
+    double tr[kMaxTBlock], ti[kMaxTBlock];
+};
+
+__device__ __forceinline__ double2 keep(double2 v, bool ghost)
+{
+    v.x = ghost ? 0.0 : v.x;
+    v.y = ghost ? 0.0 : v.y;
+    return v;
+}
+
+// NDIM 3: threads BXE x TY, each owning R rows (ty + r*TY) of an extended
+// tile BXE x (TY*R). NDIM 2: one row, TY = R = 1, "z" is the second grid
+// dimension.
+template <int OP, int BC, int NDIM, int BXE, int TY, int R, int K, bool IN_REAL, bool OUT_REAL>
+__global__ __launch_bounds__(BXE *TY) void tb_stage(TbArgs a)
+{
+    constexpr int BYE = TY * R;
+    constexpr int SX = BXE + 2;
+    constexpr int SY = (NDIM == 3) ? BYE + 2 : 1;
+    constexpr int PL = SX * SY;                     // padded plane
+    constexpr bool VC = (OP == VAR);
+    constexpr int ND = K + 1;                       // D ring: planes t-K-1 .. t-1
+    constexpr int BXO = BXE - 2 * K;                // output tile
+    constexpr int BYO = (NDIM == 3) ? BYE - 2 * K : 1;
+    static_assert(BXO > 0 && BYO > 0, "tile too small for K");
+    __shared__ double2 sL[K][PL];                   // level m plane (m = 0..K-1)
+    __shared__ double sD[VC ? ND : 1][VC ? PL : 1];
+
+    const Dims dm{a.nx, a.ny, a.nz};
+    const int tid = threadIdx.x;
+    const int tx = tid % BXE, ty = tid / BXE;
+    int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = lb % a.ntx;
+    lb /= a.ntx;
+    const int by = lb % a.nty;
+    const int bz = lb / a.nty;
+    const int xe0 = bx * BXO - K;
+    const int ye0 = (NDIM == 3) ? by * BYO - K : 0;
+    const int x = xe0 + tx;
+    const int z0 = bz * a.zchunk;
+    const int z1 = min(z0 + a.zchunk, a.nz);
+    const bool dir = (BC == DIR);
+    const bool x_in = x >= 0 && x < a.nx;
+    const bool x_out = tx >= K && tx < BXE - K && x < a.nx;
+
+    int yr[R], slot[R];
+    bool col_ghost[R], out_col[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int ly = ty + r * TY;                 // row inside the extended tile
+        yr[r] = ye0 + ly;
+        slot[r] = (NDIM == 3 ? (ly + 1) * SX : 0) + tx + 1;
+        const bool y_in = (NDIM == 3) ? (yr[r] >= 0 && yr[r] < a.ny) : true;
+        col_ghost[r] = dir && !(x_in && y_in);      // Dirichlet ghost column: all levels 0
+        const bool y_out = (NDIM == 3) ? (ly >= K && ly < BYE - K && yr[r] < a.ny) : true;
+        out_col[r] = x_out && y_out;
+    }
+    auto LW = [&](int gy, int gz) {
+        bool g;
+        const long long i = bc_index_nb<BC>(dm, x, gy, gz, g);
+        return IN_REAL ? make_double2(a.in_re[i], 0.0) : a.in_c[i];
+    };
+    auto LD = [&](int gy, int gz) {
+        bool g;
+        const long long i = bc_index_nb<BC>(dm, x, gy, gz, g);
+        return VC ? a.D[i] : 0.0;
+    };
+    auto pout = [&](int p) { return dir && (p < 0 || p >= a.nz); };
+    auto dslot = [](int p) { return ((p % ND) + ND) % ND; };
+
+    // level 0 ring: plane p in slot (p - t_begin) & 3; D of plane p alongside
+    // register windows of levels 1..K-1: planes (q-1, q, q+1) around the plane
+    // that the next level computes
+    const int t_begin = z0 - K, t_end = z1 + K;     // level 0 planes z0-K .. z1+K-1
+    double2 L0[4][R];
+    double D0[4][R];
+    double2 wm[K > 1 ? K - 1 : 1][R], wc[K > 1 ? K - 1 : 1][R], wp[K > 1 ? K - 1 : 1][R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int gy = (NDIM == 3) ? yr[r] : 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            L0[q][r] = make_double2(0.0, 0.0);
+            D0[q][r] = 0.0;
+        }
+        L0[0][r] = LW(gy, t_begin);
+        D0[0][r] = LD(gy, t_begin);
+#pragma unroll
+        for (int m = 0; m + 1 < K; ++m) wm[m][r] = wc[m][r] = wp[m][r] = make_double2(0.0, 0.0);
+    }
+
+    for (int tb = t_begin; tb < t_end; tb += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int t = tb + u;
+        if (t >= t_end) break;
+        // prefetch plane t+1 into the slot of plane t-3
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int gy = (NDIM == 3) ? yr[r] : 0;
+            L0[(u + 1) & 3][r] = LW(gy, t + 1);
+            D0[(u + 1) & 3][r] = LD(gy, t + 1);
+        }
+        // levels 1..K at planes t-1 .. t-K
+#pragma unroll
+        for (int m = 1; m <= K; ++m) {
+            const int p = t - m;
+            const double2 *L = sL[m - 1];
+            const double *Dc_ = VC ? sD[dslot(p)] : nullptr;
+            const double *Dm_ = VC ? sD[dslot(p - 1)] : nullptr;
+            const double *Dp_ = VC ? sD[dslot(p + 1)] : nullptr;
+            const bool pghost = pout(p);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int sl = slot[r];
+                double2 c, zm, zp;
+                if (m == 1) {
+                    // level 0 from the ring: planes t-2, t-1, t in slots u-2, u-1, u
+                    zm = keep(L0[(u + 2) & 3][r], col_ghost[r] || pout(t - 2));
+                    c = keep(L0[(u + 3) & 3][r], col_ghost[r] || pout(t - 1));
+                    zp = keep(L0[u & 3][r], col_ghost[r] || pout(t));
+                } else {
+                    zm = wm[m - 2][r];
+                    c = wc[m - 2][r];
+                    zp = wp[m - 2][r];
+                }
+                double dc = 0.0, dzm = 0.0, dzp = 0.0;
+                if (VC) {
+                    dc = Dc_[sl];
+                    dzm = Dm_[sl];
+                    dzp = (m == 1) ? D0[u & 3][r] : Dp_[sl];   // plane t is not in LDS yet
+                }
+                double qr_c = 0.0, qi_c = 0.0;
+                if (OP == POR) {
+                    qr_c = c.x * c.x - c.y * c.y;
+                    qi_c = 2.0 * (c.x * c.y);
+                }
+                double acc_r = 0.0, acc_i = 0.0;
+                face<OP>(acc_r, acc_i, c, L[sl - 1], dc, VC ? Dc_[sl - 1] : 0.0, dir && x == 0,
+                         qr_c, qi_c, a.d_const);
+                face<OP>(acc_r, acc_i, c, L[sl + 1], dc, VC ? Dc_[sl + 1] : 0.0,
+                         dir && x == a.nx - 1, qr_c, qi_c, a.d_const);
+                if (NDIM == 3) {
+                    face<OP>(acc_r, acc_i, c, L[sl - SX], dc, VC ? Dc_[sl - SX] : 0.0,
+                             dir && yr[r] == 0, qr_c, qi_c, a.d_const);
+                    face<OP>(acc_r, acc_i, c, L[sl + SX], dc, VC ? Dc_[sl + SX] : 0.0,
+                             dir && yr[r] == a.ny - 1, qr_c, qi_c, a.d_const);
+                }
+                face<OP>(acc_r, acc_i, c, zm, dc, dzm, dir && p == 0, qr_c, qi_c, a.d_const);
+                face<OP>(acc_r, acc_i, c, zp, dc, dzp, dir && p == a.nz - 1, qr_c, qi_c,
+                         a.d_const);
+                double2 v = euler(c, acc_r, acc_i, a.inv_h2, a.tr[m - 1], a.ti[m - 1]);
+                v = keep(v, col_ghost[r] || pghost);
+                if (m < K) {
+                    wm[m - 1][r] = wc[m - 1][r];
+                    wc[m - 1][r] = wp[m - 1][r];
+                    wp[m - 1][r] = v;
+                } else if (out_col[r] && p >= z0 && p < z1) {
+                    const int gy = (NDIM == 3) ? yr[r] : 0;
+                    const long long i = x + (long long)a.nx * (gy + (long long)a.ny * p);
+                    if (OUT_REAL) a.out_re[i] = v.x;
+                    else a.out_c[i] = v;
+                }
+            }
+        }
+        __syncthreads();   // every read of the LDS planes of this step is done
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            sL[0][slot[r]] = keep(L0[u & 3][r], col_ghost[r] || pout(t));
+#pragma unroll
+            for (int m = 1; m < K; ++m) sL[m][slot[r]] = wp[m - 1][r];
+            if (VC) sD[dslot(t)][slot[r]] = D0[u & 3][r];
+        }
+        __syncthreads();   // the planes of step t are visible to step t+1
+    }
+    }
+}
+
+int choose_zchunk(long long tiles, int nz, int target_blocks)
+{
+    int zc = nz;
+    while (zc > 16 && tiles * ((nz + zc - 1) / zc) < target_blocks) zc = (zc + 1) / 2;
+    return zc;
+}
+
+template <int OP, int BC, int NDIM, int BXE, int TY, int R, int K>
+int launch_k(const TbArgs &a0, bool ir, bool orl, hipStream_t st)
+{
+    TbArgs a = a0;
+    constexpr int BXO = BXE - 2 * K;
+    constexpr int BYO = (NDIM == 3) ? TY * R - 2 * K : 1;
+    a.ntx = (a.nx + BXO - 1) / BXO;
+    a.nty = (NDIM == 3) ? (a.ny + BYO - 1) / BYO : 1;
+    const long long tiles = (long long)a.ntx * a.nty;
+    a.zchunk = choose_zchunk(tiles, a.nz, NDIM == 3 ? 512 : 2048);
+    const long long nblk = tiles * ((a.nz + a.zchunk - 1) / a.zchunk);
+    if (nblk > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+    dim3 grid((unsigned)nblk), block(BXE * TY);
+    if (ir && orl)
+        hipLaunchKernelGGL((tb_stage<OP, BC, NDIM, BXE, TY, R, K, true, true>), grid, block, 0, st, a);
+    else if (ir)
+        hipLaunchKernelGGL((tb_stage<OP, BC, NDIM, BXE, TY, R, K, true, false>), grid, block, 0, st, a);
+    else if (orl)
+        hipLaunchKernelGGL((tb_stage<OP, BC, NDIM, BXE, TY, R, K, false, true>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((tb_stage<OP, BC, NDIM, BXE, TY, R, K, false, false>), grid, block, 0, st, a);
+    return (int)hipGetLastError();
+}
+
+// Tile shapes, chosen to fit LDS (160 KiB per workgroup) and registers:
+//  3D shape 0: 64 x 16 extended columns, 1024 threads, one row each
+//  3D shape 1: 64 x 32 extended columns, 1024 threads, two rows each (K = 2)
+//  3D shape 2: 64 x 32 (K = 2) or 64 x 24 (K = 3) with 512 threads
+//  2D shape 0: rows of 256 extended columns; shape 1: rows of 512.
+template <int OP, int BC, int K>
+int launch_shape(int ndim, int shape, const TbArgs &a, bool ir, bool orl, hipStream_t st)
+{
+    if (ndim == 3) {
+        if constexpr (K == 2) {
+            if (shape == 1) return launch_k<OP, BC, 3, 64, 16, 2, K>(a, ir, orl, st);
+            if (shape == 2) return launch_k<OP, BC, 3, 64, 8, 4, K>(a, ir, orl, st);
+        }
+        if constexpr (K == 3) {
+            if (shape == 2) return launch_k<OP, BC, 3, 64, 8, 3, K>(a, ir, orl, st);
+        }
+        if constexpr (K <= 3) return launch_k<OP, BC, 3, 64, 16, 1, K>(a, ir, orl, st);
+        else return (int)hipErrorInvalidValue;
+    }
+    if (shape == 1) return launch_k<OP, BC, 2, 512, 1, 1, K>(a, ir, orl, st);
+    return launch_k<OP, BC, 2, 256, 1, 1, K>(a, ir, orl, st);
+}
+
+template <int OP, int BC>
+int launch_kk(int ndim, int k, int shape, const TbArgs &a, bool ir, bool orl, hipStream_t st)
+{
+    switch (k) {
+    case 2: return launch_shape<OP, BC, 2>(ndim, shape, a, ir, orl, st);
+    case 3: return launch_shape<OP, BC, 3>(ndim, shape, a, ir, orl, st);
+    case 4: return launch_shape<OP, BC, 4>(ndim, shape, a, ir, orl, st);
+    case 6: return launch_shape<OP, BC, 6>(ndim, shape, a, ir, orl, st);
+    case 8: return launch_shape<OP, BC, 8>(ndim, shape, a, ir, orl, st);
+    default: return (int)hipErrorInvalidValue;
+    }
+}
+
+template <int OP>
+int launch_bc(const KGrid &g, int k, int shape, const TbArgs &a, bool ir, bool orl, hipStream_t st)
+{
+    if (g.bc == PER) return launch_kk<OP, PER>(g.ndim, k, shape, a, ir, orl, st);
+    return launch_kk<OP, DIR>(g.ndim, k, shape, a, ir, orl, st);
+}
+
+}  // namespace
+
+bool tblock_supported(const KGrid &g, int k)
+{
+    if (g.ndim == 3) return k == 2 || k == 3;
+    if (g.ndim == 2) return k == 2 || k == 3 || k == 4 || k == 6 || k == 8;
+    return false;
+}
+
+int launch_tblock(const KGrid &g, const PassArgs &p, int shape, hipStream_t st)
+{
+    if (!tblock_supported(g, p.k)) return (int)hipErrorInvalidValue;
+    TbArgs a{};
+    a.in_re = p.in_re;
+    a.in_c = reinterpret_cast<const double2 *>(p.in_c);
+    a.out_re = p.out_re;
+    a.out_c = reinterpret_cast<double2 *>(p.out_c);
+    a.D = p.D;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.nz = g.nz;
+    a.inv_h2 = g.inv_h2;
+    a.d_const = g.d_const;
+    for (int i = 0; i < kMaxTBlock; ++i) {
+        a.tr[i] = p.tr[i];
+        a.ti[i] = p.ti[i];
+    }
+    const bool ir = p.in_re != nullptr, orl = p.out_re != nullptr;
+    if (g.op == LAP) return launch_bc<LAP>(g, p.k, shape, a, ir, orl, st);
+    if (g.op == VAR) return launch_bc<VAR>(g, p.k, shape, a, ir, orl, st);
+    return launch_bc<POR>(g, p.k, shape, a, ir, orl, st);
+}
+
+}  // namespace frkc2

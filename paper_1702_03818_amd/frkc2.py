@@ -28,6 +28,7 @@ WS_ADJOINT = 1
 RED_SUMSQ, RED_SUM, RED_MAXSQ, RED_SUMSQDIFF, RED_DOT = 0, 1, 2, 3, 4
 OPT_TBLOCK = 1
 OPT_XCD_REMAP = 2
+OPT_TILE = 3
 
 
 class Frkc2Error(RuntimeError):
@@ -74,6 +75,7 @@ _SIGS = {
                                           ctypes.POINTER(ctypes.c_int), ctypes.c_double, _VP,
                                           ctypes.c_size_t, _VP]),
     "frkc2_batched_status": (ctypes.c_int, [_VP, _VP]),
+    "frkc2_batched_release": (ctypes.c_int, [_VP]),
     "frkc2_reduce": (ctypes.c_int, [ctypes.c_int, _VP, _VP, ctypes.c_size_t, _DP, _VP,
                                     ctypes.c_size_t, _VP]),
     "frkc2_set_option": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
@@ -256,8 +258,16 @@ def frkc2_step_batched(args: BatchedArgs, nu=0.01, stream=None, ws=None):
                                          _stream_ptr(stream)))
 
 
-def frkc2_batched_status(ws, stream=None):
-    return _check(load().frkc2_batched_status(ctypes.c_void_p(ws.data_ptr()), _stream_ptr(stream)))
+def frkc2_batched_status(ws=None, stream=None):
+    buf = ws if ws is not None else workspace(0, key="batched")
+    return _check(load().frkc2_batched_status(ctypes.c_void_p(buf.data_ptr()), _stream_ptr(stream)))
+
+
+def frkc2_batched_release(ws=None):
+    buf = ws if ws is not None else _ws_cache.get((_torch().cuda.current_device(), "batched"))
+    if buf is None:
+        return 0
+    return _check(load().frkc2_batched_release(ctypes.c_void_p(buf.data_ptr())))
 
 
 def frkc2_reduce(op: int, x, y=None, stream=None) -> float:

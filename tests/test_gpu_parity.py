@@ -199,3 +199,87 @@ def test_reductions(op, n):
         assert got == ref
     else:
         assert abs(got - ref) <= 1e-13 * scale
+
+
+TB_CASES = [
+    ("3d-var-dir", (70, 37, 21), 2, 0), ("3d-var-dir", (70, 37, 21), 2, 1),
+    ("3d-var-dir", (70, 37, 21), 3, 0), ("3d-var-per", (67, 30, 18), 2, 1),
+    ("3d-var-per", (67, 30, 18), 3, 0), ("3d-lap-dir", (33, 17, 9), 2, 0),
+    ("3d-lap-per", (9, 5, 4), 3, 0), ("3d-var-dir", (2, 3, 2), 2, 1),
+    ("2d-var-dir", (300, 37, 1), 2, 0), ("2d-var-dir", (300, 37, 1), 3, 0),
+    ("2d-var-per", (257, 19, 1), 4, 0), ("2d-lap-per", (513, 20, 1), 6, 0),
+    ("2d-por-per", (260, 33, 1), 8, 0), ("2d-por-dir", (70, 50, 1), 4, 0),
+    ("2d-var-dir", (5, 3, 1), 8, 0),
+]
+
+
+@pytest.mark.parametrize("kind,n,k,shape", TB_CASES)
+@pytest.mark.parametrize("s", [16, 100])
+def test_temporal_blocking_matches_oracle(kind, n, k, shape, s):
+    """k stages fused per HBM pass (with a single-stage remainder) give the same bits."""
+    F.frkc2_set_option(F.OPT_TBLOCK, k)
+    F.frkc2_set_option(F.OPT_TILE, shape)
+    try:
+        test_superstep_matches_oracle(kind, n, s)
+    finally:
+        F.frkc2_set_option(F.OPT_TBLOCK, 0)
+        F.frkc2_set_option(F.OPT_TILE, 0)
+
+
+def _batch_problems():
+    """Uneven 2D/3D problems: ragged sizes, both boundaries, both linear operators, one chunk
+    or many, s from 2 to 100."""
+    specs = [
+        ("3d-var-dir", (70, 37, 21), 16), ("3d-var-dir", (33, 17, 9), 100), ("3d-var-per", (67, 30, 18), 8),
+        ("3d-lap-dir", (33, 17, 9), 2), ("3d-lap-per", (9, 5, 4), 64), ("3d-var-dir", (2, 3, 2), 16),
+        ("2d-var-dir", (300, 37, 1), 100), ("2d-var-per", (257, 19, 1), 16), ("2d-lap-per", (513, 20, 1), 8),
+        ("2d-var-dir", (5, 3, 1), 2), ("3d-var-dir", (40, 40, 40), 32), ("2d-var-dir", (200, 200, 1), 50),
+    ]
+    out = []
+    for kind, n, s in specs:
+        p = problem(kind, n)
+        c = frkc2_coeffs(s, 0.01)
+        T = 0.9 * c.beta_bar / stage.rho_bound(p)
+        out.append((p, s, T, c))
+    return out
+
+
+def test_batched_matches_oracle_and_replays():
+    probs = _batch_problems()
+    ws_list = [dev(p.w0) for p, _, _, _ in probs]
+    D_list = [dev(p.D) if p.D is not None else None for p, _, _, _ in probs]
+    args = F.BatchedArgs([p for p, _, _, _ in probs], ws_list, D_list, [T for _, _, T, _ in probs],
+                         [s for _, s, _, _ in probs])
+    F.frkc2_step_batched(args)
+    torch.cuda.synchronize()
+    assert F.frkc2_batched_status() == 0
+    refs = []
+    for (p, s, T, c), w in zip(probs, ws_list):
+        ref = stage.superstep(p, p.w0, T * c.a_re, T * c.a_im)
+        check(host(w), ref, "batched first call %s s=%d" % (p.n, s))
+        refs.append(ref)
+    # second call with identical arguments replays the cached graph
+    F.frkc2_step_batched(args)
+    torch.cuda.synchronize()
+    assert F.frkc2_batched_status() == 0
+    for (p, s, T, c), w, r1 in zip(probs, ws_list, refs):
+        ref = stage.superstep(p, r1, T * c.a_re, T * c.a_im)
+        check(host(w), ref, "batched replay %s s=%d" % (p.n, s))
+    F.frkc2_batched_release()
+
+
+def test_batched_equals_plain_path():
+    probs = _batch_problems()
+    ws_b = [dev(p.w0) for p, _, _, _ in probs]
+    D_list = [dev(p.D) if p.D is not None else None for p, _, _, _ in probs]
+    args = F.BatchedArgs([p for p, _, _, _ in probs], ws_b, D_list, [T for _, _, T, _ in probs],
+                         [s for _, s, _, _ in probs])
+    for _ in range(3):
+        F.frkc2_step_batched(args)
+    for (p, s, T, c), wb, D in zip(probs, ws_b, D_list):
+        w = dev(p.w0)
+        F.frkc2_step(p, w, D, T=T, s=s, nsteps=3)
+        torch.cuda.synchronize()
+        assert torch.equal(w, wb), "batched vs plain %s s=%d" % (p.n, s)
+    assert F.frkc2_batched_status() == 0
+    F.frkc2_batched_release()
