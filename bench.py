@@ -37,6 +37,45 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("stage.hip", "tblock.hip", "device_common.h", "api.cpp")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1702_03818_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_stage3d_256.json")
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("sources_sha256") != kernel_sources_sha256():
+        return None, "counters were taken on different kernel sources"
+    return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"], t.get("note", "")
+
+
+def pass_schedule(s, k, supported=(2, 3)):
+    """Stages per HBM pass for one superstep, as the library schedules them (3D)."""
+    out, l = [], 0
+    while l < s:
+        kk = k if (k >= 2 and s - l >= k) else 1
+        if l == 0 and kk == s:
+            kk = s - 1
+            while kk >= 2 and kk not in supported:
+                kk -= 1
+        out.append(kk)
+        l += kk
+    return out
+
+
 def cpu_baseline(prob, T, c_lib):
     """Oracle superstep (s = 100) on the full 256^3 grid, timed on the host cores."""
     from oracle import frkc2_coeffs as ocoeffs
@@ -157,6 +196,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batched leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--tblock", type=int, default=2, choices=(1, 2, 3),
+                    help="stages fused per HBM pass in the timed run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the FRKC2 superstep here is a single-GPU build "
@@ -170,6 +211,7 @@ def main():
     from paper_1702_03818_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    F.frkc2_set_option(F.OPT_TBLOCK, args.tblock)
     log("generating the 3D workload (n=%d)" % args.n)
     prob = wl.diffusion3d(n=args.n)
     N = prob.npoints
@@ -225,19 +267,47 @@ def main():
     updates = N * S_STAGES * SUPERSTEPS * args.steps
     value = updates / (gpu_ms * 1e-3)
 
-    # Roofline of the stage pass. Algorithmic (minimal) HBM bytes per point
-    # and pass: first pass 8 (real w) + 8 (D) + 16 (complex out); interior
-    # passes 16 + 8 + 16; last pass with the diagnostic 16 + 8 + 16. The
-    # average launch time is the event-timed region divided by the stage
-    # launches in it (every other kernel in the region counts against it).
-    passes = S_STAGES * SUPERSTEPS * args.steps
-    alg_bytes = N * SUPERSTEPS * args.steps * (32 + (S_STAGES - 1) * 40)
+    # Roofline of the stage passes. Algorithmic (minimal) HBM bytes per point
+    # and pass: input 8 (real w, first pass) or 16 (complex), D 8, output 16
+    # (complex) or 8 (real w, last pass; the step's last superstep keeps W^L
+    # complex for the Im diagnostic). The average launch time is the
+    # event-timed region divided by the stage launches in it (every other
+    # kernel in the region counts against it).
+    sched = pass_schedule(S_STAGES, args.tblock)
+    passes = len(sched) * SUPERSTEPS * args.steps
+    per_superstep = []
+    for last_complex in (False, True):
+        b = 0
+        for i, _ in enumerate(sched):
+            b += (8 if i == 0 else 16) + 8
+            b += 8 if (i == len(sched) - 1 and not last_complex) else 16
+        per_superstep.append(b)
+    alg_bytes = N * args.steps * ((SUPERSTEPS - 1) * per_superstep[0] + per_superstep[1])
     avg_launch_ms = gpu_ms / passes
     achieved = alg_bytes / (gpu_ms * 1e-3) / 1e9
+    traffic, traffic_note = measured_traffic()
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "plane_stage<VARCOEF, Dirichlet, 3D> (one stage per pass)",
-            "bytes_per_point": 40, "avg_launch_ms": avg_launch_ms}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "traffic_note": traffic_note,
+            "kernel": ("tb_stage<VARCOEF, Dirichlet, 3D, K=%d>" % args.tblock if args.tblock >= 2
+                       else "plane_stage<VARCOEF, Dirichlet, 3D>"),
+            "stages_per_pass": args.tblock, "bytes_per_point_per_pass": 40,
+            "algorithmic_bytes_per_launch": 40 * N, "avg_launch_ms": avg_launch_ms}
+    # one-stage-per-pass reference on the same state (diagnostic)
+    F.frkc2_set_option(F.OPT_TBLOCK, 1)
+    F.frkc2_step(prob, w, D, T=T, s=S_STAGES, nsteps=1)
+    e0.record()
+    for _ in range(3):
+        F.frkc2_step(prob, w, D, T=T, s=S_STAGES, nsteps=1)
+    e1.record()
+    torch.cuda.synchronize()
+    k1_ms = e0.elapsed_time(e1) / 3
+    F.frkc2_set_option(F.OPT_TBLOCK, args.tblock)
+    k1_ach = N * (32 + (S_STAGES - 2) * 40 + 32) / (k1_ms * 1e-3) / 1e9
+    k1_ref = {"ms_per_superstep": k1_ms, "value": N * S_STAGES / (k1_ms * 1e-3),
+              "achieved_gbs": k1_ach, "frac": k1_ach / HBM_PEAK_GBS}
+    log("one stage per pass: %.3f ms per superstep, %.1f GB/s" % (k1_ms, k1_ach))
     out = {
         "metric": "grid-point-stage updates/s (FRKC2 superstep) + % HBM roofline",
         "value": value, "unit": "grid-point-stage updates/s", "n_gpus": 1,
@@ -250,6 +320,7 @@ def main():
                    "grid": [args.n] * 3, "s": S_STAGES, "supersteps": SUPERSTEPS, "nu": NU,
                    "T": T, "parallelism": "single GPU"},
         "roofline": roof,
+        "one_stage_per_pass": k1_ref,
         "diagnostics": {"copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                         "im_ratio": last[0]["im_ratio"], "l2_norm": float(np.sqrt(last[1])),
                         "q_realised": info["q_realised"], "n_shrink": info["n_shrink"]},
