@@ -1,5 +1,6 @@
 // Host side of frkc2_step_batched: validation, work tables, workspace layout
-// and the cached HIP graph (one kernel node per stage level).
+// and the cached HIP graph (per stage level one kernel over the 3D problems
+// and one over the 2D problems).
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -16,11 +17,12 @@ namespace frkc2 {
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kChunkPlanes = 32;   // z planes (3D) or rows (2D) per tile
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t probs, chunk_prefix, tau, bufs, total;
-    std::vector<size_t> buf_off;   // per problem (caller's order): offset of buffer A
+    size_t probs[2], prefix[2], tau, bufs, total;   // index 0: 3D list, 1: 2D list
+    std::vector<size_t> buf_off;                   // per problem (caller's order)
 };
 
 bool validate(int nprob, const frkc2_grid *grids, const int *s, std::vector<KGrid> &kg)
@@ -47,11 +49,19 @@ bool validate(int nprob, const frkc2_grid *grids, const int *s, std::vector<KGri
 Layout layout(int nprob, const std::vector<KGrid> &kg, const int *s)
 {
     Layout L;
+    int n3 = 0;
+    for (const KGrid &g : kg) n3 += (g.ndim == 3);
+    const int cnt[2] = {n3, nprob - n3};
     const size_t sum_s = std::accumulate(s, s + nprob, (size_t)0);
     size_t o = 0;
-    L.probs = o; o = align_up(o + sizeof(BatchProblem) * nprob);
-    L.chunk_prefix = o; o = align_up(o + sizeof(long long) * (nprob + 1));
-    L.tau = o; o = align_up(o + sizeof(double) * 2 * sum_s);
+    for (int d = 0; d < 2; ++d) {
+        L.probs[d] = o;
+        o = align_up(o + sizeof(BatchProblem) * (cnt[d] + 1));
+        L.prefix[d] = o;
+        o = align_up(o + sizeof(long long) * (cnt[d] + 1));
+    }
+    L.tau = o;
+    o = align_up(o + sizeof(double) * 2 * sum_s);
     L.bufs = o;
     L.buf_off.resize(nprob);
     for (int i = 0; i < nprob; ++i) {
@@ -66,8 +76,8 @@ struct GraphEntry {
     std::vector<unsigned char> key;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::vector<BatchProblem> probs;   // host copies of the uploaded tables
-    std::vector<long long> chunk_prefix;
+    std::vector<BatchProblem> probs[2];   // host copies of the uploaded tables
+    std::vector<long long> prefix[2];
     std::vector<double> tau;
 };
 
@@ -155,18 +165,19 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
         return e == hipSuccess ? FRKC2_OK : hip_err(e, "graph launch");
     }
     drop(E);
-    // ---- work tables (problems sorted by decreasing s, stable) ----
+    // ---- work tables: 3D and 2D lists, each sorted by decreasing s (stable) ----
     char *base = static_cast<char *>(ws);
     std::vector<int> order(nprob);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return s[a] > s[b]; });
-    const int max_s = s[order[0]];
-    const long long chunk = batched_chunk_points();
-    E.probs.assign(nprob, BatchProblem{});
-    E.chunk_prefix.assign(nprob + 1, 0);
+    int max_s = 0;
     E.tau.clear();
-    for (int j = 0; j < nprob; ++j) {
-        const int i = order[j];
+    for (int d = 0; d < 2; ++d) {
+        E.probs[d].clear();
+        E.prefix[d].assign(1, 0);
+    }
+    for (int i : order) {
+        const int d = (kg[i].ndim == 3) ? 0 : 1;
         const double *are, *aim;
         int crc = coeffs_cached(s[i], nu, &are, &aim, nullptr);
         if (crc < 0) return crc;
@@ -175,7 +186,7 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
             E.tau.push_back(T[i] * are[l]);
             E.tau.push_back(T[i] * aim[l]);
         }
-        BatchProblem &P = E.probs[j];
+        BatchProblem P{};
         P.w = w[i];
         P.D = D[i];
         P.bufA = reinterpret_cast<double *>(base + L.buf_off[i]);
@@ -188,42 +199,56 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
         P.bc = kg[i].bc;
         P.op = kg[i].op;
         P.s = s[i];
-        P.ntiles = (int)((kg[i].npts() + chunk - 1) / chunk);
+        int bx, by;
+        batched_tile(P.ndim, &bx, &by);
+        P.zchunk = std::min(P.nz, kChunkPlanes);
+        P.ntx = (P.nx + bx - 1) / bx;
+        P.nty = (P.ndim == 3) ? (P.ny + by - 1) / by : 1;
+        P.ntiles = P.ntx * P.nty * ((P.nz + P.zchunk - 1) / P.zchunk);
         P.inv_h2 = kg[i].inv_h2;
         P.d_const = kg[i].d_const;
-        E.chunk_prefix[j + 1] = E.chunk_prefix[j] + P.ntiles;
+        E.probs[d].push_back(P);
+        E.prefix[d].push_back(E.prefix[d].back() + P.ntiles);
+        max_s = std::max(max_s, s[i]);
     }
-    hipError_t e;
-    e = hipMemcpyAsync(base + L.probs, E.probs.data(), sizeof(BatchProblem) * nprob,
-                       hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(base + L.chunk_prefix, E.chunk_prefix.data(),
-                           sizeof(long long) * (nprob + 1), hipMemcpyHostToDevice, st);
+    hipError_t e = hipSuccess;
+    for (int d = 0; d < 2 && e == hipSuccess; ++d) {
+        if (E.probs[d].empty()) continue;
+        e = hipMemcpyAsync(base + L.probs[d], E.probs[d].data(),
+                           sizeof(BatchProblem) * E.probs[d].size(), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(base + L.prefix[d], E.prefix[d].data(),
+                               sizeof(long long) * E.prefix[d].size(), hipMemcpyHostToDevice, st);
+    }
     if (e == hipSuccess)
         e = hipMemcpyAsync(base + L.tau, E.tau.data(), sizeof(double) * E.tau.size(),
                            hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_err(e, "table upload");
 
-    // ---- capture one kernel per stage level ----
+    // ---- capture: per stage level, the 3D kernel then the 2D kernel ----
     if (!g_capture) {
         e = hipStreamCreate(&g_capture);
         if (e != hipSuccess) return hip_err(e, "capture stream");
     }
-    const int grid_max = batched_grid_size();
-    if (grid_max <= 0) return hip_err(hipErrorInvalidValue, "occupancy query");
+    int grid_max[2] = {batched_grid_size(3), batched_grid_size(2)};
+    if (grid_max[0] <= 0 || grid_max[1] <= 0) return hip_err(hipErrorInvalidValue, "occupancy query");
     e = hipStreamBeginCapture(g_capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_err(e, "begin capture");
     int lrc = 0;
-    int active = nprob;
+    int active[2] = {(int)E.probs[0].size(), (int)E.probs[1].size()};
     for (int l = 0; l < max_s && lrc == 0; ++l) {
-        while (active > 0 && E.probs[active - 1].s <= l) --active;
-        const long long items = E.chunk_prefix[active];
-        long long grid = std::min<long long>(grid_max, (items + 7) / 8 * 8);
-        if (grid < 1) grid = 1;
-        lrc = launch_batched_level(reinterpret_cast<const BatchProblem *>(base + L.probs),
-                                   reinterpret_cast<const long long *>(base + L.chunk_prefix),
-                                   items, active, l, (int)grid, g_capture);
+        for (int d = 0; d < 2 && lrc == 0; ++d) {
+            while (active[d] > 0 && E.probs[d][active[d] - 1].s <= l) --active[d];
+            if (active[d] == 0) continue;
+            const long long items = E.prefix[d][active[d]];
+            long long grid = std::min<long long>(grid_max[d], (items + 7) / 8 * 8);
+            if (grid < 1) grid = 1;
+            lrc = launch_batched_level(d == 0 ? 3 : 2,
+                                       reinterpret_cast<const BatchProblem *>(base + L.probs[d]),
+                                       reinterpret_cast<const long long *>(base + L.prefix[d]),
+                                       items, active[d], l, (int)grid, g_capture);
+        }
     }
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(g_capture, &graph);

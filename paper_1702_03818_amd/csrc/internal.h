@@ -83,13 +83,14 @@ struct BatchProblem {           // one problem's descriptor in device memory
     const double *D;
     double *bufA, *bufB;        // complex ping-pong buffers in the workspace
     const double *tau;          // 2*s doubles (re, im interleaved)
-    int nx, ny, nz, ndim, bc, op;
-    int s, ntiles;              // stages, work chunks per stage
+    int nx, ny, nz, ndim, bc, op;   // kernel layout: 3D (n0, n1, n2), 2D (n0, 1, n1)
+    int s, ntiles;                  // stages, tiles per stage
+    int zchunk, ntx, nty;           // tile grid: ntx * nty * ceil(nz / zchunk) tiles
     double inv_h2, d_const;
 };
-int batched_chunk_points();
-int batched_grid_size();
-int launch_batched_level(const BatchProblem *probs, const long long *chunk_prefix, long long items,
-                         int active, int level, int grid, hipStream_t st);
+void batched_tile(int ndim, int *bx, int *by);
+int batched_grid_size(int ndim);
+int launch_batched_level(int ndim, const BatchProblem *probs, const long long *item_prefix,
+                         long long items, int active, int level, int grid, hipStream_t st);
 
 }  // namespace frkc2

@@ -28,167 +28,25 @@
 // independent of the tile shape.
 #include <hip/hip_runtime.h>
 
-#include "device_common.h"
+#include "plane_tile.h"
 
 namespace frkc2 {
 namespace {
 
 using namespace dev;
 
-struct PlaneArgs {
-    const double *in_re;
-    const double2 *in_c;
-    double *out_re;
-    double2 *out_c;
-    const double *D;
-    int nx, ny, nz;
-    int zchunk, ntx, nty;
-    double inv_h2, d_const, tr, ti;
-};
-
-template <int BC, bool IN_REAL>
-__device__ __forceinline__ double2 load_w(const PlaneArgs &a, int gx, int gy, int gz)
-{
-    return load_c<BC, IN_REAL>(Dims{a.nx, a.ny, a.nz}, a.in_re, a.in_c, gx, gy, gz);
-}
-
-template <int BC>
-__device__ __forceinline__ double load_d(const PlaneArgs &a, int gx, int gy, int gz)
-{
-    return load_r<BC>(Dims{a.nx, a.ny, a.nz}, a.D, gx, gy, gz);
-}
-
 template <int OP, int BC, int NDIM, int BX, int BY, bool IN_REAL, bool OUT_REAL>
 __global__ __launch_bounds__(BX *BY) void plane_stage(PlaneArgs a)
 {
-    constexpr int SX = BX + 2;
-    constexpr int SY = (NDIM == 3) ? BY + 2 : 1;   // 1D/2D tiles need only the x halo
-    constexpr int NT = BX * BY;
-    constexpr int NH = 2 * BY + (NDIM == 3 ? 2 * BX : 0);   // halo cells per plane
-    static_assert(NH <= NT, "one halo cell per thread at most");
-    __shared__ double2 sW[2][SY * SX];
-    __shared__ double sD[2][(OP == VAR) ? SY * SX : 1];
-
-    const int tid = threadIdx.x;
-    const int tx = tid % BX, ty = tid / BX;
+    using S = TileShape<OP, BC, NDIM, BX, BY>;
+    __shared__ double2 sW[S::LDS_W];
+    __shared__ double sD[S::LDS_D];
     int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int bx = lb % a.ntx;
     lb /= a.ntx;
     const int by = lb % a.nty;
     const int bz = lb / a.nty;
-    const int x0 = bx * BX, y0 = by * BY;
-    const int x = x0 + tx, y = y0 + ty;
-    const bool active = x < a.nx && y < a.ny;
-    const int z0 = bz * a.zchunk;
-    const int z1 = min(z0 + a.zchunk, a.nz);
-
-    // this thread's halo cell (if any), as plane-local (hx, hy)
-    int hx = 0, hy = 0;
-    const bool has_halo = tid < NH;
-    if (has_halo) {
-        if (tid < 2 * BY) {
-            hy = tid % BY;
-            hx = (tid < BY) ? -1 : BX;
-        } else {
-            const int hh = tid - 2 * BY;
-            hx = hh % BX;
-            hy = (hh < BX) ? -1 : BY;
-        }
-    }
-    const int hslot = (NDIM == 3 ? (hy + 1) * SX : 0) + (hx + 1);
-    const int oslot = (NDIM == 3 ? (ty + 1) * SX : 0) + (tx + 1);
-
-    // Own column: planes z-1, z, z+1 in use and z+2 in flight; halo cell of
-    // plane z in use and of z+1 in flight. All loads are branch-free (a
-    // thread without a halo cell re-reads its own point), so the prefetches
-    // stay outstanding across the barrier.
-    const Dims dm{a.nx, a.ny, a.nz};
-    const int hgx = has_halo ? x0 + hx : x, hgy = has_halo ? y0 + hy : y;
-    // Raw loads at clamped (or wrapped) addresses; a Dirichlet ghost is zeroed
-    // only where the value is consumed, so nothing waits for a prefetch early.
-    auto LW = [&](int gx, int gy, int gz) {
-        bool g;
-        const long long i = bc_index_nb<BC>(dm, gx, gy, gz, g);
-        return IN_REAL ? make_double2(a.in_re[i], 0.0) : a.in_c[i];
-    };
-    auto LD = [&](int gx, int gy, int gz) {
-        bool g;
-        const long long i = bc_index_nb<BC>(dm, gx, gy, gz, g);
-        return (OP == VAR) ? a.D[i] : 0.0;   // ghost D is never used
-    };
-    const bool dirichlet = (BC == DIR);
-    const bool own_out = dirichlet && !(x < a.nx && y < a.ny);
-    const bool halo_out = dirichlet && !(hgx >= 0 && hgx < a.nx && hgy >= 0 && hgy < a.ny);
-    auto keep = [&](double2 v, bool ghost) {
-        v.x = ghost ? 0.0 : v.x;
-        v.y = ghost ? 0.0 : v.y;
-        return v;
-    };
-    auto zout = [&](int p) { return dirichlet && (p < 0 || p >= a.nz); };
-    // Plane p of the own column sits in ring slot (p - z0 + 1) & 3 and the
-    // halo cell of plane p in slot (p - z0) & 1. The z loop is unrolled by
-    // four, so every slot index is a compile-time constant: a new plane is
-    // loaded straight into the slot it will be used from, and no register
-    // copy has to wait for a load in flight.
-    double2 Wr[4] = {LW(x, y, z0 - 1), LW(x, y, z0), LW(x, y, z0 + 1), LW(x, y, z0 + 2)};
-    double Dr[4] = {LD(x, y, z0 - 1), LD(x, y, z0), LD(x, y, z0 + 1), LD(x, y, z0 + 2)};
-    double2 hWr[2] = {LW(hgx, hgy, z0), LW(hgx, hgy, z0 + 1)};
-    double hDr[2] = {LD(hgx, hgy, z0), LD(hgx, hgy, z0 + 1)};
-
-    for (int zb = z0; zb < z1; zb += 4) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int z = zb + u;
-        if (z >= z1) break;
-        const double2 Wm = keep(Wr[u & 3], own_out || zout(z - 1));
-        const double2 Wc = keep(Wr[(u + 1) & 3], own_out || zout(z));
-        const double2 Wp = keep(Wr[(u + 2) & 3], own_out || zout(z + 1));
-        const double Dm = Dr[u & 3], Dc = Dr[(u + 1) & 3], Dp = Dr[(u + 2) & 3];
-        const int b = z & 1;
-        sW[b][oslot] = Wc;
-        if (OP == VAR) sD[b][oslot] = Dc;
-        if (has_halo) {
-            sW[b][hslot] = keep(hWr[u & 1], halo_out || zout(z));
-            if (OP == VAR) sD[b][hslot] = hDr[u & 1];
-        }
-        __syncthreads();
-        hWr[u & 1] = LW(hgx, hgy, z + 2);
-        hDr[u & 1] = LD(hgx, hgy, z + 2);
-        if (active) {
-            const double2 c = Wc;
-            double qr_c = 0.0, qi_c = 0.0;
-            if (OP == POR) {
-                qr_c = c.x * c.x - c.y * c.y;
-                qi_c = 2.0 * (c.x * c.y);
-            }
-            double acc_r = 0.0, acc_i = 0.0;
-            const bool dir = (BC == DIR);
-            face<OP>(acc_r, acc_i, c, sW[b][oslot - 1], Dc, (OP == VAR) ? sD[b][oslot - 1] : 0.0,
-                     dir && x == 0, qr_c, qi_c, a.d_const);
-            face<OP>(acc_r, acc_i, c, sW[b][oslot + 1], Dc, (OP == VAR) ? sD[b][oslot + 1] : 0.0,
-                     dir && x == a.nx - 1, qr_c, qi_c, a.d_const);
-            if (NDIM == 3) {
-                face<OP>(acc_r, acc_i, c, sW[b][oslot - SX], Dc,
-                         (OP == VAR) ? sD[b][oslot - SX] : 0.0, dir && y == 0, qr_c, qi_c,
-                         a.d_const);
-                face<OP>(acc_r, acc_i, c, sW[b][oslot + SX], Dc,
-                         (OP == VAR) ? sD[b][oslot + SX] : 0.0, dir && y == a.ny - 1, qr_c, qi_c,
-                         a.d_const);
-            }
-            if (NDIM >= 2) {
-                face<OP>(acc_r, acc_i, c, Wm, Dc, Dm, dir && z == 0, qr_c, qi_c, a.d_const);
-                face<OP>(acc_r, acc_i, c, Wp, Dc, Dp, dir && z == a.nz - 1, qr_c, qi_c,
-                         a.d_const);
-            }
-            const double2 nv = euler(c, acc_r, acc_i, a.inv_h2, a.tr, a.ti);
-            const long long i = x + (long long)a.nx * (y + (long long)a.ny * z);
-            if (OUT_REAL) a.out_re[i] = nv.x;
-            else a.out_c[i] = nv;
-        }
-        Wr[u & 3] = LW(x, y, z + 3);   // the slot of plane z-1
-        Dr[u & 3] = LD(x, y, z + 3);
-    }
-    }
+    plane_tile<OP, BC, NDIM, BX, BY, IN_REAL, OUT_REAL>(a, bx, by, bz, sW, sD);
 }
 
 // Whole 1D grid resident in LDS: every stage of every superstep in one
