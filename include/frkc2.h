@@ -204,17 +204,61 @@ int frkc2_reduce(int op, const double *x, const double *y, size_t n, double *res
                  void *ws, size_t ws_bytes, hipStream_t st);
 
 /*
+ * frkc2_autotune -- pick the launch configuration of frkc2_step's passes for
+ * one grid by timing. The stages of a superstep are applied one after the
+ * other (Sec. 3, the Euler-step recursion), so any number k of consecutive
+ * stages can share one HBM pass; the best k, tile shape and z chunk length
+ * depend on the grid and the operator. Every candidate (k = 1 and each
+ * supported fused depth, tile shape, chunk length) runs `reps` whole
+ * supersteps of s stages at T = betabar / (2 rho) on the caller's data, timed
+ * with HIP events on st; the fastest is stored for grids of the same shape,
+ * operator and boundary and used by later frkc2_step calls while
+ * FRKC2_OPT_TBLOCK is 0 (automatic).
+ *   g, w, D, s, nu  as for frkc2_step; w and D are only read.
+ *   reps            timed supersteps per candidate, 1..100 (one more warms up)
+ *   ws, ws_bytes    frkc2_workspace_bytes(g, s, 0) bytes, 16-byte aligned
+ *   res             host; receives the chosen configuration and the average
+ *                   superstep time of it and of the built-in default
+ * Synchronises st. Results of frkc2_step are identical, bit for bit, for
+ * every configuration, so tuning changes only the time. Errors: FRKC2_EINVAL
+ * (arguments, checked before any HIP call), FRKC2_ENOMEM (workspace),
+ * FRKC2_EHIP.
+ */
+typedef struct {
+    int tblock;         /* stages per fused pass (1 = one stage per pass) */
+    int tile;           /* tile shape (see FRKC2_OPT_TILE) */
+    int zchunk;         /* z planes (2D: rows) per workgroup, 0 = automatic */
+    int candidates;     /* configurations timed */
+    double ms_best;     /* average superstep time of the chosen configuration */
+    double ms_default;  /* ... and of the built-in default */
+} frkc2_tune_result;
+int frkc2_autotune(const frkc2_grid *g, const double *w, const double *D, int s, double nu,
+                   int reps, void *ws, size_t ws_bytes, hipStream_t st, frkc2_tune_result *res);
+
+/*
  * frkc2_set_option -- tuning knobs (process-wide, not thread-safe to change
  * while other threads call the library):
  *   FRKC2_OPT_TBLOCK  stages fused per HBM pass of frkc2_step: 1, or 2 and 3
- *                     (3D), 2, 3, 4, 6 and 8 (2D); 0 = automatic
- *   FRKC2_OPT_TILE    3D tile shape of the fused passes: 0 = 64x16, 1 = 64x32 (k = 2)
+ *                     (3D), 2, 3, 4, 6 and 8 (2D); 0 = automatic (the entry
+ *                     frkc2_autotune stored for the grid, else 2 in 3D, 4 in
+ *                     2D, 1 in 1D)
+ *   FRKC2_OPT_TILE    tile shape of the fused passes: 3D 0 = 64x16 columns,
+ *                     1 = 64x32 (k = 2), 2 = 64x32 (k = 2) or 64x24 (k = 3)
+ *                     with 512 threads; 2D 0 = rows of 256, 1 = rows of 512
+ *   FRKC2_OPT_ZCHUNK  z planes (2D: rows) per workgroup of every pass of
+ *                     frkc2_step, 0 = automatic (halve from the whole depth
+ *                     until >= 512 workgroups for 3D fused passes, >= 2048
+ *                     otherwise)
  *   FRKC2_OPT_XCD_REMAP  reserved (1)
+ *   FRKC2_OPT_CLEAR_TUNED  forget every configuration frkc2_autotune stored
+ *                     (value ignored)
  * Results are identical, bit for bit, for every setting.
  */
 #define FRKC2_OPT_TBLOCK 1
 #define FRKC2_OPT_XCD_REMAP 2
 #define FRKC2_OPT_TILE 3
+#define FRKC2_OPT_CLEAR_TUNED 4
+#define FRKC2_OPT_ZCHUNK 5
 int frkc2_set_option(int key, int value);
 
 /* Thread-local description of the last error. */

@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -23,6 +24,7 @@ namespace {
 thread_local char g_err[512] = "";
 int g_tblock = 0;
 int g_tile = 0;
+int g_zchunk = 0;
 int g_xcd_remap = 1;
 
 constexpr size_t kAlign = 256;
@@ -161,24 +163,73 @@ int rho_bound_impl(const KGrid &kg, const double *w, const double *D, double *pa
     return FRKC2_OK;
 }
 
-// Stages fused per HBM pass: the option if set, else the measured best for
-// the grid's dimension (2D rows have little halo overhead, 3D tiles more).
-int pass_depth(const KGrid &kg)
+// Launch configuration of a superstep's passes: stages fused per pass, tile
+// shape and z planes per workgroup (0 = automatic).
+struct PassCfg {
+    int k, tile, zchunk;
+};
+
+// Configurations measured by frkc2_autotune, per grid shape and operator.
+struct TuneEntry {
+    int ndim, op, bc, nx, ny, nz;
+    PassCfg cfg;
+};
+std::vector<TuneEntry> g_tuned;
+std::mutex g_tune_mu;
+
+bool same_shape(const TuneEntry &e, const KGrid &kg)
 {
-    int k = g_tblock;
-    if (k == 0) k = (kg.ndim == 3) ? 2 : (kg.ndim == 2 ? 4 : 1);
-    if (k >= 2 && !tblock_supported(kg, k)) k = 1;
-    return k;
+    return e.ndim == kg.ndim && e.op == kg.op && e.bc == kg.bc && e.nx == kg.nx &&
+           e.ny == kg.ny && e.nz == kg.nz;
+}
+
+bool lookup_tuned(const KGrid &kg, PassCfg &c)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const TuneEntry &e : g_tuned)
+        if (same_shape(e, kg)) {
+            c = e.cfg;
+            return true;
+        }
+    return false;
+}
+
+void store_tuned(const KGrid &kg, const PassCfg &c)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (TuneEntry &e : g_tuned)
+        if (same_shape(e, kg)) {
+            e.cfg = c;
+            return;
+        }
+    g_tuned.push_back(TuneEntry{kg.ndim, kg.op, kg.bc, kg.nx, kg.ny, kg.nz, c});
+}
+
+// Measured best depth per dimension when nothing else is known (2D rows have
+// little halo overhead, 3D tiles more).
+int default_depth(const KGrid &kg) { return (kg.ndim == 3) ? 2 : (kg.ndim == 2 ? 4 : 1); }
+
+// The options if the depth is set, else the tuned entry for this grid, else
+// the default depth with the tile and chunk options.
+PassCfg pass_cfg(const KGrid &kg)
+{
+    PassCfg c{g_tblock, g_tile, g_zchunk};
+    if (c.k == 0) {
+        if (lookup_tuned(kg, c)) return c;
+        c.k = default_depth(kg);
+    }
+    if (c.k >= 2 && !tblock_supported(kg, c.k)) c.k = 1;
+    return c;
 }
 
 // One superstep of s stages from the real state w: passes of k fused stages,
 // the remainder as single stages. The first pass reads w, the last writes
 // Re W^L to w (or, with last_complex, the complex W^L to a buffer, returned).
-int run_superstep(const KGrid &kg, double *w, const double *D, double Tn, const double *are,
-                  const double *aim, int s, bool last_complex, double *const buf[2],
-                  const double **last_out, hipStream_t st)
+int run_superstep(const KGrid &kg, const PassCfg &cfg, double *w, const double *D, double Tn,
+                  const double *are, const double *aim, int s, bool last_complex,
+                  double *const buf[2], const double **last_out, hipStream_t st)
 {
-    const int k = pass_depth(kg);
+    const int k = cfg.k;
     int l = 0, pass = 0;
     const double *in = nullptr;
     while (l < s) {
@@ -192,6 +243,7 @@ int run_superstep(const KGrid &kg, double *w, const double *D, double Tn, const 
         }
         PassArgs pa{};
         pa.k = kk;
+        pa.zchunk = cfg.zchunk;
         pa.D = D;
         if (l == 0) pa.in_re = w;
         else pa.in_c = in;
@@ -203,7 +255,7 @@ int run_superstep(const KGrid &kg, double *w, const double *D, double Tn, const 
             pa.tr[i] = Tn * are[l + i];
             pa.ti[i] = Tn * aim[l + i];
         }
-        const int rc = (kk == 1) ? launch_pass(kg, pa, 1, st) : launch_tblock(kg, pa, g_tile, st);
+        const int rc = (kk == 1) ? launch_pass(kg, pa, 1, st) : launch_tblock(kg, pa, cfg.tile, st);
         if (rc != 0) return rc;
         in = out;
         l += kk;
@@ -255,6 +307,19 @@ extern "C" int frkc2_set_option(int key, int value)
             return FRKC2_EINVAL;
         }
         g_tile = value;
+        return FRKC2_OK;
+    }
+    if (key == FRKC2_OPT_ZCHUNK) {
+        if (value < 0 || value > (1 << 20)) {
+            set_error("z chunk length must lie in [0, 2^20]");
+            return FRKC2_EINVAL;
+        }
+        g_zchunk = value;
+        return FRKC2_OK;
+    }
+    if (key == FRKC2_OPT_CLEAR_TUNED) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned.clear();
         return FRKC2_OK;
     }
     if (key == FRKC2_OPT_XCD_REMAP) {
@@ -342,6 +407,7 @@ extern "C" int frkc2_step(const frkc2_grid *g, double *w, const double *D, doubl
     double *tau_dev = partials + 2 * (kReduceBlocks + 8);
 
     double rho = 0.0, Tn = T;
+    const PassCfg cfg = pass_cfg(kg);
     static thread_local std::vector<double> tau_host;
     for (int step = 0; step < nsteps; ++step) {
         if (step == 0 || kg.op == FRKC2_OP_POROUS2) {
@@ -374,7 +440,7 @@ extern "C" int frkc2_step(const frkc2_grid *g, double *w, const double *D, doubl
             continue;
         }
         const double *last_out = nullptr;
-        HIP_TRY(run_superstep(kg, w, D, Tn, are, aim, s, want_stats, buf, &last_out, st),
+        HIP_TRY(run_superstep(kg, cfg, w, D, Tn, are, aim, s, want_stats, buf, &last_out, st),
                 "stage launch");
         if (want_stats) {
             HIP_TRY(launch_finalize(kg, last_out, w, partials, st), "finalize launch");
@@ -393,6 +459,133 @@ extern "C" int frkc2_step(const frkc2_grid *g, double *w, const double *D, doubl
         if (nsteps == 0) stats->im_ratio = 0.0;
         HIP_TRY(hipStreamSynchronize(st), "step");
     }
+    return crc;
+}
+
+namespace {
+
+// Distinct launch configurations worth timing for a grid: every supported
+// depth, the tile shapes that differ for it, and a few chunk lengths.
+std::vector<PassCfg> tune_candidates(const KGrid &kg)
+{
+    std::vector<PassCfg> out;
+    std::vector<int> zcs{0};
+    for (int zc : {8, 16, 32, 64, 128})
+        if (zc < kg.nz) zcs.push_back(zc);
+    auto add = [&](int k, int tile) {
+        for (int zc : zcs) {
+            if (k >= 2 && zc != 0 && zc < 2 * k) continue;   // halo planes would dominate
+            out.push_back(PassCfg{k, tile, zc});
+        }
+    };
+    add(1, 0);
+    if (kg.ndim == 3) {
+        add(2, 0);
+        add(2, 1);
+        add(2, 2);
+        add(3, 0);
+        add(3, 2);
+    } else if (kg.ndim == 2) {
+        for (int k : {2, 3, 4, 6, 8}) {
+            add(k, 0);
+            add(k, 1);
+        }
+    }
+    return out;
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+}  // namespace
+
+extern "C" int frkc2_autotune(const frkc2_grid *g, const double *w, const double *D, int s,
+                              double nu, int reps, void *ws, size_t ws_bytes, hipStream_t st,
+                              frkc2_tune_result *res)
+{
+    KGrid kg;
+    if (!make_kgrid(g, kg)) return FRKC2_EINVAL;
+    if (!w || !res || (kg.op == FRKC2_OP_VARCOEF && !D)) {
+        set_error("w and result (and D for VARCOEF) must be non-NULL");
+        return FRKC2_EINVAL;
+    }
+    if (!check_s_nu(s, nu)) return FRKC2_EINVAL;
+    if (reps < 1 || reps > 100) {
+        set_error("reps must lie in [1, 100] (got %d)", reps);
+        return FRKC2_EINVAL;
+    }
+    const StepLayout L = step_layout(kg.npts());
+    if (!ws || ws_bytes < L.total || !aligned16(ws)) {
+        set_error("workspace needs %zu bytes (got %zu), 16-byte aligned", L.total, ws_bytes);
+        return FRKC2_ENOMEM;
+    }
+    const double *are, *aim;
+    frkc2_coeff_info info;
+    const int crc = coeffs_cached(s, nu, &are, &aim, &info);
+    if (crc < 0) return crc;
+    char *base = static_cast<char *>(ws);
+    double *buf[2] = {reinterpret_cast<double *>(base + L.bufA),
+                      reinterpret_cast<double *>(base + L.bufB)};
+    double *partials = reinterpret_cast<double *>(base + L.scratch);
+    double rho = 0.0;
+    int rc = rho_bound_impl(kg, w, D, partials, &rho, st);
+    if (rc < 0) return rc;
+    // a stable step, so that the timed values stay bounded
+    const double Tn = (rho > 0.0 && std::isfinite(rho)) ? 0.5 * info.beta_bar / rho : 0.0;
+
+    EventPair ev;
+    HIP_TRY(hipEventCreate(&ev.a), "autotune: event");
+    HIP_TRY(hipEventCreate(&ev.b), "autotune: event");
+    // Each candidate runs whole supersteps that end in the complex buffers,
+    // so the caller's w is only read.
+    auto time_cfg = [&](const PassCfg &c, double *ms) -> int {
+        HIP_TRY(run_superstep(kg, c, const_cast<double *>(w), D, Tn, are, aim, s, true, buf,
+                              nullptr, st),
+                "autotune: warm-up");
+        HIP_TRY(hipEventRecord(ev.a, st), "autotune: event");
+        for (int r = 0; r < reps; ++r)
+            HIP_TRY(run_superstep(kg, c, const_cast<double *>(w), D, Tn, are, aim, s, true, buf,
+                                  nullptr, st),
+                    "autotune: superstep");
+        HIP_TRY(hipEventRecord(ev.b, st), "autotune: event");
+        HIP_TRY(hipEventSynchronize(ev.b), "autotune: sync");
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, ev.a, ev.b), "autotune: elapsed");
+        *ms = (double)t / reps;
+        return FRKC2_OK;
+    };
+
+    PassCfg dflt{default_depth(kg), 0, 0};
+    if (dflt.k >= 2 && !tblock_supported(kg, dflt.k)) dflt.k = 1;
+    double ms_default = 0.0;
+    rc = time_cfg(dflt, &ms_default);
+    if (rc < 0) return rc;
+    PassCfg best = dflt;
+    double ms_best = ms_default;
+    int n = 1;
+    for (const PassCfg &c : tune_candidates(kg)) {
+        double ms = 0.0;
+        rc = time_cfg(c, &ms);
+        if (rc < 0) return rc;
+        ++n;
+        if (ms < ms_best) {
+            ms_best = ms;
+            best = c;
+        }
+    }
+    store_tuned(kg, best);
+    res->tblock = best.k;
+    res->tile = best.tile;
+    res->zchunk = best.zchunk;
+    res->candidates = n;
+    res->ms_best = ms_best;
+    res->ms_default = ms_default;
     return crc;
 }
 

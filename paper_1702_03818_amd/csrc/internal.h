@@ -40,6 +40,7 @@ struct PassArgs {
     double tr[kMaxTBlock];      // tau_l = T a_l of the pass's stages
     double ti[kMaxTBlock];
     int k;                      // stages in this pass
+    int zchunk;                 // z planes per workgroup (0: automatic)
 };
 
 // Launchers (stage.hip). Return hipError_t as int.

@@ -133,8 +133,11 @@ __device__ __forceinline__ void plane_tile(const PlaneArgs &a, int bx, int by, i
             if (OP == VAR) sD[b][hslot] = hDr[u & 1];
         }
         __syncthreads();
-        hWr[u & 1] = LW(hgx, hgy, z + 2);
-        hDr[u & 1] = LD(hgx, hgy, z + 2);
+        // planes past the chunk are never used: clamp so the tail re-reads a
+        // cached line instead of fetching new data
+        const int zh = min(z + 2, z1 - 1);
+        hWr[u & 1] = LW(hgx, hgy, zh);
+        hDr[u & 1] = LD(hgx, hgy, zh);
         if (active) {
             const double2 c = Wc;
             double qr_c = 0.0, qi_c = 0.0;
@@ -166,8 +169,9 @@ __device__ __forceinline__ void plane_tile(const PlaneArgs &a, int bx, int by, i
             if (OUT_REAL) a.out_re[i] = nv.x;
             else a.out_c[i] = nv;
         }
-        Wr[u & 3] = LW(x, y, z + 3);   // the slot of plane z-1
-        Dr[u & 3] = LD(x, y, z + 3);
+        const int zq = min(z + 3, z1);   // plane z1 is the last one used (z+ of z1-1)
+        Wr[u & 3] = LW(x, y, zq);        // into the slot of plane z-1
+        Dr[u & 3] = LD(x, y, zq);
     }
     }
 }

@@ -185,7 +185,8 @@ int launch_plane_t(const PlaneArgs &pa0, bool in_real, bool out_real, hipStream_
     PlaneArgs pa = pa0;
     pa.ntx = (pa.nx + BX - 1) / BX;
     pa.nty = (pa.ny + BY - 1) / BY;
-    pa.zchunk = choose_zchunk((long long)pa.ntx * pa.nty, pa.nz);
+    pa.zchunk = (pa0.zchunk > 0) ? min(pa0.zchunk, pa.nz)
+                                 : choose_zchunk((long long)pa.ntx * pa.nty, pa.nz);
     const long long nzc = (pa.nz + pa.zchunk - 1) / pa.zchunk;
     const long long nblk = (long long)pa.ntx * pa.nty * nzc;
     if (nblk > 0x7fffffffLL) return (int)hipErrorInvalidValue;
@@ -233,6 +234,7 @@ int launch_pass(const KGrid &g, const PassArgs &a, int /*tblock_hint*/, hipStrea
     pa.nz = g.nz;
     pa.inv_h2 = g.inv_h2;
     pa.d_const = g.d_const;
+    pa.zchunk = a.zchunk;
     pa.tr = a.tr[0];
     pa.ti = a.ti[0];
     const bool ir = a.in_re != nullptr, orl = a.out_re != nullptr;

@@ -148,8 +148,9 @@ __global__ __launch_bounds__(BXE *TY) void tb_stage(TbArgs a)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int gy = (NDIM == 3) ? yr[r] : 0;
-            L0[(u + 1) & 3][r] = LW(gy, t + 1);
-            D0[(u + 1) & 3][r] = LD(gy, t + 1);
+            const int tn = min(t + 1, t_end - 1);   // nothing past the last plane is used
+            L0[(u + 1) & 3][r] = LW(gy, tn);
+            D0[(u + 1) & 3][r] = LD(gy, tn);
         }
         // levels 1..K at planes t-1 .. t-K
 #pragma unroll
@@ -242,7 +243,8 @@ int launch_k(const TbArgs &a0, bool ir, bool orl, hipStream_t st)
     a.ntx = (a.nx + BXO - 1) / BXO;
     a.nty = (NDIM == 3) ? (a.ny + BYO - 1) / BYO : 1;
     const long long tiles = (long long)a.ntx * a.nty;
-    a.zchunk = choose_zchunk(tiles, a.nz, NDIM == 3 ? 512 : 2048);
+    a.zchunk = (a0.zchunk > 0) ? min(a0.zchunk, a.nz)
+                               : choose_zchunk(tiles, a.nz, NDIM == 3 ? 512 : 2048);
     const long long nblk = tiles * ((a.nz + a.zchunk - 1) / a.zchunk);
     if (nblk > 0x7fffffffLL) return (int)hipErrorInvalidValue;
     dim3 grid((unsigned)nblk), block(BXE * TY);
@@ -323,6 +325,7 @@ int launch_tblock(const KGrid &g, const PassArgs &p, int shape, hipStream_t st)
     a.nz = g.nz;
     a.inv_h2 = g.inv_h2;
     a.d_const = g.d_const;
+    a.zchunk = p.zchunk;
     for (int i = 0; i < kMaxTBlock; ++i) {
         a.tr[i] = p.tr[i];
         a.ti[i] = p.ti[i];

@@ -29,6 +29,8 @@ RED_SUMSQ, RED_SUM, RED_MAXSQ, RED_SUMSQDIFF, RED_DOT = 0, 1, 2, 3, 4
 OPT_TBLOCK = 1
 OPT_XCD_REMAP = 2
 OPT_TILE = 3
+OPT_CLEAR_TUNED = 4
+OPT_ZCHUNK = 5
 
 
 class Frkc2Error(RuntimeError):
@@ -52,6 +54,12 @@ class CoeffInfo(ctypes.Structure):
 class StepStats(ctypes.Structure):
     _fields_ = [("T_last", ctypes.c_double), ("rho_last", ctypes.c_double),
                 ("im_ratio", ctypes.c_double), ("supersteps", ctypes.c_int)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("tblock", ctypes.c_int), ("tile", ctypes.c_int), ("zchunk", ctypes.c_int),
+                ("candidates", ctypes.c_int), ("ms_best", ctypes.c_double),
+                ("ms_default", ctypes.c_double)]
 
 
 _lib = None
@@ -78,6 +86,9 @@ _SIGS = {
     "frkc2_batched_release": (ctypes.c_int, [_VP]),
     "frkc2_reduce": (ctypes.c_int, [ctypes.c_int, _VP, _VP, ctypes.c_size_t, _DP, _VP,
                                     ctypes.c_size_t, _VP]),
+    "frkc2_autotune": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_int, _VP, ctypes.c_size_t, _VP,
+                                      ctypes.POINTER(TuneResult)]),
     "frkc2_set_option": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     "frkc2_last_error": (ctypes.c_char_p, []),
     "frkc2_version": (ctypes.c_char_p, []),
@@ -209,6 +220,22 @@ def frkc2_step(grid, w, D=None, T=0.0, cfl=0.0, s=16, nu=0.01, nsteps=1, stream=
     if stats:
         return {f: getattr(st, f) for f, _ in StepStats._fields_}
     return rc
+
+
+def frkc2_autotune(grid, w, D=None, s=16, nu=0.01, reps=2, stream=None, ws=None):
+    """Time the pass configurations of frkc2_step on this grid and keep the fastest for it.
+    w and D are only read. Returns the result fields as a dict."""
+    lib = load()
+    g = make_grid(grid)
+    need = lib.frkc2_workspace_bytes(ctypes.byref(g), int(s), WS_STEP)
+    if need == 0:
+        _check(-1)
+    buf = ws if ws is not None else workspace(need)
+    r = TuneResult()
+    _check(lib.frkc2_autotune(ctypes.byref(g), _ptr(w), _ptr(D), int(s), float(nu), int(reps),
+                              ctypes.c_void_p(buf.data_ptr()), buf.numel(), _stream_ptr(stream),
+                              ctypes.byref(r)))
+    return {f: getattr(r, f) for f, _ in TuneResult._fields_}
 
 
 def frkc2_step_adjoint(grid, w_n, D, T, s, lam_next, lam_n, grad_logD=None, nu=0.01,

@@ -141,3 +141,28 @@ def test_grid_from_problem():
     p = wl.heat1d()
     g = F.make_grid(p)
     assert g.ndim == 1 and list(g.n) == [1024, 1, 1] and g.h == p.h
+
+
+def _tune(g, w=1, D=1, s=16, nu=0.01, reps=2, ws=1, ws_bytes=1 << 40, res=True):
+    lib = F.load()
+    p = lambda v: ctypes.c_void_p(4096 * 16) if v else None  # never dereferenced: validation fails first
+    r = F.TuneResult()
+    return lib.frkc2_autotune(ctypes.byref(g), p(w), p(D), s, nu, reps, p(ws), ws_bytes, None,
+                              ctypes.byref(r) if res else None)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(w=0), -1), (dict(D=0), -1), (dict(res=False), -1), (dict(s=5), -1), (dict(nu=-1.0), -1),
+    (dict(reps=0), -1), (dict(reps=101), -1), (dict(ws=0), -2), (dict(ws_bytes=64), -2),
+])
+def test_autotune_validation(kw, expect):
+    assert _tune(grid(), **kw) == expect
+    assert F.frkc2_last_error()
+
+
+def test_autotune_invalid_grid():
+    assert _tune(grid(ndim=5)) == -1
+
+
+def test_clear_tuned_option():
+    assert F.frkc2_set_option(F.OPT_CLEAR_TUNED, 0) == 0
