@@ -37,29 +37,160 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("stage.hip", "tblock.hip", "device_common.h", "api.cpp")
+# Sources that define the dominant kernel of each tile shape (k = 1: the plane kernel).
+KERNEL_SOURCES = {1: ("stage.hip", "plane_tile.h"), 2: ("tblock.hip",), 3: ("tblock.hip",),
+                  4: ("tb3d.hip",)}
+COMMON_SOURCES = ("device_common.h", "internal.h")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_stage3d_256.json")
 
 
-def kernel_sources_sha256():
+def kernel_sources_sha256(k, tile):
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in KERNEL_SOURCES[1 if k == 1 else tile] + COMMON_SOURCES:
         with open(os.path.join(ROOT, "paper_1702_03818_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(k, tile, zchunk):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic_stage3d_256.json")
-    if not os.path.exists(path):
+    summary, if it was taken on the current kernel sources and launch configuration."""
+    if not os.path.exists(TRAFFIC_JSON):
         return None, "no counter summary"
-    with open(path) as f:
+    with open(TRAFFIC_JSON) as f:
         t = json.load(f)
-    if t.get("sources_sha256") != kernel_sources_sha256():
+    if t.get("sources_sha256") != kernel_sources_sha256(k, tile):
         return None, "counters were taken on different kernel sources"
+    if t.get("config") != {"tblock": k, "tile": tile, "zchunk": zchunk}:
+        return None, "counters were taken in another launch configuration (%s)" % t.get("config")
     return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"], t.get("note", "")
+
+
+def kernel_pattern(k, tile):
+    """Name fragment rocprofv3 prints for the interior-pass kernel of the 3D workload."""
+    if k == 1:
+        return "plane_stage<1, 1, 3, 64, 4, false, false>"
+    if tile == 4:
+        return "tb3d_stage<1, 1, %d, false, false>" % k
+    shape = {1: "64, 16, 1", 2: "64, 16, 2", 3: "64, 8, %d" % (4 if k == 2 else 3)}[tile]
+    return "tb_stage<1, 1, 3, %s, %d, false, false>" % (shape, k)
+
+
+def _csv_rows(directory, suffix):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(directory, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit("no *%s under %s" % (suffix, directory))
+    rows = []
+    for fn in files:
+        with open(fn) as f:
+            rows.extend(csv.DictReader(f))
+    return rows
+
+
+def _short(name):
+    return name.replace("frkc2::(anonymous namespace)::", "")
+
+
+def summarize_trace(directory, command, k, tile, out_md):
+    """Per-(kernel, grid) durations from a rocprofv3 --kernel-trace run, as markdown."""
+    groups = {}
+    for r in _csv_rows(directory, "kernel_trace.csv"):
+        grid = int(r["Grid_Size"]) if "Grid_Size" in r else (
+            int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]))
+        key = (r["Kernel_Name"], grid)
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        groups.setdefault(key, []).append(d)
+    total = sum(sum(v) for v in groups.values())
+    pat = kernel_pattern(k, tile)
+    dom = max((key for key in groups if pat in key[0]), key=lambda kk: len(groups[kk]))
+    lines = ["# Kernel trace: 3D variable-D 256^3, s = 100 (bench step)", "",
+             "Command (from /tmp, with the repository as the working copy):", "",
+             "    " + command, "",
+             "Durations per (kernel, grid size in threads) from rocprofv3 `kernel_trace.csv`, "
+             "microseconds.", "",
+             "Dominant kernel (interior pass, k = %d, tile %d): `%s` at grid %d: %d launches, "
+             "average %.2f us." % (k, tile, _short(dom[0]), dom[1], len(groups[dom]),
+                                   sum(groups[dom]) / len(groups[dom])), "",
+             "| Kernel | grid | calls | total ms | average us | min us | max us | % |",
+             "|---|---|---|---|---|---|---|---|"]
+    for key, v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:25]:
+        lines.append("| `%s` | %d | %d | %.2f | %.2f | %.2f | %.2f | %.2f |" % (
+            _short(key[0]), key[1], len(v), sum(v) * 1e-3, sum(v) / len(v), min(v), max(v),
+            100 * sum(v) / total))
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return sum(groups[dom]) / len(groups[dom])
+
+
+def summarize_counters(fetch_dir, write_dir, fetch_cmd, write_cmd, k, tile, zchunk, out_md):
+    """HBM traffic of the dominant kernel from FETCH_SIZE / WRITE_SIZE runs, calibrated on the
+    bench's 1 GiB device copies (the six largest copy dispatches of each run)."""
+    per = {}
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        groups, copies = {}, []
+        for r in _csv_rows(d, "counter_collection.csv"):
+            if r["Counter_Name"] != name:
+                continue
+            v = float(r["Counter_Value"])
+            if "copyBuffer" in r["Kernel_Name"]:
+                copies.append(v)
+            groups.setdefault((r["Kernel_Name"], int(r["Grid_Size"])), []).append(v)
+        copies = sorted(copies)[-6:]
+        scale = (1 << 30) / (1024.0 * sum(copies) / len(copies))
+        per[name] = (groups, scale)
+    pat = kernel_pattern(k, tile)
+    fg, fs = per["FETCH_SIZE"]
+    wg, ws = per["WRITE_SIZE"]
+    dom = max((key for key in fg if pat in key[0]), key=lambda kk: len(fg[kk]))
+    fetch = 1024.0 * fs * sum(fg[dom]) / len(fg[dom])
+    write = 1024.0 * ws * sum(wg[dom]) / len(wg[dom])
+    n = 256 ** 3
+    alg = 40 * n
+    t = {"kernel": _short(dom[0]), "grid": dom[1],
+         "workload": "3D var-D 256^3, s = 100, k = %d (interior passes)" % k,
+         "config": {"tblock": k, "tile": tile, "zchunk": zchunk},
+         "sources_sha256": kernel_sources_sha256(k, tile),
+         "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+         "algorithmic_bytes_per_launch": alg, "fetch_scale": fs, "write_scale": ws,
+         "note": "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the ratio of the exact "
+                 "bytes of the bench's 1 GiB device copies to what the same counters read for "
+                 "them", "commands": [fetch_cmd, write_cmd]}
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(t, f, indent=1)
+    lines = ["# HBM traffic counters: 3D variable-D interior pass, 256^3, s = 100", "",
+             "Commands (from /tmp, with the repository as the working copy):", "",
+             "    " + fetch_cmd, "    " + write_cmd, "",
+             "Copy calibration: FETCH_SIZE scaled by %.4f, WRITE_SIZE by %.4f (exact bytes of "
+             "the bench's 1 GiB device copies over what the counters read for them)." % (fs, ws),
+             "",
+             "| Kernel | grid | dispatches | FETCH KiB/disp | WRITE KiB/disp | read MB | write MB |",
+             "|---|---|---|---|---|---|---|"]
+    for key in sorted(fg, key=lambda kk: -len(fg[kk]) * sum(fg[kk]))[:12]:
+        fv = sum(fg[key]) / len(fg[key])
+        wv = sum(wg.get(key, [0.0])) / max(1, len(wg.get(key, [])))
+        lines.append("| `%s` | %d | %d | %.1f | %.1f | %.1f | %.1f |" % (
+            _short(key[0]), key[1], len(fg[key]), fv, wv, fv * 1024 * fs / 1e6,
+            wv * 1024 * ws / 1e6))
+    lines += ["", "Dominant kernel `%s` (grid %d): %.1f MB read and %.1f MB written per launch; "
+              "algorithmic %.1f MB read (16 B complex W + 8 B D per point) and %.1f MB written "
+              "(16 B per point), so %.3f x the algorithmic bytes." % (
+                  _short(dom[0]), dom[1], fetch / 1e6, write / 1e6, 24 * n / 1e6, 16 * n / 1e6,
+                  (fetch + write) / alg)]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return t
+
+
+def kernel_name(k, tile):
+    """The dominant kernel of a superstep at fused depth k and tile shape (option numbering)."""
+    if k == 1:
+        return "plane_stage<VARCOEF, Dirichlet, 3D, 64x4>"
+    if tile == 4:
+        return "tb3d_stage<VARCOEF, Dirichlet, K=%d> (64-column output rows, halo wavefronts)" % k
+    return "tb_stage<VARCOEF, Dirichlet, 3D, shape %d, K=%d>" % (tile, k)
 
 
 def pass_schedule(s, k, supported=(2, 3)):
@@ -76,18 +207,26 @@ def pass_schedule(s, k, supported=(2, 3)):
     return out
 
 
-def cpu_baseline(prob, T, c_lib):
-    """Oracle superstep (s = 100) on the full 256^3 grid, timed on the host cores."""
+def cpu_baseline(prob, T, c_lib, min_seconds=10.0, max_supersteps=8):
+    """Oracle supersteps (s = 100) on the full 256^3 grid, timed on the host cores: repeated
+    until about min_seconds of CPU work (bounded by max_supersteps)."""
     from oracle import frkc2_coeffs as ocoeffs
     from oracle import stage as ostage
     c = ocoeffs(S_STAGES, NU)
+    w = prob.w0
+    n = 0
     t0 = time.perf_counter()
-    ostage.superstep(prob, prob.w0, T * c.a_re, T * c.a_im)
-    dt = time.perf_counter() - t0
-    ups = prob.npoints * S_STAGES / dt
+    while True:
+        w = ostage.superstep(prob, w, T * c.a_re, T * c.a_im)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds or n >= max_supersteps:
+            break
+    ups = prob.npoints * S_STAGES * n / dt
     return {"value": ups, "unit": "grid-point-stage updates/s", "cores": ostage.threads(),
             "kind": "oracle",
-            "sample": "one superstep (s=100) of the same 256^3 variable-D problem, %.1f s" % dt}
+            "sample": "%d consecutive supersteps (s=100) of the same 256^3 variable-D problem, "
+                      "%.1f s" % (n, dt)}
 
 
 def batched_leg(F, wl, torch, reps=3):
@@ -196,9 +335,32 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batched leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
-    ap.add_argument("--tblock", type=int, default=2, choices=(1, 2, 3),
-                    help="stages fused per HBM pass in the timed run")
+    ap.add_argument("--tblock", type=int, default=0, choices=(0, 1, 2, 3),
+                    help="stages fused per HBM pass in the timed run (0: autotune)")
+    ap.add_argument("--tile", type=int, default=0, help="tile shape with --tblock (0: automatic)")
+    ap.add_argument("--zchunk", type=int, default=0, help="z planes per workgroup with --tblock")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="write the kernel-trace summary under profiles/ from a rocprofv3 "
+                         "--kernel-trace run of this script (no GPU needed)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the HBM traffic summary under profiles/ from rocprofv3 --pmc "
+                         "FETCH_SIZE and WRITE_SIZE runs of this script (no GPU needed)")
+    ap.add_argument("--command", action="append", default=[],
+                    help="with --summarize-*: the command line(s) that produced the data")
     args = ap.parse_args()
+    if args.summarize_trace or args.summarize_counters:
+        k = args.tblock or 2
+        tile = args.tile or (4 if k >= 2 else 1)
+        if args.summarize_trace:
+            avg = summarize_trace(args.summarize_trace, args.command[0], k, tile,
+                                  os.path.join(ROOT, "profiles", "kernel_trace_stage3d_256.md"))
+            print("dominant kernel average %.2f us" % avg)
+        else:
+            t = summarize_counters(args.summarize_counters[0], args.summarize_counters[1],
+                                   args.command[0], args.command[1], k, tile, args.zchunk,
+                                   os.path.join(ROOT, "profiles", "counters_stage3d_256.md"))
+            print(json.dumps(t))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the FRKC2 superstep here is a single-GPU build "
               "(multi-GPU sharding is designed but not built).", file=sys.stderr)
@@ -211,7 +373,6 @@ def main():
     from paper_1702_03818_amd import workloads as wl
 
     torch.cuda.set_device(0)
-    F.frkc2_set_option(F.OPT_TBLOCK, args.tblock)
     log("generating the 3D workload (n=%d)" % args.n)
     prob = wl.diffusion3d(n=args.n)
     N = prob.npoints
@@ -222,6 +383,26 @@ def main():
     rho = F.frkc2_rho_bound(prob, None, D)
     T = CFL * info["beta_bar"] / rho
     log("rho=%.6e T=%.6e beta_bar=%.3f" % (rho, T, info["beta_bar"]))
+
+    # Launch configuration: measured by the library's autotuner on this grid
+    # (outside the timed region), or fixed from the command line.
+    if args.tblock == 0:
+        tune = F.frkc2_autotune(prob, w, D, s=S_STAGES, nu=NU, reps=2)
+        kdepth, tile, zchunk = tune["tblock"], tune["tile"], tune["zchunk"]
+        log("autotune: k=%d tile=%d zchunk=%d (%.3f ms per superstep; default %.3f ms; "
+            "%d candidates)" % (kdepth, tile, zchunk, tune["ms_best"], tune["ms_default"],
+                                tune["candidates"]))
+    else:
+        tune = None
+        kdepth, tile, zchunk = args.tblock, args.tile, args.zchunk
+        F.frkc2_set_option(F.OPT_TBLOCK, kdepth)
+        F.frkc2_set_option(F.OPT_TILE, tile)
+        F.frkc2_set_option(F.OPT_ZCHUNK, zchunk)
+        if tile == 0:
+            tile = 4 if kdepth >= 2 else 1
+
+    def restore_config():
+        F.frkc2_set_option(F.OPT_TBLOCK, 0 if tune is not None else kdepth)
 
     def step():
         st = F.frkc2_step(prob, w, D, T=T, s=S_STAGES, nsteps=SUPERSTEPS, stats=True)
@@ -273,7 +454,7 @@ def main():
     # complex for the Im diagnostic). The average launch time is the
     # event-timed region divided by the stage launches in it (every other
     # kernel in the region counts against it).
-    sched = pass_schedule(S_STAGES, args.tblock)
+    sched = pass_schedule(S_STAGES, kdepth)
     passes = len(sched) * SUPERSTEPS * args.steps
     per_superstep = []
     for last_complex in (False, True):
@@ -285,14 +466,14 @@ def main():
     alg_bytes = N * args.steps * ((SUPERSTEPS - 1) * per_superstep[0] + per_superstep[1])
     avg_launch_ms = gpu_ms / passes
     achieved = alg_bytes / (gpu_ms * 1e-3) / 1e9
-    traffic, traffic_note = measured_traffic()
+    traffic, traffic_note = measured_traffic(kdepth, tile, zchunk)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "traffic_note": traffic_note,
-            "kernel": ("tb_stage<VARCOEF, Dirichlet, 3D, K=%d>" % args.tblock if args.tblock >= 2
-                       else "plane_stage<VARCOEF, Dirichlet, 3D>"),
-            "stages_per_pass": args.tblock, "bytes_per_point_per_pass": 40,
+            "kernel": kernel_name(kdepth, tile),
+            "stages_per_pass": kdepth, "tile": tile, "zchunk": zchunk,
+            "autotuned": tune is not None, "bytes_per_point_per_pass": 40,
             "algorithmic_bytes_per_launch": 40 * N, "avg_launch_ms": avg_launch_ms}
     # one-stage-per-pass reference on the same state (diagnostic)
     F.frkc2_set_option(F.OPT_TBLOCK, 1)
@@ -303,7 +484,7 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     k1_ms = e0.elapsed_time(e1) / 3
-    F.frkc2_set_option(F.OPT_TBLOCK, args.tblock)
+    restore_config()
     k1_ach = N * (32 + (S_STAGES - 2) * 40 + 32) / (k1_ms * 1e-3) / 1e9
     k1_ref = {"ms_per_superstep": k1_ms, "value": N * S_STAGES / (k1_ms * 1e-3),
               "achieved_gbs": k1_ach, "frac": k1_ach / HBM_PEAK_GBS}

@@ -211,7 +211,8 @@ int frkc2_reduce(int op, const double *x, const double *y, size_t n, double *res
  * depend on the grid and the operator. Every candidate (k = 1 and each
  * supported fused depth, tile shape, chunk length) runs `reps` whole
  * supersteps of s stages at T = betabar / (2 rho) on the caller's data, timed
- * with HIP events on st; the fastest is stored for grids of the same shape,
+ * with HIP events on st; the fastest (the built-in default unless a candidate
+ * beats it by more than 3 %) is stored for grids of the same shape,
  * operator and boundary and used by later frkc2_step calls while
  * FRKC2_OPT_TBLOCK is 0 (automatic).
  *   g, w, D, s, nu  as for frkc2_step; w and D are only read.
@@ -226,7 +227,7 @@ int frkc2_reduce(int op, const double *x, const double *y, size_t n, double *res
  */
 typedef struct {
     int tblock;         /* stages per fused pass (1 = one stage per pass) */
-    int tile;           /* tile shape (see FRKC2_OPT_TILE) */
+    int tile;           /* tile shape, as FRKC2_OPT_TILE numbers it (>= 1) */
     int zchunk;         /* z planes (2D: rows) per workgroup, 0 = automatic */
     int candidates;     /* configurations timed */
     double ms_best;     /* average superstep time of the chosen configuration */
@@ -242,9 +243,12 @@ int frkc2_autotune(const frkc2_grid *g, const double *w, const double *D, int s,
  *                     (3D), 2, 3, 4, 6 and 8 (2D); 0 = automatic (the entry
  *                     frkc2_autotune stored for the grid, else 2 in 3D, 4 in
  *                     2D, 1 in 1D)
- *   FRKC2_OPT_TILE    tile shape of the fused passes: 3D 0 = 64x16 columns,
- *                     1 = 64x32 (k = 2), 2 = 64x32 (k = 2) or 64x24 (k = 3)
- *                     with 512 threads; 2D 0 = rows of 256, 1 = rows of 512
+ *   FRKC2_OPT_TILE    tile shape of the fused passes: 0 = automatic (3D 4,
+ *                     2D 1); 3D 1 = 64x16 extended columns, 2 = 64x32 (k = 2),
+ *                     3 = 64x32 (k = 2) or 64x24 (k = 3) with 512 threads,
+ *                     4 = 64-column output rows with halo wavefronts (64x11
+ *                     outputs for k = 2, 64x8 for k = 3); 2D 1 = rows of 256,
+ *                     2 = rows of 512
  *   FRKC2_OPT_ZCHUNK  z planes (2D: rows) per workgroup of every pass of
  *                     frkc2_step, 0 = automatic (halve from the whole depth
  *                     until >= 512 workgroups for 3D fused passes, >= 2048

@@ -56,6 +56,8 @@ int launch_zero(long long n, double *p, hipStream_t st);   // fill kernel (graph
 // Temporally blocked passes (tblock.hip): p.k stages in one HBM pass.
 bool tblock_supported(const KGrid &g, int k);
 int launch_tblock(const KGrid &g, const PassArgs &p, int shape, hipStream_t st);
+// 3D passes with 64-column output tiles and halo wavefronts (tb3d.hip), k = 2, 3.
+int launch_tb3d(const KGrid &g, const PassArgs &p, hipStream_t st);
 
 // Reductions (reduce.hip). partials must hold kReduceBlocks doubles + 2.
 constexpr int kReduceBlocks = 512;

@@ -116,14 +116,20 @@ __device__ __forceinline__ void plane_tile(const PlaneArgs &a, int bx, int by, i
     double2 hWr[2] = {LW(hgx, hgy, z0), LW(hgx, hgy, z0 + 1)};
     double hDr[2] = {LD(hgx, hgy, z0), LD(hgx, hgy, z0 + 1)};
 
+    // Planes z0-1 and z0 are consumed first; every later plane gets its
+    // Dirichlet ghosts zeroed in its ring slot when it is first used (as the
+    // z+ neighbour).
+    Wr[0] = keep(Wr[0], own_out || zout(z0 - 1));
+    Wr[1] = keep(Wr[1], own_out || zout(z0));
     for (int zb = z0; zb < z1; zb += 4) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int z = zb + u;
         if (z >= z1) break;
-        const double2 Wm = keep(Wr[u & 3], own_out || zout(z - 1));
-        const double2 Wc = keep(Wr[(u + 1) & 3], own_out || zout(z));
-        const double2 Wp = keep(Wr[(u + 2) & 3], own_out || zout(z + 1));
+        Wr[(u + 2) & 3] = keep(Wr[(u + 2) & 3], own_out || zout(z + 1));
+        const double2 Wm = Wr[u & 3];
+        const double2 Wc = Wr[(u + 1) & 3];
+        const double2 Wp = Wr[(u + 2) & 3];
         const double Dm = Dr[u & 3], Dc = Dr[(u + 1) & 3], Dp = Dr[(u + 2) & 3];
         const int b = z & 1;
         sW[b][oslot] = Wc;
@@ -146,23 +152,22 @@ __device__ __forceinline__ void plane_tile(const PlaneArgs &a, int bx, int by, i
                 qi_c = 2.0 * (c.x * c.y);
             }
             double acc_r = 0.0, acc_i = 0.0;
-            const bool dir = (BC == DIR);
+            // A Dirichlet ghost holds W = 0 and the D of the boundary cell it
+            // faces (loads are clamped), so every face takes the plain mean,
+            // which there equals D_c bit for bit.
             face<OP>(acc_r, acc_i, c, sW[b][oslot - 1], Dc, (OP == VAR) ? sD[b][oslot - 1] : 0.0,
-                     dir && x == 0, qr_c, qi_c, a.d_const);
+                     false, qr_c, qi_c, a.d_const);
             face<OP>(acc_r, acc_i, c, sW[b][oslot + 1], Dc, (OP == VAR) ? sD[b][oslot + 1] : 0.0,
-                     dir && x == a.nx - 1, qr_c, qi_c, a.d_const);
+                     false, qr_c, qi_c, a.d_const);
             if (NDIM == 3) {
                 face<OP>(acc_r, acc_i, c, sW[b][oslot - SX], Dc,
-                         (OP == VAR) ? sD[b][oslot - SX] : 0.0, dir && y == 0, qr_c, qi_c,
-                         a.d_const);
+                         (OP == VAR) ? sD[b][oslot - SX] : 0.0, false, qr_c, qi_c, a.d_const);
                 face<OP>(acc_r, acc_i, c, sW[b][oslot + SX], Dc,
-                         (OP == VAR) ? sD[b][oslot + SX] : 0.0, dir && y == a.ny - 1, qr_c, qi_c,
-                         a.d_const);
+                         (OP == VAR) ? sD[b][oslot + SX] : 0.0, false, qr_c, qi_c, a.d_const);
             }
             if (NDIM >= 2) {
-                face<OP>(acc_r, acc_i, c, Wm, Dc, Dm, dir && z == 0, qr_c, qi_c, a.d_const);
-                face<OP>(acc_r, acc_i, c, Wp, Dc, Dp, dir && z == a.nz - 1, qr_c, qi_c,
-                         a.d_const);
+                face<OP>(acc_r, acc_i, c, Wm, Dc, Dm, false, qr_c, qi_c, a.d_const);
+                face<OP>(acc_r, acc_i, c, Wp, Dc, Dp, false, qr_c, qi_c, a.d_const);
             }
             const double2 nv = euler(c, acc_r, acc_i, a.inv_h2, a.tr, a.ti);
             const long long i = x + (long long)a.nx * (y + (long long)a.ny * z);

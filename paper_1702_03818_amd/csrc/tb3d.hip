@@ -1,0 +1,302 @@
+// Temporally blocked 3D stages with full-width output tiles: K consecutive
+// Euler stages W <- W + tau_l f(W) (O'Sullivan, arXiv:1702.03818, Sec. 3,
+// Euler-step equation) in one HBM pass.
+//
+// Same pipeline as tb_stage (tblock.hip): a workgroup marches through a chunk
+// of z planes and at time step t computes level m (the state after m stages
+// of the pass) at plane t - m from level m-1, whose x/y neighbours sit in LDS
+// and whose z neighbours the thread keeps in registers. What differs is the
+// tile geometry and the synchronisation:
+//
+//  * The output tile is 64 columns wide, one wavefront per row, so it lines
+//    up with 512-byte segments of the grid and a 256-wide grid needs exactly
+//    4 tiles across. The K halo columns on each side of every row are
+//    computed by one or two extra "halo" wavefronts whose lanes each own one
+//    (row, halo column) pair. Every lane skips the levels its column is not
+//    needed for (level m is used within K - m cells of the output), so the
+//    rows near the tile edge and the halo lanes do only the work that is
+//    consumed.
+//  * The LDS planes are double-buffered by time-step parity, so one barrier
+//    per time step separates the writes of step t from the reads of step
+//    t + 1. The diffusivity ring holds K + 2 planes for the same reason.
+//  * The thread's own diffusivity of planes t-2 .. t comes from its register
+//    ring; only x/y neighbours (and older planes) are read from LDS.
+//
+// Every value is computed with the same per-point arithmetic, in the same
+// order, as the one-stage kernel (faces x-, x+, y-, y+, z-, z+; no fused
+// multiply-adds), so the results are identical to the last bit.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace frkc2 {
+namespace {
+
+using namespace dev;
+
+struct Tb3Args {
+    const double *in_re;
+    const double2 *in_c;
+    double *out_re;
+    double2 *out_c;
+    const double *D;
+    int nx, ny, nz;
+    int zchunk, ntx, nty;
+    double inv_h2, d_const;
+    double tr[kMaxTBlock], ti[kMaxTBlock];
+};
+
+// Rows of the extended tile (one wavefront each) and halo wavefronts for
+// 1024 threads: 2K halo columns per row must fit in the halo wavefronts.
+template <int K>
+struct Tb3Shape {
+    static constexpr int NHW = (K == 2) ? 1 : 2;
+    static constexpr int BYE = 16 - NHW;
+    static constexpr int BXE = 64 + 2 * K;
+    static constexpr int BYO = BYE - 2 * K;
+    static_assert(2 * K * BYE <= 64 * NHW, "halo columns must fit the halo wavefronts");
+};
+
+__device__ __forceinline__ double2 keep3(double2 v, bool ghost)
+{
+    v.x = ghost ? 0.0 : v.x;
+    v.y = ghost ? 0.0 : v.y;
+    return v;
+}
+
+template <int OP, int BC, int K, bool IN_REAL, bool OUT_REAL>
+__global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
+{
+    using S = Tb3Shape<K>;
+    constexpr int BXE = S::BXE, BYE = S::BYE, BYO = S::BYO;
+    constexpr int SX = BXE + 2, SY = BYE + 2;      // one padding cell around each plane
+    constexpr int PL = SX * SY;
+    constexpr bool VC = (OP == VAR);
+    constexpr int ND = K + 2;                       // D ring: planes t-K-1 .. t
+    __shared__ double2 sL[2][K][PL];                // level m plane, by step parity
+    __shared__ double sD[VC ? ND : 1][VC ? PL : 1];
+
+    const Dims dm{a.nx, a.ny, a.nz};
+    const int tid = threadIdx.x;
+    const int wv = tid >> 6, lane = tid & 63;
+    int lx, ly;                                     // position in the extended tile
+    if (wv < BYE) {
+        lx = K + lane;
+        ly = wv;
+    } else {
+        // halo lane: depth d = 1..K from the output columns, side, row;
+        // spare lanes repeat depth-K lanes (same values, never used)
+        int j = (wv - BYE) * 64 + lane;
+        if (j >= 2 * K * BYE) j = 2 * (K - 1) * BYE + (j % (2 * BYE));
+        const int d = 1 + j / (2 * BYE);
+        const int rem = j % (2 * BYE);
+        ly = rem % BYE;
+        lx = (rem < BYE) ? K - d : K + 63 + d;
+    }
+    // level m is needed where the tile edge is at least m cells away
+    const int need = min(min(lx, BXE - 1 - lx), min(ly, BYE - 1 - ly));
+
+    int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = lb % a.ntx;
+    lb /= a.ntx;
+    const int by = lb % a.nty;
+    const int bz = lb / a.nty;
+    const int x = bx * 64 - K + lx;
+    const int y = by * BYO - K + ly;
+    const int z0 = bz * a.zchunk;
+    const int z1 = min(z0 + a.zchunk, a.nz);
+    const bool dir = (BC == DIR);
+    const bool col_ghost = dir && !(x >= 0 && x < a.nx && y >= 0 && y < a.ny);
+    const bool out_col = lx >= K && lx < K + 64 && ly >= K && ly < BYE - K && x < a.nx &&
+                         y < a.ny;
+    const int slot = (ly + 1) * SX + lx + 1;
+
+    auto LW = [&](int gz) {
+        bool g;
+        const long long i = bc_index_nb<BC>(dm, x, y, gz, g);
+        return IN_REAL ? make_double2(a.in_re[i], 0.0) : a.in_c[i];
+    };
+    auto LD = [&](int gz) {
+        bool g;
+        const long long i = bc_index_nb<BC>(dm, x, y, gz, g);
+        return VC ? a.D[i] : 0.0;
+    };
+    auto pout = [&](int p) { return dir && (p < 0 || p >= a.nz); };
+    auto dslot = [](int p) { return ((p % ND) + ND) % ND; };
+
+    // Level 0 ring: plane p in slot (p - t_begin) % NR with its D; at step t
+    // planes t-2 .. t are in use and t+1, t+2 in flight. Windows of levels
+    // 1..K-1: planes (q-1, q, q+1) around the plane the next level computes.
+    constexpr int PF = 2;
+    constexpr int NR = PF + 3;
+    const int t_begin = z0 - K, t_end = z1 + K;     // level 0 planes z0-K .. z1+K-1
+    double2 L0[NR];
+    double D0[NR];
+    double2 wm[K - 1], wc[K - 1], wp[K - 1];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        L0[q] = make_double2(0.0, 0.0);
+        D0[q] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        const int tq = min(t_begin + q, t_end - 1);
+        L0[q] = LW(tq);
+        D0[q] = LD(tq);
+    }
+#pragma unroll
+    for (int m = 0; m + 1 < K; ++m) wm[m] = wc[m] = wp[m] = make_double2(0.0, 0.0);
+
+    for (int tb = t_begin; tb < t_end; tb += NR) {
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+        const int t = tb + u;
+        if (t >= t_end) break;
+        auto rs = [u](int d) { return (u + d + 2 * NR) % NR; };   // slot of plane t + d
+        {
+            const int tn = min(t + PF, t_end - 1);  // nothing past the last plane is used
+            L0[rs(PF)] = LW(tn);
+            D0[rs(PF)] = LD(tn);
+        }
+        L0[rs(0)] = keep3(L0[rs(0)], col_ghost || pout(t));
+        const int rb = (t - 1) & 1, wb = t & 1;     // LDS buffers read / written at step t
+#pragma unroll
+        for (int m = 1; m <= K; ++m) {
+            if (need < m) continue;
+            const int p = t - m;
+            const double2 *L = sL[rb][m - 1];
+            const double *Dp = VC ? sD[dslot(p)] : nullptr;
+            double2 c, zm, zp;
+            double dc = 0.0, dzm = 0.0, dzp = 0.0;
+            if (m == 1) {
+                zm = L0[rs(-2)];
+                c = L0[rs(-1)];
+                zp = L0[rs(0)];
+                if (VC) {
+                    dzm = D0[rs(-2)];
+                    dc = D0[rs(-1)];
+                    dzp = D0[rs(0)];
+                }
+            } else {
+                zm = wm[m - 2];
+                c = wc[m - 2];
+                zp = wp[m - 2];
+                if (VC) {
+                    dc = (m == 2) ? D0[rs(-2)] : Dp[slot];
+                    dzm = sD[dslot(p - 1)][slot];
+                    dzp = (m == 2) ? D0[rs(-1)] : (m == 3 ? D0[rs(-2)] : sD[dslot(p + 1)][slot]);
+                }
+            }
+            double qr_c = 0.0, qi_c = 0.0;
+            if (OP == POR) {
+                qr_c = c.x * c.x - c.y * c.y;
+                qi_c = 2.0 * (c.x * c.y);
+            }
+            // A Dirichlet ghost holds W = 0 and the D of the boundary cell it
+            // faces (loads are clamped), so every face takes the plain mean,
+            // which there equals D_c bit for bit.
+            double acc_r = 0.0, acc_i = 0.0;
+            face<OP>(acc_r, acc_i, c, L[slot - 1], dc, VC ? Dp[slot - 1] : 0.0, false, qr_c, qi_c,
+                     a.d_const);
+            face<OP>(acc_r, acc_i, c, L[slot + 1], dc, VC ? Dp[slot + 1] : 0.0, false, qr_c, qi_c,
+                     a.d_const);
+            face<OP>(acc_r, acc_i, c, L[slot - SX], dc, VC ? Dp[slot - SX] : 0.0, false, qr_c,
+                     qi_c, a.d_const);
+            face<OP>(acc_r, acc_i, c, L[slot + SX], dc, VC ? Dp[slot + SX] : 0.0, false, qr_c,
+                     qi_c, a.d_const);
+            face<OP>(acc_r, acc_i, c, zm, dc, dzm, false, qr_c, qi_c, a.d_const);
+            face<OP>(acc_r, acc_i, c, zp, dc, dzp, false, qr_c, qi_c, a.d_const);
+            double2 v = euler(c, acc_r, acc_i, a.inv_h2, a.tr[m - 1], a.ti[m - 1]);
+            v = keep3(v, col_ghost || pout(p));
+            if (m < K) {
+                wm[m - 1] = wc[m - 1];
+                wc[m - 1] = wp[m - 1];
+                wp[m - 1] = v;
+                sL[wb][m][slot] = v;
+            } else if (out_col && p >= z0 && p < z1) {
+                const long long i = x + (long long)a.nx * (y + (long long)a.ny * p);
+                if (OUT_REAL) a.out_re[i] = v.x;
+                else a.out_c[i] = v;
+            }
+        }
+        sL[wb][0][slot] = L0[rs(0)];
+        if (VC) sD[dslot(t)][slot] = D0[rs(0)];
+        __syncthreads();   // step t's planes are visible to step t+1, whose
+                           // writes go to the other buffer
+    }
+    }
+}
+
+int choose_zchunk3(long long tiles, int nz)
+{
+    // whole rounds of 256 workgroups, preferring long chunks
+    int zc = nz;
+    while (zc > 16 && tiles * ((nz + zc - 1) / zc) < 512) zc = (zc + 1) / 2;
+    return zc;
+}
+
+template <int OP, int BC, int K>
+int launch3_k(const Tb3Args &a0, bool ir, bool orl, hipStream_t st)
+{
+    Tb3Args a = a0;
+    a.ntx = (a.nx + 63) / 64;
+    a.nty = (a.ny + Tb3Shape<K>::BYO - 1) / Tb3Shape<K>::BYO;
+    const long long tiles = (long long)a.ntx * a.nty;
+    a.zchunk = (a0.zchunk > 0) ? min(a0.zchunk, a.nz) : choose_zchunk3(tiles, a.nz);
+    const long long nblk = tiles * ((a.nz + a.zchunk - 1) / a.zchunk);
+    if (nblk > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+    dim3 grid((unsigned)nblk), block(1024);
+    if (ir && orl)
+        hipLaunchKernelGGL((tb3d_stage<OP, BC, K, true, true>), grid, block, 0, st, a);
+    else if (ir)
+        hipLaunchKernelGGL((tb3d_stage<OP, BC, K, true, false>), grid, block, 0, st, a);
+    else if (orl)
+        hipLaunchKernelGGL((tb3d_stage<OP, BC, K, false, true>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((tb3d_stage<OP, BC, K, false, false>), grid, block, 0, st, a);
+    return (int)hipGetLastError();
+}
+
+template <int OP, int BC>
+int launch3_kk(int k, const Tb3Args &a, bool ir, bool orl, hipStream_t st)
+{
+    if (k == 2) return launch3_k<OP, BC, 2>(a, ir, orl, st);
+    if (k == 3) return launch3_k<OP, BC, 3>(a, ir, orl, st);
+    return (int)hipErrorInvalidValue;
+}
+
+template <int OP>
+int launch3_bc(const KGrid &g, int k, const Tb3Args &a, bool ir, bool orl, hipStream_t st)
+{
+    if (g.bc == PER) return launch3_kk<OP, PER>(k, a, ir, orl, st);
+    return launch3_kk<OP, DIR>(k, a, ir, orl, st);
+}
+
+}  // namespace
+
+int launch_tb3d(const KGrid &g, const PassArgs &p, hipStream_t st)
+{
+    if (g.ndim != 3 || (p.k != 2 && p.k != 3)) return (int)hipErrorInvalidValue;
+    Tb3Args a{};
+    a.in_re = p.in_re;
+    a.in_c = reinterpret_cast<const double2 *>(p.in_c);
+    a.out_re = p.out_re;
+    a.out_c = reinterpret_cast<double2 *>(p.out_c);
+    a.D = p.D;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.nz = g.nz;
+    a.inv_h2 = g.inv_h2;
+    a.d_const = g.d_const;
+    a.zchunk = p.zchunk;
+    for (int i = 0; i < kMaxTBlock; ++i) {
+        a.tr[i] = p.tr[i];
+        a.ti[i] = p.ti[i];
+    }
+    const bool ir = p.in_re != nullptr, orl = p.out_re != nullptr;
+    if (g.op == LAP) return launch3_bc<LAP>(g, p.k, a, ir, orl, st);
+    if (g.op == VAR) return launch3_bc<VAR>(g, p.k, a, ir, orl, st);
+    return launch3_bc<POR>(g, p.k, a, ir, orl, st);
+}
+
+}  // namespace frkc2

@@ -15,11 +15,11 @@
 // the previous time step). The diffusivity planes t-K-1 .. t-1 live in an LDS
 // ring. Two barriers per time step separate the LDS reads from the writes.
 //
-// Level 0 is prefetched one time step ahead into a four-slot register ring;
-// the time loop is unrolled by four so the slot indices are compile-time
+// Level 0 is prefetched two time steps ahead into a five-slot register ring;
+// the time loop is unrolled by five so the slot indices are compile-time
 // constants and a load in flight is never copied (a copy would have to wait
-// for it). Dirichlet ghosts are zeroed where a value is used, not where it is
-// loaded, for the same reason.
+// for it). Dirichlet ghosts are zeroed when a plane is first used, not where
+// it is loaded, for the same reason.
 //
 // Only level K inside the inner (BXE-2K) x (BYE-2K) region is written back;
 // the ring of halo columns is recomputed by the neighbouring tile (their
@@ -65,6 +65,7 @@ template <int OP, int BC, int NDIM, int BXE, int TY, int R, int K, bool IN_REAL,
 __global__ __launch_bounds__(BXE *TY) void tb_stage(TbArgs a)
 {
     constexpr int BYE = TY * R;
+    constexpr bool SKIP_ROWS = (BXE == 64);         // one extended row per wavefront
     constexpr int SX = BXE + 2;
     constexpr int SY = (NDIM == 3) ? BYE + 2 : 1;
     constexpr int PL = SX * SY;                     // padded plane
@@ -118,40 +119,53 @@ __global__ __launch_bounds__(BXE *TY) void tb_stage(TbArgs a)
     auto pout = [&](int p) { return dir && (p < 0 || p >= a.nz); };
     auto dslot = [](int p) { return ((p % ND) + ND) % ND; };
 
-    // level 0 ring: plane p in slot (p - t_begin) & 3; D of plane p alongside
-    // register windows of levels 1..K-1: planes (q-1, q, q+1) around the plane
-    // that the next level computes
+    // Level 0 ring: plane p in slot (p - t_begin) % NR, its D alongside. At
+    // time step t planes t-2, t-1, t are in use and t+1 .. t+PF in flight.
+    // Register windows of levels 1..K-1: planes (q-1, q, q+1) around the
+    // plane that the next level computes.
+    constexpr int PF = 2;
+    constexpr int NR = PF + 3;
     const int t_begin = z0 - K, t_end = z1 + K;     // level 0 planes z0-K .. z1+K-1
-    double2 L0[4][R];
-    double D0[4][R];
+    double2 L0[NR][R];
+    double D0[NR][R];
     double2 wm[K > 1 ? K - 1 : 1][R], wc[K > 1 ? K - 1 : 1][R], wp[K > 1 ? K - 1 : 1][R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int gy = (NDIM == 3) ? yr[r] : 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NR; ++q) {
             L0[q][r] = make_double2(0.0, 0.0);
             D0[q][r] = 0.0;
         }
-        L0[0][r] = LW(gy, t_begin);
-        D0[0][r] = LD(gy, t_begin);
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int tq = min(t_begin + q, t_end - 1);
+            L0[q][r] = LW(gy, tq);
+            D0[q][r] = LD(gy, tq);
+        }
 #pragma unroll
         for (int m = 0; m + 1 < K; ++m) wm[m][r] = wc[m][r] = wp[m][r] = make_double2(0.0, 0.0);
     }
 
-    for (int tb = t_begin; tb < t_end; tb += 4) {
+    for (int tb = t_begin; tb < t_end; tb += NR) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < NR; ++u) {
         const int t = tb + u;
         if (t >= t_end) break;
-        // prefetch plane t+1 into the slot of plane t-3
+        // slot of plane t + d
+        auto rs = [u](int d) { return (u + d + 2 * NR) % NR; };
+        // prefetch plane t+PF into the slot of plane t-3
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int gy = (NDIM == 3) ? yr[r] : 0;
-            const int tn = min(t + 1, t_end - 1);   // nothing past the last plane is used
-            L0[(u + 1) & 3][r] = LW(gy, tn);
-            D0[(u + 1) & 3][r] = LD(gy, tn);
+            const int tn = min(t + PF, t_end - 1);  // nothing past the last plane is used
+            L0[rs(PF)][r] = LW(gy, tn);
+            D0[rs(PF)][r] = LD(gy, tn);
         }
+        // plane t of level 0 is consumed from here on: zero its Dirichlet
+        // ghosts once, in its ring slot
+#pragma unroll
+        for (int r = 0; r < R; ++r) L0[rs(0)][r] = keep(L0[rs(0)][r], col_ghost[r] || pout(t));
         // levels 1..K at planes t-1 .. t-K
 #pragma unroll
         for (int m = 1; m <= K; ++m) {
@@ -163,13 +177,20 @@ __global__ __launch_bounds__(BXE *TY) void tb_stage(TbArgs a)
             const bool pghost = pout(p);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
+                // Level m is only used within m cells of the output rows; in
+                // 3D a row of 64 columns is one wavefront, so rows outside
+                // that band skip the level as a whole.
+                if (NDIM == 3 && SKIP_ROWS) {
+                    const int ly = ty + r * TY;
+                    if (ly < m || ly >= BYE - m) continue;
+                }
                 const int sl = slot[r];
                 double2 c, zm, zp;
                 if (m == 1) {
-                    // level 0 from the ring: planes t-2, t-1, t in slots u-2, u-1, u
-                    zm = keep(L0[(u + 2) & 3][r], col_ghost[r] || pout(t - 2));
-                    c = keep(L0[(u + 3) & 3][r], col_ghost[r] || pout(t - 1));
-                    zp = keep(L0[u & 3][r], col_ghost[r] || pout(t));
+                    // level 0 from the ring: planes t-2, t-1, t
+                    zm = L0[rs(-2)][r];
+                    c = L0[rs(-1)][r];
+                    zp = L0[rs(0)][r];
                 } else {
                     zm = wm[m - 2][r];
                     c = wc[m - 2][r];
@@ -179,7 +200,7 @@ __global__ __launch_bounds__(BXE *TY) void tb_stage(TbArgs a)
                 if (VC) {
                     dc = Dc_[sl];
                     dzm = Dm_[sl];
-                    dzp = (m == 1) ? D0[u & 3][r] : Dp_[sl];   // plane t is not in LDS yet
+                    dzp = (m == 1) ? D0[rs(0)][r] : Dp_[sl];   // plane t is not in LDS yet
                 }
                 double qr_c = 0.0, qi_c = 0.0;
                 if (OP == POR) {
@@ -187,19 +208,21 @@ __global__ __launch_bounds__(BXE *TY) void tb_stage(TbArgs a)
                     qi_c = 2.0 * (c.x * c.y);
                 }
                 double acc_r = 0.0, acc_i = 0.0;
-                face<OP>(acc_r, acc_i, c, L[sl - 1], dc, VC ? Dc_[sl - 1] : 0.0, dir && x == 0,
-                         qr_c, qi_c, a.d_const);
-                face<OP>(acc_r, acc_i, c, L[sl + 1], dc, VC ? Dc_[sl + 1] : 0.0,
-                         dir && x == a.nx - 1, qr_c, qi_c, a.d_const);
+                // A Dirichlet ghost holds W = 0 and the D of the boundary cell
+                // it faces (loads are clamped), so every face takes the plain
+                // mean, which there equals D_c bit for bit.
+                face<OP>(acc_r, acc_i, c, L[sl - 1], dc, VC ? Dc_[sl - 1] : 0.0, false, qr_c,
+                         qi_c, a.d_const);
+                face<OP>(acc_r, acc_i, c, L[sl + 1], dc, VC ? Dc_[sl + 1] : 0.0, false, qr_c,
+                         qi_c, a.d_const);
                 if (NDIM == 3) {
-                    face<OP>(acc_r, acc_i, c, L[sl - SX], dc, VC ? Dc_[sl - SX] : 0.0,
-                             dir && yr[r] == 0, qr_c, qi_c, a.d_const);
-                    face<OP>(acc_r, acc_i, c, L[sl + SX], dc, VC ? Dc_[sl + SX] : 0.0,
-                             dir && yr[r] == a.ny - 1, qr_c, qi_c, a.d_const);
+                    face<OP>(acc_r, acc_i, c, L[sl - SX], dc, VC ? Dc_[sl - SX] : 0.0, false,
+                             qr_c, qi_c, a.d_const);
+                    face<OP>(acc_r, acc_i, c, L[sl + SX], dc, VC ? Dc_[sl + SX] : 0.0, false,
+                             qr_c, qi_c, a.d_const);
                 }
-                face<OP>(acc_r, acc_i, c, zm, dc, dzm, dir && p == 0, qr_c, qi_c, a.d_const);
-                face<OP>(acc_r, acc_i, c, zp, dc, dzp, dir && p == a.nz - 1, qr_c, qi_c,
-                         a.d_const);
+                face<OP>(acc_r, acc_i, c, zm, dc, dzm, false, qr_c, qi_c, a.d_const);
+                face<OP>(acc_r, acc_i, c, zp, dc, dzp, false, qr_c, qi_c, a.d_const);
                 double2 v = euler(c, acc_r, acc_i, a.inv_h2, a.tr[m - 1], a.ti[m - 1]);
                 v = keep(v, col_ghost[r] || pghost);
                 if (m < K) {
@@ -217,10 +240,10 @@ __global__ __launch_bounds__(BXE *TY) void tb_stage(TbArgs a)
         __syncthreads();   // every read of the LDS planes of this step is done
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            sL[0][slot[r]] = keep(L0[u & 3][r], col_ghost[r] || pout(t));
+            sL[0][slot[r]] = L0[rs(0)][r];
 #pragma unroll
             for (int m = 1; m < K; ++m) sL[m][slot[r]] = wp[m - 1][r];
-            if (VC) sD[dslot(t)][slot[r]] = D0[u & 3][r];
+            if (VC) sD[dslot(t)][slot[r]] = D0[rs(0)][r];
         }
         __syncthreads();   // the planes of step t are visible to step t+1
     }
@@ -314,6 +337,7 @@ bool tblock_supported(const KGrid &g, int k)
 int launch_tblock(const KGrid &g, const PassArgs &p, int shape, hipStream_t st)
 {
     if (!tblock_supported(g, p.k)) return (int)hipErrorInvalidValue;
+    if (g.ndim == 3 && shape == 3) return launch_tb3d(g, p, st);
     TbArgs a{};
     a.in_re = p.in_re;
     a.in_c = reinterpret_cast<const double2 *>(p.in_c);

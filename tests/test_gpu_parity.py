@@ -202,14 +202,18 @@ def test_reductions(op, n):
 
 
 TB_CASES = [
-    ("3d-var-dir", (70, 37, 21), 2, 0), ("3d-var-dir", (70, 37, 21), 2, 1),
-    ("3d-var-dir", (70, 37, 21), 3, 0), ("3d-var-per", (67, 30, 18), 2, 1),
-    ("3d-var-per", (67, 30, 18), 3, 0), ("3d-lap-dir", (33, 17, 9), 2, 0),
-    ("3d-lap-per", (9, 5, 4), 3, 0), ("3d-var-dir", (2, 3, 2), 2, 1),
-    ("2d-var-dir", (300, 37, 1), 2, 0), ("2d-var-dir", (300, 37, 1), 3, 0),
-    ("2d-var-per", (257, 19, 1), 4, 0), ("2d-lap-per", (513, 20, 1), 6, 0),
-    ("2d-por-per", (260, 33, 1), 8, 0), ("2d-por-dir", (70, 50, 1), 4, 0),
-    ("2d-var-dir", (5, 3, 1), 8, 0),
+    ("3d-var-dir", (70, 37, 21), 2, 1), ("3d-var-dir", (70, 37, 21), 2, 2),
+    ("3d-var-dir", (70, 37, 21), 3, 1), ("3d-var-per", (67, 30, 18), 2, 2),
+    ("3d-var-per", (67, 30, 18), 3, 1), ("3d-lap-dir", (33, 17, 9), 2, 1),
+    ("3d-lap-per", (9, 5, 4), 3, 1), ("3d-var-dir", (2, 3, 2), 2, 2),
+    ("2d-var-dir", (300, 37, 1), 2, 1), ("2d-var-dir", (300, 37, 1), 3, 1),
+    ("2d-var-per", (257, 19, 1), 4, 1), ("2d-lap-per", (513, 20, 1), 6, 1),
+    ("2d-por-per", (260, 33, 1), 8, 1), ("2d-por-dir", (70, 50, 1), 4, 1),
+    ("2d-var-dir", (5, 3, 1), 8, 1),
+    ("3d-var-dir", (70, 37, 21), 2, 4), ("3d-var-dir", (70, 37, 21), 3, 4),
+    ("3d-var-per", (67, 30, 18), 2, 4), ("3d-var-per", (130, 12, 9), 3, 4),
+    ("3d-lap-dir", (33, 17, 9), 3, 4), ("3d-lap-per", (9, 5, 4), 2, 4),
+    ("3d-var-dir", (2, 3, 2), 3, 4), ("3d-var-dir", (64, 11, 5), 2, 4),
 ]
 
 
@@ -218,7 +222,7 @@ TB_CASES = [
 def test_temporal_blocking_matches_oracle(kind, n, k, shape, s):
     """k stages fused per HBM pass (with a single-stage remainder) give the same bits."""
     F.frkc2_set_option(F.OPT_TBLOCK, k)
-    F.frkc2_set_option(F.OPT_TILE, shape)
+    F.frkc2_set_option(F.OPT_TILE, shape)   # 1.. (0 = automatic)
     try:
         test_superstep_matches_oracle(kind, n, s)
     finally:

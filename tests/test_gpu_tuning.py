@@ -33,15 +33,24 @@ ZC_CASES = [
 
 @pytest.mark.parametrize("kind,n,k", ZC_CASES)
 @pytest.mark.parametrize("zchunk", [1, 3, 8, 17])
-def test_zchunk_matches_oracle(kind, n, k, zchunk):
+def test_zchunk_matches_oracle(kind, n, k, zchunk, tile=1):
     """Chunks shorter than the fused depth, ragged last chunks and one-plane chunks."""
     F.frkc2_set_option(F.OPT_TBLOCK, k)
+    F.frkc2_set_option(F.OPT_TILE, tile)
     F.frkc2_set_option(F.OPT_ZCHUNK, zchunk)
     try:
         P.test_superstep_matches_oracle(kind, n, 16)
     finally:
         F.frkc2_set_option(F.OPT_TBLOCK, 0)
+        F.frkc2_set_option(F.OPT_TILE, 0)
         F.frkc2_set_option(F.OPT_ZCHUNK, 0)
+
+
+@pytest.mark.parametrize("kind,n,k", [("3d-var-dir", (70, 37, 21), 2), ("3d-var-dir", (70, 37, 21), 3),
+                                      ("3d-var-per", (67, 30, 18), 3), ("3d-lap-per", (9, 5, 4), 2)])
+@pytest.mark.parametrize("zchunk", [1, 2, 5, 16])
+def test_zchunk_full_width_tiles(kind, n, k, zchunk):
+    test_zchunk_matches_oracle(kind, n, k, zchunk, tile=4)
 
 
 @pytest.mark.parametrize("kind,n", [("3d-var-dir", (72, 40, 36)), ("2d-por-per", (260, 33, 1)),
@@ -58,7 +67,7 @@ def test_autotune_then_step(kind, n):
     assert r["candidates"] > 10
     assert r["ms_best"] > 0 and r["ms_best"] <= r["ms_default"]
     assert r["tblock"] in ((1, 2, 3) if p.ndim == 3 else (1, 2, 3, 4, 6, 8))
-    assert r["tile"] in (0, 1, 2) and r["zchunk"] >= 0
+    assert r["tile"] in ((1, 2, 3, 4) if p.ndim == 3 else (1, 2)) and r["zchunk"] >= 0
     try:
         c = frkc2_coeffs(s, 0.01)
         if p.op == 2:
