@@ -23,14 +23,18 @@
  * Boundaries: periodic (wrap), or Dirichlet zero (ghost W = 0 and, for op 1,
  * ghost D equal to the cell's own D, so the boundary face carries D_c).
  *
- * Evaluation order (fixed; the GPU library evaluates the same expressions in
- * the same order, so results agree to the last bit):
- *   faces in the order x-, x+, y-, y+, z-, z+;
- *   acc_r = acc_r + Df*(Wr_nb - Wr_c), acc_i likewise (op 2:
- *   acc_r = acc_r + (Dr*dr - Di*di), acc_i = acc_i + (Dr*di + Di*dr));
+ * Evaluation order (fixed; the paper fixes none, and the GPU library
+ * evaluates the same expressions in the same order, so results agree to the
+ * last bit). fma(a, b, c) is the correctly rounded a*b + c (C99):
+ *   faces in the order x-, x+, y-, y+, z-, z+; dr = Wr_nb - Wr_c, di likewise;
+ *   op 0/1: acc_r = fma(Df, dr, acc_r), acc_i = fma(Df, di, acc_i);
+ *   op 2:   q = W^2 as (fma(Wr, Wr, -(Wi*Wi)), 2*(Wr*Wi)) for cell and
+ *           neighbour, Qr = (qr_c + qr_nb)/2, Qi likewise,
+ *           acc_r = fma(Qr, dr, fma(-Qi, di, acc_r)),
+ *           acc_i = fma(Qr, di, fma(Qi, dr, acc_i));
  *   f = acc*inv_h2 with inv_h2 = 1/(h*h);
- *   Wr = Wr + (tr*fr - ti*fi), Wi = Wi + (tr*fi + ti*fr).
- * Built with -ffp-contract=off, so no multiply-add is fused.
+ *   Wr = fma(tr, fr, fma(-ti, fi, Wr)), Wi = fma(tr, fi, fma(ti, fr, Wi)).
+ * Built with -ffp-contract=off, so no other multiply-add is fused.
  *
  * The adjoint runs the transposed stages in reverse order. Because A is
  * symmetric, the adjoint of W <- W + tau A W is lam <- lam + conj(tau) A lam
@@ -39,6 +43,7 @@
  * lam = lam^{l+1} and W = W^l, split half to each cell of an interior face
  * and fully to the cell of a Dirichlet boundary face.
  */
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -92,14 +97,14 @@ static void apply_op(const grid_t *g, const double *D, const double *wr, const d
             double dr = nr - wr[p];
             double di = ni - wi[p];
             if (g->op == OP_POROUS2) {
-                double qr_c = wr[p] * wr[p] - wi[p] * wi[p];
+                double qr_c = fma(wr[p], wr[p], -(wi[p] * wi[p]));
                 double qi_c = 2.0 * (wr[p] * wi[p]);
-                double qr_n = nr * nr - ni * ni;
+                double qr_n = fma(nr, nr, -(ni * ni));
                 double qi_n = 2.0 * (nr * ni);
                 double Dr = 0.5 * (qr_c + qr_n);
                 double Di = 0.5 * (qi_c + qi_n);
-                acc_r = acc_r + (Dr * dr - Di * di);
-                acc_i = acc_i + (Dr * di + Di * dr);
+                acc_r = fma(Dr, dr, fma(-Di, di, acc_r));
+                acc_i = fma(Dr, di, fma(Di, dr, acc_i));
             } else {
                 double Df;
                 if (g->op == OP_LAPLACE) {
@@ -108,8 +113,8 @@ static void apply_op(const grid_t *g, const double *D, const double *wr, const d
                     double Dn = (q < 0) ? D[p] : D[q];
                     Df = 0.5 * (D[p] + Dn);
                 }
-                acc_r = acc_r + Df * dr;
-                acc_i = acc_i + Df * di;
+                acc_r = fma(Df, dr, acc_r);
+                acc_i = fma(Df, di, acc_i);
             }
         }
         fr[p] = acc_r * g->inv_h2;
@@ -158,8 +163,8 @@ int oracle_superstep(int ndim, const long *n, int bc, int op, double inv_h2, dou
         double tr = tau_re[l], ti = tau_im[l];
 #pragma omp parallel for schedule(static)
         for (long p = 0; p < N; ++p) {
-            double nr = wr[p] + (tr * fr[p] - ti * fi[p]);
-            double ni = wi[p] + (tr * fi[p] + ti * fr[p]);
+            double nr = fma(tr, fr[p], fma(-ti, fi[p], wr[p]));
+            double ni = fma(tr, fi[p], fma(ti, fr[p], wi[p]));
             wr[p] = nr;
             wi[p] = ni;
         }

@@ -32,7 +32,7 @@ def build(force: bool = True) -> str:
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                                "-fPIC", "-shared", "-o", tmp,
-                               os.path.join(_HERE, "stage.c")])
+                               os.path.join(_HERE, "stage.c"), "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 

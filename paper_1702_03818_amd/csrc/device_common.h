@@ -110,10 +110,19 @@ __device__ __forceinline__ double load_r_nb(const Dims &d, const double *v, int 
     return ghost ? 0.0 : r;
 }
 
+// W^2 of a complex value in the fixed order the library and its CPU check
+// share: (fma(re, re, -(im*im)), 2*(re*im)).
+__device__ __forceinline__ void csq(double2 c, double &qr, double &qi)
+{
+    qr = fma(c.x, c.x, -(c.y * c.y));
+    qi = 2.0 * (c.x * c.y);
+}
+
 // One face of the flux sum of the diffusion operator, in the fixed order the
-// library and its CPU check share. nb: neighbour value (0 for a Dirichlet
-// ghost); dc, dn: cell and neighbour diffusivity; ghost selects D_f = D_c,
-// which equals (D_c + D_c)/2 bit for bit.
+// library and its CPU check share (fused multiply-adds, correctly rounded).
+// nb: neighbour value (0 for a Dirichlet ghost); dc, dn: cell and neighbour
+// diffusivity; ghost selects D_f = D_c, which equals (D_c + D_c)/2 bit for
+// bit; qr_c, qi_c: W_c^2 for the porous operator.
 template <int OP>
 __device__ __forceinline__ void face(double &acc_r, double &acc_i, double2 c, double2 nb,
                                      double dc, double dn, bool ghost, double qr_c, double qi_c,
@@ -122,28 +131,29 @@ __device__ __forceinline__ void face(double &acc_r, double &acc_i, double2 c, do
     const double dr = nb.x - c.x;
     const double di = nb.y - c.y;
     if (OP == POR) {
-        const double qr_n = nb.x * nb.x - nb.y * nb.y;
-        const double qi_n = 2.0 * (nb.x * nb.y);
+        double qr_n, qi_n;
+        csq(nb, qr_n, qi_n);
         const double Dr = 0.5 * (qr_c + qr_n);
         const double Di = 0.5 * (qi_c + qi_n);
-        acc_r = acc_r + (Dr * dr - Di * di);
-        acc_i = acc_i + (Dr * di + Di * dr);
+        acc_r = fma(Dr, dr, fma(-Di, di, acc_r));
+        acc_i = fma(Dr, di, fma(Di, dr, acc_i));
     } else {
         double Df;
         if (OP == LAP) Df = d_const;
         else Df = ghost ? dc : 0.5 * (dc + dn);
-        acc_r = acc_r + Df * dr;
-        acc_i = acc_i + Df * di;
+        acc_r = fma(Df, dr, acc_r);
+        acc_i = fma(Df, di, acc_i);
     }
 }
 
-// Forward Euler update W + tau f with f = acc * inv_h2.
+// Forward Euler update W + tau f with f = acc * inv_h2:
+// (fma(tr, fr, fma(-ti, fi, Wr)), fma(tr, fi, fma(ti, fr, Wi))).
 __device__ __forceinline__ double2 euler(double2 c, double acc_r, double acc_i, double inv_h2,
                                          double tr, double ti)
 {
     const double fr = acc_r * inv_h2;
     const double fi = acc_i * inv_h2;
-    return make_double2(c.x + (tr * fr - ti * fi), c.y + (tr * fi + ti * fr));
+    return make_double2(fma(tr, fr, fma(-ti, fi, c.x)), fma(tr, fi, fma(ti, fr, c.y)));
 }
 
 }  // namespace dev

@@ -160,66 +160,98 @@ __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
         }
         L0[rs(0)] = keep3(L0[rs(0)], col_ghost || pout(t));
         const int rb = (t - 1) & 1, wb = t & 1;     // LDS buffers read / written at step t
-#pragma unroll
-        for (int m = 1; m <= K; ++m) {
-            if (need < m) continue;
+        // LDS operands of level m: x/y neighbours of level m-1 and their D,
+        // and the cell's own D where the register ring no longer holds it.
+        // Level m+1's operands are read before level m is computed, by every
+        // lane (all slots are in range), so their latency overlaps the work.
+        struct Nb {
+            double2 w[4];
+            double d[4], dc, dzm, dzp;
+        };
+        auto read = [&](int m) {
+            Nb n;
             const int p = t - m;
             const double2 *L = sL[rb][m - 1];
-            const double *Dp = VC ? sD[dslot(p)] : nullptr;
-            double2 c, zm, zp;
-            double dc = 0.0, dzm = 0.0, dzp = 0.0;
-            if (m == 1) {
-                zm = L0[rs(-2)];
-                c = L0[rs(-1)];
-                zp = L0[rs(0)];
-                if (VC) {
-                    dzm = D0[rs(-2)];
-                    dc = D0[rs(-1)];
-                    dzp = D0[rs(0)];
+            n.w[0] = L[slot - 1];
+            n.w[1] = L[slot + 1];
+            n.w[2] = L[slot - SX];
+            n.w[3] = L[slot + SX];
+            n.dc = n.dzm = n.dzp = 0.0;
+            n.d[0] = n.d[1] = n.d[2] = n.d[3] = 0.0;
+            if (VC) {
+                const double *Dp = sD[dslot(p)];
+                n.d[0] = Dp[slot - 1];
+                n.d[1] = Dp[slot + 1];
+                n.d[2] = Dp[slot - SX];
+                n.d[3] = Dp[slot + SX];
+                if (m == 1) {
+                    n.dzm = D0[rs(-2)];
+                    n.dc = D0[rs(-1)];
+                    n.dzp = D0[rs(0)];
+                } else {
+                    n.dc = (m == 2) ? D0[rs(-2)] : Dp[slot];
+                    n.dzm = sD[dslot(p - 1)][slot];
+                    n.dzp = (m == 2) ? D0[rs(-1)] : (m == 3 ? D0[rs(-2)] : sD[dslot(p + 1)][slot]);
                 }
-            } else {
-                zm = wm[m - 2];
-                c = wc[m - 2];
-                zp = wp[m - 2];
-                if (VC) {
-                    dc = (m == 2) ? D0[rs(-2)] : Dp[slot];
-                    dzm = sD[dslot(p - 1)][slot];
-                    dzp = (m == 2) ? D0[rs(-1)] : (m == 3 ? D0[rs(-2)] : sD[dslot(p + 1)][slot]);
+            }
+            return n;
+        };
+        // (For K = 3 the operands of two levels do not fit the registers of
+        // four wavefronts per SIMD: there each level reads its own.)
+        constexpr bool RA = (K <= 2);
+        Nb cur = read(1);
+#pragma unroll
+        for (int m = 1; m <= K; ++m) {
+            Nb nxt = cur;
+            if (RA && m < K) nxt = read(m + 1);
+            if (need >= m) {
+                const int p = t - m;
+                double2 c, zm, zp;
+                if (m == 1) {
+                    zm = L0[rs(-2)];
+                    c = L0[rs(-1)];
+                    zp = L0[rs(0)];
+                } else {
+                    zm = wm[m - 2];
+                    c = wc[m - 2];
+                    zp = wp[m - 2];
+                }
+                double qr_c = 0.0, qi_c = 0.0;
+                if (OP == POR) {
+                    csq(c, qr_c, qi_c);
+                }
+                // A Dirichlet ghost holds W = 0 and the D of the boundary cell
+                // it faces (loads are clamped), so every face takes the plain
+                // mean, which there equals D_c bit for bit.
+                const double dc = cur.dc;
+                double acc_r = 0.0, acc_i = 0.0;
+                face<OP>(acc_r, acc_i, c, cur.w[0], dc, cur.d[0], false, qr_c, qi_c, a.d_const);
+                face<OP>(acc_r, acc_i, c, cur.w[1], dc, cur.d[1], false, qr_c, qi_c, a.d_const);
+                face<OP>(acc_r, acc_i, c, cur.w[2], dc, cur.d[2], false, qr_c, qi_c, a.d_const);
+                face<OP>(acc_r, acc_i, c, cur.w[3], dc, cur.d[3], false, qr_c, qi_c, a.d_const);
+                face<OP>(acc_r, acc_i, c, zm, dc, cur.dzm, false, qr_c, qi_c, a.d_const);
+                face<OP>(acc_r, acc_i, c, zp, dc, cur.dzp, false, qr_c, qi_c, a.d_const);
+                double2 v = euler(c, acc_r, acc_i, a.inv_h2, a.tr[m - 1], a.ti[m - 1]);
+                v = keep3(v, col_ghost || pout(p));
+                if (m < K) {
+                    wm[m - 1] = wc[m - 1];
+                    wc[m - 1] = wp[m - 1];
+                    wp[m - 1] = v;
+                } else if (out_col && p >= z0 && p < z1) {
+                    const long long i = x + (long long)a.nx * (y + (long long)a.ny * p);
+                    if (OUT_REAL) a.out_re[i] = v.x;
+                    else a.out_c[i] = v;
                 }
             }
-            double qr_c = 0.0, qi_c = 0.0;
-            if (OP == POR) {
-                qr_c = c.x * c.x - c.y * c.y;
-                qi_c = 2.0 * (c.x * c.y);
-            }
-            // A Dirichlet ghost holds W = 0 and the D of the boundary cell it
-            // faces (loads are clamped), so every face takes the plain mean,
-            // which there equals D_c bit for bit.
-            double acc_r = 0.0, acc_i = 0.0;
-            face<OP>(acc_r, acc_i, c, L[slot - 1], dc, VC ? Dp[slot - 1] : 0.0, false, qr_c, qi_c,
-                     a.d_const);
-            face<OP>(acc_r, acc_i, c, L[slot + 1], dc, VC ? Dp[slot + 1] : 0.0, false, qr_c, qi_c,
-                     a.d_const);
-            face<OP>(acc_r, acc_i, c, L[slot - SX], dc, VC ? Dp[slot - SX] : 0.0, false, qr_c,
-                     qi_c, a.d_const);
-            face<OP>(acc_r, acc_i, c, L[slot + SX], dc, VC ? Dp[slot + SX] : 0.0, false, qr_c,
-                     qi_c, a.d_const);
-            face<OP>(acc_r, acc_i, c, zm, dc, dzm, false, qr_c, qi_c, a.d_const);
-            face<OP>(acc_r, acc_i, c, zp, dc, dzp, false, qr_c, qi_c, a.d_const);
-            double2 v = euler(c, acc_r, acc_i, a.inv_h2, a.tr[m - 1], a.ti[m - 1]);
-            v = keep3(v, col_ghost || pout(p));
-            if (m < K) {
-                wm[m - 1] = wc[m - 1];
-                wc[m - 1] = wp[m - 1];
-                wp[m - 1] = v;
-                sL[wb][m][slot] = v;
-            } else if (out_col && p >= z0 && p < z1) {
-                const long long i = x + (long long)a.nx * (y + (long long)a.ny * p);
-                if (OUT_REAL) a.out_re[i] = v.x;
-                else a.out_c[i] = v;
-            }
+            if (!RA && m < K) nxt = read(m + 1);
+            cur = nxt;
         }
+        // All LDS writes of the step come after all its reads, so the reads
+        // of every level can be issued early. A lane that skipped level m
+        // stores a stale value that no needed cell reads.
         sL[wb][0][slot] = L0[rs(0)];
+#pragma unroll
+        for (int m = 1; m < K; ++m) sL[wb][m][slot] = wp[m - 1];
         if (VC) sD[dslot(t)][slot] = D0[rs(0)];
         __syncthreads();   // step t's planes are visible to step t+1, whose
                            // writes go to the other buffer
@@ -227,12 +259,35 @@ __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
     }
 }
 
-int choose_zchunk3(long long tiles, int nz)
+// Chunk length: one workgroup fills a CU (its LDS), so the launch runs in
+// rounds of n_cu workgroups. Pick, among nz, nz/2, ... down to 16 planes, the
+// chunk that maximises the busy fraction of the last round times the share
+// of planes that are not chunk halo (zc / (zc + 2K)).
+int choose_zchunk3(long long tiles, int nz, int K)
 {
-    // whole rounds of 256 workgroups, preferring long chunks
-    int zc = nz;
-    while (zc > 16 && tiles * ((nz + zc - 1) / zc) < 512) zc = (zc + 1) / 2;
-    return zc;
+    static int n_cu = 0;
+    if (n_cu == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            v > 0)
+            n_cu = v;
+        else
+            n_cu = 256;
+    }
+    int best = nz;
+    double best_eff = -1.0;
+    for (int zc = nz;; zc = (zc + 1) / 2) {
+        const long long nblk = tiles * ((nz + zc - 1) / zc);
+        const long long rounds = (nblk + n_cu - 1) / n_cu;
+        const double eff = (double)nblk / (double)(rounds * n_cu) * zc / (zc + 2.0 * K);
+        if (eff > best_eff + 1e-9) {
+            best_eff = eff;
+            best = zc;
+        }
+        if (zc <= 16) break;
+    }
+    return best;
 }
 
 template <int OP, int BC, int K>
@@ -242,7 +297,7 @@ int launch3_k(const Tb3Args &a0, bool ir, bool orl, hipStream_t st)
     a.ntx = (a.nx + 63) / 64;
     a.nty = (a.ny + Tb3Shape<K>::BYO - 1) / Tb3Shape<K>::BYO;
     const long long tiles = (long long)a.ntx * a.nty;
-    a.zchunk = (a0.zchunk > 0) ? min(a0.zchunk, a.nz) : choose_zchunk3(tiles, a.nz);
+    a.zchunk = (a0.zchunk > 0) ? min(a0.zchunk, a.nz) : choose_zchunk3(tiles, a.nz, K);
     const long long nblk = tiles * ((a.nz + a.zchunk - 1) / a.zchunk);
     if (nblk > 0x7fffffffLL) return (int)hipErrorInvalidValue;
     dim3 grid((unsigned)nblk), block(1024);

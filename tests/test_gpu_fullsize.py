@@ -34,22 +34,33 @@ def check(got, ref, what):
         what, int(np.sum(got != ref)), r)
 
 
-def test_diffusion3d_256_superstep():
-    """256^3 variable D, Dirichlet, s = 100 (the benchmark workload), block depth 2 as timed."""
+@pytest.fixture(scope="module")
+def c2_reference():
     p = wl.diffusion3d()
     c = frkc2_coeffs(100, 0.01)
     rho = stage.rho_bound(p)
     T = 0.9 * c.beta_bar / rho
+    return p, c, rho, T, stage.superstep(p, p.w0, T * c.a_re, T * c.a_im)
+
+
+@pytest.mark.parametrize("k,tile,zchunk", [(0, 0, 0), (2, 4, 32), (3, 4, 128), (2, 1, 0)])
+def test_diffusion3d_256_superstep(c2_reference, k, tile, zchunk):
+    """256^3 variable D, Dirichlet, s = 100 (the benchmark workload) in the launch
+    configurations the benchmark's autotuner chooses between."""
+    p, c, rho, T, ref = c2_reference
     w = dev(p.w0)
     D = dev(p.D)
     assert F.frkc2_rho_bound(p, None, D) == rho
-    F.frkc2_set_option(F.OPT_TBLOCK, 2)
+    F.frkc2_set_option(F.OPT_TBLOCK, k)
+    F.frkc2_set_option(F.OPT_TILE, tile)
+    F.frkc2_set_option(F.OPT_ZCHUNK, zchunk)
     try:
         F.frkc2_step(p, w, D, T=T, s=100, nsteps=1)
     finally:
         F.frkc2_set_option(F.OPT_TBLOCK, 0)
-    ref = stage.superstep(p, p.w0, T * c.a_re, T * c.a_im)
-    check(w.cpu().numpy(), ref, "3D 256^3 s=100")
+        F.frkc2_set_option(F.OPT_TILE, 0)
+        F.frkc2_set_option(F.OPT_ZCHUNK, 0)
+    check(w.cpu().numpy(), ref, "3D 256^3 s=100 k=%d tile=%d zchunk=%d" % (k, tile, zchunk))
 
 
 def test_diffusion3d_256_ten_supersteps_contract():
