@@ -27,8 +27,10 @@
  *    fault of an earlier asynchronous call surfaces as FRKC2_EHIP at the next
  *    call that synchronises.
  *  - Floating point: the kernels evaluate each grid point's arithmetic in one
- *    fixed order without fused multiply-adds, so results do not depend on
- *    tiling, temporal blocking or launch shape.
+ *    fixed order (faces x-, x+, y-, y+, z-, z+, each accumulated with one
+ *    correctly rounded fused multiply-add; the Euler update as two nested
+ *    fused multiply-adds per component), so results do not depend on tiling,
+ *    temporal blocking or launch shape.
  */
 #ifndef FRKC2_H
 #define FRKC2_H

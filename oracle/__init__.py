@@ -6,7 +6,9 @@ the GPU library: the two share no code, headers, tables or constants.
 
   coeffs.py  stepsizes (roots, damping, real extent, stage order), 50-digit mpmath + FP64
   stage.c    plain stage loops, adjoint and Gershgorin bound (gcc, FP64)
-  stage.py   ctypes wrapper of stage.c
+  stage.py   ctypes wrapper of stage.c (also the embedded first-order solution of Sec. 3)
+  adaptive.py  error-controlled integration of Sec. 3: error norm, accept/reject,
+             predictive controller, stage-count choice
   dense.py   dense matrix-polynomial brute force on tiny grids
 
 Pins: every function is checked against closed forms, brute force or the

@@ -142,9 +142,17 @@ static int make_grid(grid_t *g, int ndim, const long *n, int bc, int op, double 
  * If store is not NULL it receives W^0..W^{s-1} as s blocks of 2N doubles
  * (real part, then imaginary part).
  */
+/*
+ * One superstep. w: real W^0 on entry, Re W^L on exit; wi_out (may be NULL):
+ * Im W^L; store (may be NULL): every stage W^0 .. W^{s-1} (re then im);
+ * emb_out (may be NULL): the embedded first-order solution of Sec. 3, which
+ * uses only the real parts of the stepsizes and of f(W^l):
+ *   What^0 = W^0, What^{l+1} = What^l + T Re(a_l) Re f(W^l),
+ * evaluated as What = fma(tr, Re f, What) with tr = Re(tau_l).
+ */
 int oracle_superstep(int ndim, const long *n, int bc, int op, double inv_h2, double d_const,
                      const double *D, int s, const double *tau_re, const double *tau_im,
-                     double *w, double *wi_out, double *store)
+                     double *w, double *wi_out, double *store, double *emb_out)
 {
     grid_t g;
     if (make_grid(&g, ndim, n, bc, op, inv_h2, d_const)) return -1;
@@ -154,6 +162,7 @@ int oracle_superstep(int ndim, const long *n, int bc, int op, double inv_h2, dou
     if (!wr || !wi || !fr || !fi) { free(wr); free(wi); free(fr); free(fi); return -2; }
     memcpy(wr, w, sizeof(double) * N);
     memset(wi, 0, sizeof(double) * N);
+    if (emb_out) memcpy(emb_out, w, sizeof(double) * N);
     for (int l = 0; l < s; ++l) {
         if (store) {
             memcpy(store + (size_t)2 * N * l, wr, sizeof(double) * N);
@@ -167,6 +176,7 @@ int oracle_superstep(int ndim, const long *n, int bc, int op, double inv_h2, dou
             double ni = fma(tr, fi[p], fma(ti, fr[p], wi[p]));
             wr[p] = nr;
             wi[p] = ni;
+            if (emb_out) emb_out[p] = fma(tr, fr[p], emb_out[p]);
         }
     }
     memcpy(w, wr, sizeof(double) * N);
@@ -198,7 +208,7 @@ int oracle_adjoint(int ndim, const long *n, int bc, int op, double inv_h2, doubl
         return -2;
     }
     memcpy(w, w_n, sizeof(double) * N);
-    oracle_superstep(ndim, n, bc, op, inv_h2, d_const, D, s, tau_re, tau_im, w, NULL, store);
+    oracle_superstep(ndim, n, bc, op, inv_h2, d_const, D, s, tau_re, tau_im, w, NULL, store, NULL);
     memcpy(lr, lam_next, sizeof(double) * N);
     memset(li, 0, sizeof(double) * N);
     for (int l = s - 1; l >= 0; --l) {

@@ -47,7 +47,7 @@ def _load():
         lp = ctypes.POINTER(ctypes.c_long)
         common = [ctypes.c_int, lp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                   dp, ctypes.c_int, dp, dp]
-        lib.oracle_superstep.argtypes = common + [dp, dp, dp]
+        lib.oracle_superstep.argtypes = common + [dp, dp, dp, dp]
         lib.oracle_superstep.restype = ctypes.c_int
         lib.oracle_adjoint.argtypes = common + [dp, dp, dp, dp]
         lib.oracle_adjoint.restype = ctypes.c_int
@@ -90,10 +90,27 @@ def superstep(prob, w, tau_re, tau_im, D=None, want_imag=False):
     Dd = _f64(D if D is not None else prob.D) if (prob.D is not None or D is not None) else None
     tr, ti = _f64(tau_re), _f64(tau_im)
     rc = lib.oracle_superstep(prob.ndim, n, prob.bc, prob.op, inv_h2, prob.d_const, _dp(Dd),
-                              len(tr), _dp(tr), _dp(ti), _dp(wr), _dp(wi), None)
+                              len(tr), _dp(tr), _dp(ti), _dp(wr), _dp(wi), None, None)
     if rc != 0:
         raise RuntimeError("oracle_superstep failed (%d)" % rc)
     return (wr, wi) if want_imag else wr
+
+
+def superstep_embedded(prob, w, tau_re, tau_im, D=None):
+    """One superstep from real w that also carries the embedded first-order solution of
+    Sec. 3 (real parts of the stepsizes and of f only). Returns (Re W^s, Im W^s, What^s)."""
+    lib = _load()
+    n, inv_h2 = _grid_args(prob)
+    wr = _f64(w).copy()
+    wi = np.empty_like(wr)
+    wh = np.empty_like(wr)
+    Dd = _f64(D if D is not None else prob.D) if (prob.D is not None or D is not None) else None
+    tr, ti = _f64(tau_re), _f64(tau_im)
+    rc = lib.oracle_superstep(prob.ndim, n, prob.bc, prob.op, inv_h2, prob.d_const, _dp(Dd),
+                              len(tr), _dp(tr), _dp(ti), _dp(wr), _dp(wi), None, _dp(wh))
+    if rc != 0:
+        raise RuntimeError("oracle_superstep failed (%d)" % rc)
+    return wr, wi, wh
 
 
 def rho_bound(prob, w=None, D=None) -> float:

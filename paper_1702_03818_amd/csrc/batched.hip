@@ -20,7 +20,7 @@
 // (workgroup b runs on XCD b % 8), so neighbouring tiles share an L2.
 //
 // The per-point arithmetic is the one of the plain stage kernels (faces
-// x-, x+, y-, y+, z-, z+, no fused multiply-adds), so each problem's result
+// x-, x+, y-, y+, z-, z+, face() and euler()), so each problem's result
 // equals, bit for bit, the result of frkc2_step on it.
 #include <hip/hip_runtime.h>
 

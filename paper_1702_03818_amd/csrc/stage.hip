@@ -20,12 +20,12 @@
 // L2 caches). 2D grids march along their second dimension with BY = 1; 1D
 // grids use a single plane.
 //
-// Arithmetic order (identical in every kernel and in the CPU check):
-// faces x-, x+, y-, y+, z-, z+; acc = acc + Df*(W_nb - W_c) per face
-// (POROUS2: acc_r = acc_r + (Dr*dr - Di*di), acc_i = acc_i + (Dr*di + Di*dr));
-// f = acc*inv_h2; W_r + (tr*f_r - ti*f_i), W_i + (tr*f_i + ti*f_r). The library
-// is compiled with -ffp-contract=off, so nothing is fused and the result is
-// independent of the tile shape.
+// Arithmetic order (identical in every kernel and in the CPU check, see
+// face() and euler() in device_common.h): faces x-, x+, y-, y+, z-, z+;
+// acc = fma(Df, W_nb - W_c, acc) per face; f = acc*inv_h2;
+// W_r = fma(tr, f_r, fma(-ti, f_i, W_r)), W_i = fma(tr, f_i, fma(ti, f_r, W_i)).
+// The library is compiled with -ffp-contract=off, so no other operation is
+// fused and the result is independent of the tile shape.
 #include <hip/hip_runtime.h>
 
 #include "plane_tile.h"

@@ -28,8 +28,8 @@
 // per stage it drops roughly by K.
 //
 // Every value is computed with the same per-point arithmetic, in the same
-// order, as the one-stage kernel (faces x-, x+, y-, y+, z-, z+; no fused
-// multiply-adds), so the results are identical to the last bit.
+// order, as the one-stage kernel (faces x-, x+, y-, y+, z-, z+; face() and
+// euler() of device_common.h), so the results are identical to the last bit.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
