@@ -96,6 +96,7 @@ typedef struct {
 /* Workspace flags for frkc2_workspace_bytes. */
 #define FRKC2_WS_STEP    0
 #define FRKC2_WS_ADJOINT 1
+#define FRKC2_WS_ADAPT   2
 
 /*
  * frkc2_coeffs -- the s ordered stepsizes a_l (Sec. 2, 2.1, 2.2).
@@ -113,7 +114,9 @@ int frkc2_coeffs(int s, double nu, double *a_re, double *a_im, frkc2_coeff_info 
  * frkc2_workspace_bytes -- device workspace needed by the calls below for grid g.
  *   FRKC2_WS_STEP: frkc2_step and frkc2_rho_bound (two complex state buffers
  *   plus reduction scratch); FRKC2_WS_ADJOINT: frkc2_step_adjoint (s stored
- *   complex stages, two complex adjoint buffers, one real gradient buffer).
+ *   complex stages, two complex adjoint buffers, one real gradient buffer);
+ *   FRKC2_WS_ADAPT: frkc2_integrate (two complex and two real state buffers
+ *   plus scratch; s is ignored).
  * Returns 0 for an invalid grid.
  */
 size_t frkc2_workspace_bytes(const frkc2_grid *g, int s, int flags);
@@ -204,6 +207,51 @@ int frkc2_batched_release(void *ws);                  /* frees the graph cached 
 #define FRKC2_RED_DOT 4
 int frkc2_reduce(int op, const double *x, const double *y, size_t n, double *result,
                  void *ws, size_t ws_bytes, hipStream_t st);
+
+/*
+ * frkc2_integrate -- error-controlled FRKC2 integration over a time span
+ * (Sec. 3, error control). Each attempt runs one superstep that also carries
+ * the embedded first-order solution What (real parts of the stepsizes and of
+ * f(W^l) only: What^{l+1} = What^l + T Re(a_l) Re f(W^l)), estimates
+ *   err = max_points |W^L - What^L| / (tol (1 + max(|W^L|, |What^L|)))
+ * (complex modulus), rejects the step if err > 1 and retries with T scaled by
+ * SAFE / sqrt(err), and otherwise keeps Re W^L and sets the next length with
+ * the predictive controller T (SAFE / sqrt(err_n)) (T_n / T_{n-1})
+ * sqrt(err_{n-1} / err_n), SAFE = 0.8 (after two consecutive accepted steps;
+ * T SAFE / sqrt(err) otherwise; err floored at 1e-12, growth capped at 5).
+ * The stage count of each attempt is the smallest even s with
+ * betabar(s) >= T rho (rho the Gershgorin bound, recomputed per step for
+ * POROUS2); beyond s = 514, T is cut to 0.99 betabar(514) / rho. The last step
+ * ends exactly at t_span.
+ *   g, w, D, nu  as for frkc2_step; w (device) is advanced in place by t_span
+ *   t_span       time to advance, > 0
+ *   T0           first superstep length to try, > 0
+ *   tol          error tolerance of the estimate, > 0
+ *   max_attempts bound on supersteps tried (accepted + rejected); exceeding
+ *                it returns FRKC2_ETIMEOUT with w at the last accepted step
+ *   ws, ws_bytes frkc2_workspace_bytes(g, 0, FRKC2_WS_ADAPT) bytes, 16-byte aligned
+ *   trace        host array of 5 * trace_cap doubles or NULL: per attempt
+ *                (t, T, s, err, accepted 1/0), the first trace_cap attempts
+ *   stats        host or NULL
+ * Synchronises st once per attempt (the accept decision is taken on the
+ * host). The stages run one per HBM pass (the embedded solution adds 16 B per
+ * point and stage). Results are identical, bit for bit, to the same
+ * procedure evaluated on the CPU in the library's arithmetic order. Errors:
+ * FRKC2_EINVAL (arguments, checked before any HIP call), FRKC2_ENOMEM
+ * (workspace), FRKC2_ENONFINITE (non-finite error estimate), FRKC2_ETIMEOUT,
+ * FRKC2_EHIP.
+ */
+typedef struct {
+    double t;           /* time reached (t_span on success) */
+    double T_next;      /* length the controller proposes for the next superstep */
+    double err_last;    /* error estimate of the last accepted superstep */
+    long long stages;   /* stages (f evaluations) over all attempts */
+    int attempts, accepted, rejected;
+    int s_last;         /* stage count of the last attempt */
+} frkc2_adapt_stats;
+int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, double t_span, double T0,
+                    double tol, double nu, int max_attempts, void *ws, size_t ws_bytes,
+                    hipStream_t st, double *trace, int trace_cap, frkc2_adapt_stats *stats);
 
 /*
  * frkc2_autotune -- pick the launch configuration of frkc2_step's passes for

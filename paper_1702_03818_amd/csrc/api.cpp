@@ -123,6 +123,23 @@ StepLayout step_layout(long long N)
     return L;
 }
 
+struct AdaptLayout {
+    size_t bufA, bufB, embA, embB, scratch, total;
+};
+
+AdaptLayout adapt_layout(long long N)
+{
+    AdaptLayout L;
+    const size_t cbytes = align_up((size_t)N * 16), rbytes = align_up((size_t)N * 8);
+    L.bufA = 0;
+    L.bufB = cbytes;
+    L.embA = 2 * cbytes;
+    L.embB = L.embA + rbytes;
+    L.scratch = L.embB + rbytes;
+    L.total = L.scratch + kScratch;
+    return L;
+}
+
 struct AdjLayout {
     size_t store, lamA, lamB, gD, scratch, total;
 };
@@ -346,6 +363,7 @@ extern "C" size_t frkc2_workspace_bytes(const frkc2_grid *g, int s, int flags)
         if (s < 2 || s > kMaxStages || (s % 2)) return 0;
         return adj_layout(kg.npts(), s).total;
     }
+    if (flags == FRKC2_WS_ADAPT) return adapt_layout(kg.npts()).total;
     return step_layout(kg.npts()).total;
 }
 
@@ -677,6 +695,183 @@ extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const 
     }
     if (vc && grad_logD) HIP_TRY(launch_grad_finish(N, D, gD, grad_logD, st), "adjoint: gradient");
     return crc;
+}
+
+
+// ---- error-controlled integration (Sec. 3) ----
+
+namespace {
+
+constexpr double kSafe = 0.8;        // safety factor of the paper's controller
+constexpr double kFacMax = 5.0;      // growth cap (the paper gives none)
+constexpr double kErrFloor = 1e-12;  // error estimates below this count as this
+
+// Smallest even s with betabar(s) >= x, searched from the estimate
+// betabar ~ 0.33 s^2 (s = 2 ceil(sqrt(x / 1.32))) down and up in steps of 2.
+int choose_s(double x, double nu, double *bbar)
+{
+    auto bb = [&](int s, double *v) -> int {
+        const double *re, *im;
+        frkc2_coeff_info info;
+        const int rc = coeffs_cached(s, nu, &re, &im, &info);
+        if (rc < 0) return rc;
+        *v = info.beta_bar;
+        return 0;
+    };
+    const double r = std::sqrt(x / 1.32);
+    int m = (r < kMaxStages / 2) ? (int)std::ceil(r) : kMaxStages / 2;
+    if (m < 1) m = 1;
+    int s = 2 * m;
+    double v = 0.0;
+    while (s > 2) {
+        const int rc = bb(s - 2, &v);
+        if (rc < 0) return rc;
+        if (!(v >= x)) break;
+        s -= 2;
+    }
+    while (true) {
+        const int rc = bb(s, &v);
+        if (rc < 0) return rc;
+        if (v >= x || s >= kMaxStages) break;
+        s += 2;
+    }
+    *bbar = v;
+    return s;
+}
+
+}  // namespace
+
+extern "C" int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, double t_span,
+                               double T0, double tol, double nu, int max_attempts, void *ws,
+                               size_t ws_bytes, hipStream_t st, double *trace, int trace_cap,
+                               frkc2_adapt_stats *stats)
+{
+    KGrid kg;
+    if (!make_kgrid(g, kg)) return FRKC2_EINVAL;
+    if (!w || (kg.op == FRKC2_OP_VARCOEF && !D)) {
+        set_error("w (and D for VARCOEF) must be non-NULL");
+        return FRKC2_EINVAL;
+    }
+    if (!(t_span > 0.0) || !std::isfinite(t_span) || !(T0 > 0.0) || !std::isfinite(T0) ||
+        !(tol > 0.0) || !std::isfinite(tol)) {
+        set_error("t_span, T0 and tol must be positive and finite");
+        return FRKC2_EINVAL;
+    }
+    if (!(nu >= 0.0 && nu < 1.0)) {
+        set_error("nu must lie in [0, 1) (got %g)", nu);
+        return FRKC2_EINVAL;
+    }
+    if (max_attempts < 1 || trace_cap < 0 || (trace_cap > 0 && !trace)) {
+        set_error("max_attempts must be >= 1 and trace non-NULL when trace_cap > 0");
+        return FRKC2_EINVAL;
+    }
+    const long long N = kg.npts();
+    const AdaptLayout L = adapt_layout(N);
+    if (!ws || ws_bytes < L.total || !aligned16(ws)) {
+        set_error("workspace needs %zu bytes (got %zu), 16-byte aligned", L.total, ws_bytes);
+        return FRKC2_ENOMEM;
+    }
+    char *base = static_cast<char *>(ws);
+    double *buf[2] = {reinterpret_cast<double *>(base + L.bufA),
+                      reinterpret_cast<double *>(base + L.bufB)};
+    double *emb[2] = {reinterpret_cast<double *>(base + L.embA),
+                      reinterpret_cast<double *>(base + L.embB)};
+    double *partials = reinterpret_cast<double *>(base + L.scratch);
+
+    double t = 0.0, T = T0, T_prev = 0.0, err_prev = 0.0, err_last = 0.0, rho = 0.0;
+    bool have_prev = false, need_rho = true;
+    int attempts = 0, accepted = 0, rejected = 0, s_last = 0;
+    long long stages = 0;
+    while (t < t_span) {
+        if (attempts >= max_attempts) {
+            set_error("no end after %d attempts (t = %g of %g)", attempts, t, t_span);
+            return FRKC2_ETIMEOUT;
+        }
+        if (need_rho) {
+            const int rc = rho_bound_impl(kg, w, D, partials, &rho, st);
+            if (rc < 0) return rc;
+            need_rho = (kg.op == FRKC2_OP_POROUS2);
+        }
+        double Tn = std::min(T, t_span - t);
+        const double x = Tn * rho;
+        double bbar = 0.0;
+        const int s = choose_s(x, nu, &bbar);
+        if (s < 0) return s;
+        if (bbar < x) Tn = 0.99 * bbar / rho;
+        const double *are, *aim;
+        frkc2_coeff_info info;
+        int crc = coeffs_cached(s, nu, &are, &aim, &info);
+        if (crc < 0) return crc;
+        // embedded superstep: one stage per pass, complex W and real What
+        for (int l = 0; l < s; ++l) {
+            PassArgs pa{};
+            pa.k = 1;
+            pa.D = D;
+            if (l == 0) pa.in_re = w;
+            else {
+                pa.in_c = buf[(l - 1) & 1];
+                pa.emb_in = emb[(l - 1) & 1];
+            }
+            pa.out_c = buf[l & 1];
+            pa.emb_out = emb[l & 1];
+            pa.tr[0] = Tn * are[l];
+            pa.ti[0] = Tn * aim[l];
+            HIP_TRY(launch_pass(kg, pa, 1, st), "embedded stage launch");
+        }
+        const double *WL = buf[(s - 1) & 1], *EL = emb[(s - 1) & 1];
+        HIP_TRY(launch_err_max(WL, EL, N, tol, partials, st), "error estimate launch");
+        double err = 0.0;
+        HIP_TRY(hipMemcpyAsync(&err, partials + kReduceBlocks, sizeof(double),
+                               hipMemcpyDeviceToHost, st),
+                "error estimate copy");
+        HIP_TRY(hipStreamSynchronize(st), "error estimate");
+        stages += s;
+        s_last = s;
+        if (trace && attempts < trace_cap) {
+            double *r = trace + 5 * (size_t)attempts;
+            r[0] = t;
+            r[1] = Tn;
+            r[2] = s;
+            r[3] = err;
+            r[4] = (err > 1.0) ? 0.0 : 1.0;
+        }
+        ++attempts;
+        if (!std::isfinite(err)) {
+            set_error("non-finite error estimate at t = %g (T = %g, s = %d)", t, Tn, s);
+            return FRKC2_ENONFINITE;
+        }
+        if (err > 1.0) {
+            ++rejected;
+            T = Tn * (kSafe / std::sqrt(err));
+            have_prev = false;
+            continue;
+        }
+        HIP_TRY(launch_take_real(WL, w, N, st), "accept launch");
+        ++accepted;
+        t = t + Tn;
+        err_last = err;
+        const double e = std::max(err, kErrFloor);
+        double fac = kSafe / std::sqrt(e);
+        if (have_prev) fac = fac * (Tn / T_prev) * std::sqrt(err_prev / e);
+        fac = std::min(fac, kFacMax);
+        T_prev = Tn;
+        err_prev = e;
+        have_prev = true;
+        T = Tn * fac;
+        if (kg.op == FRKC2_OP_POROUS2) need_rho = true;
+    }
+    HIP_TRY(hipStreamSynchronize(st), "integrate");
+    if (stats) {
+        stats->t = t;
+        stats->T_next = T;
+        stats->err_last = err_last;
+        stats->stages = stages;
+        stats->attempts = attempts;
+        stats->accepted = accepted;
+        stats->rejected = rejected;
+        stats->s_last = s_last;
+    }
+    return FRKC2_OK;
 }
 
 extern "C" int frkc2_reduce(int op, const double *x, const double *y, size_t n, double *result,

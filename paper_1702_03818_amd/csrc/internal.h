@@ -41,6 +41,8 @@ struct PassArgs {
     double ti[kMaxTBlock];
     int k;                      // stages in this pass
     int zchunk;                 // z planes per workgroup (0: automatic)
+    const double *emb_in;       // embedded first-order solution in (not the first stage)
+    double *emb_out;            // ... and out; non-null selects the embedded variant (k = 1)
 };
 
 // Launchers (stage.hip). Return hipError_t as int.
@@ -64,6 +66,10 @@ constexpr int kReduceBlocks = 512;
 int launch_reduce(int op, const double *x, const double *y, long long n, double *partials,
                   hipStream_t st);
 int launch_rho(const KGrid &g, const double *w, const double *D, double *partials, hipStream_t st);
+// Embedded-pair error estimate: max over points into partials[kReduceBlocks].
+int launch_err_max(const double *Wc, const double *E, long long n, double tol, double *partials,
+                   hipStream_t st);
+int launch_take_real(const double *Wc, double *w, long long n, hipStream_t st);
 
 // Adjoint (adjoint.hip).
 struct AdjArgs {

@@ -15,6 +15,8 @@ struct PlaneArgs {
     double *out_re;
     double2 *out_c;
     const double *D;
+    const double *emb_in;       // embedded first-order solution in (EMB, not first stage)
+    double *emb_out;            // ... and out (EMB)
     int nx, ny, nz;
     int zchunk, ntx, nty;
     double inv_h2, d_const, tr, ti;
@@ -42,8 +44,12 @@ struct TileShape {
 };
 
 // One tile (bx, by) of BX x BY columns over the z planes of chunk bz; sWp and
-// sDp are the tile's LDS (TileShape::LDS_W double2, ::LDS_D doubles).
-template <int OP, int BC, int NDIM, int BX, int BY, bool IN_REAL, bool OUT_REAL>
+// sDp are the tile's LDS (TileShape::LDS_W double2, ::LDS_D doubles). With
+// EMB the tile also advances the embedded first-order solution of the error
+// estimate (O'Sullivan, arXiv:1702.03818, Sec. 3): What + Re(tau) Re f(W),
+// evaluated as fma(tr, f_r, What); a first stage (IN_REAL) starts it from the
+// real input.
+template <int OP, int BC, int NDIM, int BX, int BY, bool IN_REAL, bool OUT_REAL, bool EMB = false>
 __device__ __forceinline__ void plane_tile(const PlaneArgs &a, int bx, int by, int bz,
                                            double2 *sWp, double *sDp)
 {
@@ -127,6 +133,9 @@ __device__ __forceinline__ void plane_tile(const PlaneArgs &a, int bx, int by, i
         const int z = zb + u;
         if (z >= z1) break;
         Wr[(u + 2) & 3] = keep(Wr[(u + 2) & 3], own_out || zout(z + 1));
+        const long long iz = x + (long long)a.nx * (y + (long long)a.ny * z);
+        double eh = 0.0;
+        if (EMB && !IN_REAL && active) eh = a.emb_in[iz];   // issued before the barrier
         const double2 Wm = Wr[u & 3];
         const double2 Wc = Wr[(u + 1) & 3];
         const double2 Wp = Wr[(u + 2) & 3];
@@ -169,9 +178,13 @@ __device__ __forceinline__ void plane_tile(const PlaneArgs &a, int bx, int by, i
                 face<OP>(acc_r, acc_i, c, Wp, Dc, Dp, false, qr_c, qi_c, a.d_const);
             }
             const double2 nv = euler(c, acc_r, acc_i, a.inv_h2, a.tr, a.ti);
-            const long long i = x + (long long)a.nx * (y + (long long)a.ny * z);
+            const long long i = iz;
             if (OUT_REAL) a.out_re[i] = nv.x;
             else a.out_c[i] = nv;
+            if (EMB) {
+                const double fr = acc_r * a.inv_h2;
+                a.emb_out[i] = fma(a.tr, fr, IN_REAL ? c.x : eh);
+            }
         }
         const int zq = min(z + 3, z1);   // plane z1 is the last one used (z+ of z1-1)
         Wr[u & 3] = LW(x, y, zq);        // into the slot of plane z-1

@@ -157,6 +157,38 @@ int launch_rho_bc(const KGrid &g, const double *w, const double *D, double *part
     return launch_rho_t<OP, FRKC2_BC_DIRICHLET0>(g, w, D, partials, st);
 }
 
+// Scaled error of the embedded pair (O'Sullivan, arXiv:1702.03818, Sec. 3):
+// per point |W - What| / (tol (1 + max(|W|, |What|))) with the complex
+// modulus sqrt(re*re + im*im), then the maximum over points (exact in any
+// order). A NaN counts as infinity so that it cannot be lost in the maximum.
+__global__ __launch_bounds__(kThreads) void err_pass1(const double2 *W, const double *E,
+                                                      long long n, double tol, double *partials)
+{
+    double acc = 0.0;
+    for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kThreads) {
+        const double2 w = W[i];
+        const double e = E[i];
+        const double dr = w.x - e;
+        const double num = sqrt(dr * dr + w.y * w.y);
+        const double mw = sqrt(w.x * w.x + w.y * w.y);
+        const double ae = fabs(e);
+        const double den = tol * (1.0 + (mw > ae ? mw : ae));
+        double q = num / den;
+        q = (q == q) ? q : __builtin_inf();
+        acc = combine<R_MAX>(acc, q);
+    }
+    const double r = block_reduce<R_MAX>(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kThreads) void take_real(const double2 *W, double *w, long long n)
+{
+    for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kThreads)
+        w[i] = W[i].x;
+}
+
 }  // namespace
 
 int launch_reduce(int op, const double *x, const double *y, long long n, double *partials,
@@ -177,6 +209,30 @@ int launch_rho(const KGrid &g, const double *w, const double *D, double *partial
     if (g.op == FRKC2_OP_LAPLACE) return launch_rho_bc<FRKC2_OP_LAPLACE>(g, w, D, partials, st);
     if (g.op == FRKC2_OP_VARCOEF) return launch_rho_bc<FRKC2_OP_VARCOEF>(g, w, D, partials, st);
     return launch_rho_bc<FRKC2_OP_POROUS2>(g, w, D, partials, st);
+}
+
+}  // namespace frkc2
+
+namespace frkc2 {
+
+int launch_err_max(const double *Wc, const double *E, long long n, double tol, double *partials,
+                   hipStream_t st)
+{
+    hipLaunchKernelGGL(err_pass1, dim3(kReduceBlocks), dim3(kThreads), 0, st,
+                       reinterpret_cast<const double2 *>(Wc), E, n, tol, partials);
+    hipLaunchKernelGGL(reduce_pass2<R_MAX>, dim3(1), dim3(kThreads), 0, st, partials,
+                       kReduceBlocks);
+    return (int)hipGetLastError();
+}
+
+int launch_take_real(const double *Wc, double *w, long long n, hipStream_t st)
+{
+    long long nb = (n + kThreads - 1) / kThreads;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(take_real, dim3((unsigned)nb), dim3(kThreads), 0, st,
+                       reinterpret_cast<const double2 *>(Wc), w, n);
+    return (int)hipGetLastError();
 }
 
 }  // namespace frkc2

@@ -35,7 +35,7 @@ namespace {
 
 using namespace dev;
 
-template <int OP, int BC, int NDIM, int BX, int BY, bool IN_REAL, bool OUT_REAL>
+template <int OP, int BC, int NDIM, int BX, int BY, bool IN_REAL, bool OUT_REAL, bool EMB = false>
 __global__ __launch_bounds__(BX *BY) void plane_stage(PlaneArgs a)
 {
     using S = TileShape<OP, BC, NDIM, BX, BY>;
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(BX *BY) void plane_stage(PlaneArgs a)
     lb /= a.ntx;
     const int by = lb % a.nty;
     const int bz = lb / a.nty;
-    plane_tile<OP, BC, NDIM, BX, BY, IN_REAL, OUT_REAL>(a, bx, by, bz, sW, sD);
+    plane_tile<OP, BC, NDIM, BX, BY, IN_REAL, OUT_REAL, EMB>(a, bx, by, bz, sW, sD);
 }
 
 // Whole 1D grid resident in LDS: every stage of every superstep in one
@@ -190,6 +190,17 @@ int launch_plane_t(const PlaneArgs &pa0, bool in_real, bool out_real, hipStream_
     const long long nblk = (long long)pa.ntx * pa.nty * nzc;
     if (nblk > 0x7fffffffLL) return (int)hipErrorInvalidValue;
     dim3 grid((unsigned)nblk), block(BX * BY);
+    if (pa.emb_out) {
+        // embedded solution: the stage output stays complex
+        if (out_real) return (int)hipErrorInvalidValue;
+        if (in_real)
+            hipLaunchKernelGGL((plane_stage<OP, BC, NDIM, BX, BY, true, false, true>), grid, block, 0,
+                               st, pa);
+        else
+            hipLaunchKernelGGL((plane_stage<OP, BC, NDIM, BX, BY, false, false, true>), grid, block,
+                               0, st, pa);
+        return (int)hipGetLastError();
+    }
     if (in_real && out_real)
         hipLaunchKernelGGL((plane_stage<OP, BC, NDIM, BX, BY, true, true>), grid, block, 0, st, pa);
     else if (in_real)
@@ -234,6 +245,8 @@ int launch_pass(const KGrid &g, const PassArgs &a, int /*tblock_hint*/, hipStrea
     pa.inv_h2 = g.inv_h2;
     pa.d_const = g.d_const;
     pa.zchunk = a.zchunk;
+    pa.emb_in = a.emb_in;
+    pa.emb_out = a.emb_out;
     pa.tr = a.tr[0];
     pa.ti = a.ti[0];
     const bool ir = a.in_re != nullptr, orl = a.out_re != nullptr;

@@ -25,6 +25,7 @@ STATUS_NAMES = {0: "OK", 1: "WQBOUND", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP",
                 -4: "EUNSTABLE", -5: "ENONFINITE", -6: "ETIMEOUT"}
 WS_STEP = 0
 WS_ADJOINT = 1
+WS_ADAPT = 2
 RED_SUMSQ, RED_SUM, RED_MAXSQ, RED_SUMSQDIFF, RED_DOT = 0, 1, 2, 3, 4
 OPT_TBLOCK = 1
 OPT_XCD_REMAP = 2
@@ -54,6 +55,13 @@ class CoeffInfo(ctypes.Structure):
 class StepStats(ctypes.Structure):
     _fields_ = [("T_last", ctypes.c_double), ("rho_last", ctypes.c_double),
                 ("im_ratio", ctypes.c_double), ("supersteps", ctypes.c_int)]
+
+
+class AdaptStats(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("T_next", ctypes.c_double),
+                ("err_last", ctypes.c_double), ("stages", ctypes.c_longlong),
+                ("attempts", ctypes.c_int), ("accepted", ctypes.c_int),
+                ("rejected", ctypes.c_int), ("s_last", ctypes.c_int)]
 
 
 class TuneResult(ctypes.Structure):
@@ -86,6 +94,10 @@ _SIGS = {
     "frkc2_batched_release": (ctypes.c_int, [_VP]),
     "frkc2_reduce": (ctypes.c_int, [ctypes.c_int, _VP, _VP, ctypes.c_size_t, _DP, _VP,
                                     ctypes.c_size_t, _VP]),
+    "frkc2_integrate": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_int, _VP, ctypes.c_size_t, _VP, _DP, ctypes.c_int,
+                                       ctypes.POINTER(AdaptStats)]),
     "frkc2_autotune": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_int, _VP, ctypes.c_size_t, _VP,
                                       ctypes.POINTER(TuneResult)]),
@@ -220,6 +232,27 @@ def frkc2_step(grid, w, D=None, T=0.0, cfl=0.0, s=16, nu=0.01, nsteps=1, stream=
     if stats:
         return {f: getattr(st, f) for f, _ in StepStats._fields_}
     return rc
+
+
+def frkc2_integrate(grid, w, D=None, t_span=1.0, T0=1e-6, tol=1e-4, nu=0.01, max_attempts=10000,
+                    trace_cap=0, stream=None, ws=None):
+    """Error-controlled integration of w over t_span (in place). Returns (stats dict, trace),
+    trace an array of (t, T, s, err, accepted) rows for the first trace_cap attempts."""
+    lib = load()
+    g = make_grid(grid)
+    need = lib.frkc2_workspace_bytes(ctypes.byref(g), 0, WS_ADAPT)
+    if need == 0:
+        _check(-1)
+    buf = ws if ws is not None else workspace(need, key="adapt")
+    tr = np.zeros((max(int(trace_cap), 0), 5), dtype=np.float64)
+    st = AdaptStats()
+    _check(lib.frkc2_integrate(ctypes.byref(g), _ptr(w), _ptr(D), float(t_span), float(T0),
+                               float(tol), float(nu), int(max_attempts),
+                               ctypes.c_void_p(buf.data_ptr()), buf.numel(), _stream_ptr(stream),
+                               tr.ctypes.data_as(_DP) if trace_cap > 0 else None, int(trace_cap),
+                               ctypes.byref(st)))
+    stats = {f: getattr(st, f) for f, _ in AdaptStats._fields_}
+    return stats, tr[:min(stats["attempts"], tr.shape[0])]
 
 
 def frkc2_autotune(grid, w, D=None, s=16, nu=0.01, reps=2, stream=None, ws=None):

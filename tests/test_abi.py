@@ -166,3 +166,30 @@ def test_autotune_invalid_grid():
 
 def test_clear_tuned_option():
     assert F.frkc2_set_option(F.OPT_CLEAR_TUNED, 0) == 0
+
+
+def _integrate(g, w=1, D=1, t_span=1e-3, T0=1e-5, tol=1e-4, nu=0.01, max_attempts=10, ws=1,
+               ws_bytes=1 << 40, trace_cap=0):
+    lib = F.load()
+    p = lambda v: ctypes.c_void_p(4096 * 16) if v else None  # never dereferenced: validation fails first
+    st = F.AdaptStats()
+    return lib.frkc2_integrate(ctypes.byref(g), p(w), p(D), t_span, T0, tol, nu, max_attempts, p(ws),
+                               ws_bytes, None, None, trace_cap, ctypes.byref(st))
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(w=0), -1), (dict(D=0), -1), (dict(t_span=0.0), -1), (dict(t_span=float("inf")), -1),
+    (dict(T0=-1.0), -1), (dict(tol=0.0), -1), (dict(nu=1.0), -1), (dict(max_attempts=0), -1),
+    (dict(trace_cap=3), -1), (dict(ws=0), -2), (dict(ws_bytes=1024), -2),
+])
+def test_integrate_validation(kw, expect):
+    assert _integrate(grid(), **kw) == expect
+    assert F.frkc2_last_error()
+
+
+def test_adapt_workspace_bytes():
+    lib = F.load()
+    g = grid(n=(64, 32, 16))
+    N = 64 * 32 * 16
+    b = lib.frkc2_workspace_bytes(ctypes.byref(g), 0, F.WS_ADAPT)
+    assert 48 * N <= b < 48 * N + (1 << 20)

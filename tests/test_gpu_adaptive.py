@@ -1,0 +1,67 @@
+"""GPU parity of the error-controlled integration (Sec. 3): every attempt (start time, T, s,
+error estimate, accept flag), the proposed next T and the final state equal the oracle's
+bit for bit."""
+import numpy as np
+import pytest
+
+from oracle import adaptive, stage
+from paper_1702_03818_amd import frkc2 as F
+from paper_1702_03818_amd import workloads as wl
+
+from test_gpu_parity import dev, host, problem
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def run_both(p, t_span, T0, tol):
+    w_ref, trace_ref, T_ref = adaptive.integrate(p, t_span, T0, tol)
+    w = dev(p.w0)
+    D = dev(p.D) if p.D is not None else None
+    st, trace = F.frkc2_integrate(p, w, D, t_span=t_span, T0=T0, tol=tol,
+                                  trace_cap=len(trace_ref) + 8)
+    torch.cuda.synchronize()
+    ref = np.array(trace_ref, dtype=np.float64)
+    assert st["attempts"] == len(trace_ref)
+    assert st["accepted"] == int(ref[:, 4].sum())
+    assert np.array_equal(trace, ref), "first difference at attempt %d" % int(
+        np.argmax(np.any(trace != ref, axis=1)))
+    assert st["T_next"] == T_ref
+    assert st["t"] == t_span
+    got = host(w)
+    assert np.array_equal(got, w_ref), "%d values differ" % int(np.sum(got != w_ref))
+    return st, ref
+
+
+@pytest.mark.parametrize("kind,n", [("3d-var-dir", (70, 37, 21)), ("2d-por-per", (64, 64, 1)),
+                                    ("2d-var-dir", (300, 37, 1)), ("1d-lap-per", (1024, 1, 1)),
+                                    ("3d-lap-per", (65, 5, 12)), ("3d-var-per", (67, 6, 10))])
+def test_integrate_matches_oracle(kind, n):
+    p = problem(kind, n)
+    rho = stage.rho_bound(p, p.w0)
+    st, ref = run_both(p, 1500.0 / rho, 800.0 / rho, 1e-3)
+    assert (ref[:, 4] == 0).any(), "the first, long attempt should be rejected"
+
+
+def test_integrate_heat1d_many_steps():
+    p = wl.heat1d()
+    st, ref = run_both(p, 2e-3, 1e-5, 1e-5)
+    assert st["accepted"] > 200
+
+
+def test_integrate_zero_state():
+    """All-zero state: the error estimate is 0 and the controller grows T by its cap."""
+    p = problem("2d-var-dir", (64, 9, 1))
+    p.w0 = np.zeros_like(p.w0)
+    rho = stage.rho_bound(p, p.w0)
+    st, ref = run_both(p, 100.0 / rho, 1.0 / rho, 1e-3)
+    assert (ref[:, 3] == 0).all()
