@@ -277,6 +277,31 @@ def batched_leg(F, wl, torch, reps=3):
             "speedup_vs_plain": t_p / t_b}
 
 
+def adaptive_leg(F, wl, torch, prob, D, rho, info):
+    """Error-controlled integration on the 256^3 workload: the same span as one benchmark
+    step (10 supersteps at T = 0.9 betabar(100) / rho), tol = 1e-3, first trial T = that T.
+    Updates/s counts the stages of every attempt (rejected ones included)."""
+    T = CFL * info["beta_bar"] / rho
+    span = SUPERSTEPS * T
+    w0 = torch.tensor(prob.w0.reshape(-1), dtype=torch.float64, device="cuda")
+    w = w0.clone()
+    F.frkc2_integrate(prob, w, D, t_span=span, T0=T, tol=1e-3)      # warm-up, coefficients
+    torch.cuda.synchronize()
+    w.copy_(w0)
+    t0 = time.perf_counter()
+    st, trace = F.frkc2_integrate(prob, w, D, t_span=span, T0=T, tol=1e-3, trace_cap=4096)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = prob.npoints
+    log("adaptive: %d attempts (%d rejected), %d stages, %.1f ms" % (
+        st["attempts"], st["rejected"], st["stages"], dt * 1e3))
+    return {"t_span": span, "tol": 1e-3, "attempts": st["attempts"], "accepted": st["accepted"],
+            "rejected": st["rejected"], "stages": st["stages"],
+            "s_used": sorted(set(int(v) for v in trace[:, 2])), "wall_ms": dt * 1e3,
+            "value": n * st["stages"] / dt, "unit": "grid-point-stage updates/s (all attempts)",
+            "fixed_step_stages": S_STAGES * SUPERSTEPS}
+
+
 def adjoint_leg(F, wl, torch, reps=3):
     """3D 128^3 variable D, s = 64, 8 supersteps, J = sum (w - target)^2: forward alone
     and forward + adjoint through the autograd function."""
@@ -335,6 +360,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batched leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--no-adaptive", action="store_true", help="skip the error-control leg")
     ap.add_argument("--tblock", type=int, default=0, choices=(0, 1, 2, 3),
                     help="stages fused per HBM pass in the timed run (0: autotune)")
     ap.add_argument("--tile", type=int, default=0, help="tile shape with --tblock (0: automatic)")
@@ -506,6 +532,7 @@ def main():
                         "im_ratio": last[0]["im_ratio"], "l2_norm": float(np.sqrt(last[1])),
                         "q_realised": info["q_realised"], "n_shrink": info["n_shrink"]},
     }
+    out["adaptive"] = None if args.no_adaptive else adaptive_leg(F, wl, torch, prob, D, rho, info)
     del w0, w, D
     torch.cuda.empty_cache()
     out["batched"] = None if args.no_batched else batched_leg(F, wl, torch)

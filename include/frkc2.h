@@ -234,8 +234,9 @@ int frkc2_reduce(int op, const double *x, const double *y, size_t n, double *res
  *                (t, T, s, err, accepted 1/0), the first trace_cap attempts
  *   stats        host or NULL
  * Synchronises st once per attempt (the accept decision is taken on the
- * host). The stages run one per HBM pass (the embedded solution adds 16 B per
- * point and stage). Results are identical, bit for bit, to the same
+ * host). 3D grids fuse stages per HBM pass as frkc2_step does (full-width
+ * tiles; the embedded solution adds 16 B per point and pass); other grids run
+ * one stage per pass. Results are identical, bit for bit, to the same
  * procedure evaluated on the CPU in the library's arithmetic order. Errors:
  * FRKC2_EINVAL (arguments, checked before any HIP call), FRKC2_ENOMEM
  * (workspace), FRKC2_ENONFINITE (non-finite error estimate), FRKC2_ETIMEOUT,

@@ -706,6 +706,48 @@ constexpr double kSafe = 0.8;        // safety factor of the paper's controller
 constexpr double kFacMax = 5.0;      // growth cap (the paper gives none)
 constexpr double kErrFloor = 1e-12;  // error estimates below this count as this
 
+// One superstep from the real state w that also carries the embedded
+// first-order solution; W^L (complex) and What^L are left in the workspace.
+// 3D grids fuse cfg.k stages per pass with the full-width tiles, other grids
+// and tile shapes run one stage per pass.
+int run_superstep_emb(const KGrid &kg, const PassCfg &cfg, const double *w, const double *D,
+                      double Tn, const double *are, const double *aim, int s,
+                      double *const buf[2], double *const emb[2], const double **WL,
+                      const double **EL, hipStream_t st)
+{
+    const bool fused = kg.ndim == 3 && cfg.tile == 3 && cfg.k >= 2 && tblock_supported(kg, cfg.k);
+    const int k = fused ? cfg.k : 1;
+    int l = 0, pass = 0;
+    const double *in = nullptr, *ein = nullptr;
+    while (l < s) {
+        const int kk = (k >= 2 && s - l >= k) ? k : 1;
+        PassArgs pa{};
+        pa.k = kk;
+        pa.zchunk = cfg.zchunk;
+        pa.D = D;
+        if (l == 0) pa.in_re = w;
+        else {
+            pa.in_c = in;
+            pa.emb_in = ein;
+        }
+        pa.out_c = buf[pass & 1];
+        pa.emb_out = emb[pass & 1];
+        for (int i = 0; i < kk; ++i) {
+            pa.tr[i] = Tn * are[l + i];
+            pa.ti[i] = Tn * aim[l + i];
+        }
+        const int rc = (kk == 1) ? launch_pass(kg, pa, 1, st) : launch_tb3d(kg, pa, st);
+        if (rc != 0) return rc;
+        in = buf[pass & 1];
+        ein = emb[pass & 1];
+        l += kk;
+        ++pass;
+    }
+    *WL = in;
+    *EL = ein;
+    return 0;
+}
+
 // Smallest even s with betabar(s) >= x, searched from the estimate
 // betabar ~ 0.33 s^2 (s = 2 ceil(sqrt(x / 1.32))) down and up in steps of 2.
 int choose_s(double x, double nu, double *bbar)
@@ -778,6 +820,7 @@ extern "C" int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, 
                       reinterpret_cast<double *>(base + L.embB)};
     double *partials = reinterpret_cast<double *>(base + L.scratch);
 
+    const PassCfg cfg = pass_cfg(kg);
     double t = 0.0, T = T0, T_prev = 0.0, err_prev = 0.0, err_last = 0.0, rho = 0.0;
     bool have_prev = false, need_rho = true;
     int attempts = 0, accepted = 0, rejected = 0, s_last = 0;
@@ -802,23 +845,9 @@ extern "C" int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, 
         frkc2_coeff_info info;
         int crc = coeffs_cached(s, nu, &are, &aim, &info);
         if (crc < 0) return crc;
-        // embedded superstep: one stage per pass, complex W and real What
-        for (int l = 0; l < s; ++l) {
-            PassArgs pa{};
-            pa.k = 1;
-            pa.D = D;
-            if (l == 0) pa.in_re = w;
-            else {
-                pa.in_c = buf[(l - 1) & 1];
-                pa.emb_in = emb[(l - 1) & 1];
-            }
-            pa.out_c = buf[l & 1];
-            pa.emb_out = emb[l & 1];
-            pa.tr[0] = Tn * are[l];
-            pa.ti[0] = Tn * aim[l];
-            HIP_TRY(launch_pass(kg, pa, 1, st), "embedded stage launch");
-        }
-        const double *WL = buf[(s - 1) & 1], *EL = emb[(s - 1) & 1];
+        const double *WL = nullptr, *EL = nullptr;
+        HIP_TRY(run_superstep_emb(kg, cfg, w, D, Tn, are, aim, s, buf, emb, &WL, &EL, st),
+                "embedded superstep launch");
         HIP_TRY(launch_err_max(WL, EL, N, tol, partials, st), "error estimate launch");
         double err = 0.0;
         HIP_TRY(hipMemcpyAsync(&err, partials + kReduceBlocks, sizeof(double),

@@ -40,6 +40,8 @@ struct Tb3Args {
     double *out_re;
     double2 *out_c;
     const double *D;
+    const double *emb_in;       // embedded first-order solution (EMB; first pass: real input)
+    double *emb_out;
     int nx, ny, nz;
     int zchunk, ntx, nty;
     double inv_h2, d_const;
@@ -64,7 +66,10 @@ __device__ __forceinline__ double2 keep3(double2 v, bool ghost)
     return v;
 }
 
-template <int OP, int BC, int K, bool IN_REAL, bool OUT_REAL>
+// EMB: also advance the embedded first-order solution of the error estimate
+// (Sec. 3): What^m = fma(tr_m, Re f(W^{m-1}), What^{m-1}) at every level, a
+// pointwise recursion carried in registers next to the level windows.
+template <int OP, int BC, int K, bool IN_REAL, bool OUT_REAL, bool EMB = false>
 __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
 {
     using S = Tb3Shape<K>;
@@ -121,6 +126,11 @@ __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
         const long long i = bc_index_nb<BC>(dm, x, y, gz, g);
         return VC ? a.D[i] : 0.0;
     };
+    auto LE = [&](int gz) {
+        bool g;
+        const long long i = bc_index_nb<BC>(dm, x, y, gz, g);
+        return (EMB && !IN_REAL) ? a.emb_in[i] : 0.0;
+    };
     auto pout = [&](int p) { return dir && (p < 0 || p >= a.nz); };
     auto dslot = [](int p) { return ((p % ND) + ND) % ND; };
 
@@ -132,18 +142,25 @@ __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
     const int t_begin = z0 - K, t_end = z1 + K;     // level 0 planes z0-K .. z1+K-1
     double2 L0[NR];
     double D0[NR];
+    constexpr bool ER = EMB && !IN_REAL;            // embedded input read from memory
+    double E0[ER ? NR : 1];
+    double ehc[K - 1], ehn[K - 1];                  // What of levels 1..K-1: last step, this step
     double2 wm[K - 1], wc[K - 1], wp[K - 1];
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
         L0[q] = make_double2(0.0, 0.0);
         D0[q] = 0.0;
+        if (ER) E0[q] = 0.0;
     }
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
         const int tq = min(t_begin + q, t_end - 1);
         L0[q] = LW(tq);
         D0[q] = LD(tq);
+        if (ER) E0[q] = LE(tq);
     }
+#pragma unroll
+    for (int m = 0; m + 1 < K; ++m) ehc[m] = ehn[m] = 0.0;
 #pragma unroll
     for (int m = 0; m + 1 < K; ++m) wm[m] = wc[m] = wp[m] = make_double2(0.0, 0.0);
 
@@ -157,6 +174,7 @@ __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
             const int tn = min(t + PF, t_end - 1);  // nothing past the last plane is used
             L0[rs(PF)] = LW(tn);
             D0[rs(PF)] = LD(tn);
+            if (ER) E0[rs(PF)] = LE(tn);
         }
         L0[rs(0)] = keep3(L0[rs(0)], col_ghost || pout(t));
         const int rb = (t - 1) & 1, wb = t & 1;     // LDS buffers read / written at step t
@@ -196,9 +214,10 @@ __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
             }
             return n;
         };
-        // (For K = 3 the operands of two levels do not fit the registers of
-        // four wavefronts per SIMD: there each level reads its own.)
-        constexpr bool RA = (K <= 2);
+        // (For K = 3, or with the embedded solution, the operands of two levels
+        // do not fit the registers of four wavefronts per SIMD: there each
+        // level reads its own.)
+        constexpr bool RA = (K <= 2) && !EMB;
         Nb cur = read(1);
 #pragma unroll
         for (int m = 1; m <= K; ++m) {
@@ -233,14 +252,23 @@ __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
                 face<OP>(acc_r, acc_i, c, zp, dc, cur.dzp, false, qr_c, qi_c, a.d_const);
                 double2 v = euler(c, acc_r, acc_i, a.inv_h2, a.tr[m - 1], a.ti[m - 1]);
                 v = keep3(v, col_ghost || pout(p));
+                double eh = 0.0;
+                if (EMB) {
+                    // What^{m-1} at plane p: the input (level 1) or last step's level m-1
+                    const double base =
+                        (m == 1) ? (IN_REAL ? c.x : E0[ER ? rs(-1) : 0]) : ehc[m - 2];
+                    eh = fma(a.tr[m - 1], acc_r * a.inv_h2, base);
+                }
                 if (m < K) {
                     wm[m - 1] = wc[m - 1];
                     wc[m - 1] = wp[m - 1];
                     wp[m - 1] = v;
+                    if (EMB) ehn[m - 1] = eh;
                 } else if (out_col && p >= z0 && p < z1) {
                     const long long i = x + (long long)a.nx * (y + (long long)a.ny * p);
                     if (OUT_REAL) a.out_re[i] = v.x;
                     else a.out_c[i] = v;
+                    if (EMB) a.emb_out[i] = eh;
                 }
             }
             if (!RA && m < K) nxt = read(m + 1);
@@ -252,6 +280,10 @@ __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
         sL[wb][0][slot] = L0[rs(0)];
 #pragma unroll
         for (int m = 1; m < K; ++m) sL[wb][m][slot] = wp[m - 1];
+        if (EMB) {
+#pragma unroll
+            for (int m = 0; m + 1 < K; ++m) ehc[m] = ehn[m];
+        }
         if (VC) sD[dslot(t)][slot] = D0[rs(0)];
         __syncthreads();   // step t's planes are visible to step t+1, whose
                            // writes go to the other buffer
@@ -301,6 +333,14 @@ int launch3_k(const Tb3Args &a0, bool ir, bool orl, hipStream_t st)
     const long long nblk = tiles * ((a.nz + a.zchunk - 1) / a.zchunk);
     if (nblk > 0x7fffffffLL) return (int)hipErrorInvalidValue;
     dim3 grid((unsigned)nblk), block(1024);
+    if (a.emb_out) {
+        if (orl) return (int)hipErrorInvalidValue;
+        if (ir)
+            hipLaunchKernelGGL((tb3d_stage<OP, BC, K, true, false, true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((tb3d_stage<OP, BC, K, false, false, true>), grid, block, 0, st, a);
+        return (int)hipGetLastError();
+    }
     if (ir && orl)
         hipLaunchKernelGGL((tb3d_stage<OP, BC, K, true, true>), grid, block, 0, st, a);
     else if (ir)
@@ -344,6 +384,8 @@ int launch_tb3d(const KGrid &g, const PassArgs &p, hipStream_t st)
     a.inv_h2 = g.inv_h2;
     a.d_const = g.d_const;
     a.zchunk = p.zchunk;
+    a.emb_in = p.emb_in;
+    a.emb_out = p.emb_out;
     for (int i = 0; i < kMaxTBlock; ++i) {
         a.tr[i] = p.tr[i];
         a.ti[i] = p.ti[i];

@@ -65,3 +65,24 @@ def test_integrate_zero_state():
     rho = stage.rho_bound(p, p.w0)
     st, ref = run_both(p, 100.0 / rho, 1.0 / rho, 1e-3)
     assert (ref[:, 3] == 0).all()
+
+
+@pytest.mark.parametrize("k,tile,zchunk", [(1, 0, 0), (2, 4, 0), (3, 4, 0), (2, 4, 5), (3, 4, 7),
+                                          (2, 1, 0)])
+def test_integrate_launch_configurations(k, tile, zchunk):
+    """The embedded solution in fused 3D passes (K = 2, 3, chunk lengths) and one stage per
+    pass gives the same attempts and state."""
+    F.frkc2_set_option(F.OPT_TBLOCK, k)
+    F.frkc2_set_option(F.OPT_TILE, tile)
+    F.frkc2_set_option(F.OPT_ZCHUNK, zchunk)
+    try:
+        p = problem("3d-var-dir", (70, 37, 21))
+        rho = stage.rho_bound(p, p.w0)
+        run_both(p, 1500.0 / rho, 800.0 / rho, 1e-3)
+        p = problem("3d-lap-per", (65, 5, 12))
+        rho = stage.rho_bound(p, p.w0)
+        run_both(p, 1500.0 / rho, 800.0 / rho, 1e-3)
+    finally:
+        F.frkc2_set_option(F.OPT_TBLOCK, 0)
+        F.frkc2_set_option(F.OPT_TILE, 0)
+        F.frkc2_set_option(F.OPT_ZCHUNK, 0)

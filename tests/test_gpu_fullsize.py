@@ -146,3 +146,20 @@ def test_adjoint_128_superstep():
     check(lam_n.cpu().numpy(), ref_lam, "adjoint lambda 128^3")
     gg = g.cpu().numpy()
     assert np.linalg.norm(gg - ref_g) <= 1e-12 * np.linalg.norm(ref_g)
+
+
+def test_integrate_256(c2_reference):
+    """Error-controlled integration on the benchmark grid (fused embedded passes, default
+    configuration) over three superstep lengths: every attempt and the state equal the
+    oracle's."""
+    from oracle import adaptive
+    p, c, rho, T, _ = c2_reference
+    span = 3 * T
+    w_ref, trace_ref, T_ref = adaptive.integrate(p, span, T, 1e-3)
+    w = dev(p.w0)
+    st, trace = F.frkc2_integrate(p, w, dev(p.D), t_span=span, T0=T, tol=1e-3,
+                                  trace_cap=len(trace_ref) + 4)
+    torch.cuda.synchronize()
+    assert np.array_equal(trace, np.array(trace_ref))
+    assert st["T_next"] == T_ref
+    check(w.cpu().numpy(), w_ref, "integrate 256^3")
