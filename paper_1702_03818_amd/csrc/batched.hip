@@ -3,21 +3,23 @@
 //
 // Stage l of problem i is the Euler step W <- W + tau_l f(W) of its own
 // superstep (O'Sullivan, arXiv:1702.03818, Sec. 3). Stages of one problem are
-// sequential; different problems are independent. The graph holds, for each
-// stage level l = 0 .. max(s)-1, one kernel over the 3D problems and one over
-// the 2D problems with s > l (each list sorted by decreasing s, so the active
-// problems are a prefix). Consecutive kernels in the graph are ordered, and
-// that ordering is the only synchronisation: a kernel boundary makes every
-// XCD's writes visible to every other XCD, which an in-kernel wait between
-// workgroups could only get by writing back and invalidating the L2 caches
-// around every dependency.
+// sequential; different problems are independent. The graph has two
+// independent branches. The 3D branch holds, per pass level L, one kernel
+// for the fused passes (stages 3L .. 3L+2 of every problem that has them, as
+// full-width temporally blocked tiles of tb3d_tile.h) and one for the
+// single-stage passes that finish each superstep (s mod 3 stages, 64 x 16
+// plane-march tiles). The 2D branch holds, per stage level l, one kernel over
+// the 2D problems with s > l (64-column rows of the plane-march tile, so the
+// many narrow 2D problems do not idle most of a wide row). Kernels of one
+// branch are ordered, and that ordering is the only synchronisation: a kernel
+// boundary makes every XCD's writes visible to every other XCD, which an
+// in-kernel wait between workgroups could only get by writing back and
+// invalidating the L2 caches around every dependency.
 //
-// A work item is one tile of the one-stage plane-march kernel (plane_tile.h):
-// 64 x 4 columns over a chunk of z planes for 3D problems (256 threads), a
-// row of 64 columns over a chunk of rows for 2D problems (64 threads, so the
-// many narrow 2D problems do not idle three quarters of a 256-wide row). The
-// items of a level are split into eight contiguous ranges, one per XCD
-// (workgroup b runs on XCD b % 8), so neighbouring tiles share an L2.
+// A work item is one tile of a problem. The items of a level are split into
+// eight contiguous ranges, one per XCD (workgroup b runs on XCD b % 8), so
+// neighbouring tiles share an L2; an item's problem descriptor is moved to
+// scalar registers, since the whole workgroup works on one problem.
 //
 // The per-point arithmetic is the one of the plain stage kernels (faces
 // x-, x+, y-, y+, z-, z+, face() and euler()), so each problem's result
@@ -25,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include "plane_tile.h"
+#include "tb3d_tile.h"
 
 namespace frkc2 {
 namespace {
@@ -38,6 +41,22 @@ struct LevelArgs {
     int active;                        // problems with s > level
     int level;
 };
+
+// A value the whole workgroup shares, moved to scalar registers (the compiler
+// cannot prove that loads of the problem table are uniform).
+template <typename T>
+__device__ __forceinline__ T uni(T v)
+{
+    static_assert(sizeof(T) % 4 == 0, "32-bit words");
+    union {
+        T v;
+        int w[sizeof(T) / 4];
+    } u;
+    u.v = v;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) u.w[i] = __builtin_amdgcn_readfirstlane(u.w[i]);
+    return u.v;
+}
 
 template <int NDIM, int BX, int BY, int OP, int BC, bool IR, bool OR>
 __device__ void run_tile(const BatchProblem &P, const PlaneArgs &a, long long c, double2 *sW,
@@ -87,8 +106,25 @@ __global__ __launch_bounds__(BX *BY) void batched_level(LevelArgs t)
             if (t.item_prefix[mid] <= g) a = mid;
             else b = mid - 1;
         }
-        const BatchProblem &P = t.probs[a];
-        const long long c = g - t.item_prefix[a];
+        a = uni(a);
+        BatchProblem P = t.probs[a];
+        P.w = uni(P.w);
+        P.D = uni(P.D);
+        P.bufA = uni(P.bufA);
+        P.bufB = uni(P.bufB);
+        P.tau = uni(P.tau);
+        P.nx = uni(P.nx);
+        P.ny = uni(P.ny);
+        P.nz = uni(P.nz);
+        P.bc = uni(P.bc);
+        P.op = uni(P.op);
+        P.s = uni(P.s);
+        P.zchunk = uni(P.zchunk);
+        P.ntx = uni(P.ntx);
+        P.nty = uni(P.nty);
+        P.inv_h2 = uni(P.inv_h2);
+        P.d_const = uni(P.d_const);
+        const long long c = uni(g - t.item_prefix[a]);
         PlaneArgs pa{};
         const bool ir = (l == 0), orl = (l == P.s - 1);
         pa.in_re = P.w;
@@ -104,8 +140,8 @@ __global__ __launch_bounds__(BX *BY) void batched_level(LevelArgs t)
         pa.nty = P.nty;
         pa.inv_h2 = P.inv_h2;
         pa.d_const = P.d_const;
-        pa.tr = P.tau[2 * l];
-        pa.ti = P.tau[2 * l + 1];
+        pa.tr = uni(P.tau[2 * l]);
+        pa.ti = uni(P.tau[2 * l + 1]);
         const bool per = (P.bc == PER), var = (P.op == VAR);
         if (var) {
             if (per) run_io<NDIM, BX, BY, VAR, PER>(P, pa, c, ir, orl, sW, sD);
@@ -118,20 +154,185 @@ __global__ __launch_bounds__(BX *BY) void batched_level(LevelArgs t)
     }
 }
 
-constexpr int kBX3 = 64, kBY3 = 4, kBX2 = 64;
+constexpr int kBX2 = 64;
+constexpr int kPBX = 64, kPBY = 16;   // single-stage items of the 3D pass kernel (1024 threads)
+
+// Range of items of this workgroup: eight contiguous ranges, one per XCD.
+__device__ __forceinline__ void xcd_range(long long items, long long &first, long long &hi,
+                                          long long &step)
+{
+    const int xcd = blockIdx.x & 7;
+    const int per_xcd = (int)(gridDim.x >> 3);
+    if (per_xcd > 0 && (int)blockIdx.x < per_xcd * 8) {
+        const long long span = (items + 7) / 8;
+        const long long lo = xcd * span;
+        hi = lo + span < items ? lo + span : items;
+        first = lo + (blockIdx.x >> 3);
+        step = per_xcd;
+    } else {
+        hi = (per_xcd > 0) ? 0 : items;
+        first = blockIdx.x;
+        step = gridDim.x;
+    }
+}
+
+struct Pass3Args {
+    const BatchProblem *probs;         // all 3D problems
+    const long long *item_prefix;      // items of this pass level per problem (0: not active)
+    long long items;
+    int nprob, level;
+};
+
+template <int OP, int BC, bool IR, bool OR>
+__device__ void run_fused(const BatchProblem &P, Tb3Args &a, long long c, double2 *sL, double *sD)
+{
+    const int bx = (int)(c % P.ntx3);
+    const long long r = c / P.ntx3;
+    tb3d_tile<OP, BC, kBatchK, IR, OR, false>(a, bx, (int)(r % P.nty3), (int)(r / P.nty3), sL, sD);
+}
+
+template <int OP, int BC>
+__device__ void fused_io(const BatchProblem &P, Tb3Args &a, long long c, bool ir, bool orl,
+                         double2 *sL, double *sD)
+{
+    if (ir) run_fused<OP, BC, true, false>(P, a, c, sL, sD);
+    else if (orl) run_fused<OP, BC, false, true>(P, a, c, sL, sD);
+    else run_fused<OP, BC, false, false>(P, a, c, sL, sD);
+}
+
+// One pass level of the 3D problems. FUSED: each active problem's pass of
+// kBatchK stages (stages kBatchK*level ..), as tb3d_tile items; otherwise its
+// single-stage pass (the stages left after the fused ones), as 64 x 16
+// plane-march items. A problem's first pass reads w, its last writes w, the
+// passes between ping-pong the workspace buffers.
+template <bool FUSED>
+__global__ __launch_bounds__(1024) void batched_pass3(Pass3Args t)
+{
+    using S1 = TileShape<VAR, DIR, 3, kPBX, kPBY>;
+    constexpr int NL = FUSED ? Tb3Lds<VAR, kBatchK>::L : S1::LDS_W;
+    constexpr int ND = FUSED ? Tb3Lds<VAR, kBatchK>::D : S1::LDS_D;
+    __shared__ double2 sL[NL];
+    __shared__ double sD[ND];
+    long long first, hi, step;
+    xcd_range(t.items, first, hi, step);
+    const int L = t.level;
+    for (long long g = first; g < hi; g += step) {
+        int a = 0, b = t.nprob - 1;
+        while (a < b) {
+            const int mid = (a + b + 1) >> 1;
+            if (t.item_prefix[mid] <= g) a = mid;
+            else b = mid - 1;
+        }
+        a = uni(a);
+        BatchProblem P = t.probs[a];
+        P.w = uni(P.w);
+        P.D = uni(P.D);
+        P.bufA = uni(P.bufA);
+        P.bufB = uni(P.bufB);
+        P.tau = uni(P.tau);
+        P.nx = uni(P.nx);
+        P.ny = uni(P.ny);
+        P.nz = uni(P.nz);
+        P.bc = uni(P.bc);
+        P.op = uni(P.op);
+        P.zchunk = uni(P.zchunk);
+        P.ntx = uni(P.ntx);
+        P.nty = uni(P.nty);
+        P.nfull = uni(P.nfull);
+        P.npass = uni(P.npass);
+        P.zc3 = uni(P.zc3);
+        P.ntx3 = uni(P.ntx3);
+        P.nty3 = uni(P.nty3);
+        P.inv_h2 = uni(P.inv_h2);
+        P.d_const = uni(P.d_const);
+        const long long c = uni(g - t.item_prefix[a]);
+        const bool ir = (L == 0), orl = (L == P.npass - 1);
+        const double *in_c = (L & 1) ? P.bufA : P.bufB;   // pass L-1 wrote buffer (L-1) & 1
+        double *out_c = (L & 1) ? P.bufB : P.bufA;
+        const bool per = (P.bc == PER), var = (P.op == VAR);
+        if (FUSED) {
+            Tb3Args ta{};
+            ta.in_re = P.w;
+            ta.in_c = reinterpret_cast<const double2 *>(in_c);
+            ta.out_re = P.w;
+            ta.out_c = reinterpret_cast<double2 *>(out_c);
+            ta.D = P.D;
+            ta.nx = P.nx;
+            ta.ny = P.ny;
+            ta.nz = P.nz;
+            ta.zchunk = P.zc3;
+            ta.ntx = P.ntx3;
+            ta.nty = P.nty3;
+            ta.inv_h2 = P.inv_h2;
+            ta.d_const = P.d_const;
+            const int l0 = kBatchK * L;
+#pragma unroll
+            for (int i = 0; i < kBatchK; ++i) {
+                ta.tr[i] = uni(P.tau[2 * (l0 + i)]);
+                ta.ti[i] = uni(P.tau[2 * (l0 + i) + 1]);
+            }
+            if (var) {
+                if (per) fused_io<VAR, PER>(P, ta, c, ir, orl, sL, sD);
+                else fused_io<VAR, DIR>(P, ta, c, ir, orl, sL, sD);
+            } else {
+                if (per) fused_io<LAP, PER>(P, ta, c, ir, orl, sL, sD);
+                else fused_io<LAP, DIR>(P, ta, c, ir, orl, sL, sD);
+            }
+        } else {
+            const int l = kBatchK * P.nfull + (L - P.nfull);
+            PlaneArgs pa{};
+            pa.in_re = P.w;
+            pa.in_c = reinterpret_cast<const double2 *>(in_c);
+            pa.out_re = P.w;
+            pa.out_c = reinterpret_cast<double2 *>(out_c);
+            pa.D = P.D;
+            pa.nx = P.nx;
+            pa.ny = P.ny;
+            pa.nz = P.nz;
+            pa.zchunk = P.zchunk;
+            pa.ntx = P.ntx;
+            pa.nty = P.nty;
+            pa.inv_h2 = P.inv_h2;
+            pa.d_const = P.d_const;
+            pa.tr = uni(P.tau[2 * l]);
+            pa.ti = uni(P.tau[2 * l + 1]);
+            if (var) {
+                if (per) run_io<3, kPBX, kPBY, VAR, PER>(P, pa, c, ir, orl, sL, sD);
+                else run_io<3, kPBX, kPBY, VAR, DIR>(P, pa, c, ir, orl, sL, sD);
+            } else {
+                if (per) run_io<3, kPBX, kPBY, LAP, PER>(P, pa, c, ir, orl, sL, sD);
+                else run_io<3, kPBX, kPBY, LAP, DIR>(P, pa, c, ir, orl, sL, sD);
+            }
+        }
+        __syncthreads();   // the next item reuses the LDS
+    }
+}
 
 }  // namespace
 
-void batched_tile(int ndim, int *bx, int *by) { *bx = ndim == 3 ? kBX3 : kBX2; *by = ndim == 3 ? kBY3 : 1; }
+void batched_tile(int ndim, int *bx, int *by) { *bx = ndim == 3 ? kPBX : kBX2; *by = ndim == 3 ? kPBY : 1; }
+
+void batched_tile3(int *bx, int *by)
+{
+    *bx = 64;
+    *by = Tb3Shape<kBatchK>::BYO;
+}
+
+int launch_batched_pass3(bool fused, const BatchProblem *probs, const long long *item_prefix,
+                         long long items, int nprob, int level, int grid, hipStream_t st)
+{
+    Pass3Args t{probs, item_prefix, items, nprob, level};
+    if (fused) hipLaunchKernelGGL(batched_pass3<true>, dim3(grid), dim3(1024), 0, st, t);
+    else hipLaunchKernelGGL(batched_pass3<false>, dim3(grid), dim3(1024), 0, st, t);
+    return (int)hipGetLastError();
+}
 
 int launch_batched_level(int ndim, const BatchProblem *probs, const long long *item_prefix,
                          long long items, int active, int level, int grid, hipStream_t st)
 {
+    if (ndim != 2) return (int)hipErrorInvalidValue;   // 3D problems run as passes
     LevelArgs t{probs, item_prefix, items, active, level};
-    if (ndim == 3)
-        hipLaunchKernelGGL((batched_level<3, kBX3, kBY3>), dim3(grid), dim3(kBX3 * kBY3), 0, st, t);
-    else
-        hipLaunchKernelGGL((batched_level<2, kBX2, 1>), dim3(grid), dim3(kBX2), 0, st, t);
+    hipLaunchKernelGGL((batched_level<2, kBX2, 1>), dim3(grid), dim3(kBX2), 0, st, t);
     return (int)hipGetLastError();
 }
 
@@ -142,7 +343,7 @@ int batched_grid_size(int ndim)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     hipError_t e = (ndim == 3)
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_level<3, kBX3, kBY3>, kBX3 * kBY3, 0)
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_pass3<true>, 1024, 0)
         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_level<2, kBX2, 1>, kBX2, 0);
     if (e != hipSuccess) return 0;
     return cus * (per > 0 ? per : 1);

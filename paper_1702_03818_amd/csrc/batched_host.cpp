@@ -17,13 +17,20 @@ namespace frkc2 {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kChunkPlanes = 32;   // z planes (3D) or rows (2D) per tile
+constexpr int kChunkPlanes = 32;   // z planes (3D) or rows (2D) per one-stage tile
+constexpr int kChunkPlanes3 = 64;  // z planes per fused 3D tile
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t probs[2], prefix[2], tau, bufs, total;   // index 0: 3D list, 1: 2D list
+    size_t pass3;                                  // 3D pass tables: 2 * levels3 rows of n3 + 1
+    int levels3;                                   // pass levels of the 3D list
     std::vector<size_t> buf_off;                   // per problem (caller's order)
 };
+
+// Passes of a 3D problem: fused passes of kBatchK stages, then single stages.
+int nfull3(int s) { return s / kBatchK; }
+int npass3(int s) { return nfull3(s) + (s - kBatchK * nfull3(s)); }
 
 bool validate(int nprob, const frkc2_grid *grids, const int *s, std::vector<KGrid> &kg)
 {
@@ -50,7 +57,12 @@ Layout layout(int nprob, const std::vector<KGrid> &kg, const int *s)
 {
     Layout L;
     int n3 = 0;
-    for (const KGrid &g : kg) n3 += (g.ndim == 3);
+    L.levels3 = 0;
+    for (int i = 0; i < nprob; ++i)
+        if (kg[i].ndim == 3) {
+            ++n3;
+            L.levels3 = std::max(L.levels3, npass3(s[i]));
+        }
     const int cnt[2] = {n3, nprob - n3};
     const size_t sum_s = std::accumulate(s, s + nprob, (size_t)0);
     size_t o = 0;
@@ -60,6 +72,8 @@ Layout layout(int nprob, const std::vector<KGrid> &kg, const int *s)
         L.prefix[d] = o;
         o = align_up(o + sizeof(long long) * (cnt[d] + 1));
     }
+    L.pass3 = o;
+    o = align_up(o + sizeof(long long) * 2 * (size_t)L.levels3 * (n3 + 1));
     L.tau = o;
     o = align_up(o + sizeof(double) * 2 * sum_s);
     L.bufs = o;
@@ -78,12 +92,14 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     std::vector<BatchProblem> probs[2];   // host copies of the uploaded tables
     std::vector<long long> prefix[2];
+    std::vector<long long> pass3;         // 3D: per level, fused then single-stage prefixes
     std::vector<double> tau;
 };
 
 std::mutex g_mu;
 std::map<void *, GraphEntry> g_graphs;
-hipStream_t g_capture = nullptr;
+hipStream_t g_capture = nullptr, g_capture2 = nullptr;   // 3D and 2D branches of the graph
+hipEvent_t g_fork = nullptr, g_join = nullptr;
 
 void append(std::vector<unsigned char> &k, const void *p, size_t n)
 {
@@ -205,13 +221,38 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
         P.ntx = (P.nx + bx - 1) / bx;
         P.nty = (P.ndim == 3) ? (P.ny + by - 1) / by : 1;
         P.ntiles = P.ntx * P.nty * ((P.nz + P.zchunk - 1) / P.zchunk);
+        if (P.ndim == 3) {
+            int bx3, by3;
+            batched_tile3(&bx3, &by3);
+            P.nfull = nfull3(P.s);
+            P.npass = npass3(P.s);
+            P.zc3 = std::min(P.nz, kChunkPlanes3);
+            P.ntx3 = (P.nx + bx3 - 1) / bx3;
+            P.nty3 = (P.ny + by3 - 1) / by3;
+            P.ntiles3 = P.ntx3 * P.nty3 * ((P.nz + P.zc3 - 1) / P.zc3);
+        }
         P.inv_h2 = kg[i].inv_h2;
         P.d_const = kg[i].d_const;
         E.probs[d].push_back(P);
         E.prefix[d].push_back(E.prefix[d].back() + P.ntiles);
         max_s = std::max(max_s, s[i]);
     }
+    // 3D pass tables: row 2L = fused items of level L, row 2L+1 = single-stage items
+    const int n3 = (int)E.probs[0].size();
+    E.pass3.assign(2 * (size_t)L.levels3 * (n3 + 1), 0);
+    for (int lv = 0; lv < L.levels3; ++lv) {
+        long long *fa = &E.pass3[(size_t)(2 * lv) * (n3 + 1)];
+        long long *sg = &E.pass3[(size_t)(2 * lv + 1) * (n3 + 1)];
+        for (int j = 0; j < n3; ++j) {
+            const BatchProblem &P = E.probs[0][j];
+            fa[j + 1] = fa[j] + (lv < P.nfull ? P.ntiles3 : 0);
+            sg[j + 1] = sg[j] + (lv >= P.nfull && lv < P.npass ? P.ntiles : 0);
+        }
+    }
     hipError_t e = hipSuccess;
+    if (!E.pass3.empty())
+        e = hipMemcpyAsync(base + L.pass3, E.pass3.data(), sizeof(long long) * E.pass3.size(),
+                           hipMemcpyHostToDevice, st);
     for (int d = 0; d < 2 && e == hipSuccess; ++d) {
         if (E.probs[d].empty()) continue;
         e = hipMemcpyAsync(base + L.probs[d], E.probs[d].data(),
@@ -226,29 +267,54 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_err(e, "table upload");
 
-    // ---- capture: per stage level, the 3D kernel then the 2D kernel ----
+    // ---- capture: the 3D pass levels on one stream, the 2D stage levels on a
+    // second one forked from it, joined before the end ----
     if (!g_capture) {
         e = hipStreamCreate(&g_capture);
-        if (e != hipSuccess) return hip_err(e, "capture stream");
+        if (e == hipSuccess) e = hipStreamCreate(&g_capture2);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&g_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&g_join, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_err(e, "capture streams");
     }
     int grid_max[2] = {batched_grid_size(3), batched_grid_size(2)};
     if (grid_max[0] <= 0 || grid_max[1] <= 0) return hip_err(hipErrorInvalidValue, "occupancy query");
     e = hipStreamBeginCapture(g_capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_err(e, "begin capture");
     int lrc = 0;
-    int active[2] = {(int)E.probs[0].size(), (int)E.probs[1].size()};
-    for (int l = 0; l < max_s && lrc == 0; ++l) {
-        for (int d = 0; d < 2 && lrc == 0; ++d) {
-            while (active[d] > 0 && E.probs[d][active[d] - 1].s <= l) --active[d];
-            if (active[d] == 0) continue;
-            const long long items = E.prefix[d][active[d]];
-            long long grid = std::min<long long>(grid_max[d], (items + 7) / 8 * 8);
-            if (grid < 1) grid = 1;
-            lrc = launch_batched_level(d == 0 ? 3 : 2,
-                                       reinterpret_cast<const BatchProblem *>(base + L.probs[d]),
-                                       reinterpret_cast<const long long *>(base + L.prefix[d]),
-                                       items, active[d], l, (int)grid, g_capture);
+    const bool has2 = !E.probs[1].empty();
+    if (has2) {
+        lrc = (int)hipEventRecord(g_fork, g_capture);
+        if (lrc == 0) lrc = (int)hipStreamWaitEvent(g_capture2, g_fork, 0);
+    }
+    auto grid_for = [&](int d, long long items) {
+        long long grid = std::min<long long>(grid_max[d], (items + 7) / 8 * 8);
+        return (int)std::max<long long>(grid, 1);
+    };
+    const long long *pass3_dev = reinterpret_cast<const long long *>(base + L.pass3);
+    for (int lv = 0; lv < L.levels3 && lrc == 0; ++lv) {
+        for (int kind = 0; kind < 2 && lrc == 0; ++kind) {
+            const size_t row = (size_t)(2 * lv + kind) * (n3 + 1);
+            const long long items = E.pass3[row + n3];
+            if (items == 0) continue;
+            lrc = launch_batched_pass3(kind == 0,
+                                       reinterpret_cast<const BatchProblem *>(base + L.probs[0]),
+                                       pass3_dev + row, items, n3, lv, grid_for(0, items),
+                                       g_capture);
         }
+    }
+    int active2 = (int)E.probs[1].size();
+    for (int l = 0; l < max_s && lrc == 0 && has2; ++l) {
+        while (active2 > 0 && E.probs[1][active2 - 1].s <= l) --active2;
+        if (active2 == 0) break;
+        const long long items = E.prefix[1][active2];
+        lrc = launch_batched_level(2, reinterpret_cast<const BatchProblem *>(base + L.probs[1]),
+                                   reinterpret_cast<const long long *>(base + L.prefix[1]),
+                                   items, active2, l, grid_for(1, items), g_capture2);
+    }
+    if (has2) {
+        const int r1 = (int)hipEventRecord(g_join, g_capture2);
+        const int r2 = (int)hipStreamWaitEvent(g_capture, g_join, 0);
+        if (lrc == 0) lrc = r1 ? r1 : r2;
     }
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(g_capture, &graph);

@@ -86,20 +86,28 @@ int launch_adjoint_stage(const KGrid &g, const AdjArgs &a, hipStream_t st);
 int launch_grad_finish(long long n, const double *D, const double *gD, double *grad_logD,
                        hipStream_t st);
 
-// Batched persistent kernel (batched.hip).
+// Batched engine (batched.hip, batched_host.cpp).
 struct BatchProblem {           // one problem's descriptor in device memory
     double *w;                  // caller state (real)
     const double *D;
     double *bufA, *bufB;        // complex ping-pong buffers in the workspace
     const double *tau;          // 2*s doubles (re, im interleaved)
     int nx, ny, nz, ndim, bc, op;   // kernel layout: 3D (n0, n1, n2), 2D (n0, 1, n1)
-    int s, ntiles;                  // stages, tiles per stage
-    int zchunk, ntx, nty;           // tile grid: ntx * nty * ceil(nz / zchunk) tiles
+    int s, ntiles;                  // stages, tiles per one-stage pass
+    int zchunk, ntx, nty;           // one-stage tile grid: ntx * nty * ceil(nz / zchunk)
+    int nfull, npass;               // 3D: passes of kBatchK stages, then single stages
+    int zc3, ntx3, nty3, ntiles3;   // 3D fused-pass tile grid
     double inv_h2, d_const;
 };
+constexpr int kBatchK = 3;          // stages per fused 3D pass of the batch
 void batched_tile(int ndim, int *bx, int *by);
+void batched_tile3(int *bx, int *by);
 int batched_grid_size(int ndim);
 int launch_batched_level(int ndim, const BatchProblem *probs, const long long *item_prefix,
                          long long items, int active, int level, int grid, hipStream_t st);
+// 3D pass level: fused == true runs the kBatchK-stage passes of level `level`,
+// otherwise the single-stage passes; item_prefix spans all nprob 3D problems.
+int launch_batched_pass3(bool fused, const BatchProblem *probs, const long long *item_prefix,
+                         long long items, int nprob, int level, int grid, hipStream_t st);
 
 }  // namespace frkc2
