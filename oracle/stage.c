@@ -48,7 +48,7 @@
 #include <string.h>
 
 enum { BC_PERIODIC = 0, BC_DIRICHLET0 = 1 };
-enum { OP_LAPLACE = 0, OP_VARCOEF = 1, OP_POROUS2 = 2 };
+enum { OP_LAPLACE = 0, OP_VARCOEF = 1, OP_POROUS2 = 2, OP_BRUSS2 = 3 };
 
 typedef struct {
     int ndim;
@@ -58,6 +58,10 @@ typedef struct {
 } grid_t;
 
 static long npts(const grid_t *g) { return g->n[0] * g->n[1] * g->n[2]; }
+
+/* Values per grid point: the Brusselator carries two species (v then w). */
+static int nfield(const grid_t *g) { return g->op == OP_BRUSS2 ? 2 : 1; }
+static long nstate(const grid_t *g) { return nfield(g) * npts(g); }
 
 /* Index of the neighbour of point (i[0], i[1], i[2]) across face f
  * (f = 2*dim + side, side 0 = minus, 1 = plus), or -1 for a Dirichlet ghost. */
@@ -80,10 +84,57 @@ static void coords(const grid_t *g, long p, long i[3])
     i[2] = p / (g->n[0] * g->n[1]);
 }
 
+/*
+ * Two-species Brusselator of Sec. 3.1 (the default problem of the paper's
+ * public code): v_t = d lap v + 1 - 4v + w v^2, w_t = d lap w + 3v - v^2 w,
+ * with d = d_const, applied to complex stage values (a polynomial, so the
+ * complex stages need no continuation). State layout: v at [0, N), w at
+ * [N, 2N). Per point: each species' faces as for op 0 (acc = fma(d, nb - c,
+ * acc)); p = v^2 = (fma(vr, vr, -(vi*vi)), 2*(vr*vi)); q = w p =
+ * (fma(wr, pr, -(wi*pi)), fma(wr, pi, wi*pr)); R_v = (fma(-4, vr, 1) + qr,
+ * fma(-4, vi, qi)); R_w = (fma(3, vr, -qr), fma(3, vi, -qi));
+ * f = fma(acc, inv_h2, R) per component.
+ */
+static void apply_bruss(const grid_t *g, const double *wr, const double *wi, double *fr,
+                        double *fi)
+{
+    long N = npts(g);
+    double d = g->d_const;
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < N; ++p) {
+        long i[3];
+        coords(g, p, i);
+        double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+        for (int s = 0; s < 2; ++s) {
+            const double *ur = wr + s * N, *ui = wi + s * N;
+            for (int f = 0; f < 2 * g->ndim; ++f) {
+                long q = neighbour(g, i, f);
+                double nr = (q < 0) ? 0.0 : ur[q];
+                double ni = (q < 0) ? 0.0 : ui[q];
+                acc[s][0] = fma(d, nr - ur[p], acc[s][0]);
+                acc[s][1] = fma(d, ni - ui[p], acc[s][1]);
+            }
+        }
+        double vr = wr[p], vi = wi[p], xr = wr[N + p], xi = wi[N + p];
+        double pr = fma(vr, vr, -(vi * vi)), pi = 2.0 * (vr * vi);
+        double qr = fma(xr, pr, -(xi * pi)), qi = fma(xr, pi, xi * pr);
+        double rvr = fma(-4.0, vr, 1.0) + qr, rvi = fma(-4.0, vi, qi);
+        double rwr = fma(3.0, vr, -qr), rwi = fma(3.0, vi, -qi);
+        fr[p] = fma(acc[0][0], g->inv_h2, rvr);
+        fi[p] = fma(acc[0][1], g->inv_h2, rvi);
+        fr[N + p] = fma(acc[1][0], g->inv_h2, rwr);
+        fi[N + p] = fma(acc[1][1], g->inv_h2, rwi);
+    }
+}
+
 /* F = f(W) for complex W = (wr, wi), all points. */
 static void apply_op(const grid_t *g, const double *D, const double *wr, const double *wi,
                      double *fr, double *fi)
 {
+    if (g->op == OP_BRUSS2) {
+        apply_bruss(g, wr, wi, fr, fi);
+        return;
+    }
     long N = npts(g);
 #pragma omp parallel for schedule(static)
     for (long p = 0; p < N; ++p) {
@@ -137,12 +188,6 @@ static int make_grid(grid_t *g, int ndim, const long *n, int bc, int op, double 
 }
 
 /*
- * One superstep: W^0 = (w, 0); W^{l+1} = W^l + tau_l f(W^l), l = 0..s-1;
- * w <- Re W^s. If wi_out is not NULL it receives Im W^s.
- * If store is not NULL it receives W^0..W^{s-1} as s blocks of 2N doubles
- * (real part, then imaginary part).
- */
-/*
  * One superstep. w: real W^0 on entry, Re W^L on exit; wi_out (may be NULL):
  * Im W^L; store (may be NULL): every stage W^0 .. W^{s-1} (re then im);
  * emb_out (may be NULL): the embedded first-order solution of Sec. 3, which
@@ -156,7 +201,7 @@ int oracle_superstep(int ndim, const long *n, int bc, int op, double inv_h2, dou
 {
     grid_t g;
     if (make_grid(&g, ndim, n, bc, op, inv_h2, d_const)) return -1;
-    long N = npts(&g);
+    long N = nstate(&g);   /* values per state (both species for op 3) */
     double *wr = malloc(sizeof(double) * N), *wi = malloc(sizeof(double) * N);
     double *fr = malloc(sizeof(double) * N), *fi = malloc(sizeof(double) * N);
     if (!wr || !wi || !fr || !fi) { free(wr); free(wi); free(fr); free(fi); return -2; }
@@ -195,7 +240,7 @@ int oracle_adjoint(int ndim, const long *n, int bc, int op, double inv_h2, doubl
                    const double *w_n, const double *lam_next, double *lam_n, double *grad_logD)
 {
     grid_t g;
-    if (op == OP_POROUS2) return -1;
+    if (op == OP_POROUS2 || op == OP_BRUSS2) return -1;
     if (make_grid(&g, ndim, n, bc, op, inv_h2, d_const)) return -1;
     long N = npts(&g);
     double *store = malloc(sizeof(double) * 2 * N * (size_t)s);
@@ -255,7 +300,9 @@ int oracle_adjoint(int ndim, const long *n, int bc, int op, double inv_h2, doubl
 /*
  * Gershgorin bound on the spectral radius of the Jacobian of f at real w:
  * rho = (2*inv_h2) * max_c sum_faces D_f, with D_f of the operator (op 2: the
- * face value (w_c^2 + w_nb^2)/2 of the current state).
+ * face value (w_c^2 + w_nb^2)/2 of the current state). Op 3 adds the
+ * reaction rows: rho = (2*inv_h2) * (4d) + max_c max(|2vw - 4| + v^2,
+ * v^2 + |3 - 2vw|) (diagonal and coupling entries of each row).
  */
 double oracle_rho_bound(int ndim, const long *n, int bc, int op, double inv_h2, double d_const,
                         const double *D, const double *w)
@@ -271,7 +318,7 @@ double oracle_rho_bound(int ndim, const long *n, int bc, int op, double inv_h2, 
         for (int f = 0; f < 2 * ndim; ++f) {
             long q = neighbour(&g, i, f);
             double Df;
-            if (op == OP_LAPLACE) {
+            if (op == OP_LAPLACE || op == OP_BRUSS2) {
                 Df = d_const;
             } else if (op == OP_VARCOEF) {
                 Df = 0.5 * (D[p] + ((q < 0) ? D[p] : D[q]));
@@ -282,6 +329,18 @@ double oracle_rho_bound(int ndim, const long *n, int bc, int op, double inv_h2, 
             sum = sum + Df;
         }
         if (sum > m) m = sum;
+    }
+    if (op == OP_BRUSS2) {
+        double r = 0.0;
+        for (long p = 0; p < N; ++p) {
+            double v = w[p], x = w[N + p];
+            double vx = v * x, v2 = v * v;
+            double a = fabs(2.0 * vx - 4.0) + v2;
+            double b = v2 + fabs(3.0 - 2.0 * vx);
+            double c = a > b ? a : b;
+            if (c > r) r = c;
+        }
+        return (2.0 * inv_h2) * m + r;
     }
     return (2.0 * inv_h2) * m;
 }

@@ -14,6 +14,8 @@ Workloads (seeded numpy PCG64; the recipe is stated next to each generator):
   porous2d      2D u_t = div(u^2 grad u), 4096^2, periodic
   batched       512 independent 2D/3D variable-D problems of uneven size and s
   adjoint3d     3D variable-D problem, 128^3, with a seeded target field
+  brusselator   2D two-species Brusselator, 200^2, periodic (the paper's default user
+                problem, Sec. 3.1; its initial data are fixed, no random draw)
 """
 from __future__ import annotations
 
@@ -26,6 +28,7 @@ BC_DIRICHLET0 = 1
 OP_LAPLACE = 0
 OP_VARCOEF = 1
 OP_POROUS2 = 2
+OP_BRUSS2 = 3
 
 
 @dataclass
@@ -41,13 +44,23 @@ class Problem:
     meta: dict = field(default_factory=dict)
 
     @property
+    def nfield(self) -> int:
+        """Values per grid point (the Brusselator stores v, then w)."""
+        return 2 if self.op == OP_BRUSS2 else 1
+
+    @property
     def shape(self):
         nx, ny, nz = self.n
-        return {1: (nx,), 2: (ny, nx), 3: (nz, ny, nx)}[self.ndim]
+        s = {1: (nx,), 2: (ny, nx), 3: (nz, ny, nx)}[self.ndim]
+        return (2,) + s if self.nfield == 2 else s
 
     @property
     def npoints(self) -> int:
         return int(self.n[0]) * int(self.n[1]) * int(self.n[2])
+
+    @property
+    def nstate(self) -> int:
+        return self.nfield * self.npoints
 
 
 def _rng(seed) -> np.random.Generator:
@@ -196,3 +209,18 @@ def random_state(shape, seed: int, smooth: float | None = None) -> np.ndarray:
     if smooth is None:
         return rng.standard_normal(shape)
     return smooth_field(shape, smooth, rng)
+
+
+def brusselator(n: int = 200, d: float = 0.02) -> Problem:
+    """Sec. 3.1's two-species Brusselator on the periodic unit square, n x n cells at
+    x_i = i/n: v0 = 1 + sin(2 pi x), w0 = 3 + cos(2 pi y); diffusion d = 0.02 (spectral
+    radius about 8 d n^2 = 6400 at n = 200). State: v then w, each (n, n) with x fastest."""
+    x = np.arange(n) / n
+    X = x[None, :]
+    Y = x[:, None]
+    v0 = np.broadcast_to(1.0 + np.sin(2 * np.pi * X), (n, n))
+    w0 = np.broadcast_to(3.0 + np.cos(2 * np.pi * Y), (n, n))
+    p = Problem(2, (n, n, 1), 1.0 / n, BC_PERIODIC, OP_BRUSS2, d)
+    p.w0 = np.ascontiguousarray(np.stack([v0, w0]))
+    p.meta = {"A": 1.0, "B": 3.0}
+    return p
