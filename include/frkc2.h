@@ -63,10 +63,26 @@ typedef enum { FRKC2_BC_PERIODIC = 0, FRKC2_BC_DIRICHLET0 = 1 } frkc2_bc;
  *           Q_f = (W_c^2 + W_nb^2)/2, evaluated on the complex stage values
  *           (the continuation of u^2 is holomorphic, as the complex Euler
  *           steps of Sec. 3 require).
+ *  BRUSS2   the two-species Brusselator of Sec. 3.1 (the default problem of
+ *           the paper's public code), periodic 2D grids only:
+ *           v_t = d lap v + 1 - 4v + w v^2, w_t = d lap w + 3v - v^2 w,
+ *           d = d_const. The state holds 2N values, v then w (each x fastest);
+ *           D is not used. Faces as LAPLACE per species; then
+ *           p = v^2 = (fma(vr, vr, -(vi*vi)), 2*(vr*vi)), q = w p =
+ *           (fma(wr, pr, -(wi*pi)), fma(wr, pi, wi*pr)), R_v = (fma(-4, vr, 1) + qr,
+ *           fma(-4, vi, qi)), R_w = (fma(3, vr, -qr), fma(3, vi, -qi)) and
+ *           f = fma(acc, 1/h^2, R) per component. Gershgorin bound:
+ *           (2/h^2)(4d) + max_c max(|2vw - 4| + v^2, v^2 + |3 - 2vw|).
+ *           One stage per pass; not available to the batched and adjoint calls.
  * Dirichlet-zero boundaries use a ghost value W = 0 and, for VARCOEF, a ghost
  * diffusivity equal to the boundary cell's own D.
  */
-typedef enum { FRKC2_OP_LAPLACE = 0, FRKC2_OP_VARCOEF = 1, FRKC2_OP_POROUS2 = 2 } frkc2_op;
+typedef enum {
+    FRKC2_OP_LAPLACE = 0,
+    FRKC2_OP_VARCOEF = 1,
+    FRKC2_OP_POROUS2 = 2,
+    FRKC2_OP_BRUSS2 = 3
+} frkc2_op;
 
 typedef struct {
     int ndim;          /* 1, 2 or 3 */

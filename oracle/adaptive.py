@@ -24,7 +24,8 @@ Readings (the section leaves these open; the GPU library takes the same ones):
     T_n SAFE / sqrt(err_n) otherwise; err values below 1e-12 count as 1e-12,
     and the growth factor is capped at 5;
   * each attempt takes the smallest even s whose betabar(s) covers T rho
-    (rho the Gershgorin bound; for the porous operator of the current state),
+    (rho the Gershgorin bound; for the porous operator and the Brusselator, of
+    the current state),
     searched from s = 2 ceil(sqrt(T rho / 1.32)) downward and upward in steps
     of 2 (betabar ~ 0.33 s^2); if betabar(514) is too small, T is cut to
     0.99 betabar(514) / rho;
@@ -89,7 +90,7 @@ def integrate(prob, t_span, T0, tol, nu=0.01, w=None, max_attempts=10000):
     while t < t_span:
         if len(trace) >= max_attempts:
             raise RuntimeError("attempt limit reached")
-        if rho is None or prob.op == 2:
+        if rho is None or prob.op in (2, 3):
             rho = stage.rho_bound(prob, cur)
         Tn = min(T, t_span - t)
         x = Tn * rho
@@ -118,6 +119,6 @@ def integrate(prob, t_span, T0, tol, nu=0.01, w=None, max_attempts=10000):
         err_prev = e
         have_prev = True
         T = Tn * fac
-        if prob.op == 2:
+        if prob.op in (2, 3):
             rho = None
     return cur, trace, T

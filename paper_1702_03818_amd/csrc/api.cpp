@@ -47,6 +47,12 @@ int hip_fail(hipError_t e, const char *what)
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+// Operators whose Jacobian (and so the Gershgorin bound) depends on the state.
+bool nonlinear(const KGrid &kg)
+{
+    return kg.op == FRKC2_OP_POROUS2 || kg.op == FRKC2_OP_BRUSS2;
+}
+
 }  // namespace
 
 void set_error(const char *fmt, ...)
@@ -82,12 +88,18 @@ bool make_kgrid(const frkc2_grid *g, KGrid &k)
         set_error("unknown boundary condition %d", g->bc);
         return false;
     }
-    if (g->op != FRKC2_OP_LAPLACE && g->op != FRKC2_OP_VARCOEF && g->op != FRKC2_OP_POROUS2) {
+    if (g->op != FRKC2_OP_LAPLACE && g->op != FRKC2_OP_VARCOEF && g->op != FRKC2_OP_POROUS2 &&
+        g->op != FRKC2_OP_BRUSS2) {
         set_error("unknown operator %d", g->op);
         return false;
     }
-    if (g->op == FRKC2_OP_LAPLACE && !(g->d_const >= 0.0 && std::isfinite(g->d_const))) {
+    if ((g->op == FRKC2_OP_LAPLACE || g->op == FRKC2_OP_BRUSS2) &&
+        !(g->d_const >= 0.0 && std::isfinite(g->d_const))) {
         set_error("d_const must be finite and non-negative");
+        return false;
+    }
+    if (g->op == FRKC2_OP_BRUSS2 && (g->ndim != 2 || g->bc != FRKC2_BC_PERIODIC)) {
+        set_error("the Brusselator runs on periodic 2D grids");
         return false;
     }
     const long long N = (long long)g->n[0] * g->n[1] * g->n[2];
@@ -98,6 +110,7 @@ bool make_kgrid(const frkc2_grid *g, KGrid &k)
     k.ndim = g->ndim;
     k.bc = g->bc;
     k.op = g->op;
+    k.nfield = (g->op == FRKC2_OP_BRUSS2) ? 2 : 1;
     k.inv_h2 = 1.0 / (g->h * g->h);
     k.d_const = g->d_const;
     if (g->ndim == 1) { k.nx = g->n[0]; k.ny = 1; k.nz = 1; }
@@ -162,7 +175,7 @@ int rho_bound_impl(const KGrid &kg, const double *w, const double *D, double *pa
                    double *rho, hipStream_t st)
 {
     double m;
-    if (kg.op == FRKC2_OP_LAPLACE) {
+    if (kg.op == FRKC2_OP_LAPLACE || kg.op == FRKC2_OP_BRUSS2) {
         double sum = 0.0;
         for (int f = 0; f < 2 * kg.ndim; ++f) sum = sum + kg.d_const;
         m = sum;
@@ -174,6 +187,17 @@ int rho_bound_impl(const KGrid &kg, const double *w, const double *D, double *pa
         HIP_TRY(hipStreamSynchronize(st), "rho bound");
     }
     *rho = (2.0 * kg.inv_h2) * m;
+    if (kg.op == FRKC2_OP_BRUSS2) {
+        // reaction rows of the Jacobian (diagonal and species coupling)
+        double r = 0.0;
+        HIP_TRY(launch_bruss_react_max(kg, w, partials, st), "rho bound launch");
+        HIP_TRY(launch_max_partials(partials, st), "rho bound launch");
+        HIP_TRY(hipMemcpyAsync(&r, partials + kReduceBlocks, sizeof(double), hipMemcpyDeviceToHost,
+                               st),
+                "rho bound copy");
+        HIP_TRY(hipStreamSynchronize(st), "rho bound");
+        *rho = *rho + r;
+    }
     if (!std::isfinite(*rho)) {
         set_error("Gershgorin bound is not finite");
         return FRKC2_ENONFINITE;
@@ -363,8 +387,8 @@ extern "C" size_t frkc2_workspace_bytes(const frkc2_grid *g, int s, int flags)
         if (s < 2 || s > kMaxStages || (s % 2)) return 0;
         return adj_layout(kg.npts(), s).total;
     }
-    if (flags == FRKC2_WS_ADAPT) return adapt_layout(kg.npts()).total;
-    return step_layout(kg.npts()).total;
+    if (flags == FRKC2_WS_ADAPT) return adapt_layout(kg.nstate()).total;
+    return step_layout(kg.nstate()).total;
 }
 
 extern "C" int frkc2_rho_bound(const frkc2_grid *g, const double *w, const double *D, double *rho,
@@ -380,7 +404,7 @@ extern "C" int frkc2_rho_bound(const frkc2_grid *g, const double *w, const doubl
         set_error("VARCOEF needs D");
         return FRKC2_EINVAL;
     }
-    if (kg.op == FRKC2_OP_POROUS2 && !w) {
+    if ((kg.op == FRKC2_OP_POROUS2 || kg.op == FRKC2_OP_BRUSS2) && !w) {
         set_error("POROUS2 needs w");
         return FRKC2_EINVAL;
     }
@@ -416,7 +440,7 @@ extern "C" int frkc2_step(const frkc2_grid *g, double *w, const double *D, doubl
         set_error("exactly one of T and cfl must be positive and finite (T=%g, cfl=%g)", T, cfl);
         return FRKC2_EINVAL;
     }
-    const long long N = kg.npts();
+    const long long N = kg.nstate();
     const StepLayout L = step_layout(N);
     if (!ws || ws_bytes < L.total || !aligned16(ws)) {
         set_error("workspace needs %zu bytes (got %zu), 16-byte aligned", L.total, ws_bytes);
@@ -436,7 +460,7 @@ extern "C" int frkc2_step(const frkc2_grid *g, double *w, const double *D, doubl
     const PassCfg cfg = pass_cfg(kg);
     static thread_local std::vector<double> tau_host;
     for (int step = 0; step < nsteps; ++step) {
-        if (step == 0 || kg.op == FRKC2_OP_POROUS2) {
+        if (step == 0 || nonlinear(kg)) {
             int rc = rho_bound_impl(kg, w, D, partials, &rho, st);
             if (rc < 0) return rc;
             if (adaptive) {
@@ -499,6 +523,7 @@ std::vector<PassCfg> tune_candidates(const KGrid &kg)
     for (int zc : {8, 16, 32, 64, 128})
         if (zc < kg.nz) zcs.push_back(zc);
     auto add = [&](int k, int tile) {
+        if (k >= 2 && !tblock_supported(kg, k)) return;
         for (int zc : zcs) {
             if (k >= 2 && zc != 0 && zc < 2 * k) continue;   // halo planes would dominate
             out.push_back(PassCfg{k, tile, zc});
@@ -548,7 +573,7 @@ extern "C" int frkc2_autotune(const frkc2_grid *g, const double *w, const double
         set_error("reps must lie in [1, 100] (got %d)", reps);
         return FRKC2_EINVAL;
     }
-    const StepLayout L = step_layout(kg.npts());
+    const StepLayout L = step_layout(kg.nstate());
     if (!ws || ws_bytes < L.total || !aligned16(ws)) {
         set_error("workspace needs %zu bytes (got %zu), 16-byte aligned", L.total, ws_bytes);
         return FRKC2_ENOMEM;
@@ -635,7 +660,7 @@ extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const 
 {
     KGrid kg;
     if (!make_kgrid(g, kg)) return FRKC2_EINVAL;
-    if (kg.op == FRKC2_OP_POROUS2) {
+    if (nonlinear(kg)) {
         set_error("the adjoint supports the linear operators (LAPLACE, VARCOEF)");
         return FRKC2_EINVAL;
     }
@@ -807,7 +832,7 @@ extern "C" int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, 
         set_error("max_attempts must be >= 1 and trace non-NULL when trace_cap > 0");
         return FRKC2_EINVAL;
     }
-    const long long N = kg.npts();
+    const long long N = kg.nstate();
     const AdaptLayout L = adapt_layout(N);
     if (!ws || ws_bytes < L.total || !aligned16(ws)) {
         set_error("workspace needs %zu bytes (got %zu), 16-byte aligned", L.total, ws_bytes);
@@ -833,7 +858,7 @@ extern "C" int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, 
         if (need_rho) {
             const int rc = rho_bound_impl(kg, w, D, partials, &rho, st);
             if (rc < 0) return rc;
-            need_rho = (kg.op == FRKC2_OP_POROUS2);
+            need_rho = nonlinear(kg);
         }
         double Tn = std::min(T, t_span - t);
         const double x = Tn * rho;
@@ -887,7 +912,7 @@ extern "C" int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, 
         err_prev = e;
         have_prev = true;
         T = Tn * fac;
-        if (kg.op == FRKC2_OP_POROUS2) need_rho = true;
+        if (nonlinear(kg)) need_rho = true;
     }
     HIP_TRY(hipStreamSynchronize(st), "integrate");
     if (stats) {

@@ -24,8 +24,10 @@ int coeffs_cached(int s, double nu, const double **re, const double **im, frkc2_
 struct KGrid {
     int ndim, nx, ny, nz;
     int bc, op;
+    int nfield;                 // values per point: 2 for the Brusselator (v, then w)
     double inv_h2, d_const;
     long long npts() const { return (long long)nx * ny * nz; }
+    long long nstate() const { return nfield * npts(); }
 };
 
 bool make_kgrid(const frkc2_grid *g, KGrid &k);
@@ -54,6 +56,12 @@ int launch_finalize(const KGrid &g, const double *in_c, double *out_re, double *
                     hipStream_t st);
 int launch_real_to_complex(long long n, const double *in, double *out_c, hipStream_t st);
 int launch_zero(long long n, double *p, hipStream_t st);   // fill kernel (graph-safe)
+
+// Two-species Brusselator (bruss.hip): one stage per pass; reaction part of
+// the Gershgorin bound into partials[kReduceBlocks].
+int launch_bruss(const KGrid &g, const PassArgs &p, hipStream_t st);
+int launch_bruss_react_max(const KGrid &g, const double *w, double *partials, hipStream_t st);
+int launch_max_partials(double *partials, hipStream_t st);   // max of kReduceBlocks partials
 
 // Temporally blocked passes (tblock.hip): p.k stages in one HBM pass.
 bool tblock_supported(const KGrid &g, int k);

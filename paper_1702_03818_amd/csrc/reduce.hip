@@ -225,6 +225,13 @@ int launch_err_max(const double *Wc, const double *E, long long n, double tol, d
     return (int)hipGetLastError();
 }
 
+int launch_max_partials(double *partials, hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_pass2<R_MAX>, dim3(1), dim3(kThreads), 0, st, partials,
+                       kReduceBlocks);
+    return (int)hipGetLastError();
+}
+
 int launch_take_real(const double *Wc, double *w, long long n, hipStream_t st)
 {
     long long nb = (n + kThreads - 1) / kThreads;

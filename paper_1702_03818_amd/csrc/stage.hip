@@ -233,6 +233,7 @@ int launch_pass(const KGrid &g, const PassArgs &a, int /*tblock_hint*/, hipStrea
 {
     // one stage per pass (k = 1)
     if (a.k != 1) return (int)hipErrorInvalidValue;
+    if (g.op == FRKC2_OP_BRUSS2) return launch_bruss(g, a, st);
     PlaneArgs pa{};
     pa.in_re = a.in_re;
     pa.in_c = reinterpret_cast<const double2 *>(a.in_c);
@@ -293,7 +294,7 @@ int launch_stage1d_lds(const KGrid &g, const double *w_in, double *w_out, const 
 int launch_finalize(const KGrid &g, const double *in_c, double *out_re, double *partials,
                     hipStream_t st)
 {
-    const long long n = g.npts();
+    const long long n = g.nstate();
     hipLaunchKernelGGL(finalize_kernel, dim3(kReduceBlocks), dim3(kFinThreads), 0, st,
                        reinterpret_cast<const double2 *>(in_c), out_re, n, partials);
     hipLaunchKernelGGL(finalize_sum, dim3(1), dim3(64), 0, st, partials, kReduceBlocks);
