@@ -39,7 +39,7 @@ def log(msg):
 
 # Sources that define the dominant kernel of each tile shape (k = 1: the plane kernel).
 KERNEL_SOURCES = {1: ("stage.hip", "plane_tile.h"), 2: ("tblock.hip",), 3: ("tblock.hip",),
-                  4: ("tb3d.hip",)}
+                  4: ("tb3d.hip", "tb3d_tile.h")}
 COMMON_SOURCES = ("device_common.h", "internal.h")
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_stage3d_256.json")
 
@@ -72,7 +72,7 @@ def kernel_pattern(k, tile):
     if k == 1:
         return "plane_stage<1, 1, 3, 64, 4, false, false>"
     if tile == 4:
-        return "tb3d_stage<1, 1, %d, false, false>" % k
+        return "tb3d_stage<1, 1, %d, false, false, false>" % k
     shape = {1: "64, 16, 1", 2: "64, 16, 2", 3: "64, 8, %d" % (4 if k == 2 else 3)}[tile]
     return "tb_stage<1, 1, 3, %s, %d, false, false>" % (shape, k)
 
@@ -302,6 +302,52 @@ def adaptive_leg(F, wl, torch, prob, D, rho, info):
             "fixed_step_stages": S_STAGES * SUPERSTEPS}
 
 
+def brusselator_leg(F, wl, torch):
+    """The paper's two-species Brusselator (Sec. 3.1). Throughput: 5 supersteps (s = 100,
+    T = 0.9 betabar / rho of the current state) on a 2048^2 grid. Accuracy: error-controlled
+    runs on the paper's 200^2 grid from its initial data to t = 1 at several tolerances, with
+    the accepted steps, the stages and the max error against a tol = 1e-8 run (the paper's
+    steps-to-error comparison, FRKC2 alone)."""
+    big = wl.brusselator(2048)
+    w = torch.tensor(big.w0.reshape(-1), dtype=torch.float64, device="cuda")
+    F.frkc2_step(big, w, None, cfl=CFL, s=S_STAGES, nsteps=1)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    F.frkc2_step(big, w, None, cfl=CFL, s=S_STAGES, nsteps=5)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    n = big.npoints
+    thr = {"grid": [2048, 2048], "s": S_STAGES, "ms_per_superstep": ms,
+           "value": n * S_STAGES / (ms * 1e-3), "unit": "grid-point-stage updates/s (2 species)",
+           "bytes_per_point_stage": 64,
+           "achieved_gbs": 64 * n * S_STAGES / (ms * 1e-3) / 1e9}
+    del w
+    p = wl.brusselator(200)
+    runs = []
+    ref = torch.tensor(p.w0.reshape(-1), dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    st_ref, _ = F.frkc2_integrate(p, ref, None, t_span=1.0, T0=1e-4, tol=1e-8, max_attempts=200000)
+    ref_s = time.perf_counter() - t0
+    for tol in (1e-3, 1e-4, 1e-5, 1e-6):
+        w = torch.tensor(p.w0.reshape(-1), dtype=torch.float64, device="cuda")
+        t0 = time.perf_counter()
+        st, _ = F.frkc2_integrate(p, w, None, t_span=1.0, T0=1e-4, tol=tol, max_attempts=200000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        err = float(torch.max(torch.abs(w - ref)))
+        runs.append({"tol": tol, "accepted": st["accepted"], "rejected": st["rejected"],
+                     "stages": st["stages"], "max_error": err, "wall_ms": dt * 1e3})
+        log("brusselator tol %.0e: %d steps, %d stages, error %.2e" % (tol, st["accepted"],
+                                                                     st["stages"], err))
+    return {"throughput": thr, "t_end": 1.0, "reference": {"tol": 1e-8, "accepted": st_ref["accepted"],
+                                                          "stages": st_ref["stages"],
+                                                          "wall_s": ref_s},
+            "steps_to_error": runs}
+
+
 def adjoint_leg(F, wl, torch, reps=3):
     """3D 128^3 variable D, s = 64, 8 supersteps, J = sum (w - target)^2: forward alone
     and forward + adjoint through the autograd function."""
@@ -361,6 +407,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batched leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the error-control leg")
+    ap.add_argument("--no-bruss", action="store_true", help="skip the Brusselator leg")
     ap.add_argument("--tblock", type=int, default=0, choices=(0, 1, 2, 3),
                     help="stages fused per HBM pass in the timed run (0: autotune)")
     ap.add_argument("--tile", type=int, default=0, help="tile shape with --tblock (0: automatic)")
@@ -539,6 +586,8 @@ def main():
     torch.cuda.empty_cache()
     F.release_workspaces()
     out["adjoint"] = None if args.no_adjoint else adjoint_leg(F, wl, torch)
+    torch.cuda.empty_cache()
+    out["brusselator"] = None if args.no_bruss else brusselator_leg(F, wl, torch)
     if not args.no_cpu:
         log("timing the CPU oracle on one superstep")
         out["cpu_baseline"] = cpu_baseline(prob, T, info)
