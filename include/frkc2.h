@@ -127,6 +127,21 @@ typedef struct {
 int frkc2_coeffs(int s, double nu, double *a_re, double *a_im, frkc2_coeff_info *info);
 
 /*
+ * frkc2_write_table -- the stepsize table in the layout of the paper's public
+ * code (Sec. 3.1, "FRKC2 public code"): for M = 1 .. m_max (s = 2M stages),
+ * line 3M-2 holds betabar and the realised Q, line 3M-1 the real parts and
+ * line 3M the imaginary parts of a_1 .. a_s in execution order (%.17g,
+ * space separated). The section prints "lines 3M-2 and 3M" for the real and
+ * imaginary parts; with betabar and Q already on line 3M-2 the real parts are
+ * taken to be on line 3M-1.
+ *   path   file to write (created or truncated), host string
+ *   nu     damping, 0 <= nu < 1
+ *   m_max  1 .. 257
+ * Host only, no GPU use. Errors: FRKC2_EINVAL (arguments, file).
+ */
+int frkc2_write_table(const char *path, double nu, int m_max);
+
+/*
  * frkc2_workspace_bytes -- device workspace needed by the calls below for grid g.
  *   FRKC2_WS_STEP: frkc2_step and frkc2_rho_bound (two complex state buffers
  *   plus reduction scratch); FRKC2_WS_ADJOINT: frkc2_step_adjoint (s stored

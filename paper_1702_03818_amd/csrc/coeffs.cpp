@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -307,4 +308,42 @@ extern "C" int frkc2_coeffs(int s, double nu, double *a_re, double *a_im, frkc2_
     if (a_re) std::memcpy(a_re, re, sizeof(double) * (size_t)s);
     if (a_im) std::memcpy(a_im, im, sizeof(double) * (size_t)s);
     return rc;
+}
+
+extern "C" int frkc2_write_table(const char *path, double nu, int m_max)
+{
+    if (!path || m_max < 1 || m_max > frkc2::kMaxStages / 2) {
+        frkc2::set_error("write_table: need a path and 1 <= m_max <= %d", frkc2::kMaxStages / 2);
+        return FRKC2_EINVAL;
+    }
+    if (!(nu >= 0.0 && nu < 1.0)) {
+        frkc2::set_error("write_table: nu must lie in [0, 1) (got %g)", nu);
+        return FRKC2_EINVAL;
+    }
+    // generate everything first, so a bad entry leaves no partial file
+    std::vector<const double *> re(m_max + 1), im(m_max + 1);
+    std::vector<frkc2_coeff_info> info(m_max + 1);
+    for (int M = 1; M <= m_max; ++M) {
+        const int rc = frkc2::coeffs_cached(2 * M, nu, &re[M], &im[M], &info[M]);
+        if (rc < 0) return rc;
+    }
+    FILE *f = std::fopen(path, "w");
+    if (!f) {
+        frkc2::set_error("write_table: cannot open %s for writing", path);
+        return FRKC2_EINVAL;
+    }
+    for (int M = 1; M <= m_max; ++M) {
+        std::fprintf(f, "%.17g %.17g\n", info[M].beta_bar, info[M].q_realised);
+        for (int part = 0; part < 2; ++part) {
+            const double *a = part ? im[M] : re[M];
+            for (int l = 0; l < 2 * M; ++l) std::fprintf(f, l ? " %.17g" : "%.17g", a[l]);
+            std::fputc('\n', f);
+        }
+    }
+    const bool bad = std::ferror(f) != 0;
+    if (std::fclose(f) != 0 || bad) {
+        frkc2::set_error("write_table: write to %s failed", path);
+        return FRKC2_EINVAL;
+    }
+    return FRKC2_OK;
 }

@@ -101,6 +101,7 @@ _SIGS = {
     "frkc2_autotune": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_int, _VP, ctypes.c_size_t, _VP,
                                       ctypes.POINTER(TuneResult)]),
+    "frkc2_write_table": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_double, ctypes.c_int]),
     "frkc2_set_option": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     "frkc2_last_error": (ctypes.c_char_p, []),
     "frkc2_version": (ctypes.c_char_p, []),
@@ -337,6 +338,11 @@ def frkc2_reduce(op: int, x, y=None, stream=None) -> float:
     _check(lib.frkc2_reduce(int(op), _ptr(x), _ptr(y), x.numel(), ctypes.byref(out),
                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
     return out.value
+
+
+def frkc2_write_table(path, nu: float = 0.01, m_max: int = 257):
+    """Write the stepsize table (betabar, Q / Re a / Im a per M) in the public-code layout."""
+    return _check(load().frkc2_write_table(os.fsencode(path), float(nu), int(m_max)))
 
 
 def frkc2_set_option(key: int, value: int):

@@ -193,3 +193,29 @@ def test_adapt_workspace_bytes():
     N = 64 * 32 * 16
     b = lib.frkc2_workspace_bytes(ctypes.byref(g), 0, F.WS_ADAPT)
     assert 48 * N <= b < 48 * N + (1 << 20)
+
+
+@pytest.mark.parametrize("nu", [0.01, 0.25])
+def test_write_table_layout_and_values(tmp_path, nu):
+    """Three lines per M: betabar and Q, then Re a and Im a of the s = 2M stages, equal to the
+    oracle's stepsizes (betabar and a exactly, Q to rounding)."""
+    path = tmp_path / "frkc2arks.dat"
+    m_max = 12
+    F.frkc2_write_table(str(path), nu, m_max)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 3 * m_max
+    for M in range(1, m_max + 1):
+        bb, q = (float(v) for v in lines[3 * M - 3].split())
+        re_ = np.array([float(v) for v in lines[3 * M - 2].split()])
+        im_ = np.array([float(v) for v in lines[3 * M - 1].split()])
+        o = oracle_coeffs(2 * M, nu)
+        assert bb == o.beta_bar
+        assert abs(q / o.q_realised - 1) < 1e-12
+        assert np.array_equal(re_, o.a_re) and np.array_equal(im_, o.a_im)
+
+
+def test_write_table_rejects():
+    assert F.load().frkc2_write_table(b"/tmp/x", 0.01, 0) == -1
+    assert F.load().frkc2_write_table(b"/tmp/x", 0.01, 258) == -1
+    assert F.load().frkc2_write_table(b"/nonexistent-dir/x", 0.01, 2) == -1
+    assert F.load().frkc2_write_table(None, 0.01, 2) == -1
