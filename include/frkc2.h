@@ -286,6 +286,29 @@ int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, double t_sp
                     hipStream_t st, double *trace, int trace_cap, frkc2_adapt_stats *stats);
 
 /*
+ * frkc2_step_user -- supersteps with a caller-supplied operator, the split of
+ * the paper's public code into the scheme's core and the problem's f
+ * (Sec. 3.1). The library keeps the complex stage W (interleaved re, im, n
+ * values) and the stepsizes; per stage it calls f(W, F, n, user, st), which
+ * must write F = f(W) (complex, the holomorphic continuation of the caller's
+ * real operator) on stream st and return 0, and then applies
+ * W <- W + T a_l F on the GPU (fma order of frkc2_step). The first stage
+ * starts from (w, 0); the superstep keeps Re W^L in w.
+ *   n, w     values per state, device state (in/out)
+ *   f, user  callback and its context; W and F are device pointers into ws
+ *   T, rho   superstep length and a bound on the spectral radius of f's
+ *            Jacobian (T rho <= betabar(s) is required; rho = 0 skips it)
+ *   s, nu, nsteps  as for frkc2_step
+ *   ws       frkc2_workspace_bytes of any grid with n points (32 n bytes +
+ *            scratch), 16-byte aligned
+ * Errors: FRKC2_EINVAL (arguments, checked before any HIP call; a non-zero
+ * return of f), FRKC2_EUNSTABLE, FRKC2_ENOMEM, FRKC2_EHIP.
+ */
+typedef int (*frkc2_user_f)(const double *W, double *F, long long n, void *user, hipStream_t st);
+int frkc2_step_user(long long n, double *w, frkc2_user_f f, void *user, double T, double rho,
+                    int s, double nu, int nsteps, void *ws, size_t ws_bytes, hipStream_t st);
+
+/*
  * frkc2_autotune -- pick the launch configuration of frkc2_step's passes for
  * one grid by timing. The stages of a superstep are applied one after the
  * other (Sec. 3, the Euler-step recursion), so any number k of consecutive

@@ -928,6 +928,50 @@ extern "C" int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, 
     return FRKC2_OK;
 }
 
+extern "C" int frkc2_step_user(long long n, double *w, frkc2_user_f f, void *user, double T,
+                               double rho, int s, double nu, int nsteps, void *ws,
+                               size_t ws_bytes, hipStream_t st)
+{
+    if (n < 1 || !w || !f) {
+        set_error("user step: need n >= 1, w and f");
+        return FRKC2_EINVAL;
+    }
+    if (!check_s_nu(s, nu)) return FRKC2_EINVAL;
+    if (nsteps < 0 || !(T > 0.0) || !std::isfinite(T) || !(rho >= 0.0) || !std::isfinite(rho)) {
+        set_error("user step: need nsteps >= 0, T > 0 and rho >= 0, finite");
+        return FRKC2_EINVAL;
+    }
+    const StepLayout L = step_layout(n);
+    if (!ws || ws_bytes < L.total || !aligned16(ws)) {
+        set_error("workspace needs %zu bytes (got %zu), 16-byte aligned", L.total, ws_bytes);
+        return FRKC2_ENOMEM;
+    }
+    const double *are, *aim;
+    frkc2_coeff_info info;
+    const int crc = coeffs_cached(s, nu, &are, &aim, &info);
+    if (crc < 0) return crc;
+    if (T * rho > info.beta_bar) {
+        set_error("T*rho = %g exceeds beta_bar = %g", T * rho, info.beta_bar);
+        return FRKC2_EUNSTABLE;
+    }
+    char *base = static_cast<char *>(ws);
+    double *W = reinterpret_cast<double *>(base + L.bufA);
+    double *F = reinterpret_cast<double *>(base + L.bufB);
+    for (int step = 0; step < nsteps; ++step) {
+        HIP_TRY(launch_real_to_complex(n, w, W, st), "user step: W^0");
+        for (int l = 0; l < s; ++l) {
+            const int urc = f(W, F, n, user, st);
+            if (urc != 0) {
+                set_error("user step: f returned %d at stage %d", urc, l);
+                return FRKC2_EINVAL;
+            }
+            HIP_TRY(launch_euler_axpy(n, W, F, T * are[l], T * aim[l], st), "user step: update");
+        }
+        HIP_TRY(launch_take_real(W, w, n, st), "user step: Re W^L");
+    }
+    return crc;
+}
+
 extern "C" int frkc2_reduce(int op, const double *x, const double *y, size_t n, double *result,
                             void *ws, size_t ws_bytes, hipStream_t st)
 {

@@ -72,6 +72,8 @@ class TuneResult(ctypes.Structure):
 
 _lib = None
 _VP = ctypes.c_void_p
+USER_F = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong,
+                          ctypes.c_void_p, ctypes.c_void_p)
 _DP = ctypes.POINTER(ctypes.c_double)
 
 _SIGS = {
@@ -98,6 +100,9 @@ _SIGS = {
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_int, _VP, ctypes.c_size_t, _VP, _DP, ctypes.c_int,
                                        ctypes.POINTER(AdaptStats)]),
+    "frkc2_step_user": (ctypes.c_int, [ctypes.c_longlong, _VP, USER_F, _VP, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                       _VP, ctypes.c_size_t, _VP]),
     "frkc2_autotune": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_int, _VP, ctypes.c_size_t, _VP,
                                       ctypes.POINTER(TuneResult)]),
@@ -254,6 +259,39 @@ def frkc2_integrate(grid, w, D=None, t_span=1.0, T0=1e-6, tol=1e-4, nu=0.01, max
                                ctypes.byref(st)))
     stats = {f: getattr(st, f) for f, _ in AdaptStats._fields_}
     return stats, tr[:min(stats["attempts"], tr.shape[0])]
+
+
+def frkc2_step_user(w, f, T, rho=0.0, s=16, nu=0.01, nsteps=1, stream=None):
+    """nsteps supersteps of w (float64, device) under a caller operator: f(W, F) receives the
+    complex128 stage W and must write f(W) into F (both views of the library's workspace),
+    on the current stream. The library applies the stepsizes and the Euler updates."""
+    torch = _torch()
+    lib = load()
+    n = int(w.numel())
+    need = 32 * n + 4 * 256 + 64 * 1024
+    buf = workspace(need, key="user")
+    base = buf.data_ptr()
+    off_b = (16 * n + 255) // 256 * 256
+    Wv = buf[: 16 * n].view(torch.float64).view(torch.complex128)
+    Fv = buf[off_b: off_b + 16 * n].view(torch.float64).view(torch.complex128)
+    err = []
+
+    def cb(W, F, nn, user, st):
+        try:
+            if W != base or F != base + off_b or nn != n:
+                return 2
+            f(Wv, Fv)
+            return 0
+        except Exception as e:   # reported after the call returns
+            err.append(e)
+            return 1
+
+    cfun = USER_F(cb)
+    rc = lib.frkc2_step_user(n, _ptr(w), cfun, None, float(T), float(rho), int(s), float(nu),
+                             int(nsteps), ctypes.c_void_p(base), buf.numel(), _stream_ptr(stream))
+    if err:
+        raise err[0]
+    return _check(rc)
 
 
 def frkc2_autotune(grid, w, D=None, s=16, nu=0.01, reps=2, stream=None, ws=None):

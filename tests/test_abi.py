@@ -219,3 +219,26 @@ def test_write_table_rejects():
     assert F.load().frkc2_write_table(b"/tmp/x", 0.01, 258) == -1
     assert F.load().frkc2_write_table(b"/nonexistent-dir/x", 0.01, 2) == -1
     assert F.load().frkc2_write_table(None, 0.01, 2) == -1
+
+
+def test_step_user_validation():
+    lib = F.load()
+    cb = F.USER_F(lambda W, Fp, n, user, st: 0)   # never called: validation fails first
+    p = ctypes.c_void_p(4096 * 16)
+    ok = dict(n=1000, w=p, f=cb, T=1e-3, rho=10.0, s=16, nu=0.01, nsteps=1, ws=p, wsb=1 << 40)
+
+    def call(**kw):
+        a = dict(ok)
+        a.update(kw)
+        return lib.frkc2_step_user(a["n"], a["w"], a["f"], None, a["T"], a["rho"], a["s"], a["nu"],
+                                   a["nsteps"], a["ws"], a["wsb"], None)
+    assert call(n=0) == -1
+    assert call(w=None) == -1
+    assert call(f=F.USER_F()) == -1
+    assert call(s=7) == -1
+    assert call(T=0.0) == -1
+    assert call(rho=-1.0) == -1
+    assert call(nsteps=-1) == -1
+    assert call(ws=None) == -2
+    assert call(wsb=100) == -2
+    assert call(T=1.0, rho=1e6) == -4          # T rho beyond betabar(16)
