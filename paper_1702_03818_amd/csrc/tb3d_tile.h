@@ -32,6 +32,19 @@ struct Tb3Shape {
     static constexpr int BXE = 64 + 2 * K;
     static constexpr int BYO = BYE - 2 * K;
     static_assert(2 * K * BYE <= 64 * NHW, "halo columns must fit the halo wavefronts");
+    // Role of wavefront w (rows 0..BYE-1, then the halo wavefronts). The
+    // wavefronts of a workgroup are dealt to the CU's four SIMDs in turn
+    // (w % 4), and a row computes min(row, BYE-1-row, K) levels, so the roles
+    // are permuted to give every SIMD the same work before the barrier: for
+    // K = 3 each SIMD gets 8 row-levels (rows 3 4 2 0 | 5 6 11 13 | 7 8 A B |
+    // 9 10 1 12) instead of 7 to 10 in natural order; for K = 2 the natural
+    // order is already balanced (6 6 6 7).
+    static __device__ __forceinline__ int role(int w)
+    {
+        if (K != 3) return w;
+        constexpr int perm[16] = {3, 5, 7, 9, 4, 6, 8, 10, 2, 11, 14, 1, 0, 13, 15, 12};
+        return perm[w];
+    }
 };
 
 __device__ __forceinline__ double2 keep3(double2 v, bool ghost)
@@ -68,7 +81,7 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
 
     const Dims dm{a.nx, a.ny, a.nz};
     const int tid = threadIdx.x;
-    const int wv = tid >> 6, lane = tid & 63;
+    const int wv = S::role(tid >> 6), lane = tid & 63;
     int lx, ly;                                     // position in the extended tile
     if (wv < BYE) {
         lx = K + lane;
