@@ -13,7 +13,8 @@
 // same column, which the thread keeps in registers, and level m-1 at the x/y
 // neighbours of plane p, which sit in LDS (one plane per level, written in
 // the previous time step). The diffusivity planes t-K-1 .. t-1 live in an LDS
-// ring. Two barriers per time step separate the LDS reads from the writes.
+// ring. Two barriers per time step separate the LDS reads from the writes
+// (one for 2D rows, whose planes are double-buffered where LDS allows).
 //
 // Level 0 is prefetched two time steps ahead into a five-slot register ring;
 // the time loop is unrolled by five so the slot indices are compile-time
@@ -70,11 +71,18 @@ __global__ __launch_bounds__(BXE *TY) void tb_stage(TbArgs a)
     constexpr int SY = (NDIM == 3) ? BYE + 2 : 1;
     constexpr int PL = SX * SY;                     // padded plane
     constexpr bool VC = (OP == VAR);
-    constexpr int ND = K + 1;                       // D ring: planes t-K-1 .. t-1
+    // 2D rows are small: where LDS allows, their level planes are
+    // double-buffered by step parity, so one barrier per step suffices; 3D
+    // tiles keep one buffer and separate reads from writes with a second
+    // barrier.
+    constexpr bool DB = (NDIM == 2) &&
+                        (2 * K * PL * 16 + (VC ? (K + 2) * PL * 8 : 0) <= 160 * 1024);
+    constexpr int NB = DB ? 2 : 1;
+    constexpr int ND = DB ? K + 2 : K + 1;          // D ring: planes t-K-1 .. t-1 (and t)
     constexpr int BXO = BXE - 2 * K;                // output tile
     constexpr int BYO = (NDIM == 3) ? BYE - 2 * K : 1;
     static_assert(BXO > 0 && BYO > 0, "tile too small for K");
-    __shared__ double2 sL[K][PL];                   // level m plane (m = 0..K-1)
+    __shared__ double2 sL[NB][K][PL];               // level m plane (m = 0..K-1)
     __shared__ double sD[VC ? ND : 1][VC ? PL : 1];
 
     const Dims dm{a.nx, a.ny, a.nz};
@@ -166,11 +174,12 @@ __global__ __launch_bounds__(BXE *TY) void tb_stage(TbArgs a)
         // ghosts once, in its ring slot
 #pragma unroll
         for (int r = 0; r < R; ++r) L0[rs(0)][r] = keep(L0[rs(0)][r], col_ghost[r] || pout(t));
+        const int rb = DB ? ((t - 1) & 1) : 0, wb = DB ? (t & 1) : 0;
         // levels 1..K at planes t-1 .. t-K
 #pragma unroll
         for (int m = 1; m <= K; ++m) {
             const int p = t - m;
-            const double2 *L = sL[m - 1];
+            const double2 *L = sL[rb][m - 1];
             const double *Dc_ = VC ? sD[dslot(p)] : nullptr;
             const double *Dm_ = VC ? sD[dslot(p - 1)] : nullptr;
             const double *Dp_ = VC ? sD[dslot(p + 1)] : nullptr;
@@ -236,12 +245,12 @@ __global__ __launch_bounds__(BXE *TY) void tb_stage(TbArgs a)
                 }
             }
         }
-        __syncthreads();   // every read of the LDS planes of this step is done
+        if (!DB) __syncthreads();   // every read of the LDS planes of this step is done
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            sL[0][slot[r]] = L0[rs(0)][r];
+            sL[wb][0][slot[r]] = L0[rs(0)][r];
 #pragma unroll
-            for (int m = 1; m < K; ++m) sL[m][slot[r]] = wp[m - 1][r];
+            for (int m = 1; m < K; ++m) sL[wb][m][slot[r]] = wp[m - 1][r];
             if (VC) sD[dslot(t)][slot[r]] = D0[rs(0)][r];
         }
         __syncthreads();   // the planes of step t are visible to step t+1
