@@ -50,7 +50,7 @@ typedef enum {
     FRKC2_EHIP = -3,        /* HIP runtime error (including earlier asynchronous faults) */
     FRKC2_EUNSTABLE = -4,   /* T * rho > betabar: the superstep would leave the stability interval */
     FRKC2_ENONFINITE = -5,  /* a norm or bound came out NaN or infinite */
-    FRKC2_ETIMEOUT = -6     /* batched: a bounded dependency wait expired (results invalid) */
+    FRKC2_ETIMEOUT = -6     /* frkc2_integrate: attempt limit reached before the end time */
 } frkc2_status;
 
 typedef enum { FRKC2_BC_PERIODIC = 0, FRKC2_BC_DIRICHLET0 = 1 } frkc2_bc;
@@ -201,8 +201,10 @@ int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const double *D, 
 /*
  * frkc2_step_batched -- one superstep for each of nprob independent problems
  * (VARCOEF or LAPLACE, 2D or 3D, each with its own grid, T and s) in a single
- * HIP graph launch: one kernel per stage level l, covering stage l of every
- * problem with s > l.
+ * HIP graph launch. The graph has two concurrent branches: 3D problems
+ * advance in pass levels (level L: stages 3L .. 3L+2 of every problem that has
+ * them, fused in one HBM pass, then the remaining single stages), 2D problems
+ * in stage levels (level l: stage l of every problem with s > l).
  *   grids  host array of nprob grids
  *   w      host array of nprob device pointers (in/out states, real)
  *   D      host array of nprob device pointers (NULL entries for LAPLACE)
@@ -358,13 +360,11 @@ int frkc2_autotune(const frkc2_grid *g, const double *w, const double *D, int s,
  *                     frkc2_step, 0 = automatic (halve from the whole depth
  *                     until >= 512 workgroups for 3D fused passes, >= 2048
  *                     otherwise)
- *   FRKC2_OPT_XCD_REMAP  reserved (1)
  *   FRKC2_OPT_CLEAR_TUNED  forget every configuration frkc2_autotune stored
  *                     (value ignored)
  * Results are identical, bit for bit, for every setting.
  */
 #define FRKC2_OPT_TBLOCK 1
-#define FRKC2_OPT_XCD_REMAP 2
 #define FRKC2_OPT_TILE 3
 #define FRKC2_OPT_CLEAR_TUNED 4
 #define FRKC2_OPT_ZCHUNK 5

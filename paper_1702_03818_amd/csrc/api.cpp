@@ -26,7 +26,6 @@ thread_local char g_err[512] = "";
 int g_tblock = 0;
 int g_tile = 0;
 int g_zchunk = 0;
-int g_xcd_remap = 1;
 
 constexpr size_t kAlign = 256;
 constexpr size_t kScratch = 64 * 1024;   // reduction partials + stepsize table
@@ -329,8 +328,6 @@ bool check_s_nu(int s, double nu)
 
 }  // namespace
 
-int get_tblock() { return g_tblock; }
-int get_xcd_remap() { return g_xcd_remap; }
 
 }  // namespace frkc2
 
@@ -369,10 +366,6 @@ extern "C" int frkc2_set_option(int key, int value)
     if (key == FRKC2_OPT_CLEAR_TUNED) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tuned.clear();
-        return FRKC2_OK;
-    }
-    if (key == FRKC2_OPT_XCD_REMAP) {
-        g_xcd_remap = value ? 1 : 0;
         return FRKC2_OK;
     }
     set_error("unknown option %d", key);

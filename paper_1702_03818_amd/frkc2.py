@@ -28,7 +28,6 @@ WS_ADJOINT = 1
 WS_ADAPT = 2
 RED_SUMSQ, RED_SUM, RED_MAXSQ, RED_SUMSQDIFF, RED_DOT = 0, 1, 2, 3, 4
 OPT_TBLOCK = 1
-OPT_XCD_REMAP = 2
 OPT_TILE = 3
 OPT_CLEAR_TUNED = 4
 OPT_ZCHUNK = 5
