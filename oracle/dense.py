@@ -61,6 +61,16 @@ def R_hp(a: np.ndarray, x: float) -> float:
         return float(mp.re(r))
 
 
+def R_hp_complex(a: np.ndarray, z: complex) -> complex:
+    """R(z) for complex z, in 50-digit arithmetic from the FP64 stepsizes."""
+    with mp.workdps(50):
+        r = mp.mpc(1)
+        zm = mp.mpc(float(z.real), float(z.imag))
+        for al in a:
+            r *= 1 + mp.mpc(float(al.real), float(al.imag)) * zm
+        return complex(r)
+
+
 def superstep(prob, w, a: np.ndarray, T: float, D=None) -> np.ndarray:
     """R(T A) w via the eigendecomposition of the assembled symmetric A."""
     A = assemble(prob, D)

@@ -48,16 +48,35 @@
 #include <string.h>
 
 enum { BC_PERIODIC = 0, BC_DIRICHLET0 = 1 };
-enum { OP_LAPLACE = 0, OP_VARCOEF = 1, OP_POROUS2 = 2, OP_BRUSS2 = 3 };
+enum { OP_LAPLACE = 0, OP_VARCOEF = 1, OP_POROUS2 = 2, OP_BRUSS2 = 3, OP_ADVDIFF = 4 };
 
 typedef struct {
     int ndim;
     long n[3];
     int bc, op;
     double inv_h2, d_const;
+    double fc[6];   /* op 4: coefficient of face f = 2*dim + side */
 } grid_t;
 
+/* Op 4, advection-diffusion f = d lap u - v . grad u with central differences
+ * (Sec. 2.1: the damped schemes for problems with a small hyperbolic part):
+ * the flux form d (u_nb - u_c)/h^2 per face plus -v_k (u_{+} - u_{-})/(2h)
+ * per dimension gives face coefficients d + v_k h/2 (minus side) and
+ * d - v_k h/2 (plus side); the caller passes them in fc, computed as
+ * d + (0.5*h)*v_k and d - (0.5*h)*v_k. */
+
 static long npts(const grid_t *g) { return g->n[0] * g->n[1] * g->n[2]; }
+
+/* Face coefficients of op 4 for the calls that follow (set from Python before
+ * each call; the oracle is not called from several threads at once). */
+static double g_fc[6];
+static int g_fc_set = 0;
+
+void oracle_set_faces(const double *fc)
+{
+    g_fc_set = fc != NULL;
+    for (int f = 0; f < 6; ++f) g_fc[f] = fc ? fc[f] : 0.0;
+}
 
 /* Values per grid point: the Brusselator carries two species (v then w). */
 static int nfield(const grid_t *g) { return g->op == OP_BRUSS2 ? 2 : 1; }
@@ -160,6 +179,8 @@ static void apply_op(const grid_t *g, const double *D, const double *wr, const d
                 double Df;
                 if (g->op == OP_LAPLACE) {
                     Df = g->d_const;
+                } else if (g->op == OP_ADVDIFF) {
+                    Df = g->fc[f];
                 } else {
                     double Dn = (q < 0) ? D[p] : D[q];
                     Df = 0.5 * (D[p] + Dn);
@@ -176,6 +197,7 @@ static void apply_op(const grid_t *g, const double *D, const double *wr, const d
 static int make_grid(grid_t *g, int ndim, const long *n, int bc, int op, double inv_h2,
                      double d_const)
 {
+    for (int f = 0; f < 6; ++f) g->fc[f] = (op == OP_ADVDIFF && g_fc_set) ? g_fc[f] : d_const;
     if (ndim < 1 || ndim > 3) return -1;
     g->ndim = ndim;
     for (int d = 0; d < 3; ++d) g->n[d] = (d < ndim) ? n[d] : 1;
@@ -240,7 +262,7 @@ int oracle_adjoint(int ndim, const long *n, int bc, int op, double inv_h2, doubl
                    const double *w_n, const double *lam_next, double *lam_n, double *grad_logD)
 {
     grid_t g;
-    if (op == OP_POROUS2 || op == OP_BRUSS2) return -1;
+    if (op == OP_POROUS2 || op == OP_BRUSS2 || op == OP_ADVDIFF) return -1;
     if (make_grid(&g, ndim, n, bc, op, inv_h2, d_const)) return -1;
     long N = npts(&g);
     double *store = malloc(sizeof(double) * 2 * N * (size_t)s);
@@ -309,6 +331,15 @@ double oracle_rho_bound(int ndim, const long *n, int bc, int op, double inv_h2, 
 {
     grid_t g;
     if (make_grid(&g, ndim, n, bc, op, inv_h2, d_const)) return -1.0;
+    if (op == OP_ADVDIFF) {
+        /* |a_ii| + sum_j |a_ij| with a_ii = -sum_f fc_f / h^2, a_ij = fc_f / h^2 */
+        double sum = 0.0, asum = 0.0;
+        for (int f = 0; f < 2 * ndim; ++f) {
+            sum = sum + g.fc[f];
+            asum = asum + fabs(g.fc[f]);
+        }
+        return (fabs(sum) + asum) * inv_h2;
+    }
     long N = npts(&g);
     double m = 0.0;
     for (long p = 0; p < N; ++p) {

@@ -54,6 +54,8 @@ def _load():
         lib.oracle_rho_bound.argtypes = [ctypes.c_int, lp, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_double, ctypes.c_double, dp, dp]
         lib.oracle_rho_bound.restype = ctypes.c_double
+        lib.oracle_set_faces.argtypes = [dp]
+        lib.oracle_set_faces.restype = None
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
@@ -66,9 +68,26 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+def face_coefficients(prob):
+    """Op 4 (advection-diffusion, central differences): coefficient of face f = 2*dim + side,
+    d + (0.5*h)*v_dim on the minus side and d - (0.5*h)*v_dim on the plus side."""
+    vel = list(getattr(prob, "vel", (0.0, 0.0, 0.0))) + [0.0] * 3
+    fc = np.empty(6)
+    for k in range(3):
+        fc[2 * k] = prob.d_const + (0.5 * prob.h) * vel[k]
+        fc[2 * k + 1] = prob.d_const - (0.5 * prob.h) * vel[k]
+    return fc
+
+
 def _grid_args(prob):
     n = (ctypes.c_long * 3)(*[int(v) for v in prob.n])
     inv_h2 = 1.0 / (prob.h * prob.h)
+    lib = _load()
+    if prob.op == 4:
+        _grid_args.fc = face_coefficients(prob)
+        lib.oracle_set_faces(_dp(_grid_args.fc))
+    else:
+        lib.oracle_set_faces(None)
     return n, inv_h2
 
 

@@ -29,6 +29,7 @@ OP_LAPLACE = 0
 OP_VARCOEF = 1
 OP_POROUS2 = 2
 OP_BRUSS2 = 3
+OP_ADVDIFF = 4
 
 
 @dataclass
@@ -42,6 +43,7 @@ class Problem:
     D: np.ndarray | None = None     # cell diffusivity (op = OP_VARCOEF)
     w0: np.ndarray | None = None    # initial state
     meta: dict = field(default_factory=dict)
+    vel: tuple = (0.0, 0.0, 0.0)    # advection velocity per dimension (op = OP_ADVDIFF)
 
     @property
     def nfield(self) -> int:
