@@ -74,6 +74,15 @@ typedef enum { FRKC2_BC_PERIODIC = 0, FRKC2_BC_DIRICHLET0 = 1 } frkc2_bc;
  *           f = fma(acc, 1/h^2, R) per component. Gershgorin bound:
  *           (2/h^2)(4d) + max_c max(|2vw - 4| + v^2, v^2 + |3 - 2vw|).
  *           One stage per pass; not available to the batched and adjoint calls.
+ *  ADVDIFF  f = d lap u - v . grad u with central differences (Sec. 2.1:
+ *           damping makes the schemes usable for problems with a small
+ *           hyperbolic part): a LAPLACE stencil whose face coefficients are
+ *           d + (0.5 h) v_k on the minus face and d - (0.5 h) v_k on the plus
+ *           face of dimension k (d = d_const, v = vel). Gershgorin bound:
+ *           (|sum_f c_f| + sum_f |c_f|) / h^2. The spectrum leaves the real
+ *           axis; a damping nu that keeps it inside the stability domain is
+ *           the caller's choice (the real extent shrinks by about nu).
+ *           Not available to the batched and adjoint calls.
  * Dirichlet-zero boundaries use a ghost value W = 0 and, for VARCOEF, a ghost
  * diffusivity equal to the boundary cell's own D.
  */
@@ -81,7 +90,8 @@ typedef enum {
     FRKC2_OP_LAPLACE = 0,
     FRKC2_OP_VARCOEF = 1,
     FRKC2_OP_POROUS2 = 2,
-    FRKC2_OP_BRUSS2 = 3
+    FRKC2_OP_BRUSS2 = 3,
+    FRKC2_OP_ADVDIFF = 4
 } frkc2_op;
 
 typedef struct {
@@ -90,7 +100,8 @@ typedef struct {
     double h;          /* grid spacing (all dimensions); the stencil uses 1/(h*h) */
     int bc;            /* frkc2_bc */
     int op;            /* frkc2_op */
-    double d_const;    /* diffusivity of FRKC2_OP_LAPLACE (ignored otherwise) */
+    double d_const;    /* diffusivity of FRKC2_OP_LAPLACE, BRUSS2 and ADVDIFF */
+    double vel[3];     /* advection velocity per dimension (FRKC2_OP_ADVDIFF only) */
 } frkc2_grid;
 
 typedef struct {

@@ -88,11 +88,11 @@ bool make_kgrid(const frkc2_grid *g, KGrid &k)
         return false;
     }
     if (g->op != FRKC2_OP_LAPLACE && g->op != FRKC2_OP_VARCOEF && g->op != FRKC2_OP_POROUS2 &&
-        g->op != FRKC2_OP_BRUSS2) {
+        g->op != FRKC2_OP_BRUSS2 && g->op != FRKC2_OP_ADVDIFF) {
         set_error("unknown operator %d", g->op);
         return false;
     }
-    if ((g->op == FRKC2_OP_LAPLACE || g->op == FRKC2_OP_BRUSS2) &&
+    if ((g->op == FRKC2_OP_LAPLACE || g->op == FRKC2_OP_BRUSS2 || g->op == FRKC2_OP_ADVDIFF) &&
         !(g->d_const >= 0.0 && std::isfinite(g->d_const))) {
         set_error("d_const must be finite and non-negative");
         return false;
@@ -112,6 +112,25 @@ bool make_kgrid(const frkc2_grid *g, KGrid &k)
     k.nfield = (g->op == FRKC2_OP_BRUSS2) ? 2 : 1;
     k.inv_h2 = 1.0 / (g->h * g->h);
     k.d_const = g->d_const;
+    // face coefficients: d, or d + (0.5 h) v_k / d - (0.5 h) v_k for ADVDIFF,
+    // in the caller's dimension order and in the kernels' (2D grids march in z)
+    for (int f = 0; f < 6; ++f) k.fcg[f] = g->d_const;
+    if (g->op == FRKC2_OP_ADVDIFF) {
+        for (int d = 0; d < g->ndim; ++d) {
+            if (!std::isfinite(g->vel[d])) {
+                set_error("vel must be finite");
+                return false;
+            }
+            k.fcg[2 * d] = g->d_const + (0.5 * g->h) * g->vel[d];
+            k.fcg[2 * d + 1] = g->d_const - (0.5 * g->h) * g->vel[d];
+        }
+    }
+    for (int f = 0; f < 6; ++f) k.fc[f] = g->d_const;
+    const int kd[3] = {0, g->ndim == 2 ? 2 : 1, 2};   // kernel dimension of caller dimension d
+    for (int d = 0; d < g->ndim; ++d) {
+        k.fc[2 * kd[d]] = k.fcg[2 * d];
+        k.fc[2 * kd[d] + 1] = k.fcg[2 * d + 1];
+    }
     if (g->ndim == 1) { k.nx = g->n[0]; k.ny = 1; k.nz = 1; }
     else if (g->ndim == 2) { k.nx = g->n[0]; k.ny = 1; k.nz = g->n[1]; }
     else { k.nx = g->n[0]; k.ny = g->n[1]; k.nz = g->n[2]; }
@@ -173,6 +192,16 @@ AdjLayout adj_layout(long long N, int s)
 int rho_bound_impl(const KGrid &kg, const double *w, const double *D, double *partials,
                    double *rho, hipStream_t st)
 {
+    if (kg.op == FRKC2_OP_ADVDIFF) {
+        // |a_ii| + sum_j |a_ij|, a_ii = -sum_f c_f / h^2, a_ij = c_f / h^2
+        double sum = 0.0, asum = 0.0;
+        for (int f = 0; f < 2 * kg.ndim; ++f) {
+            sum = sum + kg.fcg[f];
+            asum = asum + std::fabs(kg.fcg[f]);
+        }
+        *rho = (std::fabs(sum) + asum) * kg.inv_h2;
+        return FRKC2_OK;
+    }
     double m;
     if (kg.op == FRKC2_OP_LAPLACE || kg.op == FRKC2_OP_BRUSS2) {
         double sum = 0.0;
@@ -401,7 +430,8 @@ extern "C" int frkc2_rho_bound(const frkc2_grid *g, const double *w, const doubl
         set_error("POROUS2 needs w");
         return FRKC2_EINVAL;
     }
-    if (kg.op != FRKC2_OP_LAPLACE && (!ws || ws_bytes < kScratch || !aligned16(ws))) {
+    const bool host_only = kg.op == FRKC2_OP_LAPLACE || kg.op == FRKC2_OP_ADVDIFF;
+    if (!host_only && (!ws || ws_bytes < kScratch || !aligned16(ws))) {
         set_error("workspace needs at least %zu bytes, 16-byte aligned", kScratch);
         return FRKC2_ENOMEM;
     }
@@ -653,8 +683,8 @@ extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const 
 {
     KGrid kg;
     if (!make_kgrid(g, kg)) return FRKC2_EINVAL;
-    if (nonlinear(kg)) {
-        set_error("the adjoint supports the linear operators (LAPLACE, VARCOEF)");
+    if (nonlinear(kg) || kg.op == FRKC2_OP_ADVDIFF) {
+        set_error("the adjoint supports the symmetric operators (LAPLACE, VARCOEF)");
         return FRKC2_EINVAL;
     }
     if (!w_n || !lam_next || !lam_n || (kg.op == FRKC2_OP_VARCOEF && !D)) {

@@ -140,6 +140,7 @@ __global__ __launch_bounds__(BX *BY) void batched_level(LevelArgs t)
         pa.nty = P.nty;
         pa.inv_h2 = P.inv_h2;
         pa.d_const = P.d_const;
+        for (int k = 0; k < 6; ++k) pa.fc[k] = P.d_const;
         pa.tr = uni(P.tau[2 * l]);
         pa.ti = uni(P.tau[2 * l + 1]);
         const bool per = (P.bc == PER), var = (P.op == VAR);
@@ -265,6 +266,7 @@ __global__ __launch_bounds__(1024) void batched_pass3(Pass3Args t)
             ta.nty = P.nty3;
             ta.inv_h2 = P.inv_h2;
             ta.d_const = P.d_const;
+            for (int k = 0; k < 6; ++k) ta.fc[k] = P.d_const;
             const int l0 = kBatchK * L;
 #pragma unroll
             for (int i = 0; i < kBatchK; ++i) {
@@ -294,6 +296,7 @@ __global__ __launch_bounds__(1024) void batched_pass3(Pass3Args t)
             pa.nty = P.nty;
             pa.inv_h2 = P.inv_h2;
             pa.d_const = P.d_const;
+            for (int k = 0; k < 6; ++k) pa.fc[k] = P.d_const;
             pa.tr = uni(P.tau[2 * l]);
             pa.ti = uni(P.tau[2 * l + 1]);
             if (var) {

@@ -41,7 +41,8 @@ bool validate(int nprob, const frkc2_grid *grids, const int *s, std::vector<KGri
     kg.resize(nprob);
     for (int i = 0; i < nprob; ++i) {
         if (!make_kgrid(&grids[i], kg[i])) return false;
-        if (kg[i].ndim < 2 || kg[i].op == FRKC2_OP_POROUS2 || kg[i].op == FRKC2_OP_BRUSS2) {
+        if (kg[i].ndim < 2 ||
+            (kg[i].op != FRKC2_OP_LAPLACE && kg[i].op != FRKC2_OP_VARCOEF)) {
             set_error("batched: problem %d must be 2D or 3D with a linear operator", i);
             return false;
         }

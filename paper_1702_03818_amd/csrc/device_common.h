@@ -8,7 +8,8 @@
 namespace frkc2 {
 namespace dev {
 
-enum { LAP = FRKC2_OP_LAPLACE, VAR = FRKC2_OP_VARCOEF, POR = FRKC2_OP_POROUS2 };
+enum { LAP = FRKC2_OP_LAPLACE, VAR = FRKC2_OP_VARCOEF, POR = FRKC2_OP_POROUS2,
+       ADV = FRKC2_OP_ADVDIFF };
 enum { PER = FRKC2_BC_PERIODIC, DIR = FRKC2_BC_DIRICHLET0 };
 
 struct Dims {
@@ -122,7 +123,8 @@ __device__ __forceinline__ void csq(double2 c, double &qr, double &qi)
 // library and its CPU check share (fused multiply-adds, correctly rounded).
 // nb: neighbour value (0 for a Dirichlet ghost); dc, dn: cell and neighbour
 // diffusivity; ghost selects D_f = D_c, which equals (D_c + D_c)/2 bit for
-// bit; qr_c, qi_c: W_c^2 for the porous operator.
+// bit; qr_c, qi_c: W_c^2 for the porous operator; d_const: the face's
+// coefficient for LAPLACE (d) and ADVDIFF (d -+ v h/2).
 template <int OP>
 __device__ __forceinline__ void face(double &acc_r, double &acc_i, double2 c, double2 nb,
                                      double dc, double dn, bool ghost, double qr_c, double qi_c,
@@ -139,7 +141,7 @@ __device__ __forceinline__ void face(double &acc_r, double &acc_i, double2 c, do
         acc_i = fma(Dr, di, fma(Di, dr, acc_i));
     } else {
         double Df;
-        if (OP == LAP) Df = d_const;
+        if (OP == LAP || OP == ADV) Df = d_const;   // the face's own coefficient
         else Df = ghost ? dc : 0.5 * (dc + dn);
         acc_r = fma(Df, dr, acc_r);
         acc_i = fma(Df, di, acc_i);

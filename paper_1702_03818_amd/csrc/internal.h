@@ -26,6 +26,9 @@ struct KGrid {
     int bc, op;
     int nfield;                 // values per point: 2 for the Brusselator (v, then w)
     double inv_h2, d_const;
+    double fc[6];               // face coefficients in kernel order x-, x+, y-, y+, z-, z+
+                                // (d_const, or d -+ v h/2 for ADVDIFF)
+    double fcg[6];              // the same in grid order (dimension 0, 1, 2 of the caller)
     long long npts() const { return (long long)nx * ny * nz; }
     long long nstate() const { return nfield * npts(); }
 };

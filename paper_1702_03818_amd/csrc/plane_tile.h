@@ -20,6 +20,8 @@ struct PlaneArgs {
     int nx, ny, nz;
     int zchunk, ntx, nty;
     double inv_h2, d_const, tr, ti;
+    double fc[6];               // face coefficient per face x-, x+, y-, y+, z-, z+ (LAPLACE,
+                                // ADVDIFF; d_const for LAPLACE)
 };
 
 template <int BC, bool IN_REAL>
@@ -164,18 +166,18 @@ __device__ __forceinline__ void plane_tile(const PlaneArgs &a, int bx, int by, i
             // faces (loads are clamped), so every face takes the plain mean,
             // which there equals D_c bit for bit.
             face<OP>(acc_r, acc_i, c, sW[b][oslot - 1], Dc, (OP == VAR) ? sD[b][oslot - 1] : 0.0,
-                     false, qr_c, qi_c, a.d_const);
+                     false, qr_c, qi_c, a.fc[0]);
             face<OP>(acc_r, acc_i, c, sW[b][oslot + 1], Dc, (OP == VAR) ? sD[b][oslot + 1] : 0.0,
-                     false, qr_c, qi_c, a.d_const);
+                     false, qr_c, qi_c, a.fc[1]);
             if (NDIM == 3) {
                 face<OP>(acc_r, acc_i, c, sW[b][oslot - SX], Dc,
-                         (OP == VAR) ? sD[b][oslot - SX] : 0.0, false, qr_c, qi_c, a.d_const);
+                         (OP == VAR) ? sD[b][oslot - SX] : 0.0, false, qr_c, qi_c, a.fc[2]);
                 face<OP>(acc_r, acc_i, c, sW[b][oslot + SX], Dc,
-                         (OP == VAR) ? sD[b][oslot + SX] : 0.0, false, qr_c, qi_c, a.d_const);
+                         (OP == VAR) ? sD[b][oslot + SX] : 0.0, false, qr_c, qi_c, a.fc[3]);
             }
             if (NDIM >= 2) {
-                face<OP>(acc_r, acc_i, c, Wm, Dc, Dm, false, qr_c, qi_c, a.d_const);
-                face<OP>(acc_r, acc_i, c, Wp, Dc, Dp, false, qr_c, qi_c, a.d_const);
+                face<OP>(acc_r, acc_i, c, Wm, Dc, Dm, false, qr_c, qi_c, a.fc[4]);
+                face<OP>(acc_r, acc_i, c, Wp, Dc, Dp, false, qr_c, qi_c, a.fc[5]);
             }
             const double2 nv = euler(c, acc_r, acc_i, a.inv_h2, a.tr, a.ti);
             const long long i = iz;

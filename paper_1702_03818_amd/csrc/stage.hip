@@ -59,7 +59,7 @@ template <int OP, int BC>
 __global__ __launch_bounds__(k1dThreads) void stage1d_lds(const double *w_in, double *w_out,
                                                           const double *D, const double2 *tau,
                                                           int n, int s, int nsteps,
-                                                          double inv_h2, double d_const)
+                                                          double inv_h2, double fcl, double fcr)
 {
     extern __shared__ double2 s1[];
     double2 *sW = s1;
@@ -93,9 +93,9 @@ __global__ __launch_bounds__(k1dThreads) void stage1d_lds(const double *w_in, do
                 const double dc = (OP == VAR) ? sD[i] : 0.0;
                 double acc_r = 0.0, acc_i = 0.0;
                 face<OP>(acc_r, acc_i, c, wl, dc, (OP == VAR) ? sD[il] : 0.0, gl, qr_c, qi_c,
-                         d_const);
+                         fcl);
                 face<OP>(acc_r, acc_i, c, wr, dc, (OP == VAR) ? sD[ir] : 0.0, gr, qr_c, qi_c,
-                         d_const);
+                         fcr);
                 const double2 u = euler(c, acc_r, acc_i, inv_h2, tr, ti);
                 // a superstep keeps Re W^L; the next one starts from a real state
                 nv[p] = make_double2(u.x, last ? 0.0 : u.y);
@@ -261,8 +261,10 @@ int launch_pass(const KGrid &g, const PassArgs &a, int /*tblock_hint*/, hipStrea
     pa.emb_out = a.emb_out;
     pa.tr = a.tr[0];
     pa.ti = a.ti[0];
+    for (int k = 0; k < 6; ++k) pa.fc[k] = g.fc[k];
     const bool ir = a.in_re != nullptr, orl = a.out_re != nullptr;
     if (g.op == LAP) return launch_plane_bc<LAP>(g, pa, ir, orl, st);
+    if (g.op == ADV) return launch_plane_bc<ADV>(g, pa, ir, orl, st);
     if (g.op == VAR) return launch_plane_bc<VAR>(g, pa, ir, orl, st);
     return launch_plane_bc<POR>(g, pa, ir, orl, st);
 }
@@ -281,7 +283,7 @@ int launch_1d_t(const KGrid &g, const double *w_in, double *w_out, const double 
     if (e != hipSuccess) return (int)e;
     hipLaunchKernelGGL(kern, dim3(1), dim3(k1dThreads), shm, st, w_in, w_out, D,
                        reinterpret_cast<const double2 *>(tau), g.nx, s, nsteps, g.inv_h2,
-                       g.d_const);
+                       g.fc[0], g.fc[1]);
     return (int)hipGetLastError();
 }
 template <int OP>
@@ -298,6 +300,7 @@ int launch_stage1d_lds(const KGrid &g, const double *w_in, double *w_out, const 
 {
     if (!stage1d_lds_fits(g)) return (int)hipErrorInvalidValue;
     if (g.op == LAP) return launch_1d_bc<LAP>(g, w_in, w_out, D, tau, s, nsteps, st);
+    if (g.op == ADV) return launch_1d_bc<ADV>(g, w_in, w_out, D, tau, s, nsteps, st);
     if (g.op == VAR) return launch_1d_bc<VAR>(g, w_in, w_out, D, tau, s, nsteps, st);
     return launch_1d_bc<POR>(g, w_in, w_out, D, tau, s, nsteps, st);
 }

@@ -148,8 +148,10 @@ int launch_tb3d(const KGrid &g, const PassArgs &p, hipStream_t st)
         a.tr[i] = p.tr[i];
         a.ti[i] = p.ti[i];
     }
+    for (int k = 0; k < 6; ++k) a.fc[k] = g.fc[k];
     const bool ir = p.in_re != nullptr, orl = p.out_re != nullptr;
     if (g.op == LAP) return launch3_bc<LAP>(g, p.k, a, ir, orl, st);
+    if (g.op == ADV) return launch3_bc<ADV>(g, p.k, a, ir, orl, st);
     if (g.op == VAR) return launch3_bc<VAR>(g, p.k, a, ir, orl, st);
     return launch3_bc<POR>(g, p.k, a, ir, orl, st);
 }

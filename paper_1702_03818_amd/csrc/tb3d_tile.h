@@ -21,6 +21,7 @@ struct Tb3Args {
     int zchunk, ntx, nty;
     double inv_h2, d_const;
     double tr[kMaxTBlock], ti[kMaxTBlock];
+    double fc[6];               // face coefficients x-, x+, y-, y+, z-, z+ (LAPLACE, ADVDIFF)
 };
 
 // Rows of the extended tile (one wavefront each) and halo wavefronts for
@@ -237,12 +238,12 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
                 // mean, which there equals D_c bit for bit.
                 const double dc = cur.dc;
                 double acc_r = 0.0, acc_i = 0.0;
-                face<OP>(acc_r, acc_i, c, cur.w[0], dc, cur.d[0], false, qr_c, qi_c, a.d_const);
-                face<OP>(acc_r, acc_i, c, cur.w[1], dc, cur.d[1], false, qr_c, qi_c, a.d_const);
-                face<OP>(acc_r, acc_i, c, cur.w[2], dc, cur.d[2], false, qr_c, qi_c, a.d_const);
-                face<OP>(acc_r, acc_i, c, cur.w[3], dc, cur.d[3], false, qr_c, qi_c, a.d_const);
-                face<OP>(acc_r, acc_i, c, zm, dc, cur.dzm, false, qr_c, qi_c, a.d_const);
-                face<OP>(acc_r, acc_i, c, zp, dc, cur.dzp, false, qr_c, qi_c, a.d_const);
+                face<OP>(acc_r, acc_i, c, cur.w[0], dc, cur.d[0], false, qr_c, qi_c, a.fc[0]);
+                face<OP>(acc_r, acc_i, c, cur.w[1], dc, cur.d[1], false, qr_c, qi_c, a.fc[1]);
+                face<OP>(acc_r, acc_i, c, cur.w[2], dc, cur.d[2], false, qr_c, qi_c, a.fc[2]);
+                face<OP>(acc_r, acc_i, c, cur.w[3], dc, cur.d[3], false, qr_c, qi_c, a.fc[3]);
+                face<OP>(acc_r, acc_i, c, zm, dc, cur.dzm, false, qr_c, qi_c, a.fc[4]);
+                face<OP>(acc_r, acc_i, c, zp, dc, cur.dzp, false, qr_c, qi_c, a.fc[5]);
                 double2 v = euler(c, acc_r, acc_i, a.inv_h2, a.tr[m - 1], a.ti[m - 1]);
                 v = keep3(v, col_ghost || pout(p));
                 double eh = 0.0;

@@ -50,6 +50,7 @@ struct TbArgs {
     int zchunk, ntx, nty;
     double inv_h2, d_const;
     double tr[kMaxTBlock], ti[kMaxTBlock];
+    double fc[6];
 };
 
 __device__ __forceinline__ double2 keep(double2 v, bool ghost)
@@ -220,17 +221,17 @@ __global__ __launch_bounds__(BXE *TY) void tb_stage(TbArgs a)
                 // it faces (loads are clamped), so every face takes the plain
                 // mean, which there equals D_c bit for bit.
                 face<OP>(acc_r, acc_i, c, L[sl - 1], dc, VC ? Dc_[sl - 1] : 0.0, false, qr_c,
-                         qi_c, a.d_const);
+                         qi_c, a.fc[0]);
                 face<OP>(acc_r, acc_i, c, L[sl + 1], dc, VC ? Dc_[sl + 1] : 0.0, false, qr_c,
-                         qi_c, a.d_const);
+                         qi_c, a.fc[1]);
                 if (NDIM == 3) {
                     face<OP>(acc_r, acc_i, c, L[sl - SX], dc, VC ? Dc_[sl - SX] : 0.0, false,
-                             qr_c, qi_c, a.d_const);
+                             qr_c, qi_c, a.fc[2]);
                     face<OP>(acc_r, acc_i, c, L[sl + SX], dc, VC ? Dc_[sl + SX] : 0.0, false,
-                             qr_c, qi_c, a.d_const);
+                             qr_c, qi_c, a.fc[3]);
                 }
-                face<OP>(acc_r, acc_i, c, zm, dc, dzm, false, qr_c, qi_c, a.d_const);
-                face<OP>(acc_r, acc_i, c, zp, dc, dzp, false, qr_c, qi_c, a.d_const);
+                face<OP>(acc_r, acc_i, c, zm, dc, dzm, false, qr_c, qi_c, a.fc[4]);
+                face<OP>(acc_r, acc_i, c, zp, dc, dzp, false, qr_c, qi_c, a.fc[5]);
                 double2 v = euler(c, acc_r, acc_i, a.inv_h2, a.tr[m - 1], a.ti[m - 1]);
                 v = keep(v, col_ghost[r] || pghost);
                 if (m < K) {
@@ -363,8 +364,10 @@ int launch_tblock(const KGrid &g, const PassArgs &p, int shape, hipStream_t st)
         a.tr[i] = p.tr[i];
         a.ti[i] = p.ti[i];
     }
+    for (int k = 0; k < 6; ++k) a.fc[k] = g.fc[k];
     const bool ir = p.in_re != nullptr, orl = p.out_re != nullptr;
     if (g.op == LAP) return launch_bc<LAP>(g, p.k, shape, a, ir, orl, st);
+    if (g.op == ADV) return launch_bc<ADV>(g, p.k, shape, a, ir, orl, st);
     if (g.op == VAR) return launch_bc<VAR>(g, p.k, shape, a, ir, orl, st);
     return launch_bc<POR>(g, p.k, shape, a, ir, orl, st);
 }

@@ -41,7 +41,8 @@ class Frkc2Error(RuntimeError):
 
 class Grid(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double),
-                ("bc", ctypes.c_int), ("op", ctypes.c_int), ("d_const", ctypes.c_double)]
+                ("bc", ctypes.c_int), ("op", ctypes.c_int), ("d_const", ctypes.c_double),
+                ("vel", ctypes.c_double * 3)]
 
 
 class CoeffInfo(ctypes.Structure):
@@ -143,8 +144,14 @@ def make_grid(g) -> Grid:
         return g
     get = (lambda k: g[k]) if isinstance(g, dict) else (lambda k: getattr(g, k))
     n = list(get("n")) + [1] * (3 - len(get("n")))
+    try:
+        vel = list(get("vel"))
+    except (KeyError, AttributeError):
+        vel = []
+    vel = [float(v) for v in vel] + [0.0] * (3 - len(vel))
     return Grid(int(get("ndim")), (ctypes.c_int * 3)(*[int(v) for v in n[:3]]), float(get("h")),
-                int(get("bc")), int(get("op")), float(get("d_const")))
+                int(get("bc")), int(get("op")), float(get("d_const")),
+                (ctypes.c_double * 3)(*vel[:3]))
 
 
 # ---- device plumbing (torch) ----

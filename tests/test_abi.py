@@ -242,3 +242,22 @@ def test_step_user_validation():
     assert call(ws=None) == -2
     assert call(wsb=100) == -2
     assert call(T=1.0, rho=1e6) == -4          # T rho beyond betabar(16)
+
+
+@pytest.mark.parametrize("ndim,vel,bc", [(1, (12.0,), 0), (2, (3.0, -40.0), 1), (3, (1.0, 2.0, 500.0), 0)])
+def test_advdiff_rho_bound_on_host(ndim, vel, bc):
+    """The advection-diffusion bound is computed on the host: equal to the oracle's."""
+    from oracle import stage as ostage
+    n = (16, 12, 10)[:ndim]
+    p = wl.Problem(ndim, tuple(n) + (1,) * (3 - ndim), 0.05, bc, wl.OP_ADVDIFF, 0.7)
+    p.vel = tuple(vel) + (0.0,) * (3 - ndim)
+    g = F.make_grid(p)
+    rho = ctypes.c_double()
+    assert F.load().frkc2_rho_bound(ctypes.byref(g), None, None, ctypes.byref(rho), None, 0,
+                                    None) == 0
+    assert rho.value == ostage.rho_bound(p)
+
+
+def test_advdiff_rejects_nonfinite_velocity():
+    g = grid(op=4, vel=(1.0, float("nan"), 0.0))
+    assert F.load().frkc2_workspace_bytes(ctypes.byref(g), 16, F.WS_STEP) == 0

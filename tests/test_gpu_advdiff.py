@@ -1,0 +1,78 @@
+"""GPU parity of the advection-diffusion operator with damping (Sec. 2.1): supersteps in every
+launch configuration and error-controlled runs, bit for bit against the oracle."""
+import numpy as np
+import pytest
+
+from oracle import adaptive, frkc2_coeffs, stage
+from paper_1702_03818_amd import frkc2 as F
+from paper_1702_03818_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+NU = 0.1
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F.load()
+    yield
+    for key in (F.OPT_TBLOCK, F.OPT_TILE, F.OPT_ZCHUNK):
+        F.frkc2_set_option(key, 0)
+    torch.cuda.synchronize()
+
+
+def adv(n, vel, bc, seed=0):
+    ndim = len(n)
+    p = wl.Problem(ndim, tuple(n) + (1,) * (3 - ndim), 1.0 / max(n), bc, wl.OP_ADVDIFF, 1.0)
+    p.vel = tuple(vel) + (0.0,) * (3 - ndim)
+    p.w0 = wl.random_state(p.shape, seed, smooth=1.5)
+    return p
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(-1), device="cuda")
+
+
+CASES = [
+    ((256,), (10.0,), 0), ((5000,), (-7.0,), 1),
+    ((300, 37), (8.0, -3.0), 0), ((130, 21), (-5.0, 9.0), 1),
+    ((70, 37, 21), (4.0, -6.0, 8.0), 1), ((67, 30, 18), (-9.0, 2.0, 5.0), 0),
+]
+
+
+@pytest.mark.parametrize("n,vel,bc", CASES)
+@pytest.mark.parametrize("k,tile", [(0, 0), (1, 0), (2, 1), (3, 4), (2, 4)])
+def test_superstep_matches_oracle(n, vel, bc, k, tile):
+    p = adv(n, vel, bc)
+    s = 16
+    c = frkc2_coeffs(s, NU)
+    rho = stage.rho_bound(p)
+    T = 0.9 * c.beta_bar / rho
+    ref, _ = stage.run(p, s, 2, T=T, coeffs=c)
+    F.frkc2_set_option(F.OPT_TBLOCK, k)
+    F.frkc2_set_option(F.OPT_TILE, tile)
+    try:
+        w = dev(p.w0)
+        F.frkc2_step(p, w, None, T=T, s=s, nu=NU, nsteps=2)
+        torch.cuda.synchronize()
+    finally:
+        F.frkc2_set_option(F.OPT_TBLOCK, 0)
+        F.frkc2_set_option(F.OPT_TILE, 0)
+    got = w.cpu().numpy()
+    assert np.array_equal(got, ref), "%d values differ" % int(np.sum(got != ref))
+
+
+@pytest.mark.parametrize("n,vel,bc", [((70, 37, 21), (4.0, -6.0, 8.0), 1), ((300, 37), (8.0, -3.0), 0)])
+def test_integrate_matches_oracle(n, vel, bc):
+    p = adv(n, vel, bc)
+    rho = stage.rho_bound(p)
+    w_ref, trace_ref, T_ref = adaptive.integrate(p, 1500.0 / rho, 800.0 / rho, 1e-3, nu=NU)
+    w = dev(p.w0)
+    st, trace = F.frkc2_integrate(p, w, None, t_span=1500.0 / rho, T0=800.0 / rho, tol=1e-3,
+                                  nu=NU, trace_cap=len(trace_ref) + 4)
+    torch.cuda.synchronize()
+    assert np.array_equal(trace, np.array(trace_ref))
+    assert st["T_next"] == T_ref
+    assert np.array_equal(w.cpu().numpy(), w_ref)
