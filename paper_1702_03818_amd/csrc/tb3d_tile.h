@@ -33,6 +33,12 @@ struct Tb3Shape {
     static constexpr int BXE = 64 + 2 * K;
     static constexpr int BYO = BYE - 2 * K;
     static_assert(2 * K * BYE <= 64 * NHW, "halo columns must fit the halo wavefronts");
+    // LDS row stride in cells: at least one padding cell on each side, made
+    // odd so that the halo wavefronts, whose consecutive lanes walk down a
+    // column, hit distinct banks (an even stride of 72 cells put 16-byte
+    // accesses of a 16-lane group on two bank groups only).
+    static constexpr int SX = (BXE + 2) | 1;
+    static constexpr int SY = BYE + 2;
     // Role of wavefront w (rows 0..BYE-1, then the halo wavefronts). The
     // wavefronts of a workgroup are dealt to the CU's four SIMDs in turn
     // (w % 4), and a row computes min(row, BYE-1-row, K) levels, so the roles
@@ -48,17 +54,10 @@ struct Tb3Shape {
     }
 };
 
-__device__ __forceinline__ double2 keep3(double2 v, bool ghost)
-{
-    v.x = ghost ? 0.0 : v.x;
-    v.y = ghost ? 0.0 : v.y;
-    return v;
-}
-
 // LDS of one tile: level planes (double2) and the diffusivity ring (double).
 template <int OP, int K>
 struct Tb3Lds {
-    static constexpr int PL = (Tb3Shape<K>::BXE + 2) * (Tb3Shape<K>::BYE + 2);
+    static constexpr int PL = Tb3Shape<K>::SX * Tb3Shape<K>::SY;
     static constexpr int L = 2 * K * PL;
     static constexpr int D = (OP == FRKC2_OP_VARCOEF) ? (K + 2) * PL : 1;
 };
@@ -72,15 +71,14 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
 {
     using S = Tb3Shape<K>;
     constexpr int BXE = S::BXE, BYE = S::BYE, BYO = S::BYO;
-    constexpr int SX = BXE + 2, SY = BYE + 2;      // one padding cell around each plane
-    constexpr int PL = SX * SY;
+    constexpr int SX = S::SX;                       // padding cells around each plane
+    constexpr int PL = Tb3Lds<OP, K>::PL;
     constexpr bool VC = (OP == VAR);
     constexpr int ND = K + 2;                       // D ring: planes t-K-1 .. t
     // level m plane, by step parity; D ring
     double2 (*sL)[K][PL] = reinterpret_cast<double2 (*)[K][PL]>(sLp);
     double (*sD)[VC ? PL : 1] = reinterpret_cast<double (*)[VC ? PL : 1]>(sDp);
 
-    const Dims dm{a.nx, a.ny, a.nz};
     const int tid = threadIdx.x;
     const int wv = S::role(tid >> 6), lane = tid & 63;
     int lx, ly;                                     // position in the extended tile
@@ -97,34 +95,46 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
         ly = rem % BYE;
         lx = (rem < BYE) ? K - d : K + 63 + d;
     }
-    // level m is needed where the tile edge is at least m cells away
-    const int need = min(min(lx, BXE - 1 - lx), min(ly, BYE - 1 - ly));
-
     const int x = bx * 64 - K + lx;
     const int y = by * BYO - K + ly;
     const int z0 = bz * a.zchunk;
     const int z1 = min(z0 + a.zchunk, a.nz);
     const bool dir = (BC == DIR);
     const bool col_ghost = dir && !(x >= 0 && x < a.nx && y >= 0 && y < a.ny);
+    // Level m is needed where the tile edge is at least m cells away. A
+    // wavefront computes every level one of its lanes needs, on all lanes, so
+    // each level's registers are rewritten every step; a lane that does not
+    // need the level computes a value nobody reads. A Dirichlet ghost column
+    // never writes LDS, whose planes start at 0, the ghost value its
+    // neighbours read.
+    const int need = min(min(lx, BXE - 1 - lx), min(ly, BYE - 1 - ly));
+    int wneed = 0;
+#pragma unroll
+    for (int m = 1; m <= K; ++m)
+        if (__any(need >= m)) wneed = m;
+    wneed = __builtin_amdgcn_readfirstlane(wneed);
     const bool out_col = lx >= K && lx < K + 64 && ly >= K && ly < BYE - K && x < a.nx &&
                          y < a.ny;
     const int slot = (ly + 1) * SX + lx + 1;
 
+    // Global addresses: a fixed column offset per lane (clamped into the grid
+    // for Dirichlet, wrapped for periodic) plus a uniform plane offset.
+    const int cx = (BC == PER) ? wrap(x, a.nx) : min(max(x, 0), a.nx - 1);
+    const int cy = (BC == PER) ? wrap(y, a.ny) : min(max(y, 0), a.ny - 1);
+    const long long ixy = cx + (long long)a.nx * cy;
+    const long long pst = (long long)a.nx * a.ny;
+    auto zoff = [&](int gz) {
+        return pst * ((BC == PER) ? wrap(gz, a.nz) : min(max(gz, 0), a.nz - 1));
+    };
+    const double2 *pWc = IN_REAL ? nullptr : a.in_c + ixy;
+    const double *pWr = IN_REAL ? a.in_re + ixy : nullptr;
+    const double *pD = VC ? a.D + ixy : nullptr;
+    const double *pE = (EMB && !IN_REAL) ? a.emb_in + ixy : nullptr;
     auto LW = [&](int gz) {
-        bool g;
-        const long long i = bc_index_nb<BC>(dm, x, y, gz, g);
-        return IN_REAL ? make_double2(a.in_re[i], 0.0) : a.in_c[i];
+        return IN_REAL ? make_double2(pWr[zoff(gz)], 0.0) : pWc[zoff(gz)];
     };
-    auto LD = [&](int gz) {
-        bool g;
-        const long long i = bc_index_nb<BC>(dm, x, y, gz, g);
-        return VC ? a.D[i] : 0.0;
-    };
-    auto LE = [&](int gz) {
-        bool g;
-        const long long i = bc_index_nb<BC>(dm, x, y, gz, g);
-        return (EMB && !IN_REAL) ? a.emb_in[i] : 0.0;
-    };
+    auto LD = [&](int gz) { return VC ? pD[zoff(gz)] : 0.0; };
+    auto LE = [&](int gz) { return (EMB && !IN_REAL) ? pE[zoff(gz)] : 0.0; };
     auto pout = [&](int p) { return dir && (p < 0 || p >= a.nz); };
     auto dslot = [](int p) { return ((p % ND) + ND) % ND; };
 
@@ -139,7 +149,10 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
     constexpr bool ER = EMB && !IN_REAL;            // embedded input read from memory
     double E0[ER ? NR : 1];
     double ehc[K - 1], ehn[K - 1];                  // What of levels 1..K-1: last step, this step
-    double2 wm[K - 1], wc[K - 1], wp[K - 1];
+    // Levels 1..K-1 by step: WR[m-1][slot of step t] holds level m at plane
+    // t-m; the window of level m+1 at step t is the slots of steps t-2..t.
+    // The step loop is unrolled by NR, so every index is static.
+    double2 WR[K - 1][NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
         L0[q] = make_double2(0.0, 0.0);
@@ -156,8 +169,25 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
 #pragma unroll
     for (int m = 0; m + 1 < K; ++m) ehc[m] = ehn[m] = 0.0;
 #pragma unroll
-    for (int m = 0; m + 1 < K; ++m) wm[m] = wc[m] = wp[m] = make_double2(0.0, 0.0);
+    for (int m = 0; m + 1 < K; ++m) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) WR[m][q] = make_double2(0.0, 0.0);
+    }
 
+    if (dir) {
+        for (int i = tid; i < 2 * K * PL; i += 1024) sLp[i] = make_double2(0.0, 0.0);
+        __syncthreads();
+    }
+
+    // A plane outside the grid (Dirichlet) holds the ghost value 0 at every
+    // level. The test is uniform and true only near the ends of the grid;
+    // the empty asm keeps it a branch rather than selects on every step.
+    auto zero_if = [](bool c, double2 &v) {
+        if (c) {
+            asm volatile("" ::: "memory");
+            v = make_double2(0.0, 0.0);
+        }
+    };
     for (int tb = t_begin; tb < t_end; tb += NR) {
 #pragma unroll
     for (int u = 0; u < NR; ++u) {
@@ -170,7 +200,7 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
             D0[rs(PF)] = LD(tn);
             if (ER) E0[rs(PF)] = LE(tn);
         }
-        L0[rs(0)] = keep3(L0[rs(0)], col_ghost || pout(t));
+        zero_if(pout(t), L0[rs(0)]);
         const int rb = (t - 1) & 1, wb = t & 1;     // LDS buffers read / written at step t
         // LDS operands of level m: x/y neighbours of level m-1 and their D,
         // and the cell's own D where the register ring no longer holds it.
@@ -217,17 +247,21 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
         for (int m = 1; m <= K; ++m) {
             Nb nxt = cur;
             if (RA && m < K) nxt = read(m + 1);
-            if (need >= m) {
-                const int p = t - m;
+            const int p = t - m;
+            if (m > wneed) {
+                // keep the slot written every step (the value is never read)
+                if (m < K) WR[m - 1][rs(0)] = make_double2(0.0, 0.0);
+                if (EMB && m < K) ehn[m - 1] = 0.0;
+            } else {
                 double2 c, zm, zp;
                 if (m == 1) {
                     zm = L0[rs(-2)];
                     c = L0[rs(-1)];
                     zp = L0[rs(0)];
                 } else {
-                    zm = wm[m - 2];
-                    c = wc[m - 2];
-                    zp = wp[m - 2];
+                    zm = WR[m - 2][rs(-2)];
+                    c = WR[m - 2][rs(-1)];
+                    zp = WR[m - 2][rs(0)];
                 }
                 double qr_c = 0.0, qi_c = 0.0;
                 if (OP == POR) {
@@ -245,7 +279,7 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
                 face<OP>(acc_r, acc_i, c, zm, dc, cur.dzm, false, qr_c, qi_c, a.fc[4]);
                 face<OP>(acc_r, acc_i, c, zp, dc, cur.dzp, false, qr_c, qi_c, a.fc[5]);
                 double2 v = euler(c, acc_r, acc_i, a.inv_h2, a.tr[m - 1], a.ti[m - 1]);
-                v = keep3(v, col_ghost || pout(p));
+                zero_if(pout(p), v);
                 double eh = 0.0;
                 if (EMB) {
                     // What^{m-1} at plane p: the input (level 1) or last step's level m-1
@@ -254,12 +288,11 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
                     eh = fma(a.tr[m - 1], acc_r * a.inv_h2, base);
                 }
                 if (m < K) {
-                    wm[m - 1] = wc[m - 1];
-                    wc[m - 1] = wp[m - 1];
-                    wp[m - 1] = v;
+                    WR[m - 1][rs(0)] = v;
                     if (EMB) ehn[m - 1] = eh;
                 } else if (out_col && p >= z0 && p < z1) {
-                    const long long i = x + (long long)a.nx * (y + (long long)a.ny * p);
+                    // an output column is inside the grid: ixy is its own offset
+                    const long long i = ixy + pst * p;
                     if (OUT_REAL) a.out_re[i] = v.x;
                     else a.out_c[i] = v;
                     if (EMB) a.emb_out[i] = eh;
@@ -269,11 +302,14 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
             cur = nxt;
         }
         // All LDS writes of the step come after all its reads, so the reads
-        // of every level can be issued early. A lane that skipped level m
-        // stores a stale value that no needed cell reads.
-        sL[wb][0][slot] = L0[rs(0)];
+        // of every level can be issued early. A lane that does not need
+        // level m stores a value no needed cell reads; a ghost column stores
+        // nothing, so its cells keep the ghost value 0.
+        if (!col_ghost) {
+            sL[wb][0][slot] = L0[rs(0)];
 #pragma unroll
-        for (int m = 1; m < K; ++m) sL[wb][m][slot] = wp[m - 1];
+            for (int m = 1; m < K; ++m) sL[wb][m][slot] = WR[m - 1][rs(0)];
+        }
         if (EMB) {
 #pragma unroll
             for (int m = 0; m + 1 < K; ++m) ehc[m] = ehn[m];
