@@ -27,6 +27,8 @@
  * evaluates the same expressions in the same order, so results agree to the
  * last bit). fma(a, b, c) is the correctly rounded a*b + c (C99):
  *   faces in the order x-, x+, y-, y+, z-, z+; dr = Wr_nb - Wr_c, di likewise;
+ *   op 1:   Df = 0.5*D_c + 0.5*D_nb (each half exact; equal to (D_c + D_nb)/2
+ *           to the last bit whenever the halves are normal and the sum finite);
  *   op 0/1: acc_r = fma(Df, dr, acc_r), acc_i = fma(Df, di, acc_i);
  *   op 2:   q = W^2 as (fma(Wr, Wr, -(Wi*Wi)), 2*(Wr*Wi)) for cell and
  *           neighbour, Qr = (qr_c + qr_nb)/2, Qi likewise,
@@ -183,7 +185,7 @@ static void apply_op(const grid_t *g, const double *D, const double *wr, const d
                     Df = g->fc[f];
                 } else {
                     double Dn = (q < 0) ? D[p] : D[q];
-                    Df = 0.5 * (D[p] + Dn);
+                    Df = 0.5 * D[p] + 0.5 * Dn;
                 }
                 acc_r = fma(Df, dr, acc_r);
                 acc_i = fma(Df, di, acc_i);
@@ -352,7 +354,7 @@ double oracle_rho_bound(int ndim, const long *n, int bc, int op, double inv_h2, 
             if (op == OP_LAPLACE || op == OP_BRUSS2) {
                 Df = d_const;
             } else if (op == OP_VARCOEF) {
-                Df = 0.5 * (D[p] + ((q < 0) ? D[p] : D[q]));
+                Df = 0.5 * D[p] + 0.5 * ((q < 0) ? D[p] : D[q]);
             } else {
                 double un = (q < 0) ? 0.0 : w[q];
                 Df = 0.5 * (w[p] * w[p] + un * un);

@@ -139,9 +139,9 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
     auto dslot = [](int p) { return ((p % ND) + ND) % ND; };
 
     // Level 0 ring: plane p in slot (p - t_begin) % NR with its D; at step t
-    // planes t-2 .. t are in use and t+1, t+2 in flight. Windows of levels
+    // planes t-2 .. t are in use and the next PF planes in flight. Windows of levels
     // 1..K-1: planes (q-1, q, q+1) around the plane the next level computes.
-    constexpr int PF = 2;
+    constexpr int PF = EMB ? 1 : 2;                 // EMB: registers for the What rings
     constexpr int NR = PF + 3;
     const int t_begin = z0 - K, t_end = z1 + K;     // level 0 planes z0-K .. z1+K-1
     double2 L0[NR];
