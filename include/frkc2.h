@@ -58,7 +58,9 @@ typedef enum { FRKC2_BC_PERIODIC = 0, FRKC2_BC_DIRICHLET0 = 1 } frkc2_bc;
 /*
  * Diffusion operators f (cell-centred, faces in the order x-, x+, y-, y+, z-, z+):
  *  LAPLACE  f = d_const * sum_f (W_nb - W_c) / h^2
- *  VARCOEF  f = sum_f D_f (W_nb - W_c) / h^2,  D_f = (D_c + D_nb)/2
+ *  VARCOEF  f = sum_f D_f (W_nb - W_c) / h^2,  D_f = D_c/2 + D_nb/2 (the mean; each
+ *           half is exact, so this equals (D_c + D_nb)/2 bit for bit for
+ *           normal diffusivities)
  *  POROUS2  f = div(u^2 grad u): sum_f Q_f (W_nb - W_c) / h^2 with
  *           Q_f = (W_c^2 + W_nb^2)/2, evaluated on the complex stage values
  *           (the continuation of u^2 is holomorphic, as the complex Euler

@@ -5,7 +5,7 @@
 // lam = dJ/dRe W + i dJ/dIm W, the transpose lam^l = lam^{l+1} + conj(tau_l) A lam^{l+1}.
 // Its dependence on the face diffusivity D_f of the face between cells c and
 // nb is dJ/dD_f = -Re(tau_l conj(lam_nb - lam_c) (W_nb - W_c)) / h^2 with
-// lam = lam^{l+1} and W = W^l; D_f = (D_c + D_nb)/2 hands half of it to each
+// lam = lam^{l+1} and W = W^l; D_f = D_c/2 + D_nb/2 hands half of it to each
 // cell, a Dirichlet boundary face (D_f = D_c, ghost W = lam = 0) all of it.
 // The kernel fuses both: for every cell it accumulates its share into gD and
 // writes lam^l. The stages run in reverse order; the reversed sequence has
@@ -114,9 +114,9 @@ __global__ __launch_bounds__(BX *BY) void adjoint_stage(AdjPlaneArgs a)
         Wm = ldW(x, y, z0 - 1);
         Wc = ldW(x, y, z0);
         Wp = ldW(x, y, z0 + 1);
-        Dm = load_r<BC>(dm, a.D, x, y, z0 - 1);
-        Dc = load_r<BC>(dm, a.D, x, y, z0);
-        Dp = load_r<BC>(dm, a.D, x, y, z0 + 1);
+        Dm = 0.5 * load_r<BC>(dm, a.D, x, y, z0 - 1);
+        Dc = 0.5 * load_r<BC>(dm, a.D, x, y, z0);
+        Dp = 0.5 * load_r<BC>(dm, a.D, x, y, z0 + 1);
     }
     double2 hL = make_double2(0.0, 0.0), hW = hL;
     double hD = 0.0;
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(BX *BY) void adjoint_stage(AdjPlaneArgs a)
         hL = ldL(x0 + hx, y0 + hy, z0);
         if (VC) {
             hW = ldW(x0 + hx, y0 + hy, z0);
-            hD = load_r<BC>(dm, a.D, x0 + hx, y0 + hy, z0);
+            hD = 0.5 * load_r<BC>(dm, a.D, x0 + hx, y0 + hy, z0);
         }
     }
 
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(BX *BY) void adjoint_stage(AdjPlaneArgs a)
             hL = ldL(x0 + hx, y0 + hy, z + 1);
             if (VC) {
                 hW = ldW(x0 + hx, y0 + hy, z + 1);
-                hD = load_r<BC>(dm, a.D, x0 + hx, y0 + hy, z + 1);
+                hD = 0.5 * load_r<BC>(dm, a.D, x0 + hx, y0 + hy, z + 1);
             }
         }
         if (active) {
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(BX *BY) void adjoint_stage(AdjPlaneArgs a)
             Lp = ldL(x, y, z + 2);
             if (VC) {
                 Wp = ldW(x, y, z + 2);
-                Dp = load_r<BC>(dm, a.D, x, y, z + 2);
+                Dp = 0.5 * load_r<BC>(dm, a.D, x, y, z + 2);
             }
         }
     }

@@ -121,10 +121,11 @@ __device__ __forceinline__ void csq(double2 c, double &qr, double &qi)
 
 // One face of the flux sum of the diffusion operator, in the fixed order the
 // library and its CPU check share (fused multiply-adds, correctly rounded).
-// nb: neighbour value (0 for a Dirichlet ghost); dc, dn: cell and neighbour
-// diffusivity; ghost selects D_f = D_c, which equals (D_c + D_c)/2 bit for
-// bit; qr_c, qi_c: W_c^2 for the porous operator; d_const: the face's
-// coefficient for LAPLACE (d) and ADVDIFF (d -+ v h/2).
+// nb: neighbour value (0 for a Dirichlet ghost); dc, dn: halves of the cell
+// and neighbour diffusivity (0.5 * D, exact; the kernels halve D once when
+// they load it), D_f = dc + dn, the mean of the two; ghost takes dn = dc, so
+// the face carries D_c; qr_c, qi_c: W_c^2 for the porous operator; d_const:
+// the face's coefficient for LAPLACE (d) and ADVDIFF (d -+ v h/2).
 template <int OP>
 __device__ __forceinline__ void face(double &acc_r, double &acc_i, double2 c, double2 nb,
                                      double dc, double dn, bool ghost, double qr_c, double qi_c,
@@ -142,7 +143,7 @@ __device__ __forceinline__ void face(double &acc_r, double &acc_i, double2 c, do
     } else {
         double Df;
         if (OP == LAP || OP == ADV) Df = d_const;   // the face's own coefficient
-        else Df = ghost ? dc : 0.5 * (dc + dn);
+        else Df = dc + (ghost ? dc : dn);
         acc_r = fma(Df, dr, acc_r);
         acc_i = fma(Df, di, acc_i);
     }

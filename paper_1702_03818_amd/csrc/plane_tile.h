@@ -30,12 +30,6 @@ __device__ __forceinline__ double2 load_w(const PlaneArgs &a, int gx, int gy, in
     return load_c<BC, IN_REAL>(Dims{a.nx, a.ny, a.nz}, a.in_re, a.in_c, gx, gy, gz);
 }
 
-template <int BC>
-__device__ __forceinline__ double load_d(const PlaneArgs &a, int gx, int gy, int gz)
-{
-    return load_r<BC>(Dims{a.nx, a.ny, a.nz}, a.D, gx, gy, gz);
-}
-
 template <int OP, int BC, int NDIM, int BX, int BY>
 struct TileShape {
     static constexpr int SX = BX + 2;
@@ -103,7 +97,7 @@ __device__ __forceinline__ void plane_tile(const PlaneArgs &a, int bx, int by, i
     auto LD = [&](int gx, int gy, int gz) {
         bool g;
         const long long i = bc_index_nb<BC>(dm, gx, gy, gz, g);
-        return (OP == VAR) ? a.D[i] : 0.0;   // ghost D is never used
+        return (OP == VAR) ? 0.5 * a.D[i] : 0.0;   // D/2 (face rule); ghost D is never used
     };
     const bool dirichlet = (BC == DIR);
     const bool own_out = dirichlet && !(x < a.nx && y < a.ny);

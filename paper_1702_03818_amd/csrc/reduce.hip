@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kThreads) void rho_pass1(const double *w, const dou
             if (OP == FRKC2_OP_LAPLACE) {
                 Df = d_const;
             } else if (OP == FRKC2_OP_VARCOEF) {
-                Df = 0.5 * (D[p] + (ghost ? D[p] : D[q]));
+                Df = 0.5 * D[p] + 0.5 * (ghost ? D[p] : D[q]);
             } else {
                 const double un = ghost ? 0.0 : w[q];
                 Df = 0.5 * (w[p] * w[p] + un * un);

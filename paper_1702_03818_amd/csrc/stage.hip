@@ -67,7 +67,7 @@ __global__ __launch_bounds__(k1dThreads) void stage1d_lds(const double *w_in, do
     const int tid = threadIdx.x;
     for (int i = tid; i < n; i += k1dThreads) {
         sW[i] = make_double2(w_in[i], 0.0);
-        if (OP == VAR) sD[i] = D[i];
+        if (OP == VAR) sD[i] = 0.5 * D[i];   // D/2, as the face rule takes it
     }
     __syncthreads();
     for (int step = 0; step < nsteps; ++step) {

@@ -133,7 +133,7 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
     auto LW = [&](int gz) {
         return IN_REAL ? make_double2(pWr[zoff(gz)], 0.0) : pWc[zoff(gz)];
     };
-    auto LD = [&](int gz) { return VC ? pD[zoff(gz)] : 0.0; };
+    auto LD = [&](int gz) { return VC ? 0.5 * pD[zoff(gz)] : 0.0; };   // D/2 (face rule)
     auto LE = [&](int gz) { return (EMB && !IN_REAL) ? pE[zoff(gz)] : 0.0; };
     auto pout = [&](int p) { return dir && (p < 0 || p >= a.nz); };
     auto dslot = [](int p) { return ((p % ND) + ND) % ND; };

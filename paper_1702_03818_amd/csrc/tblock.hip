@@ -123,7 +123,7 @@ __global__ __launch_bounds__(BXE *TY) void tb_stage(TbArgs a)
     auto LD = [&](int gy, int gz) {
         bool g;
         const long long i = bc_index_nb<BC>(dm, x, gy, gz, g);
-        return VC ? a.D[i] : 0.0;
+        return VC ? 0.5 * a.D[i] : 0.0;   // D/2, as the face rule takes it
     };
     auto pout = [&](int p) { return dir && (p < 0 || p >= a.nz); };
     auto dslot = [](int p) { return ((p % ND) + ND) % ND; };
