@@ -223,10 +223,24 @@ def cpu_baseline(prob, T, c_lib, min_seconds=10.0, max_supersteps=8):
         if dt >= min_seconds or n >= max_supersteps:
             break
     ups = prob.npoints * S_STAGES * n / dt
+    # the 1D heat run in full (20 supersteps of s = 16 on 1024 points), median of 3
+    from paper_1702_03818_amd import workloads as wl
+    p1 = wl.heat1d()
+    c16 = ocoeffs(16, NU)
+    T1 = CFL * c16.beta_bar / (4.0 / (p1.h * p1.h))
+    t1 = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        ostage.run(p1, 16, 20, T=T1, coeffs=c16)
+        t1.append(time.perf_counter() - t0)
+    ms1 = sorted(t1)[1] * 1e3
     return {"value": ups, "unit": "grid-point-stage updates/s", "cores": ostage.threads(),
             "kind": "oracle",
             "sample": "%d consecutive supersteps (s=100) of the same 256^3 variable-D problem, "
-                      "%.1f s" % (n, dt)}
+                      "%.1f s" % (n, dt),
+            "heat1d": {"cpu_ms": ms1, "value": p1.npoints * 16 * 20 / (ms1 * 1e-3),
+                       "sample": "the whole 1D heat run (20 supersteps, s = 16, 1024 points), "
+                                 "median of 3"}}
 
 
 def batched_leg(F, wl, torch, reps=3):
@@ -275,6 +289,67 @@ def batched_leg(F, wl, torch, reps=3):
             "unit": "grid-point-stage updates/s",
             "plain_sequential_ms": t_p, "plain_sequential_value": work / (t_p * 1e-3),
             "speedup_vs_plain": t_p / t_b}
+
+
+def heat1d_leg(F, wl, torch, reps=10):
+    """1D heat equation, 1024 points periodic, s = 16, 20 supersteps with T = 0.9 betabar / rho
+    (rho = 4/h^2, exact for the periodic Laplacian): the whole run fits in LDS, so it is
+    timed as a latency figure (median of reps runs), not against the HBM roofline."""
+    p = wl.heat1d()
+    s, nsup = 16, 20
+    _, _, info16, _ = F.frkc2_coeffs(s, NU)
+    T = CFL * info16["beta_bar"] / (4.0 / (p.h * p.h))
+    w0 = torch.tensor(p.w0.reshape(-1), dtype=torch.float64, device="cuda")
+    w = w0.clone()
+    F.frkc2_step(p, w, None, T=T, s=s, nsteps=nsup)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        w.copy_(w0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        F.frkc2_step(p, w, None, T=T, s=s, nsteps=nsup)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = sorted(times)[len(times) // 2]
+    work = p.npoints * s * nsup
+    return {"grid": [p.npoints], "s": s, "supersteps": nsup, "T": T, "gpu_ms": ms,
+            "value": work / (ms * 1e-3), "unit": "grid-point-stage updates/s"}
+
+
+def porous2d_leg(F, wl, torch, nsup=5):
+    """2D porous-medium equation u_t = div(u^2 grad u), 4096^2 periodic, s = 400, 5 supersteps
+    with T = cfl betabar / rho of the current state at cfl = 0.002 (the complex stages of the
+    nonlinear operator are stable there), launch configuration from the library's autotuner.
+    Algorithmic bytes: 32 per point and pass (complex W in and out)."""
+    p = wl.porous2d()
+    s = 400
+    w0 = torch.tensor(p.w0.reshape(-1), dtype=torch.float64, device="cuda")
+    w = w0.clone()
+    tune = F.frkc2_autotune(p, w, None, s=s, nu=NU, reps=1)
+    w.copy_(w0)
+    F.frkc2_step(p, w, None, cfl=0.002, s=s, nsteps=1)
+    torch.cuda.synchronize()
+    w.copy_(w0)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    F.frkc2_step(p, w, None, cfl=0.002, s=s, nsteps=nsup)
+    e1.record()
+    torch.cuda.synchronize()
+    F.frkc2_set_option(F.OPT_CLEAR_TUNED, 0)
+    ms = e0.elapsed_time(e1) / nsup
+    k = max(1, tune["tblock"])
+    npass = -(-s // k)
+    gbs = 32.0 * p.npoints * npass / (ms * 1e-3) / 1e9
+    log("porous 2D: %.3f ms per superstep (k=%d tile=%d)" % (ms, tune["tblock"], tune["tile"]))
+    return {"grid": [4096, 4096], "s": s, "supersteps": nsup, "cfl": 0.002,
+            "ms_per_superstep": ms, "value": p.npoints * s / (ms * 1e-3),
+            "unit": "grid-point-stage updates/s", "stages_per_pass": tune["tblock"],
+            "tile": tune["tile"], "bytes_per_point_per_pass": 32, "achieved_gbs": gbs,
+            "frac": gbs / HBM_PEAK_GBS}
 
 
 def adaptive_leg(F, wl, torch, prob, D, rho, info):
@@ -408,6 +483,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the error-control leg")
     ap.add_argument("--no-bruss", action="store_true", help="skip the Brusselator leg")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 1D heat and 2D porous-medium legs")
     ap.add_argument("--tblock", type=int, default=0, choices=(0, 1, 2, 3),
                     help="stages fused per HBM pass in the timed run (0: autotune)")
     ap.add_argument("--tile", type=int, default=0, help="tile shape with --tblock (0: automatic)")
@@ -588,6 +665,9 @@ def main():
     out["adjoint"] = None if args.no_adjoint else adjoint_leg(F, wl, torch)
     torch.cuda.empty_cache()
     out["brusselator"] = None if args.no_bruss else brusselator_leg(F, wl, torch)
+    torch.cuda.empty_cache()
+    out["heat1d"] = None if args.no_small else heat1d_leg(F, wl, torch)
+    out["porous2d"] = None if args.no_small else porous2d_leg(F, wl, torch)
     if not args.no_cpu:
         log("timing the CPU oracle on one superstep")
         out["cpu_baseline"] = cpu_baseline(prob, T, info)

@@ -210,14 +210,15 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
             double2 w[4];
             double d[4], dc, dzm, dzp;
         };
-        auto read = [&](int m) {
-            Nb n;
-            const int p = t - m;
+        auto readw = [&](int m, Nb &n) {
             const double2 *L = sL[rb][m - 1];
             n.w[0] = L[slot - 1];
             n.w[1] = L[slot + 1];
             n.w[2] = L[slot - SX];
             n.w[3] = L[slot + SX];
+        };
+        auto readd = [&](int m, Nb &n) {
+            const int p = t - m;
             n.dc = n.dzm = n.dzp = 0.0;
             n.d[0] = n.d[1] = n.d[2] = n.d[3] = 0.0;
             if (VC) {
@@ -236,17 +237,23 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
                     n.dzp = (m == 2) ? D0[rs(-1)] : (m == 3 ? D0[rs(-2)] : sD[dslot(p + 1)][slot]);
                 }
             }
-            return n;
         };
         // (For K = 3, or with the embedded solution, the operands of two levels
         // do not fit the registers of four wavefronts per SIMD: there each
-        // level reads its own.)
+        // level reads its own; reading only the next level's W neighbours
+        // ahead, or writing each level's plane as soon as it is computed,
+        // measured no faster.)
         constexpr bool RA = (K <= 2) && !EMB;
-        Nb cur = read(1);
+        Nb cur;
+        readw(1, cur);
+        readd(1, cur);
 #pragma unroll
         for (int m = 1; m <= K; ++m) {
             Nb nxt = cur;
-            if (RA && m < K) nxt = read(m + 1);
+            if (RA && m < K) {
+                readw(m + 1, nxt);
+                readd(m + 1, nxt);
+            }
             const int p = t - m;
             if (m > wneed) {
                 // keep the slot written every step (the value is never read)
@@ -298,7 +305,10 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
                     if (EMB) a.emb_out[i] = eh;
                 }
             }
-            if (!RA && m < K) nxt = read(m + 1);
+            if (!RA && m < K) {
+                readw(m + 1, nxt);
+                readd(m + 1, nxt);
+            }
             cur = nxt;
         }
         // All LDS writes of the step come after all its reads, so the reads
