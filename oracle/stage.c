@@ -31,7 +31,8 @@
  *           to the last bit whenever the halves are normal and the sum finite);
  *   op 0/1: acc_r = fma(Df, dr, acc_r), acc_i = fma(Df, di, acc_i);
  *   op 2:   q = W^2 as (fma(Wr, Wr, -(Wi*Wi)), 2*(Wr*Wi)) for cell and
- *           neighbour, Qr = (qr_c + qr_nb)/2, Qi likewise,
+ *           neighbour, Qr = qr_c/2 + qr_nb/2, Qi likewise (halves exact: the
+ *           same bits as (qr_c + qr_nb)/2 whenever they are normal),
  *           acc_r = fma(Qr, dr, fma(-Qi, di, acc_r)),
  *           acc_i = fma(Qr, di, fma(Qi, dr, acc_i));
  *   f = acc*inv_h2 with inv_h2 = 1/(h*h);
@@ -173,8 +174,8 @@ static void apply_op(const grid_t *g, const double *D, const double *wr, const d
                 double qi_c = 2.0 * (wr[p] * wi[p]);
                 double qr_n = fma(nr, nr, -(ni * ni));
                 double qi_n = 2.0 * (nr * ni);
-                double Dr = 0.5 * (qr_c + qr_n);
-                double Di = 0.5 * (qi_c + qi_n);
+                double Dr = 0.5 * qr_c + 0.5 * qr_n;
+                double Di = 0.5 * qi_c + 0.5 * qi_n;
                 acc_r = fma(Dr, dr, fma(-Di, di, acc_r));
                 acc_i = fma(Dr, di, fma(Di, dr, acc_i));
             } else {

@@ -214,6 +214,8 @@ TB_CASES = [
     ("3d-var-per", (67, 30, 18), 2, 4), ("3d-var-per", (130, 12, 9), 3, 4),
     ("3d-lap-dir", (33, 17, 9), 3, 4), ("3d-lap-per", (9, 5, 4), 2, 4),
     ("3d-var-dir", (2, 3, 2), 3, 4), ("3d-var-dir", (64, 11, 5), 2, 4),
+    ("3d-var-dir", (70, 20, 1), 3, 4), ("3d-var-per", (65, 9, 1), 3, 4),
+    ("3d-var-dir", (1, 19, 7), 3, 4),
 ]
 
 
