@@ -119,28 +119,46 @@ __device__ __forceinline__ void csq(double2 c, double &qr, double &qi)
     qi = 2.0 * (c.x * c.y);
 }
 
+// W^2 / 2 of a complex value: (0.5 * fma(re, re, -(im*im)), re*im), the exact
+// halves of csq(); a porous face value is the sum of the two cells' halves.
+__device__ __forceinline__ void csqh(double2 c, double &qr, double &qi)
+{
+    qr = 0.5 * fma(c.x, c.x, -(c.y * c.y));
+    qi = c.x * c.y;
+}
+
+// Porous face with both cells' W^2/2 given: Q = qh_c + qh_n,
+// acc_r = fma(Qr, dr, fma(-Qi, di, acc_r)), acc_i = fma(Qr, di, fma(Qi, dr, acc_i)).
+__device__ __forceinline__ void face_por(double &acc_r, double &acc_i, double2 c, double2 nb,
+                                         double qr_c, double qi_c, double qr_n, double qi_n)
+{
+    const double dr = nb.x - c.x;
+    const double di = nb.y - c.y;
+    const double Dr = qr_c + qr_n;
+    const double Di = qi_c + qi_n;
+    acc_r = fma(Dr, dr, fma(-Di, di, acc_r));
+    acc_i = fma(Dr, di, fma(Di, dr, acc_i));
+}
+
 // One face of the flux sum of the diffusion operator, in the fixed order the
 // library and its CPU check share (fused multiply-adds, correctly rounded).
 // nb: neighbour value (0 for a Dirichlet ghost); dc, dn: halves of the cell
 // and neighbour diffusivity (0.5 * D, exact; the kernels halve D once when
 // they load it), D_f = dc + dn, the mean of the two; ghost takes dn = dc, so
-// the face carries D_c; qr_c, qi_c: W_c^2 for the porous operator; d_const:
+// the face carries D_c; qr_c, qi_c: W_c^2/2 (csqh) for the porous operator; d_const:
 // the face's coefficient for LAPLACE (d) and ADVDIFF (d -+ v h/2).
 template <int OP>
 __device__ __forceinline__ void face(double &acc_r, double &acc_i, double2 c, double2 nb,
                                      double dc, double dn, bool ghost, double qr_c, double qi_c,
                                      double d_const)
 {
-    const double dr = nb.x - c.x;
-    const double di = nb.y - c.y;
     if (OP == POR) {
         double qr_n, qi_n;
-        csq(nb, qr_n, qi_n);
-        const double Dr = 0.5 * (qr_c + qr_n);
-        const double Di = 0.5 * (qi_c + qi_n);
-        acc_r = fma(Dr, dr, fma(-Di, di, acc_r));
-        acc_i = fma(Dr, di, fma(Di, dr, acc_i));
+        csqh(nb, qr_n, qi_n);
+        face_por(acc_r, acc_i, c, nb, qr_c, qi_c, qr_n, qi_n);
     } else {
+        const double dr = nb.x - c.x;
+        const double di = nb.y - c.y;
         double Df;
         if (OP == LAP || OP == ADV) Df = d_const;   // the face's own coefficient
         else Df = dc + (ghost ? dc : dn);

@@ -153,7 +153,7 @@ __device__ __forceinline__ void plane_tile(const PlaneArgs &a, int bx, int by, i
             const double2 c = Wc;
             double qr_c = 0.0, qi_c = 0.0;
             if (OP == POR) {
-                csq(c, qr_c, qi_c);
+                csqh(c, qr_c, qi_c);
             }
             double acc_r = 0.0, acc_i = 0.0;
             // A Dirichlet ghost holds W = 0 and the D of the boundary cell it

@@ -82,7 +82,7 @@ __global__ __launch_bounds__(k1dThreads) void stage1d_lds(const double *w_in, do
                 const double2 c = sW[i];
                 double qr_c = 0.0, qi_c = 0.0;
                 if (OP == POR) {
-                    csq(c, qr_c, qi_c);
+                    csqh(c, qr_c, qi_c);
                 }
                 const bool gl = (BC == DIR) && i == 0;
                 const bool gr = (BC == DIR) && i == n - 1;

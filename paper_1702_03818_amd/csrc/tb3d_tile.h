@@ -272,7 +272,7 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
                 }
                 double qr_c = 0.0, qi_c = 0.0;
                 if (OP == POR) {
-                    csq(c, qr_c, qi_c);
+                    csqh(c, qr_c, qi_c);
                 }
                 // A Dirichlet ghost holds W = 0 and the D of the boundary cell
                 // it faces (loads are clamped), so every face takes the plain

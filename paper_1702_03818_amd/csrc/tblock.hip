@@ -214,7 +214,7 @@ __global__ __launch_bounds__(BXE *TY) void tb_stage(TbArgs a)
                 }
                 double qr_c = 0.0, qi_c = 0.0;
                 if (OP == POR) {
-                    csq(c, qr_c, qi_c);
+                    csqh(c, qr_c, qi_c);
                 }
                 double acc_r = 0.0, acc_i = 0.0;
                 // A Dirichlet ghost holds W = 0 and the D of the boundary cell
