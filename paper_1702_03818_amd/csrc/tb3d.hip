@@ -12,15 +12,17 @@
 //    up with 512-byte segments of the grid and a 256-wide grid needs exactly
 //    4 tiles across. The K halo columns on each side of every row are
 //    computed by one or two extra "halo" wavefronts whose lanes each own one
-//    (row, halo column) pair. Every lane skips the levels its column is not
-//    needed for (level m is used within K - m cells of the output), so the
-//    rows near the tile edge and the halo lanes do only the work that is
-//    consumed.
+//    (row, halo column) pair. A wavefront computes the levels one of its
+//    lanes needs (level m is used within K - m cells of the output), so rows
+//    near the tile edge skip whole levels.
 //  * The LDS planes are double-buffered by time-step parity, so one barrier
 //    per time step separates the writes of step t from the reads of step
-//    t + 1. The diffusivity ring holds K + 2 planes for the same reason.
+//    t + 1. The diffusivity ring holds K + 2 planes for the same reason. The
+//    plane row stride is odd, which keeps the column-wise halo wavefronts
+//    free of bank conflicts.
 //  * The thread's own diffusivity of planes t-2 .. t comes from its register
-//    ring; only x/y neighbours (and older planes) are read from LDS.
+//    ring; only x/y neighbours (and older planes) are read from LDS. The
+//    level windows live in a register ring indexed by the unrolled step.
 //
 // Every value is computed with the same per-point arithmetic, in the same
 // order, as the one-stage kernel (faces x-, x+, y-, y+, z-, z+; face() and
