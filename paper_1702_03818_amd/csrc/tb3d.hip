@@ -52,9 +52,10 @@ __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
 }
 
 // Chunk length: one workgroup fills a CU (its LDS), so the launch runs in
-// rounds of n_cu workgroups. Pick, among nz, nz/2, ... down to 16 planes, the
-// chunk that maximises the busy fraction of the last round times the share
-// of planes that are not chunk halo (zc / (zc + 2K)).
+// rounds of n_cu workgroups, each as long as a full chunk of zc + 2K steps.
+// Pick the chunk length (every one down to 8 planes) that maximises the
+// useful planes per CU-step, tiles * nz / (rounds * n_cu * (zc + 2K)); on a
+// tie the longest.
 int choose_zchunk3(long long tiles, int nz, int K)
 {
     static int n_cu = 0;
@@ -67,17 +68,20 @@ int choose_zchunk3(long long tiles, int nz, int K)
         else
             n_cu = 256;
     }
+    // every chunk length down to 8 planes (a host loop of at most nz steps);
+    // the longest of equally good ones
     int best = nz;
     double best_eff = -1.0;
-    for (int zc = nz;; zc = (zc + 1) / 2) {
+    for (int zc = nz; zc >= 1; --zc) {
+        if (zc < 8 && zc < nz) break;
         const long long nblk = tiles * ((nz + zc - 1) / zc);
         const long long rounds = (nblk + n_cu - 1) / n_cu;
-        const double eff = (double)nblk / (double)(rounds * n_cu) * zc / (zc + 2.0 * K);
+        const double eff =
+            (double)tiles * nz / ((double)rounds * n_cu * (zc + 2.0 * K));
         if (eff > best_eff + 1e-9) {
             best_eff = eff;
             best = zc;
         }
-        if (zc <= 16) break;
     }
     return best;
 }
