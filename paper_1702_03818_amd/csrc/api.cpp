@@ -713,17 +713,28 @@ extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const 
                       reinterpret_cast<double *>(base + L.lamB)};
     double *gD = reinterpret_cast<double *>(base + L.gD);
 
-    // forward recompute, storing W^0 .. W^{s-1}
+    // forward recompute, storing W^0 .. W^{s-1}: 3D grids fuse three stages
+    // per pass and write the two intermediate states as well
     HIP_TRY(launch_real_to_complex(N, w_n, S(0), st), "adjoint: W^0");
-    for (int l = 0; l + 1 < s; ++l) {
+    for (int l = 0; l + 1 < s;) {
+        const int k = (kg.ndim == 3 && s - 1 - l >= 3) ? 3 : 1;
         PassArgs pa{};
-        pa.k = 1;
+        pa.k = k;
         pa.D = D;
         pa.in_c = S(l);
-        pa.out_c = S(l + 1);
-        pa.tr[0] = T * are[l];
-        pa.ti[0] = T * aim[l];
-        HIP_TRY(launch_pass(kg, pa, 0, st), "adjoint: forward stage");
+        pa.out_c = S(l + k);
+        for (int i = 0; i < k; ++i) {
+            pa.tr[i] = T * are[l + i];
+            pa.ti[i] = T * aim[l + i];
+        }
+        if (k > 1) {
+            pa.lvl_out = S(l + 1);
+            pa.lvl_stride = (long long)(cbytes / 16);
+            HIP_TRY(launch_tb3d(kg, pa, st), "adjoint: forward pass");
+        } else {
+            HIP_TRY(launch_pass(kg, pa, 0, st), "adjoint: forward stage");
+        }
+        l += k;
     }
     const bool vc = kg.op == FRKC2_OP_VARCOEF;
     if (vc) HIP_TRY(launch_zero(N, gD, st), "adjoint: zero gD");

@@ -48,6 +48,8 @@ struct PassArgs {
     int zchunk;                 // z planes per workgroup (0: automatic)
     const double *emb_in;       // embedded first-order solution in (not the first stage)
     double *emb_out;            // ... and out; non-null selects the embedded variant (k = 1)
+    double *lvl_out;            // 3D fused passes: levels 1..k-1 also written to
+    long long lvl_stride;       // lvl_out + (m-1)*lvl_stride complex values (non-null selects it)
 };
 
 // Launchers (stage.hip). Return hipError_t as int.

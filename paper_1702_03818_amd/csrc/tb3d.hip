@@ -38,7 +38,7 @@ using namespace dev;
 
 // tb3d_stage: one workgroup per tile, the block index remapped so that each
 // XCD receives a contiguous range of tiles.
-template <int OP, int BC, int K, bool IN_REAL, bool OUT_REAL, bool EMB = false>
+template <int OP, int BC, int K, bool IN_REAL, bool OUT_REAL, bool EMB = false, bool ST = false>
 __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
 {
     __shared__ double2 sL[Tb3Lds<OP, K>::L];
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
     lb /= a.ntx;
     const int by = lb % a.nty;
     const int bz = lb / a.nty;
-    tb3d_tile<OP, BC, K, IN_REAL, OUT_REAL, EMB>(a, bx, by, bz, sL, sD);
+    tb3d_tile<OP, BC, K, IN_REAL, OUT_REAL, EMB, ST>(a, bx, by, bz, sL, sD);
 }
 
 // Chunk length: one workgroup fills a CU (its LDS), so the launch runs in
@@ -97,6 +97,14 @@ int launch3_k(const Tb3Args &a0, bool ir, bool orl, hipStream_t st)
     const long long nblk = tiles * ((a.nz + a.zchunk - 1) / a.zchunk);
     if (nblk > 0x7fffffffLL) return (int)hipErrorInvalidValue;
     dim3 grid((unsigned)nblk), block(1024);
+    if (a.lvl_out) {
+        // stage states of the adjoint's forward recompute: complex in and out
+        if (ir || orl || a.emb_out || !(OP == LAP || OP == VAR)) return (int)hipErrorInvalidValue;
+        if constexpr (OP == LAP || OP == VAR)
+            hipLaunchKernelGGL((tb3d_stage<OP, BC, K, false, false, false, true>), grid, block, 0,
+                               st, a);
+        return (int)hipGetLastError();
+    }
     if (a.emb_out) {
         if (orl) return (int)hipErrorInvalidValue;
         if (ir)
@@ -150,6 +158,8 @@ int launch_tb3d(const KGrid &g, const PassArgs &p, hipStream_t st)
     a.zchunk = p.zchunk;
     a.emb_in = p.emb_in;
     a.emb_out = p.emb_out;
+    a.lvl_out = reinterpret_cast<double2 *>(p.lvl_out);
+    a.lvl_stride = p.lvl_stride;
     for (int i = 0; i < kMaxTBlock; ++i) {
         a.tr[i] = p.tr[i];
         a.ti[i] = p.ti[i];

@@ -22,6 +22,8 @@ struct Tb3Args {
     double inv_h2, d_const;
     double tr[kMaxTBlock], ti[kMaxTBlock];
     double fc[6];               // face coefficients x-, x+, y-, y+, z-, z+ (LAPLACE, ADVDIFF)
+    double2 *lvl_out;           // ST: level m (1..K-1) written to lvl_out + (m-1)*lvl_stride
+    long long lvl_stride;
 };
 
 // Rows of the extended tile (one wavefront each) and halo wavefronts for
@@ -65,7 +67,9 @@ struct Tb3Lds {
 // EMB: also advance the embedded first-order solution of the error estimate
 // (Sec. 3): What^m = fma(tr_m, Re f(W^{m-1}), What^{m-1}) at every level, a
 // pointwise recursion carried in registers next to the level windows.
-template <int OP, int BC, int K, bool IN_REAL, bool OUT_REAL, bool EMB = false>
+// ST: also write the intermediate levels 1..K-1 of the output columns (the
+// stage states the adjoint's reverse sweep reads).
+template <int OP, int BC, int K, bool IN_REAL, bool OUT_REAL, bool EMB = false, bool ST = false>
 __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int bz, double2 *sLp,
                                           double *sDp)
 {
@@ -297,6 +301,8 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
                 if (m < K) {
                     WR[m - 1][rs(0)] = v;
                     if (EMB) ehn[m - 1] = eh;
+                    if (ST && out_col && p >= z0 && p < z1)
+                        a.lvl_out[(m - 1) * a.lvl_stride + ixy + pst * p] = v;
                 } else if (out_col && p >= z0 && p < z1) {
                     // an output column is inside the grid: ixy is its own offset
                     const long long i = ixy + pst * p;
