@@ -72,7 +72,7 @@ def kernel_pattern(k, tile):
     if k == 1:
         return "plane_stage<1, 1, 3, 64, 4, false, false>"
     if tile == 4:
-        return "tb3d_stage<1, 1, %d, false, false, false>" % k
+        return "tb3d_stage<1, 1, %d, false, false, false, false>" % k
     shape = {1: "64, 16, 1", 2: "64, 16, 2", 3: "64, 8, %d" % (4 if k == 2 else 3)}[tile]
     return "tb_stage<1, 1, 3, %s, %d, false, false>" % (shape, k)
 
