@@ -39,7 +39,7 @@ def log(msg):
 
 # Sources that define the dominant kernel of each tile shape (k = 1: the plane kernel).
 KERNEL_SOURCES = {1: ("stage.hip", "plane_tile.h"), 2: ("tblock.hip",), 3: ("tblock.hip",),
-                  4: ("tb3d.hip", "tb3d_tile.h")}
+                  4: ("tb3d.hip", "tb3d_tile.h"), 5: ("tb3d.hip", "tb3d_tile.h")}
 COMMON_SOURCES = ("device_common.h", "internal.h")
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_stage3d_256.json")
 
@@ -71,8 +71,8 @@ def kernel_pattern(k, tile):
     """Name fragment rocprofv3 prints for the interior-pass kernel of the 3D workload."""
     if k == 1:
         return "plane_stage<1, 1, 3, 64, 4, false, false>"
-    if tile == 4:
-        return "tb3d_stage<1, 1, %d, false, false, false, false>" % k
+    if tile in (4, 5):
+        return "tb3d_stage<1, 1, %d, false, false, false, false, %d>" % (k, 64 if tile == 4 else 32)
     shape = {1: "64, 16, 1", 2: "64, 16, 2", 3: "64, 8, %d" % (4 if k == 2 else 3)}[tile]
     return "tb_stage<1, 1, 3, %s, %d, false, false>" % (shape, k)
 
@@ -188,8 +188,9 @@ def kernel_name(k, tile):
     """The dominant kernel of a superstep at fused depth k and tile shape (option numbering)."""
     if k == 1:
         return "plane_stage<VARCOEF, Dirichlet, 3D, 64x4>"
-    if tile == 4:
-        return "tb3d_stage<VARCOEF, Dirichlet, K=%d> (64-column output rows, halo wavefronts)" % k
+    if tile in (4, 5):
+        return ("tb3d_stage<VARCOEF, Dirichlet, K=%d> (%d-column output rows, halo wavefronts)"
+                % (k, 64 if tile == 4 else 32))
     return "tb_stage<VARCOEF, Dirichlet, 3D, shape %d, K=%d>" % (tile, k)
 
 

@@ -363,16 +363,20 @@ int frkc2_autotune(const frkc2_grid *g, const double *w, const double *D, int s,
  *                     (3D), 2, 3, 4, 6 and 8 (2D); 0 = automatic (the entry
  *                     frkc2_autotune stored for the grid, else 3 in 3D, 4 in
  *                     2D, 1 in 1D)
- *   FRKC2_OPT_TILE    tile shape of the fused passes: 0 = automatic (3D 4,
+ *   FRKC2_OPT_TILE    tile shape of the fused passes: 0 = automatic (3D 4 or
+ *                     5, whichever a pass-time model prefers for the grid;
  *                     2D 1); 3D 1 = 64x16 extended columns, 2 = 64x32 (k = 2),
  *                     3 = 64x32 (k = 2) or 64x24 (k = 3) with 512 threads,
  *                     4 = 64-column output rows with halo wavefronts (64x11
- *                     outputs for k = 2, 64x8 for k = 3); 2D 1 = rows of 256,
- *                     2 = rows of 512
+ *                     outputs for k = 2, 64x8 for k = 3), 5 = 32-column output
+ *                     rows, two per wavefront (32x24 for k = 2, 32x20 for
+ *                     k = 3); 2D 1 = rows of 256, 2 = rows of 512
  *   FRKC2_OPT_ZCHUNK  z planes (2D: rows) per workgroup of every pass of
- *                     frkc2_step, 0 = automatic (halve from the whole depth
- *                     until >= 512 workgroups for 3D fused passes, >= 2048
- *                     otherwise)
+ *                     frkc2_step, 0 = automatic (3D shapes 4 and 5: the length
+ *                     with the most useful planes per CU-step over whole
+ *                     rounds of one workgroup per CU; otherwise halve from the
+ *                     whole depth until >= 512 workgroups for 3D fused passes,
+ *                     >= 2048 otherwise)
  *   FRKC2_OPT_CLEAR_TUNED  forget every configuration frkc2_autotune stored
  *                     (value ignored)
  * Results are identical, bit for bit, for every setting.

@@ -282,9 +282,15 @@ int default_depth(const KGrid &kg) { return (kg.ndim == 3) ? 3 : (kg.ndim == 2 ?
 
 // Tile shapes as the launchers number them (the option's value minus one):
 // 3D 0 = 64x16 extended columns, 1 = 64x32, 2 = 64x32 / 64x24 with 512
-// threads, 3 = 64-column output rows with halo wavefronts; 2D 0 = rows of
-// 256, 1 = rows of 512.
-int default_tile(const KGrid &kg) { return (kg.ndim == 3) ? 3 : 0; }
+// threads, 3 = 64-column output rows with halo wavefronts, 4 = the same with
+// 32-column rows, two per wavefront; 2D 0 = rows of 256, 1 = rows of 512.
+// The 3D default is the full-width tile whose width the pass-time model
+// prefers for this grid.
+int default_tile(const KGrid &kg)
+{
+    if (kg.ndim != 3) return 0;
+    return tb3d_pick_cols(kg, default_depth(kg)) == 32 ? 4 : 3;
+}
 
 // The options if the depth is set, else the tuned entry for this grid, else
 // the default depth with the tile and chunk options.
@@ -377,8 +383,8 @@ extern "C" int frkc2_set_option(int key, int value)
         return FRKC2_OK;
     }
     if (key == FRKC2_OPT_TILE) {
-        if (value < 0 || value > 4) {
-            set_error("tile shape must lie in [0, 4]");
+        if (value < 0 || value > 5) {
+            set_error("tile shape must lie in [0, 5]");
             return FRKC2_EINVAL;
         }
         g_tile = value;
@@ -558,9 +564,11 @@ std::vector<PassCfg> tune_candidates(const KGrid &kg)
         add(2, 1);
         add(2, 2);
         add(2, 3);
+        add(2, 4);
         add(3, 0);
         add(3, 2);
         add(3, 3);
+        add(3, 4);
     } else if (kg.ndim == 2) {
         for (int k : {2, 3, 4, 6, 8}) {
             add(k, 0);
@@ -728,6 +736,7 @@ extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const 
             pa.ti[i] = T * aim[l + i];
         }
         if (k > 1) {
+            pa.cols = tb3d_pick_cols(kg, 3);
             pa.lvl_out = S(l + 1);
             pa.lvl_stride = (long long)(cbytes / 16);
             HIP_TRY(launch_tb3d(kg, pa, st), "adjoint: forward pass");
@@ -774,7 +783,8 @@ int run_superstep_emb(const KGrid &kg, const PassCfg &cfg, const double *w, cons
                       double *const buf[2], double *const emb[2], const double **WL,
                       const double **EL, hipStream_t st)
 {
-    const bool fused = kg.ndim == 3 && cfg.tile == 3 && cfg.k >= 2 && tblock_supported(kg, cfg.k);
+    const bool fused = kg.ndim == 3 && (cfg.tile == 3 || cfg.tile == 4) && cfg.k >= 2 &&
+                       tblock_supported(kg, cfg.k);
     const int k = fused ? cfg.k : 1;
     int l = 0, pass = 0;
     const double *in = nullptr, *ein = nullptr;
@@ -791,6 +801,7 @@ int run_superstep_emb(const KGrid &kg, const PassCfg &cfg, const double *w, cons
         }
         pa.out_c = buf[pass & 1];
         pa.emb_out = emb[pass & 1];
+        pa.cols = (cfg.tile == 4) ? 32 : 64;
         for (int i = 0; i < kk; ++i) {
             pa.tr[i] = Tn * are[l + i];
             pa.ti[i] = Tn * aim[l + i];

@@ -6,7 +6,8 @@
 // sequential; different problems are independent. The graph has two
 // independent branches. The 3D branch holds, per pass level L, one kernel
 // for the fused passes (stages 3L .. 3L+2 of every problem that has them, as
-// full-width temporally blocked tiles of tb3d_tile.h) and one for the
+// full-width temporally blocked tiles of tb3d_tile.h, 64 or 32 output columns
+// wide, one width for the whole batch) and one for the
 // single-stage passes that finish each superstep (s mod 3 stages, 64 x 16
 // plane-march tiles). The 2D branch holds, per stage level l, one kernel over
 // the 2D problems with s > l (64-column rows of the plane-march tile, so the
@@ -184,34 +185,36 @@ struct Pass3Args {
     int nprob, level;
 };
 
-template <int OP, int BC, bool IR, bool OR>
+template <int OP, int BC, bool IR, bool OR, int W>
 __device__ void run_fused(const BatchProblem &P, Tb3Args &a, long long c, double2 *sL, double *sD)
 {
     const int bx = (int)(c % P.ntx3);
     const long long r = c / P.ntx3;
-    tb3d_tile<OP, BC, kBatchK, IR, OR, false>(a, bx, (int)(r % P.nty3), (int)(r / P.nty3), sL, sD);
+    tb3d_tile<OP, BC, kBatchK, IR, OR, false, false, W>(a, bx, (int)(r % P.nty3),
+                                                       (int)(r / P.nty3), sL, sD);
 }
 
-template <int OP, int BC>
-__device__ void fused_io(const BatchProblem &P, Tb3Args &a, long long c, bool ir, bool orl,
-                         double2 *sL, double *sD)
+template <int OP, int BC, int W>
+__device__ void fused_io_w(const BatchProblem &P, Tb3Args &a, long long c, bool ir, bool orl,
+                           double2 *sL, double *sD)
 {
-    if (ir) run_fused<OP, BC, true, false>(P, a, c, sL, sD);
-    else if (orl) run_fused<OP, BC, false, true>(P, a, c, sL, sD);
-    else run_fused<OP, BC, false, false>(P, a, c, sL, sD);
+    if (ir) run_fused<OP, BC, true, false, W>(P, a, c, sL, sD);
+    else if (orl) run_fused<OP, BC, false, true, W>(P, a, c, sL, sD);
+    else run_fused<OP, BC, false, false, W>(P, a, c, sL, sD);
 }
+
 
 // One pass level of the 3D problems. FUSED: each active problem's pass of
 // kBatchK stages (stages kBatchK*level ..), as tb3d_tile items; otherwise its
 // single-stage pass (the stages left after the fused ones), as 64 x 16
 // plane-march items. A problem's first pass reads w, its last writes w, the
 // passes between ping-pong the workspace buffers.
-template <bool FUSED>
+template <bool FUSED, int W>
 __global__ __launch_bounds__(1024) void batched_pass3(Pass3Args t)
 {
     using S1 = TileShape<VAR, DIR, 3, kPBX, kPBY>;
-    constexpr int NL = FUSED ? Tb3Lds<VAR, kBatchK>::L : S1::LDS_W;
-    constexpr int ND = FUSED ? Tb3Lds<VAR, kBatchK>::D : S1::LDS_D;
+    constexpr int NL = FUSED ? Tb3Lds<VAR, kBatchK, W>::L : S1::LDS_W;
+    constexpr int ND = FUSED ? Tb3Lds<VAR, kBatchK, W>::D : S1::LDS_D;
     __shared__ double2 sL[NL];
     __shared__ double sD[ND];
     long long first, hi, step;
@@ -274,11 +277,11 @@ __global__ __launch_bounds__(1024) void batched_pass3(Pass3Args t)
                 ta.ti[i] = uni(P.tau[2 * (l0 + i) + 1]);
             }
             if (var) {
-                if (per) fused_io<VAR, PER>(P, ta, c, ir, orl, sL, sD);
-                else fused_io<VAR, DIR>(P, ta, c, ir, orl, sL, sD);
+                if (per) fused_io_w<VAR, PER, W>(P, ta, c, ir, orl, sL, sD);
+                else fused_io_w<VAR, DIR, W>(P, ta, c, ir, orl, sL, sD);
             } else {
-                if (per) fused_io<LAP, PER>(P, ta, c, ir, orl, sL, sD);
-                else fused_io<LAP, DIR>(P, ta, c, ir, orl, sL, sD);
+                if (per) fused_io_w<LAP, PER, W>(P, ta, c, ir, orl, sL, sD);
+                else fused_io_w<LAP, DIR, W>(P, ta, c, ir, orl, sL, sD);
             }
         } else {
             const int l = kBatchK * P.nfull + (L - P.nfull);
@@ -315,18 +318,21 @@ __global__ __launch_bounds__(1024) void batched_pass3(Pass3Args t)
 
 void batched_tile(int ndim, int *bx, int *by) { *bx = ndim == 3 ? kPBX : kBX2; *by = ndim == 3 ? kPBY : 1; }
 
-void batched_tile3(int *bx, int *by)
+void batched_tile3(int cols, int *bx, int *by)
 {
-    *bx = 64;
-    *by = Tb3Shape<kBatchK>::BYO;
+    *bx = cols;
+    *by = (cols == 32) ? Tb3Shape<kBatchK, 32>::BYO : Tb3Shape<kBatchK, 64>::BYO;
 }
 
-int launch_batched_pass3(bool fused, const BatchProblem *probs, const long long *item_prefix,
-                         long long items, int nprob, int level, int grid, hipStream_t st)
+int launch_batched_pass3(bool fused, int cols, const BatchProblem *probs,
+                         const long long *item_prefix, long long items, int nprob, int level,
+                         int grid, hipStream_t st)
 {
+    // the single-stage kernel does not depend on the width: one instance
     Pass3Args t{probs, item_prefix, items, nprob, level};
-    if (fused) hipLaunchKernelGGL(batched_pass3<true>, dim3(grid), dim3(1024), 0, st, t);
-    else hipLaunchKernelGGL(batched_pass3<false>, dim3(grid), dim3(1024), 0, st, t);
+    if (!fused) hipLaunchKernelGGL((batched_pass3<false, 64>), dim3(grid), dim3(1024), 0, st, t);
+    else if (cols == 32) hipLaunchKernelGGL((batched_pass3<true, 32>), dim3(grid), dim3(1024), 0, st, t);
+    else hipLaunchKernelGGL((batched_pass3<true, 64>), dim3(grid), dim3(1024), 0, st, t);
     return (int)hipGetLastError();
 }
 
@@ -346,7 +352,7 @@ int batched_grid_size(int ndim)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     hipError_t e = (ndim == 3)
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_pass3<true>, 1024, 0)
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_pass3<true, 64>, 1024, 0)
         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_level<2, kBX2, 1>, kBX2, 0);
     if (e != hipSuccess) return 0;
     return cus * (per > 0 ? per : 1);

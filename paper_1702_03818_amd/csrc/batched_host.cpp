@@ -94,6 +94,7 @@ struct GraphEntry {
     std::vector<BatchProblem> probs[2];   // host copies of the uploaded tables
     std::vector<long long> prefix[2];
     std::vector<long long> pass3;         // 3D: per level, fused then single-stage prefixes
+    int cols3 = 64;                       // 3D fused tiles: output columns (one width per batch)
     std::vector<double> tau;
 };
 
@@ -188,6 +189,19 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return s[a] > s[b]; });
     int max_s = 0;
+    // One tile width for all 3D problems (a pass kernel that carries both
+    // widths needs more registers than it has): the one with less total work
+    // over the fused passes. The items always fill the GPU, so work decides.
+    {
+        long long w32 = 0, w64 = 0;
+        for (int i = 0; i < nprob; ++i) {
+            if (kg[i].ndim != 3) continue;
+            const int zc = std::min(kg[i].nz, kChunkPlanes3);
+            w32 += (long long)nfull3(s[i]) * tb3d_work(32, kg[i].nx, kg[i].ny, kg[i].nz, zc);
+            w64 += (long long)nfull3(s[i]) * tb3d_work(64, kg[i].nx, kg[i].ny, kg[i].nz, zc);
+        }
+        E.cols3 = (w32 < w64) ? 32 : 64;
+    }
     E.tau.clear();
     for (int d = 0; d < 2; ++d) {
         E.probs[d].clear();
@@ -224,10 +238,11 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
         P.ntiles = P.ntx * P.nty * ((P.nz + P.zchunk - 1) / P.zchunk);
         if (P.ndim == 3) {
             int bx3, by3;
-            batched_tile3(&bx3, &by3);
             P.nfull = nfull3(P.s);
             P.npass = npass3(P.s);
             P.zc3 = std::min(P.nz, kChunkPlanes3);
+            P.cols3 = E.cols3;
+            batched_tile3(P.cols3, &bx3, &by3);
             P.ntx3 = (P.nx + bx3 - 1) / bx3;
             P.nty3 = (P.ny + by3 - 1) / by3;
             P.ntiles3 = P.ntx3 * P.nty3 * ((P.nz + P.zc3 - 1) / P.zc3);
@@ -297,7 +312,7 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
             const size_t row = (size_t)(2 * lv + kind) * (n3 + 1);
             const long long items = E.pass3[row + n3];
             if (items == 0) continue;
-            lrc = launch_batched_pass3(kind == 0,
+            lrc = launch_batched_pass3(kind == 0, E.cols3,
                                        reinterpret_cast<const BatchProblem *>(base + L.probs[0]),
                                        pass3_dev + row, items, n3, lv, grid_for(0, items),
                                        g_capture);

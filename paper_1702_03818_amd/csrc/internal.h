@@ -50,6 +50,7 @@ struct PassArgs {
     double *emb_out;            // ... and out; non-null selects the embedded variant (k = 1)
     double *lvl_out;            // 3D fused passes: levels 1..k-1 also written to
     long long lvl_stride;       // lvl_out + (m-1)*lvl_stride complex values (non-null selects it)
+    int cols;                   // 3D fused passes: output columns per tile, 64 (0) or 32
 };
 
 // Launchers (stage.hip). Return hipError_t as int.
@@ -75,6 +76,11 @@ bool tblock_supported(const KGrid &g, int k);
 int launch_tblock(const KGrid &g, const PassArgs &p, int shape, hipStream_t st);
 // 3D passes with 64-column output tiles and halo wavefronts (tb3d.hip), k = 2, 3.
 int launch_tb3d(const KGrid &g, const PassArgs &p, hipStream_t st);
+// Output columns (64 or 32) of the fused 3D tile with the lower predicted
+// pass time on this grid (rounds of workgroups x steps x step cost).
+int tb3d_pick_cols(const KGrid &g, int k);
+// Steps x step cost of all fused-tile items of one batched 3D problem.
+int tb3d_work(int cols, int nx, int ny, int nz, int zc);
 
 // Reductions (reduce.hip). partials must hold kReduceBlocks doubles + 2.
 constexpr int kReduceBlocks = 512;
@@ -112,17 +118,19 @@ struct BatchProblem {           // one problem's descriptor in device memory
     int zchunk, ntx, nty;           // one-stage tile grid: ntx * nty * ceil(nz / zchunk)
     int nfull, npass;               // 3D: passes of kBatchK stages, then single stages
     int zc3, ntx3, nty3, ntiles3;   // 3D fused-pass tile grid
+    int cols3;                      // its output columns per tile (64 or 32)
     double inv_h2, d_const;
 };
 constexpr int kBatchK = 3;          // stages per fused 3D pass of the batch
 void batched_tile(int ndim, int *bx, int *by);
-void batched_tile3(int *bx, int *by);
+void batched_tile3(int cols, int *bx, int *by);
 int batched_grid_size(int ndim);
 int launch_batched_level(int ndim, const BatchProblem *probs, const long long *item_prefix,
                          long long items, int active, int level, int grid, hipStream_t st);
 // 3D pass level: fused == true runs the kBatchK-stage passes of level `level`,
 // otherwise the single-stage passes; item_prefix spans all nprob 3D problems.
-int launch_batched_pass3(bool fused, const BatchProblem *probs, const long long *item_prefix,
+int launch_batched_pass3(bool fused, int cols, const BatchProblem *probs,
+                         const long long *item_prefix,
                          long long items, int nprob, int level, int grid, hipStream_t st);
 
 }  // namespace frkc2

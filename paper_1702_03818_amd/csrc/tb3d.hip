@@ -29,6 +29,8 @@
 // euler() of device_common.h), so the results are identical to the last bit.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "tb3d_tile.h"
 
 namespace frkc2 {
@@ -38,17 +40,18 @@ using namespace dev;
 
 // tb3d_stage: one workgroup per tile, the block index remapped so that each
 // XCD receives a contiguous range of tiles.
-template <int OP, int BC, int K, bool IN_REAL, bool OUT_REAL, bool EMB = false, bool ST = false>
+template <int OP, int BC, int K, bool IN_REAL, bool OUT_REAL, bool EMB = false, bool ST = false,
+          int W = 64>
 __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
 {
-    __shared__ double2 sL[Tb3Lds<OP, K>::L];
-    __shared__ double sD[Tb3Lds<OP, K>::D];
+    __shared__ double2 sL[Tb3Lds<OP, K, W>::L];
+    __shared__ double sD[Tb3Lds<OP, K, W>::D];
     int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int bx = lb % a.ntx;
     lb /= a.ntx;
     const int by = lb % a.nty;
     const int bz = lb / a.nty;
-    tb3d_tile<OP, BC, K, IN_REAL, OUT_REAL, EMB, ST>(a, bx, by, bz, sL, sD);
+    tb3d_tile<OP, BC, K, IN_REAL, OUT_REAL, EMB, ST, W>(a, bx, by, bz, sL, sD);
 }
 
 // Chunk length: one workgroup fills a CU (its LDS), so the launch runs in
@@ -56,7 +59,7 @@ __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
 // Pick the chunk length (every one down to 8 planes) that maximises the
 // useful planes per CU-step, tiles * nz / (rounds * n_cu * (zc + 2K)); on a
 // tie the longest.
-int choose_zchunk3(long long tiles, int nz, int K)
+int cu_count()
 {
     static int n_cu = 0;
     if (n_cu == 0) {
@@ -68,6 +71,12 @@ int choose_zchunk3(long long tiles, int nz, int K)
         else
             n_cu = 256;
     }
+    return n_cu;
+}
+
+int choose_zchunk3(long long tiles, int nz, int K)
+{
+    const int n_cu = cu_count();
     // every chunk length down to 8 planes (a host loop of at most nz steps);
     // the longest of equally good ones
     int best = nz;
@@ -86,12 +95,12 @@ int choose_zchunk3(long long tiles, int nz, int K)
     return best;
 }
 
-template <int OP, int BC, int K>
+template <int OP, int BC, int K, int W>
 int launch3_k(const Tb3Args &a0, bool ir, bool orl, hipStream_t st)
 {
     Tb3Args a = a0;
-    a.ntx = (a.nx + 63) / 64;
-    a.nty = (a.ny + Tb3Shape<K>::BYO - 1) / Tb3Shape<K>::BYO;
+    a.ntx = (a.nx + W - 1) / W;
+    a.nty = (a.ny + Tb3Shape<K, W>::BYO - 1) / Tb3Shape<K, W>::BYO;
     const long long tiles = (long long)a.ntx * a.nty;
     a.zchunk = (a0.zchunk > 0) ? min(a0.zchunk, a.nz) : choose_zchunk3(tiles, a.nz, K);
     const long long nblk = tiles * ((a.nz + a.zchunk - 1) / a.zchunk);
@@ -101,42 +110,61 @@ int launch3_k(const Tb3Args &a0, bool ir, bool orl, hipStream_t st)
         // stage states of the adjoint's forward recompute: complex in and out
         if (ir || orl || a.emb_out || !(OP == LAP || OP == VAR)) return (int)hipErrorInvalidValue;
         if constexpr (OP == LAP || OP == VAR)
-            hipLaunchKernelGGL((tb3d_stage<OP, BC, K, false, false, false, true>), grid, block, 0,
+            hipLaunchKernelGGL((tb3d_stage<OP, BC, K, false, false, false, true, W>), grid, block, 0,
                                st, a);
         return (int)hipGetLastError();
     }
     if (a.emb_out) {
         if (orl) return (int)hipErrorInvalidValue;
         if (ir)
-            hipLaunchKernelGGL((tb3d_stage<OP, BC, K, true, false, true>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((tb3d_stage<OP, BC, K, true, false, true, false, W>), grid, block, 0, st, a);
         else
-            hipLaunchKernelGGL((tb3d_stage<OP, BC, K, false, false, true>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((tb3d_stage<OP, BC, K, false, false, true, false, W>), grid, block, 0, st, a);
         return (int)hipGetLastError();
     }
     if (ir && orl)
-        hipLaunchKernelGGL((tb3d_stage<OP, BC, K, true, true>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((tb3d_stage<OP, BC, K, true, true, false, false, W>), grid, block, 0, st, a);
     else if (ir)
-        hipLaunchKernelGGL((tb3d_stage<OP, BC, K, true, false>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((tb3d_stage<OP, BC, K, true, false, false, false, W>), grid, block, 0, st, a);
     else if (orl)
-        hipLaunchKernelGGL((tb3d_stage<OP, BC, K, false, true>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((tb3d_stage<OP, BC, K, false, true, false, false, W>), grid, block, 0, st, a);
     else
-        hipLaunchKernelGGL((tb3d_stage<OP, BC, K, false, false>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((tb3d_stage<OP, BC, K, false, false, false, false, W>), grid, block, 0, st, a);
     return (int)hipGetLastError();
 }
 
 template <int OP, int BC>
-int launch3_kk(int k, const Tb3Args &a, bool ir, bool orl, hipStream_t st)
+int launch3_kk(int k, int cols, const Tb3Args &a, bool ir, bool orl, hipStream_t st)
 {
-    if (k == 2) return launch3_k<OP, BC, 2>(a, ir, orl, st);
-    if (k == 3) return launch3_k<OP, BC, 3>(a, ir, orl, st);
+    if (cols == 32) {
+        if (k == 2) return launch3_k<OP, BC, 2, 32>(a, ir, orl, st);
+        if (k == 3) return launch3_k<OP, BC, 3, 32>(a, ir, orl, st);
+        return (int)hipErrorInvalidValue;
+    }
+    if (k == 2) return launch3_k<OP, BC, 2, 64>(a, ir, orl, st);
+    if (k == 3) return launch3_k<OP, BC, 3, 64>(a, ir, orl, st);
     return (int)hipErrorInvalidValue;
 }
 
 template <int OP>
-int launch3_bc(const KGrid &g, int k, const Tb3Args &a, bool ir, bool orl, hipStream_t st)
+int launch3_bc(const KGrid &g, int k, int cols, const Tb3Args &a, bool ir, bool orl,
+               hipStream_t st)
 {
-    if (g.bc == PER) return launch3_kk<OP, PER>(k, a, ir, orl, st);
-    return launch3_kk<OP, DIR>(k, a, ir, orl, st);
+    if (g.bc == PER) return launch3_kk<OP, PER>(k, cols, a, ir, orl, st);
+    return launch3_kk<OP, DIR>(k, cols, a, ir, orl, st);
+}
+
+// Predicted time of a pass in units of one time step of the 64-column tile:
+// rounds of n_cu workgroups, each zc + 2K steps of the tile's step cost.
+template <int K, int W>
+double tb3d_cost(const KGrid &g)
+{
+    const long long tiles = (long long)((g.nx + W - 1) / W) *
+                            ((g.ny + Tb3Shape<K, W>::BYO - 1) / Tb3Shape<K, W>::BYO);
+    const int zc = choose_zchunk3(tiles, g.nz, K);
+    const long long nblk = tiles * ((g.nz + zc - 1) / zc);
+    const long long rounds = (nblk + cu_count() - 1) / cu_count();
+    return (double)rounds * (zc + 2.0 * K) * Tb3Shape<K, W>::STEP_COST;
 }
 
 }  // namespace
@@ -166,10 +194,27 @@ int launch_tb3d(const KGrid &g, const PassArgs &p, hipStream_t st)
     }
     for (int k = 0; k < 6; ++k) a.fc[k] = g.fc[k];
     const bool ir = p.in_re != nullptr, orl = p.out_re != nullptr;
-    if (g.op == LAP) return launch3_bc<LAP>(g, p.k, a, ir, orl, st);
-    if (g.op == ADV) return launch3_bc<ADV>(g, p.k, a, ir, orl, st);
-    if (g.op == VAR) return launch3_bc<VAR>(g, p.k, a, ir, orl, st);
-    return launch3_bc<POR>(g, p.k, a, ir, orl, st);
+    const int cols = (p.cols == 32) ? 32 : 64;
+    if (g.op == LAP) return launch3_bc<LAP>(g, p.k, cols, a, ir, orl, st);
+    if (g.op == ADV) return launch3_bc<ADV>(g, p.k, cols, a, ir, orl, st);
+    if (g.op == VAR) return launch3_bc<VAR>(g, p.k, cols, a, ir, orl, st);
+    return launch3_bc<POR>(g, p.k, cols, a, ir, orl, st);
+}
+
+int tb3d_pick_cols(const KGrid &g, int k)
+{
+    if (k == 2) return tb3d_cost<2, 32>(g) < tb3d_cost<2, 64>(g) ? 32 : 64;
+    return tb3d_cost<3, 32>(g) < tb3d_cost<3, 64>(g) ? 32 : 64;
+}
+
+int tb3d_work(int cols, int nx, int ny, int nz, int zc)
+{
+    // steps x step cost of all tiles of a grid with chunk zc (batched items)
+    const int bxo = cols, byo = (cols == 32) ? Tb3Shape<kBatchK, 32>::BYO : Tb3Shape<kBatchK, 64>::BYO;
+    const int cost = (cols == 32) ? Tb3Shape<kBatchK, 32>::STEP_COST : Tb3Shape<kBatchK, 64>::STEP_COST;
+    const long long tiles = (long long)((nx + bxo - 1) / bxo) * ((ny + byo - 1) / byo);
+    const int chunks = (nz + zc - 1) / zc;
+    return (int)std::min<long long>(tiles * ((long long)nz + 2LL * kBatchK * chunks) * cost, 0x7fffffff);
 }
 
 }  // namespace frkc2

@@ -26,13 +26,18 @@ struct Tb3Args {
     long long lvl_stride;
 };
 
-// Rows of the extended tile (one wavefront each) and halo wavefronts for
-// 1024 threads: 2K halo columns per row must fit in the halo wavefronts.
-template <int K>
+// Extended tile of W output columns (64: one row per wavefront; 32: two
+// rows per wavefront, lanes 0-31 and 32-63) plus K halo columns on each side,
+// which the halo wavefronts compute: 2K halo columns per row must fit in them.
+// 1024 threads either way.
+template <int K, int W = 64>
 struct Tb3Shape {
-    static constexpr int NHW = (K == 2) ? 1 : 2;
-    static constexpr int BYE = 16 - NHW;
-    static constexpr int BXE = 64 + 2 * K;
+    static_assert(W == 64 || W == 32, "64 or 32 output columns");
+    static constexpr int RPW = 64 / W;                           // rows per row wavefront
+    static constexpr int NHW = (W == 64) ? (K == 2 ? 1 : 2) : (K == 2 ? 2 : 3);
+    static constexpr int NRW = 16 - NHW;                         // row wavefronts
+    static constexpr int BYE = NRW * RPW;
+    static constexpr int BXE = W + 2 * K;
     static constexpr int BYO = BYE - 2 * K;
     static_assert(2 * K * BYE <= 64 * NHW, "halo columns must fit the halo wavefronts");
     // LDS row stride in cells: at least one padding cell on each side, made
@@ -41,25 +46,33 @@ struct Tb3Shape {
     // accesses of a 16-lane group on two bank groups only).
     static constexpr int SX = (BXE + 2) | 1;
     static constexpr int SY = BYE + 2;
-    // Role of wavefront w (rows 0..BYE-1, then the halo wavefronts). The
-    // wavefronts of a workgroup are dealt to the CU's four SIMDs in turn
-    // (w % 4), and a row computes min(row, BYE-1-row, K) levels, so the roles
-    // are permuted to give every SIMD the same work before the barrier: for
-    // K = 3 each SIMD gets 8 row-levels (rows 3 4 2 0 | 5 6 11 13 | 7 8 A B |
-    // 9 10 1 12) instead of 7 to 10 in natural order; for K = 2 the natural
-    // order is already balanced (6 6 6 7).
+    // Role of wavefront w (row wavefronts first, then the halo wavefronts).
+    // The wavefronts of a workgroup are dealt to the CU's four SIMDs in turn
+    // (w % 4), and a wavefront computes as many levels as its most central
+    // cell needs, so the roles are permuted to even out the levels per SIMD
+    // before each barrier: 8 8 8 8 (W = 64, K = 3; 7 to 10 in natural order)
+    // and 10 10 9 9 (W = 32, K = 3; 8 to 11); the other shapes are balanced
+    // in natural order.
     static __device__ __forceinline__ int role(int w)
     {
-        if (K != 3) return w;
-        constexpr int perm[16] = {3, 5, 7, 9, 4, 6, 8, 10, 2, 11, 14, 1, 0, 13, 15, 12};
-        return perm[w];
+        if (K == 3 && W == 64) {
+            constexpr int perm[16] = {3, 5, 7, 9, 4, 6, 8, 10, 2, 11, 14, 1, 0, 13, 15, 12};
+            return perm[w];
+        }
+        if (K == 3 && W == 32) {
+            constexpr int perm[16] = {1, 2, 3, 0, 5, 6, 7, 4, 9, 10, 11, 8, 12, 14, 15, 13};
+            return perm[w];
+        }
+        return w;
     }
+    // The largest per-SIMD level count above: the work of one time step
+    static constexpr int STEP_COST = (K == 3) ? (W == 64 ? 8 : 10) : 7;
 };
 
 // LDS of one tile: level planes (double2) and the diffusivity ring (double).
-template <int OP, int K>
+template <int OP, int K, int W = 64>
 struct Tb3Lds {
-    static constexpr int PL = Tb3Shape<K>::SX * Tb3Shape<K>::SY;
+    static constexpr int PL = Tb3Shape<K, W>::SX * Tb3Shape<K, W>::SY;
     static constexpr int L = 2 * K * PL;
     static constexpr int D = (OP == FRKC2_OP_VARCOEF) ? (K + 2) * PL : 1;
 };
@@ -69,14 +82,15 @@ struct Tb3Lds {
 // pointwise recursion carried in registers next to the level windows.
 // ST: also write the intermediate levels 1..K-1 of the output columns (the
 // stage states the adjoint's reverse sweep reads).
-template <int OP, int BC, int K, bool IN_REAL, bool OUT_REAL, bool EMB = false, bool ST = false>
+template <int OP, int BC, int K, bool IN_REAL, bool OUT_REAL, bool EMB = false, bool ST = false,
+          int W = 64>
 __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int bz, double2 *sLp,
                                           double *sDp)
 {
-    using S = Tb3Shape<K>;
+    using S = Tb3Shape<K, W>;
     constexpr int BXE = S::BXE, BYE = S::BYE, BYO = S::BYO;
     constexpr int SX = S::SX;                       // padding cells around each plane
-    constexpr int PL = Tb3Lds<OP, K>::PL;
+    constexpr int PL = Tb3Lds<OP, K, W>::PL;
     constexpr bool VC = (OP == VAR);
     constexpr int ND = K + 2;                       // D ring: planes t-K-1 .. t
     // level m plane, by step parity; D ring
@@ -86,20 +100,20 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
     const int tid = threadIdx.x;
     const int wv = S::role(tid >> 6), lane = tid & 63;
     int lx, ly;                                     // position in the extended tile
-    if (wv < BYE) {
-        lx = K + lane;
-        ly = wv;
+    if (wv < S::NRW) {
+        lx = K + lane % W;
+        ly = wv * S::RPW + lane / W;
     } else {
         // halo lane: depth d = 1..K from the output columns, side, row;
         // spare lanes repeat depth-K lanes (same values, never used)
-        int j = (wv - BYE) * 64 + lane;
+        int j = (wv - S::NRW) * 64 + lane;
         if (j >= 2 * K * BYE) j = 2 * (K - 1) * BYE + (j % (2 * BYE));
         const int d = 1 + j / (2 * BYE);
         const int rem = j % (2 * BYE);
         ly = rem % BYE;
-        lx = (rem < BYE) ? K - d : K + 63 + d;
+        lx = (rem < BYE) ? K - d : K + W - 1 + d;
     }
-    const int x = bx * 64 - K + lx;
+    const int x = bx * W - K + lx;
     const int y = by * BYO - K + ly;
     const int z0 = bz * a.zchunk;
     const int z1 = min(z0 + a.zchunk, a.nz);
@@ -117,7 +131,7 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
     for (int m = 1; m <= K; ++m)
         if (__any(need >= m)) wneed = m;
     wneed = __builtin_amdgcn_readfirstlane(wneed);
-    const bool out_col = lx >= K && lx < K + 64 && ly >= K && ly < BYE - K && x < a.nx &&
+    const bool out_col = lx >= K && lx < K + W && ly >= K && ly < BYE - K && x < a.nx &&
                          y < a.ny;
     const int slot = (ly + 1) * SX + lx + 1;
 

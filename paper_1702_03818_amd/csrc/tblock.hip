@@ -347,7 +347,11 @@ bool tblock_supported(const KGrid &g, int k)
 int launch_tblock(const KGrid &g, const PassArgs &p, int shape, hipStream_t st)
 {
     if (!tblock_supported(g, p.k)) return (int)hipErrorInvalidValue;
-    if (g.ndim == 3 && shape == 3) return launch_tb3d(g, p, st);
+    if (g.ndim == 3 && (shape == 3 || shape == 4)) {
+        PassArgs q = p;
+        q.cols = (shape == 4) ? 32 : 64;
+        return launch_tb3d(g, q, st);
+    }
     TbArgs a{};
     a.in_re = p.in_re;
     a.in_c = reinterpret_cast<const double2 *>(p.in_c);

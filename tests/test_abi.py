@@ -135,6 +135,9 @@ def test_set_option_validation():
     assert F.load().frkc2_set_option(F.OPT_TBLOCK, 99) == -1
     assert F.load().frkc2_set_option(12345, 1) == -1
     assert F.frkc2_set_option(F.OPT_TBLOCK, 0) == 0
+    assert F.load().frkc2_set_option(F.OPT_TILE, 6) == -1
+    assert F.frkc2_set_option(F.OPT_TILE, 5) == 0
+    assert F.frkc2_set_option(F.OPT_TILE, 0) == 0
 
 
 def test_grid_from_problem():

@@ -68,7 +68,7 @@ def test_integrate_zero_state():
 
 
 @pytest.mark.parametrize("k,tile,zchunk", [(1, 0, 0), (2, 4, 0), (3, 4, 0), (2, 4, 5), (3, 4, 7),
-                                          (2, 1, 0)])
+                                          (2, 1, 0), (3, 5, 0), (2, 5, 6)])
 def test_integrate_launch_configurations(k, tile, zchunk):
     """The embedded solution in fused 3D passes (K = 2, 3, chunk lengths) and one stage per
     pass gives the same attempts and state."""

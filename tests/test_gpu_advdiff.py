@@ -43,7 +43,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("n,vel,bc", CASES)
-@pytest.mark.parametrize("k,tile", [(0, 0), (1, 0), (2, 1), (3, 4), (2, 4)])
+@pytest.mark.parametrize("k,tile", [(0, 0), (1, 0), (2, 1), (3, 4), (2, 4), (3, 5)])
 def test_superstep_matches_oracle(n, vel, bc, k, tile):
     p = adv(n, vel, bc)
     s = 16

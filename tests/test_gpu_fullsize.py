@@ -43,7 +43,8 @@ def c2_reference():
     return p, c, rho, T, stage.superstep(p, p.w0, T * c.a_re, T * c.a_im)
 
 
-@pytest.mark.parametrize("k,tile,zchunk", [(0, 0, 0), (2, 4, 32), (3, 4, 128), (2, 1, 0)])
+@pytest.mark.parametrize("k,tile,zchunk", [(0, 0, 0), (2, 4, 32), (3, 4, 128), (2, 1, 0),
+                                          (3, 5, 0)])
 def test_diffusion3d_256_superstep(c2_reference, k, tile, zchunk):
     """256^3 variable D, Dirichlet, s = 100 (the benchmark workload) in the launch
     configurations the benchmark's autotuner chooses between."""

@@ -216,6 +216,10 @@ TB_CASES = [
     ("3d-var-dir", (2, 3, 2), 3, 4), ("3d-var-dir", (64, 11, 5), 2, 4),
     ("3d-var-dir", (70, 20, 1), 3, 4), ("3d-var-per", (65, 9, 1), 3, 4),
     ("3d-var-dir", (1, 19, 7), 3, 4),
+    ("3d-var-dir", (70, 37, 21), 3, 5), ("3d-var-dir", (70, 37, 21), 2, 5),
+    ("3d-var-per", (67, 30, 18), 3, 5), ("3d-lap-dir", (33, 17, 9), 2, 5),
+    ("3d-var-per", (97, 23, 11), 2, 5), ("3d-lap-per", (9, 5, 4), 3, 5),
+    ("3d-var-dir", (2, 3, 2), 3, 5), ("3d-var-dir", (40, 45, 1), 3, 5),
 ]
 
 

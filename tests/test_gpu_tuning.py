@@ -49,8 +49,9 @@ def test_zchunk_matches_oracle(kind, n, k, zchunk, tile=1):
 @pytest.mark.parametrize("kind,n,k", [("3d-var-dir", (70, 37, 21), 2), ("3d-var-dir", (70, 37, 21), 3),
                                       ("3d-var-per", (67, 30, 18), 3), ("3d-lap-per", (9, 5, 4), 2)])
 @pytest.mark.parametrize("zchunk", [1, 2, 5, 16])
-def test_zchunk_full_width_tiles(kind, n, k, zchunk):
-    test_zchunk_matches_oracle(kind, n, k, zchunk, tile=4)
+@pytest.mark.parametrize("tile", [4, 5])
+def test_zchunk_full_width_tiles(kind, n, k, zchunk, tile):
+    test_zchunk_matches_oracle(kind, n, k, zchunk, tile=tile)
 
 
 @pytest.mark.parametrize("kind,n", [("3d-var-dir", (72, 40, 36)), ("2d-por-per", (260, 33, 1)),
