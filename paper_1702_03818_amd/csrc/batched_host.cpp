@@ -18,7 +18,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kChunkPlanes = 32;   // z planes (3D) or rows (2D) per one-stage tile
-constexpr int kChunkPlanes3 = 64;  // z planes per fused 3D tile
+constexpr int kChunkPlanes3 = 128;  // z planes per fused 3D tile (nz <= 128: one chunk)
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
