@@ -217,7 +217,7 @@ int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const double *D, 
  * HIP graph launch. The graph has two concurrent branches: 3D problems
  * advance in pass levels (level L: stages 3L .. 3L+2 of every problem that has
  * them, fused in one HBM pass, then the remaining single stages), 2D problems
- * in stage levels (level l: stage l of every problem with s > l).
+ * likewise with passes of 4 stages (s = 4: four single stages).
  *   grids  host array of nprob grids
  *   w      host array of nprob device pointers (in/out states, real)
  *   D      host array of nprob device pointers (NULL entries for LAPLACE)

@@ -9,9 +9,12 @@
 // full-width temporally blocked tiles of tb3d_tile.h, 64 or 32 output columns
 // wide, one width for the whole batch) and one for the
 // single-stage passes that finish each superstep (s mod 3 stages, 64 x 16
-// plane-march tiles). The 2D branch holds, per stage level l, one kernel over
-// the 2D problems with s > l (64-column rows of the plane-march tile, so the
-// many narrow 2D problems do not idle most of a wide row). Kernels of one
+// plane-march tiles). The 2D branch is built the same way with passes of 4
+// stages, as rows of 64 extended columns (tb_tile.h, one wavefront each, so
+// the many narrow 2D problems do not idle most of a wide row) marching up to
+// 128 rows, and 64-column plane-march tiles for the single stages (s mod 4;
+// a problem with s = 4 runs single stages, since one fused pass would read
+// and write its state in place). Kernels of one
 // branch are ordered, and that ordering is the only synchronisation: a kernel
 // boundary makes every XCD's writes visible to every other XCD, which an
 // in-kernel wait between workgroups could only get by writing back and
@@ -29,19 +32,13 @@
 
 #include "plane_tile.h"
 #include "tb3d_tile.h"
+#include "tb_tile.h"
 
 namespace frkc2 {
 namespace {
 
 using namespace dev;
 
-struct LevelArgs {
-    const BatchProblem *probs;         // one dimension's list, sorted by decreasing s
-    const long long *item_prefix;      // prefix sums of tiles per stage over that list
-    long long items;                   // tiles of the active problems at this level
-    int active;                        // problems with s > level
-    int level;
-};
 
 // A value the whole workgroup shares, moved to scalar registers (the compiler
 // cannot prove that loads of the problem table are uniform).
@@ -79,85 +76,9 @@ __device__ void run_io(const BatchProblem &P, const PlaneArgs &a, long long c, b
     else run_tile<NDIM, BX, BY, OP, BC, false, false>(P, a, c, sW, sD);
 }
 
-template <int NDIM, int BX, int BY>
-__global__ __launch_bounds__(BX *BY) void batched_level(LevelArgs t)
-{
-    using S = TileShape<VAR, DIR, NDIM, BX, BY>;   // the largest LDS footprint
-    __shared__ double2 sW[S::LDS_W];
-    __shared__ double sD[S::LDS_D];
-    const int xcd = blockIdx.x & 7;
-    const int per_xcd = (int)(gridDim.x >> 3);
-    long long hi, step, first;
-    if (per_xcd > 0 && (int)blockIdx.x < per_xcd * 8) {
-        const long long span = (t.items + 7) / 8;
-        const long long lo = xcd * span;
-        hi = lo + span < t.items ? lo + span : t.items;
-        first = lo + (blockIdx.x >> 3);
-        step = per_xcd;
-    } else {
-        hi = (per_xcd > 0) ? 0 : t.items;
-        first = blockIdx.x;
-        step = gridDim.x;
-    }
-    const int l = t.level;
-    for (long long g = first; g < hi; g += step) {
-        int a = 0, b = t.active - 1;
-        while (a < b) {
-            const int mid = (a + b + 1) >> 1;
-            if (t.item_prefix[mid] <= g) a = mid;
-            else b = mid - 1;
-        }
-        a = uni(a);
-        BatchProblem P = t.probs[a];
-        P.w = uni(P.w);
-        P.D = uni(P.D);
-        P.bufA = uni(P.bufA);
-        P.bufB = uni(P.bufB);
-        P.tau = uni(P.tau);
-        P.nx = uni(P.nx);
-        P.ny = uni(P.ny);
-        P.nz = uni(P.nz);
-        P.bc = uni(P.bc);
-        P.op = uni(P.op);
-        P.s = uni(P.s);
-        P.zchunk = uni(P.zchunk);
-        P.ntx = uni(P.ntx);
-        P.nty = uni(P.nty);
-        P.inv_h2 = uni(P.inv_h2);
-        P.d_const = uni(P.d_const);
-        const long long c = uni(g - t.item_prefix[a]);
-        PlaneArgs pa{};
-        const bool ir = (l == 0), orl = (l == P.s - 1);
-        pa.in_re = P.w;
-        pa.in_c = reinterpret_cast<const double2 *>((l & 1) ? P.bufA : P.bufB);
-        pa.out_re = P.w;
-        pa.out_c = reinterpret_cast<double2 *>((l & 1) ? P.bufB : P.bufA);
-        pa.D = P.D;
-        pa.nx = P.nx;
-        pa.ny = P.ny;
-        pa.nz = P.nz;
-        pa.zchunk = P.zchunk;
-        pa.ntx = P.ntx;
-        pa.nty = P.nty;
-        pa.inv_h2 = P.inv_h2;
-        pa.d_const = P.d_const;
-        for (int k = 0; k < 6; ++k) pa.fc[k] = P.d_const;
-        pa.tr = uni(P.tau[2 * l]);
-        pa.ti = uni(P.tau[2 * l + 1]);
-        const bool per = (P.bc == PER), var = (P.op == VAR);
-        if (var) {
-            if (per) run_io<NDIM, BX, BY, VAR, PER>(P, pa, c, ir, orl, sW, sD);
-            else run_io<NDIM, BX, BY, VAR, DIR>(P, pa, c, ir, orl, sW, sD);
-        } else {
-            if (per) run_io<NDIM, BX, BY, LAP, PER>(P, pa, c, ir, orl, sW, sD);
-            else run_io<NDIM, BX, BY, LAP, DIR>(P, pa, c, ir, orl, sW, sD);
-        }
-        __syncthreads();   // the next item reuses the LDS tile
-    }
-}
-
-constexpr int kBX2 = 64;
+constexpr int kBX2 = 64;             // single-stage 2D items: 64-column plane-march tiles
 constexpr int kPBX = 64, kPBY = 16;   // single-stage items of the 3D pass kernel (1024 threads)
+constexpr int kBXE2 = 64;             // fused 2D items: rows of 64 extended columns (one wavefront)
 
 // Range of items of this workgroup: eight contiguous ranges, one per XCD.
 __device__ __forceinline__ void xcd_range(long long items, long long &first, long long &hi,
@@ -203,6 +124,14 @@ __device__ void fused_io_w(const BatchProblem &P, Tb3Args &a, long long c, bool 
     else run_fused<OP, BC, false, false, W>(P, a, c, sL, sD);
 }
 
+
+template <int OP, int BC>
+__device__ void row_io(const TbArgs &a, int bx, int bz, bool ir, bool orl, double2 *sL, double *sD)
+{
+    if (ir) tb_tile<OP, BC, 2, kBXE2, 1, 1, kBatchK2, true, false>(a, bx, 0, bz, sL, sD);
+    else if (orl) tb_tile<OP, BC, 2, kBXE2, 1, 1, kBatchK2, false, true>(a, bx, 0, bz, sL, sD);
+    else tb_tile<OP, BC, 2, kBXE2, 1, 1, kBatchK2, false, false>(a, bx, 0, bz, sL, sD);
+}
 
 // One pass level of the 3D problems. FUSED: each active problem's pass of
 // kBatchK stages (stages kBatchK*level ..), as tb3d_tile items; otherwise its
@@ -314,6 +243,114 @@ __global__ __launch_bounds__(1024) void batched_pass3(Pass3Args t)
     }
 }
 
+// One pass level of the 2D problems. FUSED: each active problem's pass of
+// kBatchK2 stages (stages kBatchK2*level ..), as row items of tb_tile.h (64
+// extended columns marching up to 128 rows); otherwise its single-stage pass,
+// as 64-column plane-march items. Buffers as in the 3D pass kernel.
+template <bool FUSED>
+__global__ __launch_bounds__(64) void batched_pass2(Pass3Args t)
+{
+    using S1 = TileShape<VAR, DIR, 2, kBX2, 1>;
+    using S2 = TbLds<VAR, 2, kBXE2, 1, 1, kBatchK2>;
+    __shared__ double2 sL[FUSED ? S2::L : S1::LDS_W];
+    __shared__ double sD[FUSED ? S2::D : S1::LDS_D];
+    long long first, hi, step;
+    xcd_range(t.items, first, hi, step);
+    const int L = t.level;
+    for (long long g = first; g < hi; g += step) {
+        int a = 0, b = t.nprob - 1;
+        while (a < b) {
+            const int mid = (a + b + 1) >> 1;
+            if (t.item_prefix[mid] <= g) a = mid;
+            else b = mid - 1;
+        }
+        a = uni(a);
+        BatchProblem P = t.probs[a];
+        P.w = uni(P.w);
+        P.D = uni(P.D);
+        P.bufA = uni(P.bufA);
+        P.bufB = uni(P.bufB);
+        P.tau = uni(P.tau);
+        P.nx = uni(P.nx);
+        P.ny = uni(P.ny);
+        P.nz = uni(P.nz);
+        P.bc = uni(P.bc);
+        P.op = uni(P.op);
+        P.zchunk = uni(P.zchunk);
+        P.ntx = uni(P.ntx);
+        P.nty = uni(P.nty);
+        P.nfull = uni(P.nfull);
+        P.npass = uni(P.npass);
+        P.zc3 = uni(P.zc3);
+        P.ntx3 = uni(P.ntx3);
+        P.inv_h2 = uni(P.inv_h2);
+        P.d_const = uni(P.d_const);
+        const long long c = uni(g - t.item_prefix[a]);
+        const bool ir = (L == 0), orl = (L == P.npass - 1);
+        const double *in_c = (L & 1) ? P.bufA : P.bufB;   // pass L-1 wrote buffer (L-1) & 1
+        double *out_c = (L & 1) ? P.bufB : P.bufA;
+        const bool per = (P.bc == PER), var = (P.op == VAR);
+        if (FUSED) {
+            TbArgs ta{};
+            ta.in_re = P.w;
+            ta.in_c = reinterpret_cast<const double2 *>(in_c);
+            ta.out_re = P.w;
+            ta.out_c = reinterpret_cast<double2 *>(out_c);
+            ta.D = P.D;
+            ta.nx = P.nx;
+            ta.ny = P.ny;
+            ta.nz = P.nz;
+            ta.zchunk = P.zc3;
+            ta.ntx = P.ntx3;
+            ta.nty = 1;
+            ta.inv_h2 = P.inv_h2;
+            ta.d_const = P.d_const;
+            for (int k = 0; k < 6; ++k) ta.fc[k] = P.d_const;
+            const int l0 = kBatchK2 * L;
+#pragma unroll
+            for (int i = 0; i < kBatchK2; ++i) {
+                ta.tr[i] = uni(P.tau[2 * (l0 + i)]);
+                ta.ti[i] = uni(P.tau[2 * (l0 + i) + 1]);
+            }
+            const int bx = (int)(c % P.ntx3), bz = (int)(c / P.ntx3);
+            if (var) {
+                if (per) row_io<VAR, PER>(ta, bx, bz, ir, orl, sL, sD);
+                else row_io<VAR, DIR>(ta, bx, bz, ir, orl, sL, sD);
+            } else {
+                if (per) row_io<LAP, PER>(ta, bx, bz, ir, orl, sL, sD);
+                else row_io<LAP, DIR>(ta, bx, bz, ir, orl, sL, sD);
+            }
+        } else {
+            const int l = kBatchK2 * P.nfull + (L - P.nfull);
+            PlaneArgs pa{};
+            pa.in_re = P.w;
+            pa.in_c = reinterpret_cast<const double2 *>(in_c);
+            pa.out_re = P.w;
+            pa.out_c = reinterpret_cast<double2 *>(out_c);
+            pa.D = P.D;
+            pa.nx = P.nx;
+            pa.ny = P.ny;
+            pa.nz = P.nz;
+            pa.zchunk = P.zchunk;
+            pa.ntx = P.ntx;
+            pa.nty = P.nty;
+            pa.inv_h2 = P.inv_h2;
+            pa.d_const = P.d_const;
+            for (int k = 0; k < 6; ++k) pa.fc[k] = P.d_const;
+            pa.tr = uni(P.tau[2 * l]);
+            pa.ti = uni(P.tau[2 * l + 1]);
+            if (var) {
+                if (per) run_io<2, kBX2, 1, VAR, PER>(P, pa, c, ir, orl, sL, sD);
+                else run_io<2, kBX2, 1, VAR, DIR>(P, pa, c, ir, orl, sL, sD);
+            } else {
+                if (per) run_io<2, kBX2, 1, LAP, PER>(P, pa, c, ir, orl, sL, sD);
+                else run_io<2, kBX2, 1, LAP, DIR>(P, pa, c, ir, orl, sL, sD);
+            }
+        }
+        __syncthreads();   // the next item reuses the LDS
+    }
+}
+
 }  // namespace
 
 void batched_tile(int ndim, int *bx, int *by) { *bx = ndim == 3 ? kPBX : kBX2; *by = ndim == 3 ? kPBY : 1; }
@@ -336,12 +373,14 @@ int launch_batched_pass3(bool fused, int cols, const BatchProblem *probs,
     return (int)hipGetLastError();
 }
 
-int launch_batched_level(int ndim, const BatchProblem *probs, const long long *item_prefix,
-                         long long items, int active, int level, int grid, hipStream_t st)
+int batched_row2() { return kBXE2 - 2 * kBatchK2; }
+
+int launch_batched_pass2(bool fused, const BatchProblem *probs, const long long *item_prefix,
+                         long long items, int nprob, int level, int grid, hipStream_t st)
 {
-    if (ndim != 2) return (int)hipErrorInvalidValue;   // 3D problems run as passes
-    LevelArgs t{probs, item_prefix, items, active, level};
-    hipLaunchKernelGGL((batched_level<2, kBX2, 1>), dim3(grid), dim3(kBX2), 0, st, t);
+    Pass3Args t{probs, item_prefix, items, nprob, level};
+    if (fused) hipLaunchKernelGGL((batched_pass2<true>), dim3(grid), dim3(64), 0, st, t);
+    else hipLaunchKernelGGL((batched_pass2<false>), dim3(grid), dim3(64), 0, st, t);
     return (int)hipGetLastError();
 }
 
@@ -353,7 +392,7 @@ int batched_grid_size(int ndim)
         return 0;
     hipError_t e = (ndim == 3)
         ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_pass3<true, 64>, 1024, 0)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_level<2, kBX2, 1>, kBX2, 0);
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_pass2<true>, 64, 0);
     if (e != hipSuccess) return 0;
     return cus * (per > 0 ? per : 1);
 }

@@ -25,12 +25,19 @@ struct Layout {
     size_t probs[2], prefix[2], tau, bufs, total;   // index 0: 3D list, 1: 2D list
     size_t pass3;                                  // 3D pass tables: 2 * levels3 rows of n3 + 1
     int levels3;                                   // pass levels of the 3D list
+    size_t pass2;                                  // 2D pass tables: 2 * levels2 rows of n2 + 1
+    int levels2;
     std::vector<size_t> buf_off;                   // per problem (caller's order)
 };
 
 // Passes of a 3D problem: fused passes of kBatchK stages, then single stages.
 int nfull3(int s) { return s / kBatchK; }
 int npass3(int s) { return nfull3(s) + (s - kBatchK * nfull3(s)); }
+// 2D: fused passes of kBatchK2 stages, then single stages. A lone fused pass
+// would read and write w (its tiles read a halo around them), so s = kBatchK2
+// runs as single stages.
+int nfull2(int s) { return (s == kBatchK2) ? 0 : s / kBatchK2; }
+int npass2(int s) { return nfull2(s) + (s - kBatchK2 * nfull2(s)); }
 
 bool validate(int nprob, const frkc2_grid *grids, const int *s, std::vector<KGrid> &kg)
 {
@@ -59,10 +66,13 @@ Layout layout(int nprob, const std::vector<KGrid> &kg, const int *s)
     Layout L;
     int n3 = 0;
     L.levels3 = 0;
+    L.levels2 = 0;
     for (int i = 0; i < nprob; ++i)
         if (kg[i].ndim == 3) {
             ++n3;
             L.levels3 = std::max(L.levels3, npass3(s[i]));
+        } else {
+            L.levels2 = std::max(L.levels2, npass2(s[i]));
         }
     const int cnt[2] = {n3, nprob - n3};
     const size_t sum_s = std::accumulate(s, s + nprob, (size_t)0);
@@ -75,6 +85,8 @@ Layout layout(int nprob, const std::vector<KGrid> &kg, const int *s)
     }
     L.pass3 = o;
     o = align_up(o + sizeof(long long) * 2 * (size_t)L.levels3 * (n3 + 1));
+    L.pass2 = o;
+    o = align_up(o + sizeof(long long) * 2 * (size_t)L.levels2 * (cnt[1] + 1));
     L.tau = o;
     o = align_up(o + sizeof(double) * 2 * sum_s);
     L.bufs = o;
@@ -94,6 +106,7 @@ struct GraphEntry {
     std::vector<BatchProblem> probs[2];   // host copies of the uploaded tables
     std::vector<long long> prefix[2];
     std::vector<long long> pass3;         // 3D: per level, fused then single-stage prefixes
+    std::vector<long long> pass2;         // 2D: the same
     int cols3 = 64;                       // 3D fused tiles: output columns (one width per batch)
     std::vector<double> tau;
 };
@@ -188,7 +201,6 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
     std::vector<int> order(nprob);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return s[a] > s[b]; });
-    int max_s = 0;
     // One tile width for all 3D problems (a pass kernel that carries both
     // widths needs more registers than it has): the one with less total work
     // over the fused passes. The items always fill the GPU, so work decides.
@@ -246,12 +258,19 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
             P.ntx3 = (P.nx + bx3 - 1) / bx3;
             P.nty3 = (P.ny + by3 - 1) / by3;
             P.ntiles3 = P.ntx3 * P.nty3 * ((P.nz + P.zc3 - 1) / P.zc3);
+        } else {
+            // fused rows: batched_row2() output columns, up to kChunkPlanes3 rows
+            P.nfull = nfull2(P.s);
+            P.npass = npass2(P.s);
+            P.zc3 = std::min(P.nz, kChunkPlanes3);
+            P.ntx3 = (P.nx + batched_row2() - 1) / batched_row2();
+            P.nty3 = 1;
+            P.ntiles3 = P.ntx3 * ((P.nz + P.zc3 - 1) / P.zc3);
         }
         P.inv_h2 = kg[i].inv_h2;
         P.d_const = kg[i].d_const;
         E.probs[d].push_back(P);
         E.prefix[d].push_back(E.prefix[d].back() + P.ntiles);
-        max_s = std::max(max_s, s[i]);
     }
     // 3D pass tables: row 2L = fused items of level L, row 2L+1 = single-stage items
     const int n3 = (int)E.probs[0].size();
@@ -265,9 +284,24 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
             sg[j + 1] = sg[j] + (lv >= P.nfull && lv < P.npass ? P.ntiles : 0);
         }
     }
+    // 2D pass tables, the same layout over the 2D list
+    const int n2 = (int)E.probs[1].size();
+    E.pass2.assign(2 * (size_t)L.levels2 * (n2 + 1), 0);
+    for (int lv = 0; lv < L.levels2; ++lv) {
+        long long *fa = &E.pass2[(size_t)(2 * lv) * (n2 + 1)];
+        long long *sg = &E.pass2[(size_t)(2 * lv + 1) * (n2 + 1)];
+        for (int j = 0; j < n2; ++j) {
+            const BatchProblem &P = E.probs[1][j];
+            fa[j + 1] = fa[j] + (lv < P.nfull ? P.ntiles3 : 0);
+            sg[j + 1] = sg[j] + (lv >= P.nfull && lv < P.npass ? P.ntiles : 0);
+        }
+    }
     hipError_t e = hipSuccess;
     if (!E.pass3.empty())
         e = hipMemcpyAsync(base + L.pass3, E.pass3.data(), sizeof(long long) * E.pass3.size(),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !E.pass2.empty())
+        e = hipMemcpyAsync(base + L.pass2, E.pass2.data(), sizeof(long long) * E.pass2.size(),
                            hipMemcpyHostToDevice, st);
     for (int d = 0; d < 2 && e == hipSuccess; ++d) {
         if (E.probs[d].empty()) continue;
@@ -318,14 +352,17 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
                                        g_capture);
         }
     }
-    int active2 = (int)E.probs[1].size();
-    for (int l = 0; l < max_s && lrc == 0 && has2; ++l) {
-        while (active2 > 0 && E.probs[1][active2 - 1].s <= l) --active2;
-        if (active2 == 0) break;
-        const long long items = E.prefix[1][active2];
-        lrc = launch_batched_level(2, reinterpret_cast<const BatchProblem *>(base + L.probs[1]),
-                                   reinterpret_cast<const long long *>(base + L.prefix[1]),
-                                   items, active2, l, grid_for(1, items), g_capture2);
+    const long long *pass2_dev = reinterpret_cast<const long long *>(base + L.pass2);
+    for (int lv = 0; lv < L.levels2 && lrc == 0 && has2; ++lv) {
+        for (int kind = 0; kind < 2 && lrc == 0; ++kind) {
+            const size_t row = (size_t)(2 * lv + kind) * (n2 + 1);
+            const long long items = E.pass2[row + n2];
+            if (items == 0) continue;
+            lrc = launch_batched_pass2(kind == 0,
+                                       reinterpret_cast<const BatchProblem *>(base + L.probs[1]),
+                                       pass2_dev + row, items, n2, lv, grid_for(1, items),
+                                       g_capture2);
+        }
     }
     if (has2) {
         const int r1 = (int)hipEventRecord(g_join, g_capture2);

@@ -116,17 +116,22 @@ struct BatchProblem {           // one problem's descriptor in device memory
     int nx, ny, nz, ndim, bc, op;   // kernel layout: 3D (n0, n1, n2), 2D (n0, 1, n1)
     int s, ntiles;                  // stages, tiles per one-stage pass
     int zchunk, ntx, nty;           // one-stage tile grid: ntx * nty * ceil(nz / zchunk)
-    int nfull, npass;               // 3D: passes of kBatchK stages, then single stages
-    int zc3, ntx3, nty3, ntiles3;   // 3D fused-pass tile grid
-    int cols3;                      // its output columns per tile (64 or 32)
+    int nfull, npass;               // passes of kBatchK (3D) / kBatchK2 (2D) stages, then single stages
+    int zc3, ntx3, nty3, ntiles3;   // fused-pass tile grid (3D: full-width tiles; 2D: rows)
+    int cols3;                      // 3D: its output columns per tile (64 or 32)
     double inv_h2, d_const;
 };
 constexpr int kBatchK = 3;          // stages per fused 3D pass of the batch
+constexpr int kBatchK2 = 4;         // stages per fused 2D pass of the batch
 void batched_tile(int ndim, int *bx, int *by);
 void batched_tile3(int cols, int *bx, int *by);
+int batched_row2();                 // output columns of a fused 2D row item
 int batched_grid_size(int ndim);
-int launch_batched_level(int ndim, const BatchProblem *probs, const long long *item_prefix,
-                         long long items, int active, int level, int grid, hipStream_t st);
+// 2D pass level: fused == true runs the kBatchK2-stage passes of level
+// `level`, otherwise the single-stage passes; item_prefix spans all nprob 2D
+// problems.
+int launch_batched_pass2(bool fused, const BatchProblem *probs, const long long *item_prefix,
+                         long long items, int nprob, int level, int grid, hipStream_t st);
 // 3D pass level: fused == true runs the kBatchK-stage passes of level `level`,
 // otherwise the single-stage passes; item_prefix spans all nprob 3D problems.
 int launch_batched_pass3(bool fused, int cols, const BatchProblem *probs,
