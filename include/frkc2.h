@@ -214,7 +214,8 @@ int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const double *D, 
 /*
  * frkc2_step_batched -- one superstep for each of nprob independent problems
  * (VARCOEF or LAPLACE, 2D or 3D, each with its own grid, T and s) in a single
- * HIP graph launch. The graph has two concurrent branches: 3D problems
+ * HIP graph launch. The graph has concurrent branches: 3D problems (two
+ * interleaved groups, one branch each)
  * advance in pass levels (level L: stages 3L .. 3L+2 of every problem that has
  * them, fused in one HBM pass, then the remaining single stages), 2D problems
  * likewise with passes of 4 stages (s = 4: four single stages).

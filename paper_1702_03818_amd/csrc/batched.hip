@@ -3,8 +3,10 @@
 //
 // Stage l of problem i is the Euler step W <- W + tau_l f(W) of its own
 // superstep (O'Sullivan, arXiv:1702.03818, Sec. 3). Stages of one problem are
-// sequential; different problems are independent. The graph has two
-// independent branches. The 3D branch holds, per pass level L, one kernel
+// sequential; different problems are independent. The graph has independent
+// branches: the 3D problems in two interleaved groups (so that one group's
+// level tail shares the GPU with the other's work) and the 2D problems. A 3D
+// branch holds, per pass level L, one kernel
 // for the fused passes (stages 3L .. 3L+2 of every problem that has them, as
 // full-width temporally blocked tiles of tb3d_tile.h, 64 or 32 output columns
 // wide, one width for the whole batch) and one for the

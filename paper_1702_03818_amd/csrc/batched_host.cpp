@@ -18,12 +18,17 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kChunkPlanes = 32;   // z planes (3D) or rows (2D) per one-stage tile
+// The 3D problems run as kGroups3 interleaved groups (alternate problems in
+// order of decreasing s), each a chain of pass levels on its own graph
+// branch, so that the tail of one group's level, when few tiles are left,
+// shares the GPU with the other group's work.
+constexpr int kGroups3 = 2;
 constexpr int kChunkPlanes3 = 128;  // z planes per fused 3D tile (nz <= 128: one chunk)
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t probs[2], prefix[2], tau, bufs, total;   // index 0: 3D list, 1: 2D list
-    size_t pass3;                                  // 3D pass tables: 2 * levels3 rows of n3 + 1
+    size_t pass3;                                  // 3D pass tables: kGroups3 * 2 * levels3 rows of n3 + 1
     int levels3;                                   // pass levels of the 3D list
     size_t pass2;                                  // 2D pass tables: 2 * levels2 rows of n2 + 1
     int levels2;
@@ -84,7 +89,7 @@ Layout layout(int nprob, const std::vector<KGrid> &kg, const int *s)
         o = align_up(o + sizeof(long long) * (cnt[d] + 1));
     }
     L.pass3 = o;
-    o = align_up(o + sizeof(long long) * 2 * (size_t)L.levels3 * (n3 + 1));
+    o = align_up(o + sizeof(long long) * kGroups3 * 2 * (size_t)L.levels3 * (n3 + 1));
     L.pass2 = o;
     o = align_up(o + sizeof(long long) * 2 * (size_t)L.levels2 * (cnt[1] + 1));
     L.tau = o;
@@ -113,8 +118,9 @@ struct GraphEntry {
 
 std::mutex g_mu;
 std::map<void *, GraphEntry> g_graphs;
-hipStream_t g_capture = nullptr, g_capture2 = nullptr;   // 3D and 2D branches of the graph
-hipEvent_t g_fork = nullptr, g_join = nullptr;
+hipStream_t g_capture = nullptr, g_capture2 = nullptr;   // 3D group 0 and 2D branches
+hipStream_t g_group[kGroups3] = {};                       // 3D groups 1.. (0 = g_capture)
+hipEvent_t g_fork = nullptr, g_join = nullptr, g_gjoin[kGroups3] = {};
 
 void append(std::vector<unsigned char> &k, const void *p, size_t n)
 {
@@ -274,16 +280,20 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
     }
     // 3D pass tables: row 2L = fused items of level L, row 2L+1 = single-stage items
     const int n3 = (int)E.probs[0].size();
-    E.pass3.assign(2 * (size_t)L.levels3 * (n3 + 1), 0);
-    for (int lv = 0; lv < L.levels3; ++lv) {
-        long long *fa = &E.pass3[(size_t)(2 * lv) * (n3 + 1)];
-        long long *sg = &E.pass3[(size_t)(2 * lv + 1) * (n3 + 1)];
-        for (int j = 0; j < n3; ++j) {
-            const BatchProblem &P = E.probs[0][j];
-            fa[j + 1] = fa[j] + (lv < P.nfull ? P.ntiles3 : 0);
-            sg[j + 1] = sg[j] + (lv >= P.nfull && lv < P.npass ? P.ntiles : 0);
+    // row (g, L, kind): group g's items of pass level L (kind 0 fused, 1 single)
+    E.pass3.assign(kGroups3 * 2 * (size_t)L.levels3 * (n3 + 1), 0);
+    for (int g = 0; g < kGroups3; ++g)
+        for (int lv = 0; lv < L.levels3; ++lv) {
+            const size_t r0 = (size_t)(g * 2 * L.levels3 + 2 * lv);
+            long long *fa = &E.pass3[r0 * (n3 + 1)];
+            long long *sg = &E.pass3[(r0 + 1) * (n3 + 1)];
+            for (int j = 0; j < n3; ++j) {
+                const BatchProblem &P = E.probs[0][j];
+                const bool mine = (j % kGroups3) == g;
+                fa[j + 1] = fa[j] + (mine && lv < P.nfull ? P.ntiles3 : 0);
+                sg[j + 1] = sg[j] + (mine && lv >= P.nfull && lv < P.npass ? P.ntiles : 0);
+            }
         }
-    }
     // 2D pass tables, the same layout over the 2D list
     const int n2 = (int)E.probs[1].size();
     E.pass2.assign(2 * (size_t)L.levels2 * (n2 + 1), 0);
@@ -322,6 +332,10 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
     if (!g_capture) {
         e = hipStreamCreate(&g_capture);
         if (e == hipSuccess) e = hipStreamCreate(&g_capture2);
+        for (int g = 1; g < kGroups3 && e == hipSuccess; ++g) {
+            e = hipStreamCreate(&g_group[g]);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&g_gjoin[g], hipEventDisableTiming);
+        }
         if (e == hipSuccess) e = hipEventCreateWithFlags(&g_fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&g_join, hipEventDisableTiming);
         if (e != hipSuccess) return hip_err(e, "capture streams");
@@ -332,26 +346,26 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
     if (e != hipSuccess) return hip_err(e, "begin capture");
     int lrc = 0;
     const bool has2 = !E.probs[1].empty();
-    if (has2) {
-        lrc = (int)hipEventRecord(g_fork, g_capture);
-        if (lrc == 0) lrc = (int)hipStreamWaitEvent(g_capture2, g_fork, 0);
-    }
+    lrc = (int)hipEventRecord(g_fork, g_capture);
+    for (int g = 1; g < kGroups3 && lrc == 0; ++g) lrc = (int)hipStreamWaitEvent(g_group[g], g_fork, 0);
+    if (has2 && lrc == 0) lrc = (int)hipStreamWaitEvent(g_capture2, g_fork, 0);
     auto grid_for = [&](int d, long long items) {
         long long grid = std::min<long long>(grid_max[d], (items + 7) / 8 * 8);
         return (int)std::max<long long>(grid, 1);
     };
     const long long *pass3_dev = reinterpret_cast<const long long *>(base + L.pass3);
-    for (int lv = 0; lv < L.levels3 && lrc == 0; ++lv) {
-        for (int kind = 0; kind < 2 && lrc == 0; ++kind) {
-            const size_t row = (size_t)(2 * lv + kind) * (n3 + 1);
-            const long long items = E.pass3[row + n3];
-            if (items == 0) continue;
-            lrc = launch_batched_pass3(kind == 0, E.cols3,
-                                       reinterpret_cast<const BatchProblem *>(base + L.probs[0]),
-                                       pass3_dev + row, items, n3, lv, grid_for(0, items),
-                                       g_capture);
+    for (int g = 0; g < kGroups3 && lrc == 0; ++g)
+        for (int lv = 0; lv < L.levels3 && lrc == 0; ++lv) {
+            for (int kind = 0; kind < 2 && lrc == 0; ++kind) {
+                const size_t row = (size_t)(g * 2 * L.levels3 + 2 * lv + kind) * (n3 + 1);
+                const long long items = E.pass3[row + n3];
+                if (items == 0) continue;
+                lrc = launch_batched_pass3(
+                    kind == 0, E.cols3, reinterpret_cast<const BatchProblem *>(base + L.probs[0]),
+                    pass3_dev + row, items, n3, lv, grid_for(0, items),
+                    g == 0 ? g_capture : g_group[g]);
+            }
         }
-    }
     const long long *pass2_dev = reinterpret_cast<const long long *>(base + L.pass2);
     for (int lv = 0; lv < L.levels2 && lrc == 0 && has2; ++lv) {
         for (int kind = 0; kind < 2 && lrc == 0; ++kind) {
@@ -363,6 +377,11 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
                                        pass2_dev + row, items, n2, lv, grid_for(1, items),
                                        g_capture2);
         }
+    }
+    for (int g = 1; g < kGroups3; ++g) {
+        const int r1 = (int)hipEventRecord(g_gjoin[g], g_group[g]);
+        const int r2 = (int)hipStreamWaitEvent(g_capture, g_gjoin[g], 0);
+        if (lrc == 0) lrc = r1 ? r1 : r2;
     }
     if (has2) {
         const int r1 = (int)hipEventRecord(g_join, g_capture2);
