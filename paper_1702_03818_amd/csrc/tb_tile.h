@@ -124,6 +124,12 @@ __device__ __forceinline__ void tb_tile(const TbArgs &a, int bx, int by, int bz,
     double2 L0[NR][R];
     double D0[NR][R];
     double2 wm[K > 1 ? K - 1 : 1][R], wc[K > 1 ? K - 1 : 1][R], wp[K > 1 ? K - 1 : 1][R];
+    // 2D rows compute every level on every lane, so their level windows can
+    // live in a ring indexed by the unrolled step (slot of step t = plane t-m
+    // of level m) instead of being shifted through registers every step; 3D
+    // tiles skip levels per row and keep the shifting windows.
+    constexpr bool RING = (NDIM == 2) && (K > 1);
+    double2 WR[RING ? K - 1 : 1][RING ? NR : 1][R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int gy = (NDIM == 3) ? yr[r] : 0;
@@ -140,6 +146,12 @@ __device__ __forceinline__ void tb_tile(const TbArgs &a, int bx, int by, int bz,
         }
 #pragma unroll
         for (int m = 0; m + 1 < K; ++m) wm[m][r] = wc[m][r] = wp[m][r] = make_double2(0.0, 0.0);
+        if (RING) {
+#pragma unroll
+            for (int m = 0; m + 1 < K; ++m)
+#pragma unroll
+                for (int q = 0; q < NR; ++q) WR[m][q][r] = make_double2(0.0, 0.0);
+        }
     }
 
     for (int tb = t_begin; tb < t_end; tb += NR) {
@@ -188,9 +200,15 @@ __device__ __forceinline__ void tb_tile(const TbArgs &a, int bx, int by, int bz,
                     c = L0[rs(-1)][r];
                     zp = L0[rs(0)][r];
                 } else {
-                    zm = wm[m - 2][r];
-                    c = wc[m - 2][r];
-                    zp = wp[m - 2][r];
+                    if (RING) {
+                        zm = WR[(m - 2) % (K - 1)][rs(-2)][r];
+                        c = WR[(m - 2) % (K - 1)][rs(-1)][r];
+                        zp = WR[(m - 2) % (K - 1)][rs(0)][r];
+                    } else {
+                        zm = wm[m - 2][r];
+                        c = wc[m - 2][r];
+                        zp = wp[m - 2][r];
+                    }
                 }
                 double dc = 0.0, dzm = 0.0, dzp = 0.0;
                 if (VC) {
@@ -221,9 +239,13 @@ __device__ __forceinline__ void tb_tile(const TbArgs &a, int bx, int by, int bz,
                 double2 v = euler(c, acc_r, acc_i, a.inv_h2, a.tr[m - 1], a.ti[m - 1]);
                 v = keep(v, col_ghost[r] || pghost);
                 if (m < K) {
-                    wm[m - 1][r] = wc[m - 1][r];
-                    wc[m - 1][r] = wp[m - 1][r];
-                    wp[m - 1][r] = v;
+                    if (RING) {
+                        WR[(m - 1) % (K - 1)][rs(0)][r] = v;
+                    } else {
+                        wm[m - 1][r] = wc[m - 1][r];
+                        wc[m - 1][r] = wp[m - 1][r];
+                        wp[m - 1][r] = v;
+                    }
                 } else if (out_col[r] && p >= z0 && p < z1) {
                     const int gy = (NDIM == 3) ? yr[r] : 0;
                     const long long i = x + (long long)a.nx * (gy + (long long)a.ny * p);
@@ -237,7 +259,8 @@ __device__ __forceinline__ void tb_tile(const TbArgs &a, int bx, int by, int bz,
         for (int r = 0; r < R; ++r) {
             sL[wb][0][slot[r]] = L0[rs(0)][r];
 #pragma unroll
-            for (int m = 1; m < K; ++m) sL[wb][m][slot[r]] = wp[m - 1][r];
+            for (int m = 1; m < K; ++m)
+                sL[wb][m][slot[r]] = RING ? WR[(m - 1) % (K - 1)][rs(0)][r] : wp[m - 1][r];
             if (VC) sD[dslot(t)][slot[r]] = D0[rs(0)][r];
         }
         __syncthreads();   // the planes of step t are visible to step t+1
