@@ -27,7 +27,7 @@ constexpr int kChunkPlanes3 = 128;  // z planes per fused 3D tile (nz <= 128: on
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t probs[2], prefix[2], tau, bufs, total;   // index 0: 3D list, 1: 2D list
+    size_t probs[2], tau, bufs, total;             // index 0: 3D list, 1: 2D list
     size_t pass3;                                  // 3D pass tables: kGroups3 * 2 * levels3 rows of n3 + 1
     int levels3;                                   // pass levels of the 3D list
     size_t pass2;                                  // 2D pass tables: 2 * levels2 rows of n2 + 1
@@ -85,8 +85,6 @@ Layout layout(int nprob, const std::vector<KGrid> &kg, const int *s)
     for (int d = 0; d < 2; ++d) {
         L.probs[d] = o;
         o = align_up(o + sizeof(BatchProblem) * (cnt[d] + 1));
-        L.prefix[d] = o;
-        o = align_up(o + sizeof(long long) * (cnt[d] + 1));
     }
     L.pass3 = o;
     o = align_up(o + sizeof(long long) * kGroups3 * 2 * (size_t)L.levels3 * (n3 + 1));
@@ -109,7 +107,6 @@ struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<BatchProblem> probs[2];   // host copies of the uploaded tables
-    std::vector<long long> prefix[2];
     std::vector<long long> pass3;         // 3D: per level, fused then single-stage prefixes
     std::vector<long long> pass2;         // 2D: the same
     int cols3 = 64;                       // 3D fused tiles: output columns (one width per batch)
@@ -221,10 +218,7 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
         E.cols3 = (w32 < w64) ? 32 : 64;
     }
     E.tau.clear();
-    for (int d = 0; d < 2; ++d) {
-        E.probs[d].clear();
-        E.prefix[d].assign(1, 0);
-    }
+    for (int d = 0; d < 2; ++d) E.probs[d].clear();
     for (int i : order) {
         const int d = (kg[i].ndim == 3) ? 0 : 1;
         const double *are, *aim;
@@ -276,7 +270,6 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
         P.inv_h2 = kg[i].inv_h2;
         P.d_const = kg[i].d_const;
         E.probs[d].push_back(P);
-        E.prefix[d].push_back(E.prefix[d].back() + P.ntiles);
     }
     // 3D pass tables: row 2L = fused items of level L, row 2L+1 = single-stage items
     const int n3 = (int)E.probs[0].size();
@@ -317,9 +310,6 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
         if (E.probs[d].empty()) continue;
         e = hipMemcpyAsync(base + L.probs[d], E.probs[d].data(),
                            sizeof(BatchProblem) * E.probs[d].size(), hipMemcpyHostToDevice, st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(base + L.prefix[d], E.prefix[d].data(),
-                               sizeof(long long) * E.prefix[d].size(), hipMemcpyHostToDevice, st);
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(base + L.tau, E.tau.data(), sizeof(double) * E.tau.size(),
