@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
 S_STAGES = 100
 SUPERSTEPS = 10
 NU = 0.01
@@ -626,6 +627,16 @@ def main():
             "stages_per_pass": kdepth, "tile": tile, "zchunk": zchunk,
             "autotuned": tune is not None, "bytes_per_point_per_pass": 40,
             "algorithmic_bytes_per_launch": 40 * N, "avg_launch_ms": avg_launch_ms}
+    # Update-rate caps: HBM at the pass schedule's minimal bytes per point-stage, and FP64
+    # at the stage's flops per point (variable D, fused order: per face 2 subtractions,
+    # 1 add and 2 fma; then 2 multiplies and 4 fma; an fma counts 2 flops: 52 flops).
+    sched = pass_schedule(S_STAGES, kdepth)
+    bytes_per_update = 40.0 * len(sched) / S_STAGES
+    roof["update_caps"] = {
+        "hbm": HBM_PEAK_GBS * 1e9 / bytes_per_update, "fp64": FP64_PEAK_TFLOPS * 1e12 / 52.0,
+        "bytes_per_update": bytes_per_update, "flops_per_update": 52,
+        "value_over_min_cap": value / min(HBM_PEAK_GBS * 1e9 / bytes_per_update,
+                                          FP64_PEAK_TFLOPS * 1e12 / 52.0)}
     # one-stage-per-pass reference on the same state (diagnostic)
     F.frkc2_set_option(F.OPT_TBLOCK, 1)
     F.frkc2_step(prob, w, D, T=T, s=S_STAGES, nsteps=1)
