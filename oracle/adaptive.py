@@ -122,3 +122,64 @@ def integrate(prob, t_span, T0, tol, nu=0.01, w=None, max_attempts=10000):
         if prob.op in (2, 3):
             rho = None
     return cur, trace, T
+
+
+def superstep_user(f, w, tau_re, tau_im):
+    """One superstep around a caller operator f(wr, wi) -> (fr, fi) (the core/user split of the
+    paper's public code, Sec. 3.1), carrying the embedded solution. Returns (Wr, Wi, What)."""
+    wr = np.ascontiguousarray(w, dtype=np.float64).reshape(-1).copy()
+    wi = np.zeros_like(wr)
+    emb = wr.copy()
+    for tr, ti in zip(tau_re, tau_im):
+        fr, fi = f(wr, wi)
+        stage.euler_update(wr, wi, np.ascontiguousarray(fr, dtype=np.float64),
+                           np.ascontiguousarray(fi, dtype=np.float64), tr, ti, emb)
+    return wr, wi, emb
+
+
+def integrate_user(f, rho, w0, t_span, T0, tol, nu=0.01, max_attempts=10000):
+    """Error control of Sec. 3 (the readings above) around a caller operator f. rho is a
+    spectral-radius bound: a number, or a function of the current real state, evaluated
+    before the first attempt and after every accepted step. Returns (w, trace, T_next)."""
+    cur = np.ascontiguousarray(w0, dtype=np.float64).reshape(-1).copy()
+    t = 0.0
+    T = float(T0)
+    have_prev = False
+    T_prev = err_prev = 0.0
+    r = None
+    trace = []
+    while t < t_span:
+        if len(trace) >= max_attempts:
+            raise RuntimeError("attempt limit reached")
+        if r is None:
+            r = float(rho(cur)) if callable(rho) else float(rho)
+        Tn = min(T, t_span - t)
+        x = Tn * r
+        s = choose_s(x, nu)
+        c = coeffs(s, nu)
+        if c.beta_bar < x:
+            Tn = 0.99 * c.beta_bar / r
+        wr, wi, wh = superstep_user(f, cur, Tn * c.a_re, Tn * c.a_im)
+        err = error_norm(wr, wi, wh, tol)
+        if not math.isfinite(err):
+            raise FloatingPointError("non-finite error estimate")
+        if err > 1.0:
+            trace.append((t, Tn, s, err, 0))
+            T = Tn * (SAFE / math.sqrt(err))
+            have_prev = False
+            continue
+        trace.append((t, Tn, s, err, 1))
+        cur = wr
+        t = t + Tn
+        e = max(err, ERR_FLOOR)
+        fac = SAFE / math.sqrt(e)
+        if have_prev:
+            fac = fac * (Tn / T_prev) * math.sqrt(err_prev / e)
+        fac = min(fac, FACMAX)
+        T_prev = Tn
+        err_prev = e
+        have_prev = True
+        T = Tn * fac
+        if callable(rho):
+            r = None
+    return cur, trace, T

@@ -256,6 +256,25 @@ int oracle_superstep(int ndim, const long *n, int bc, int op, double inv_h2, dou
 }
 
 /*
+ * One forward Euler stage W <- W + tau f (Sec. 3, the Euler-step equation)
+ * for a caller-supplied f, in the same expressions as the stage loop above;
+ * emb (may be NULL) is the embedded first-order solution of Sec. 3's error
+ * estimate, advanced by Re tau Re f.
+ */
+void oracle_euler_update(long N, double *wr, double *wi, const double *fr, const double *fi,
+                         double tr, double ti, double *emb)
+{
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < N; ++p) {
+        double nr = fma(tr, fr[p], fma(-ti, fi[p], wr[p]));
+        double ni = fma(tr, fi[p], fma(ti, fr[p], wi[p]));
+        wr[p] = nr;
+        wi[p] = ni;
+        if (emb) emb[p] = fma(tr, fr[p], emb[p]);
+    }
+}
+
+/*
  * Adjoint of one superstep (ops 0 and 1). Given w_n, the stepsizes and
  * lam_next = dJ/dw^{n+1}, writes lam_n = dJ/dw^n and adds D * dJ/dD to
  * grad_logD (op 1 only; grad_logD may be NULL for op 0).

@@ -57,6 +57,9 @@ def _load():
         lib.oracle_rho_bound.restype = ctypes.c_double
         lib.oracle_set_faces.argtypes = [dp]
         lib.oracle_set_faces.restype = None
+        lib.oracle_euler_update.argtypes = [ctypes.c_long, dp, dp, dp, dp, ctypes.c_double,
+                                            ctypes.c_double, dp]
+        lib.oracle_euler_update.restype = None
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
@@ -177,3 +180,11 @@ def adjoint(prob, w_n, lam_next, tau_re, tau_im, grad_logD=None, D=None):
     if rc != 0:
         raise RuntimeError("oracle_adjoint failed (%d)" % rc)
     return out, g
+
+
+def euler_update(wr, wi, fr, fi, tr, ti, emb=None):
+    """W <- W + tau f in place (wr, wi: contiguous float64), and emb <- emb + Re tau Re f."""
+    for a in (wr, wi, fr, fi) + ((emb,) if emb is not None else ()):
+        assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    _load().oracle_euler_update(wr.size, _dp(wr), _dp(wi), _dp(fr), _dp(fi), float(tr), float(ti),
+                                _dp(emb))

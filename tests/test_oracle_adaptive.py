@@ -9,7 +9,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle import adaptive, frkc2_coeffs, stage
+from oracle import adaptive, dense, frkc2_coeffs, stage
 from paper_1702_03818_amd import workloads as wl
 
 
@@ -142,3 +142,50 @@ def test_porous_operator_runs():
     w, trace, _ = adaptive.integrate(p, 2e-4, 1e-6, 1e-4)
     assert all(r[3] <= 1 for r in trace if r[4])
     assert abs(w.sum() - p.w0.sum()) < 1e-10 * abs(p.w0.sum())
+
+
+def test_user_operator_matches_builtin_operator():
+    """Error control around a caller operator (Sec. 3.1 core/user split): the periodic heat
+    operator written with numpy takes the same attempts and stage counts as the built-in one
+    and ends within rounding of it (the two evaluate the stencil in different orders)."""
+    p = wl.heat1d()
+    inv_h2 = 1.0 / (p.h * p.h)
+
+    def lap(wr, wi):
+        return ((np.roll(wr, 1) + np.roll(wr, -1) - 2.0 * wr) * inv_h2,
+                (np.roll(wi, 1) + np.roll(wi, -1) - 2.0 * wi) * inv_h2)
+
+    rho = 4.0 * inv_h2
+    w_u, tr_u, _ = adaptive.integrate_user(lap, rho, p.w0, 2000.0 / rho, 100.0 / rho, 1e-4)
+    w_b, tr_b, _ = adaptive.integrate(p, 2000.0 / rho, 100.0 / rho, 1e-4)
+    assert [(t[2], t[4]) for t in tr_u] == [(t[2], t[4]) for t in tr_b]
+    assert np.linalg.norm(w_u - w_b) <= 1e-12 * np.linalg.norm(w_b)
+
+
+def test_user_scalar_operator_follows_the_stability_polynomial():
+    """f = lam W: every accepted step multiplies the state by R(T_n lam) (50-digit product of
+    the FP64 stepsizes), so the end state is the product over the accepted steps."""
+    lam = -7.0
+    w0 = np.linspace(0.5, 1.5, 64)
+    w, trace, _ = adaptive.integrate_user(lambda wr, wi: (lam * wr, lam * wi), abs(lam), w0,
+                                          3.0, 0.05, 1e-5)
+    fac = 1.0
+    for t, T, s, err, acc in trace:
+        if acc:
+            c = adaptive.coeffs(int(s), 0.01)
+            fac *= dense.R_hp(c.a, T * lam)
+    assert np.max(np.abs(w - fac * w0)) <= 1e-12 * np.max(np.abs(w0))
+    assert sum(1 for *_, a in trace if a) > 3
+
+
+def test_user_rho_function_evaluated_per_accepted_step():
+    calls = []
+
+    def rho(w):
+        calls.append(float(np.max(np.abs(w))))
+        return 3.0
+
+    _, trace, _ = adaptive.integrate_user(lambda wr, wi: (-3.0 * wr, -3.0 * wi), rho,
+                                          np.ones(8), 2.0, 0.1, 1e-4)
+    accepted = sum(1 for *_, a in trace if a)
+    assert len(calls) == accepted   # before the first attempt and after every accept but the last
