@@ -315,14 +315,50 @@ int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, double t_sp
  *   T, rho   superstep length and a bound on the spectral radius of f's
  *            Jacobian (T rho <= betabar(s) is required; rho = 0 skips it)
  *   s, nu, nsteps  as for frkc2_step
- *   ws       frkc2_workspace_bytes of any grid with n points (32 n bytes +
- *            scratch), 16-byte aligned
+ *   ws       frkc2_user_workspace_bytes(n, FRKC2_WS_STEP) bytes, 16-byte
+ *            aligned
  * Errors: FRKC2_EINVAL (arguments, checked before any HIP call; a non-zero
  * return of f), FRKC2_EUNSTABLE, FRKC2_ENOMEM, FRKC2_EHIP.
  */
 typedef int (*frkc2_user_f)(const double *W, double *F, long long n, void *user, hipStream_t st);
 int frkc2_step_user(long long n, double *w, frkc2_user_f f, void *user, double T, double rho,
                     int s, double nu, int nsteps, void *ws, size_t ws_bytes, hipStream_t st);
+
+/*
+ * frkc2_user_workspace_bytes -- device workspace of frkc2_step_user
+ * (flags FRKC2_WS_STEP) or frkc2_integrate_user (FRKC2_WS_ADAPT) for states of
+ * n values; 0 for n < 1 or other flags.
+ */
+size_t frkc2_user_workspace_bytes(long long n, int flags);
+
+/*
+ * frkc2_integrate_user -- the error control of frkc2_integrate (Sec. 3, the
+ * same readings and controller) around a caller-supplied operator as in
+ * frkc2_step_user: the paper's public code runs its error-controlled core
+ * around the user's f in the same way (Sec. 3.1). Per attempt the library
+ * starts W from (w, 0) and the embedded solution from w, calls f before each
+ * stage and applies W <- W + tau_l F and What <- What + Re tau_l Re F (fma
+ * order of frkc2_step), then takes the error estimate and the accept decision.
+ *   n, w, f, user      as for frkc2_step_user
+ *   rho_f, rho_const   spectral-radius bound of f's Jacobian: rho_f(w, n, user,
+ *                      st, &rho) is called on the host with the current real
+ *                      state before the first attempt and after every accepted
+ *                      step and must return 0 and a positive finite rho; with
+ *                      rho_f NULL the constant rho_const (> 0) is used
+ *   t_span, T0, tol, nu, max_attempts, trace, trace_cap, stats
+ *                      as for frkc2_integrate
+ *   ws                 frkc2_user_workspace_bytes(n, FRKC2_WS_ADAPT) bytes,
+ *                      16-byte aligned
+ * Errors: FRKC2_EINVAL (arguments, checked before any HIP call; a non-zero
+ * return of f or rho_f), FRKC2_ENOMEM, FRKC2_ENONFINITE, FRKC2_ETIMEOUT,
+ * FRKC2_EHIP.
+ */
+typedef int (*frkc2_user_rho)(const double *w, long long n, void *user, hipStream_t st,
+                              double *rho);
+int frkc2_integrate_user(long long n, double *w, frkc2_user_f f, frkc2_user_rho rho_f,
+                         double rho_const, void *user, double t_span, double T0, double tol,
+                         double nu, int max_attempts, void *ws, size_t ws_bytes, hipStream_t st,
+                         double *trace, int trace_cap, frkc2_adapt_stats *stats);
 
 /*
  * frkc2_autotune -- pick the launch configuration of frkc2_step's passes for

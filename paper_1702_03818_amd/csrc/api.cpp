@@ -853,44 +853,19 @@ int choose_s(double x, double nu, double *bbar)
 
 }  // namespace
 
-extern "C" int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, double t_span,
-                               double T0, double tol, double nu, int max_attempts, void *ws,
-                               size_t ws_bytes, hipStream_t st, double *trace, int trace_cap,
-                               frkc2_adapt_stats *stats)
-{
-    KGrid kg;
-    if (!make_kgrid(g, kg)) return FRKC2_EINVAL;
-    if (!w || (kg.op == FRKC2_OP_VARCOEF && !D)) {
-        set_error("w (and D for VARCOEF) must be non-NULL");
-        return FRKC2_EINVAL;
-    }
-    if (!(t_span > 0.0) || !std::isfinite(t_span) || !(T0 > 0.0) || !std::isfinite(T0) ||
-        !(tol > 0.0) || !std::isfinite(tol)) {
-        set_error("t_span, T0 and tol must be positive and finite");
-        return FRKC2_EINVAL;
-    }
-    if (!(nu >= 0.0 && nu < 1.0)) {
-        set_error("nu must lie in [0, 1) (got %g)", nu);
-        return FRKC2_EINVAL;
-    }
-    if (max_attempts < 1 || trace_cap < 0 || (trace_cap > 0 && !trace)) {
-        set_error("max_attempts must be >= 1 and trace non-NULL when trace_cap > 0");
-        return FRKC2_EINVAL;
-    }
-    const long long N = kg.nstate();
-    const AdaptLayout L = adapt_layout(N);
-    if (!ws || ws_bytes < L.total || !aligned16(ws)) {
-        set_error("workspace needs %zu bytes (got %zu), 16-byte aligned", L.total, ws_bytes);
-        return FRKC2_ENOMEM;
-    }
-    char *base = static_cast<char *>(ws);
-    double *buf[2] = {reinterpret_cast<double *>(base + L.bufA),
-                      reinterpret_cast<double *>(base + L.bufB)};
-    double *emb[2] = {reinterpret_cast<double *>(base + L.embA),
-                      reinterpret_cast<double *>(base + L.embB)};
-    double *partials = reinterpret_cast<double *>(base + L.scratch);
+namespace {
 
-    const PassCfg cfg = pass_cfg(kg);
+// The controller of Sec. 3 with the readings stated in frkc2.h: attempts until t reaches
+// t_span. rho_fn(&rho) bounds the spectral radius of the current state (before the first
+// attempt and, with rho_every, after every accepted step); step_fn(Tn, s, a_re, a_im, &WL,
+// &EL) runs one superstep from w that carries the embedded solution and leaves W^L
+// (complex) and What^L in the workspace. Both return a frkc2_status.
+template <class RhoFn, class StepFn>
+int adapt_loop(long long N, double *w, double t_span, double T0, double tol, double nu,
+               int max_attempts, bool rho_every, double *partials, hipStream_t st,
+               double *trace, int trace_cap, frkc2_adapt_stats *stats, RhoFn rho_fn,
+               StepFn step_fn)
+{
     double t = 0.0, T = T0, T_prev = 0.0, err_prev = 0.0, err_last = 0.0, rho = 0.0;
     bool have_prev = false, need_rho = true;
     int attempts = 0, accepted = 0, rejected = 0, s_last = 0;
@@ -901,9 +876,9 @@ extern "C" int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, 
             return FRKC2_ETIMEOUT;
         }
         if (need_rho) {
-            const int rc = rho_bound_impl(kg, w, D, partials, &rho, st);
+            const int rc = rho_fn(&rho);
             if (rc < 0) return rc;
-            need_rho = nonlinear(kg);
+            need_rho = false;
         }
         double Tn = std::min(T, t_span - t);
         const double x = Tn * rho;
@@ -916,8 +891,8 @@ extern "C" int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, 
         int crc = coeffs_cached(s, nu, &are, &aim, &info);
         if (crc < 0) return crc;
         const double *WL = nullptr, *EL = nullptr;
-        HIP_TRY(run_superstep_emb(kg, cfg, w, D, Tn, are, aim, s, buf, emb, &WL, &EL, st),
-                "embedded superstep launch");
+        const int src = step_fn(Tn, s, are, aim, &WL, &EL);
+        if (src < 0) return src;
         HIP_TRY(launch_err_max(WL, EL, N, tol, partials, st), "error estimate launch");
         double err = 0.0;
         HIP_TRY(hipMemcpyAsync(&err, partials + kReduceBlocks, sizeof(double),
@@ -957,7 +932,7 @@ extern "C" int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, 
         err_prev = e;
         have_prev = true;
         T = Tn * fac;
-        if (nonlinear(kg)) need_rho = true;
+        if (rho_every) need_rho = true;
     }
     HIP_TRY(hipStreamSynchronize(st), "integrate");
     if (stats) {
@@ -971,6 +946,133 @@ extern "C" int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, 
         stats->s_last = s_last;
     }
     return FRKC2_OK;
+}
+
+bool check_adapt_args(double t_span, double T0, double tol, double nu, int max_attempts,
+                      double *trace, int trace_cap)
+{
+    if (!(t_span > 0.0) || !std::isfinite(t_span) || !(T0 > 0.0) || !std::isfinite(T0) ||
+        !(tol > 0.0) || !std::isfinite(tol)) {
+        set_error("t_span, T0 and tol must be positive and finite");
+        return false;
+    }
+    if (!(nu >= 0.0 && nu < 1.0)) {
+        set_error("nu must lie in [0, 1) (got %g)", nu);
+        return false;
+    }
+    if (max_attempts < 1 || trace_cap < 0 || (trace_cap > 0 && !trace)) {
+        set_error("max_attempts must be >= 1 and trace non-NULL when trace_cap > 0");
+        return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, double t_span,
+                               double T0, double tol, double nu, int max_attempts, void *ws,
+                               size_t ws_bytes, hipStream_t st, double *trace, int trace_cap,
+                               frkc2_adapt_stats *stats)
+{
+    KGrid kg;
+    if (!make_kgrid(g, kg)) return FRKC2_EINVAL;
+    if (!w || (kg.op == FRKC2_OP_VARCOEF && !D)) {
+        set_error("w (and D for VARCOEF) must be non-NULL");
+        return FRKC2_EINVAL;
+    }
+    if (!check_adapt_args(t_span, T0, tol, nu, max_attempts, trace, trace_cap)) return FRKC2_EINVAL;
+    const long long N = kg.nstate();
+    const AdaptLayout L = adapt_layout(N);
+    if (!ws || ws_bytes < L.total || !aligned16(ws)) {
+        set_error("workspace needs %zu bytes (got %zu), 16-byte aligned", L.total, ws_bytes);
+        return FRKC2_ENOMEM;
+    }
+    char *base = static_cast<char *>(ws);
+    double *buf[2] = {reinterpret_cast<double *>(base + L.bufA),
+                      reinterpret_cast<double *>(base + L.bufB)};
+    double *emb[2] = {reinterpret_cast<double *>(base + L.embA),
+                      reinterpret_cast<double *>(base + L.embB)};
+    double *partials = reinterpret_cast<double *>(base + L.scratch);
+    const PassCfg cfg = pass_cfg(kg);
+    return adapt_loop(
+        N, w, t_span, T0, tol, nu, max_attempts, nonlinear(kg), partials, st, trace, trace_cap,
+        stats, [&](double *rho) { return rho_bound_impl(kg, w, D, partials, rho, st); },
+        [&](double Tn, int s, const double *are, const double *aim, const double **WL,
+            const double **EL) -> int {
+            HIP_TRY(run_superstep_emb(kg, cfg, w, D, Tn, are, aim, s, buf, emb, WL, EL, st),
+                    "embedded superstep launch");
+            return FRKC2_OK;
+        });
+}
+
+extern "C" size_t frkc2_user_workspace_bytes(long long n, int flags)
+{
+    if (n < 1) return 0;
+    if (flags == FRKC2_WS_STEP) return step_layout(n).total;
+    if (flags == FRKC2_WS_ADAPT) return adapt_layout(n).total;
+    return 0;
+}
+
+extern "C" int frkc2_integrate_user(long long n, double *w, frkc2_user_f f,
+                                    frkc2_user_rho rho_f, double rho_const, void *user,
+                                    double t_span, double T0, double tol, double nu,
+                                    int max_attempts, void *ws, size_t ws_bytes, hipStream_t st,
+                                    double *trace, int trace_cap, frkc2_adapt_stats *stats)
+{
+    if (n < 1 || !w || !f) {
+        set_error("user integrate: need n >= 1, w and f");
+        return FRKC2_EINVAL;
+    }
+    if (!rho_f && (!(rho_const > 0.0) || !std::isfinite(rho_const))) {
+        set_error("user integrate: need rho_f or a positive finite rho_const");
+        return FRKC2_EINVAL;
+    }
+    if (!check_adapt_args(t_span, T0, tol, nu, max_attempts, trace, trace_cap)) return FRKC2_EINVAL;
+    const AdaptLayout L = adapt_layout(n);
+    if (!ws || ws_bytes < L.total || !aligned16(ws)) {
+        set_error("workspace needs %zu bytes (got %zu), 16-byte aligned", L.total, ws_bytes);
+        return FRKC2_ENOMEM;
+    }
+    char *base = static_cast<char *>(ws);
+    double *W = reinterpret_cast<double *>(base + L.bufA);
+    double *F = reinterpret_cast<double *>(base + L.bufB);
+    double *E = reinterpret_cast<double *>(base + L.embA);
+    double *partials = reinterpret_cast<double *>(base + L.scratch);
+    return adapt_loop(
+        n, w, t_span, T0, tol, nu, max_attempts, rho_f != nullptr, partials, st, trace,
+        trace_cap, stats,
+        [&](double *rho) -> int {
+            if (!rho_f) {
+                *rho = rho_const;
+                return FRKC2_OK;
+            }
+            double r = -1.0;
+            const int urc = rho_f(w, n, user, st, &r);
+            if (urc != 0 || !(r > 0.0) || !std::isfinite(r)) {
+                set_error("user integrate: rho_f returned %d with rho = %g", urc, r);
+                return FRKC2_EINVAL;
+            }
+            *rho = r;
+            return FRKC2_OK;
+        },
+        [&](double Tn, int s, const double *are, const double *aim, const double **WL,
+            const double **EL) -> int {
+            HIP_TRY(launch_real_to_complex(n, w, W, st), "user integrate: W^0");
+            HIP_TRY(hipMemcpyAsync(E, w, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, st),
+                    "user integrate: What^0");
+            for (int l = 0; l < s; ++l) {
+                const int urc = f(W, F, n, user, st);
+                if (urc != 0) {
+                    set_error("user integrate: f returned %d at stage %d", urc, l);
+                    return FRKC2_EINVAL;
+                }
+                HIP_TRY(launch_euler_axpy(n, W, F, Tn * are[l], Tn * aim[l], st, E),
+                        "user integrate: update");
+            }
+            *WL = W;
+            *EL = E;
+            return FRKC2_OK;
+        });
 }
 
 extern "C" int frkc2_step_user(long long n, double *w, frkc2_user_f f, void *user, double T,

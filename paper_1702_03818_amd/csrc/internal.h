@@ -61,8 +61,9 @@ bool stage1d_lds_fits(const KGrid &g);
 int launch_finalize(const KGrid &g, const double *in_c, double *out_re, double *partials,
                     hipStream_t st);
 int launch_real_to_complex(long long n, const double *in, double *out_c, hipStream_t st);
+// W <- W + tau F (complex, interleaved); emb, if given, <- emb + Re tau Re F
 int launch_euler_axpy(long long n, double *W, const double *F, double tr, double ti,
-                      hipStream_t st);
+                      hipStream_t st, double *emb = nullptr);
 int launch_zero(long long n, double *p, hipStream_t st);   // fill kernel (graph-safe)
 
 // Two-species Brusselator (bruss.hip): one stage per pass; reaction part of

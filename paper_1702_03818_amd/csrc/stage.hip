@@ -165,12 +165,16 @@ __global__ void real_to_complex(const double *in, double2 *out, long long n)
 
 // W <- W + tau F for a user-supplied F = f(W) (Sec. 3, Euler step), in the
 // library's order: (fma(tr, Fr, fma(-ti, Fi, Wr)), fma(tr, Fi, fma(ti, Fr, Wi))).
-__global__ void euler_axpy(double2 *W, const double2 *F, long long n, double tr, double ti)
+// emb (may be null): the embedded first-order solution of the error estimate
+// (Sec. 3), advanced by Re tau Re f.
+__global__ void euler_axpy(double2 *W, const double2 *F, double *emb, long long n, double tr,
+                           double ti)
 {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         const double2 w = W[i], f = F[i];
         W[i] = make_double2(fma(tr, f.x, fma(-ti, f.y, w.x)), fma(tr, f.y, fma(ti, f.x, w.y)));
+        if (emb) emb[i] = fma(tr, f.x, emb[i]);
     }
 }
 
@@ -316,14 +320,14 @@ int launch_finalize(const KGrid &g, const double *in_c, double *out_re, double *
 }
 
 int launch_euler_axpy(long long n, double *W, const double *F, double tr, double ti,
-                      hipStream_t st)
+                      hipStream_t st, double *emb)
 {
     long long blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(euler_axpy, dim3((unsigned)blocks), dim3(256), 0, st,
-                       reinterpret_cast<double2 *>(W), reinterpret_cast<const double2 *>(F), n,
-                       tr, ti);
+                       reinterpret_cast<double2 *>(W), reinterpret_cast<const double2 *>(F), emb,
+                       n, tr, ti);
     return (int)hipGetLastError();
 }
 

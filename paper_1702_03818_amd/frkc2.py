@@ -75,6 +75,8 @@ _VP = ctypes.c_void_p
 USER_F = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong,
                           ctypes.c_void_p, ctypes.c_void_p)
 _DP = ctypes.POINTER(ctypes.c_double)
+USER_RHO = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p,
+                            ctypes.c_void_p, _DP)
 
 _SIGS = {
     "frkc2_coeffs": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, _DP, _DP, ctypes.POINTER(CoeffInfo)]),
@@ -103,6 +105,12 @@ _SIGS = {
     "frkc2_step_user": (ctypes.c_int, [ctypes.c_longlong, _VP, USER_F, _VP, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                        _VP, ctypes.c_size_t, _VP]),
+    "frkc2_user_workspace_bytes": (ctypes.c_size_t, [ctypes.c_longlong, ctypes.c_int]),
+    "frkc2_integrate_user": (ctypes.c_int, [ctypes.c_longlong, _VP, USER_F, USER_RHO,
+                                            ctypes.c_double, _VP, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_int, _VP,
+                                            ctypes.c_size_t, _VP, _DP, ctypes.c_int,
+                                            ctypes.POINTER(AdaptStats)]),
     "frkc2_autotune": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_int, _VP, ctypes.c_size_t, _VP,
                                       ctypes.POINTER(TuneResult)]),
@@ -267,26 +275,40 @@ def frkc2_integrate(grid, w, D=None, t_span=1.0, T0=1e-6, tol=1e-4, nu=0.01, max
     return stats, tr[:min(stats["attempts"], tr.shape[0])]
 
 
+def _user_views(buf, n):
+    """Complex views into the workspace for the pointers the library passes to f."""
+    torch = _torch()
+    base = buf.data_ptr()
+    cache = {}
+
+    def view(ptr):
+        off = int(ptr) - base
+        if off < 0 or off + 16 * n > buf.numel() or off % 16:
+            raise ValueError("stage pointer outside the workspace")
+        if off not in cache:
+            cache[off] = buf[off: off + 16 * n].view(torch.float64).view(torch.complex128)
+        return cache[off]
+    return view
+
+
 def frkc2_step_user(w, f, T, rho=0.0, s=16, nu=0.01, nsteps=1, stream=None):
     """nsteps supersteps of w (float64, device) under a caller operator: f(W, F) receives the
     complex128 stage W and must write f(W) into F (both views of the library's workspace),
     on the current stream. The library applies the stepsizes and the Euler updates."""
-    torch = _torch()
     lib = load()
     n = int(w.numel())
-    need = 32 * n + 4 * 256 + 64 * 1024
+    need = lib.frkc2_user_workspace_bytes(n, WS_STEP)
+    if need == 0:
+        _check(-1)
     buf = workspace(need, key="user")
-    base = buf.data_ptr()
-    off_b = (16 * n + 255) // 256 * 256
-    Wv = buf[: 16 * n].view(torch.float64).view(torch.complex128)
-    Fv = buf[off_b: off_b + 16 * n].view(torch.float64).view(torch.complex128)
+    view = _user_views(buf, n)
     err = []
 
     def cb(W, F, nn, user, st):
         try:
-            if W != base or F != base + off_b or nn != n:
+            if nn != n:
                 return 2
-            f(Wv, Fv)
+            f(view(W), view(F))
             return 0
         except Exception as e:   # reported after the call returns
             err.append(e)
@@ -294,10 +316,64 @@ def frkc2_step_user(w, f, T, rho=0.0, s=16, nu=0.01, nsteps=1, stream=None):
 
     cfun = USER_F(cb)
     rc = lib.frkc2_step_user(n, _ptr(w), cfun, None, float(T), float(rho), int(s), float(nu),
-                             int(nsteps), ctypes.c_void_p(base), buf.numel(), _stream_ptr(stream))
+                             int(nsteps), ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                             _stream_ptr(stream))
     if err:
         raise err[0]
     return _check(rc)
+
+
+def frkc2_integrate_user(w, f, rho, t_span, T0, tol, nu=0.01, max_attempts=100000, trace_cap=0,
+                         stream=None):
+    """Error-controlled integration of w (float64, device, in place) over t_span under a caller
+    operator f(W, F) as in frkc2_step_user. rho is a spectral-radius bound of f's Jacobian: a
+    number, or a function of the current state w (the caller's tensor) returning one, called
+    before the first attempt and after every accepted step. Returns (stats dict, trace)."""
+    lib = load()
+    n = int(w.numel())
+    need = lib.frkc2_user_workspace_bytes(n, WS_ADAPT)
+    if need == 0:
+        _check(-1)
+    buf = workspace(need, key="user_adapt")
+    view = _user_views(buf, n)
+    err = []
+
+    def cb(W, F, nn, user, st):
+        try:
+            if nn != n:
+                return 2
+            f(view(W), view(F))
+            return 0
+        except Exception as e:
+            err.append(e)
+            return 1
+
+    def rcb(wp, nn, user, st, out):
+        try:
+            if nn != n or int(wp) != w.data_ptr():
+                return 2
+            out[0] = float(rho(w))
+            return 0
+        except Exception as e:
+            err.append(e)
+            return 1
+
+    cfun = USER_F(cb)
+    rfun = USER_RHO(rcb) if callable(rho) else ctypes.cast(None, USER_RHO)
+    rho_const = 0.0 if callable(rho) else float(rho)
+    tr = np.zeros((max(int(trace_cap), 0), 5), dtype=np.float64)
+    st = AdaptStats()
+    rc = lib.frkc2_integrate_user(n, _ptr(w), cfun, rfun, rho_const, None, float(t_span),
+                                  float(T0), float(tol), float(nu), int(max_attempts),
+                                  ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                  _stream_ptr(stream),
+                                  tr.ctypes.data_as(_DP) if trace_cap > 0 else None,
+                                  int(trace_cap), ctypes.byref(st))
+    if err:
+        raise err[0]
+    _check(rc)
+    stats = {f: getattr(st, f) for f, _ in AdaptStats._fields_}
+    return stats, tr[:min(stats["attempts"], tr.shape[0])]
 
 
 def frkc2_autotune(grid, w, D=None, s=16, nu=0.01, reps=2, stream=None, ws=None):

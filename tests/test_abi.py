@@ -264,3 +264,30 @@ def test_advdiff_rho_bound_on_host(ndim, vel, bc):
 def test_advdiff_rejects_nonfinite_velocity():
     g = grid(op=4, vel=(1.0, float("nan"), 0.0))
     assert F.load().frkc2_workspace_bytes(ctypes.byref(g), 16, F.WS_STEP) == 0
+
+
+def test_user_workspace_and_integrate_validation():
+    lib = F.load()
+    assert lib.frkc2_user_workspace_bytes(0, F.WS_STEP) == 0
+    assert lib.frkc2_user_workspace_bytes(1000, 7) == 0
+    step = lib.frkc2_user_workspace_bytes(1000, F.WS_STEP)
+    adapt = lib.frkc2_user_workspace_bytes(1000, F.WS_ADAPT)
+    assert step >= 32 * 1000 and adapt >= step + 16 * 1000
+    f = F.USER_F(lambda *a: 0)
+    nul = ctypes.cast(None, F.USER_RHO)
+    args = dict(t_span=1.0, T0=0.1, tol=1e-3, nu=0.01, max_attempts=10)
+
+    def call(n=8, w=1, fn=f, rho_f=nul, rho_const=1.0, **kw):
+        a = dict(args, **kw)
+        return lib.frkc2_integrate_user(n, ctypes.c_void_p(w), fn, rho_f, rho_const, None,
+                                        a["t_span"], a["T0"], a["tol"], a["nu"],
+                                        a["max_attempts"], None, 0, None, None, 0, None)
+
+    assert call(n=0) == -1
+    assert call(fn=ctypes.cast(None, F.USER_F)) == -1
+    assert call(rho_const=0.0) == -1
+    assert call(rho_const=float("inf")) == -1
+    assert call(tol=0.0) == -1
+    assert call(nu=1.0) == -1
+    assert call(max_attempts=0) == -1
+    assert call() == -2            # arguments fine, no workspace

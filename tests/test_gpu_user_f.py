@@ -65,3 +65,69 @@ def test_operator_error_is_reported():
 
     with pytest.raises(ValueError):
         F.frkc2_step_user(w, bad, T=1e-3, rho=1.0, s=8)
+
+
+def _heat_ops(p):
+    inv_h2 = 1.0 / (p.h * p.h)
+
+    def lap_np(wr, wi):
+        return ((np.roll(wr, 1) + np.roll(wr, -1) - 2.0 * wr) * inv_h2,
+                (np.roll(wi, 1) + np.roll(wi, -1) - 2.0 * wi) * inv_h2)
+
+    def lap_torch(W, Fo):
+        Fo.copy_((torch.roll(W, 1) + torch.roll(W, -1) - 2.0 * W) * inv_h2)
+
+    return lap_np, lap_torch, 4.0 * inv_h2
+
+
+@pytest.mark.parametrize("rho_fn", [False, True])
+def test_integrate_user_matches_oracle(rho_fn):
+    """Error control around a torch operator against the oracle's controller around the same
+    operator in numpy (both evaluate it elementwise in the same order): identical attempts
+    and state, bit for bit; rho as a number or as a function of the state."""
+    from oracle import adaptive
+    p = wl.heat1d()
+    lap_np, lap_torch, rho = _heat_ops(p)
+    t_span, T0, tol = 2000.0 / rho, 100.0 / rho, 1e-4
+    w_ref, tr_ref, T_ref = adaptive.integrate_user(lap_np, rho, p.w0, t_span, T0, tol)
+    w = torch.tensor(p.w0.reshape(-1), device="cuda")
+    calls = []
+
+    def rho_of(wt):
+        calls.append(1)
+        return rho
+
+    st, trace = F.frkc2_integrate_user(w, lap_torch, rho_of if rho_fn else rho, t_span, T0, tol,
+                                       trace_cap=len(tr_ref) + 4)
+    torch.cuda.synchronize()
+    assert np.array_equal(trace, np.array(tr_ref))
+    assert st["T_next"] == T_ref
+    assert np.array_equal(w.cpu().numpy(), w_ref)
+    if rho_fn:
+        assert len(calls) == st["accepted"]
+
+
+def test_integrate_user_scalar_operator():
+    from oracle import adaptive
+    lam = -7.0
+    w0 = np.linspace(0.5, 1.5, 4096)
+    w_ref, tr_ref, _ = adaptive.integrate_user(lambda wr, wi: (lam * wr, lam * wi), abs(lam), w0,
+                                               3.0, 0.05, 1e-5)
+    w = torch.tensor(w0, device="cuda")
+    st, trace = F.frkc2_integrate_user(w, lambda W, Fo: Fo.copy_(lam * W), abs(lam), 3.0, 0.05,
+                                       1e-5, trace_cap=len(tr_ref) + 4)
+    torch.cuda.synchronize()
+    assert np.array_equal(trace, np.array(tr_ref))
+    assert np.array_equal(w.cpu().numpy(), w_ref)
+
+
+def test_integrate_user_errors_are_reported():
+    w = torch.ones(64, dtype=torch.float64, device="cuda")
+
+    def bad(W, Fo):
+        raise ValueError("operator failed")
+
+    with pytest.raises(ValueError):
+        F.frkc2_integrate_user(w, bad, 1.0, 1.0, 0.1, 1e-3)
+    with pytest.raises(ZeroDivisionError):
+        F.frkc2_integrate_user(w, lambda W, Fo: Fo.copy_(-W), lambda wt: 1 / 0, 1.0, 0.1, 1e-3)
