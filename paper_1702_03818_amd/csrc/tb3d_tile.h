@@ -222,8 +222,9 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
         const int rb = (t - 1) & 1, wb = t & 1;     // LDS buffers read / written at step t
         // LDS operands of level m: x/y neighbours of level m-1 and their D,
         // and the cell's own D where the register ring no longer holds it.
-        // Level m+1's operands are read before level m is computed, by every
-        // lane (all slots are in range), so their latency overlaps the work.
+        // Every lane reads them (all slots are in range). With RA, level
+        // m+1's operands are read before level m is computed, so their
+        // latency overlaps the work.
         struct Nb {
             double2 w[4];
             double d[4], dc, dzm, dzp;
