@@ -316,7 +316,10 @@ int run_superstep(const KGrid &kg, const PassCfg &cfg, double *w, const double *
     int l = 0, pass = 0;
     const double *in = nullptr;
     while (l < s) {
+        // passes of k stages; a remainder of r >= 2 stages as one pass of
+        // depth r where the tile supports it
         int kk = (k >= 2 && s - l >= k) ? k : 1;
+        if (kk == 1 && k > 2 && s - l >= 2 && tblock_supported(kg, s - l)) kk = s - l;
         // A fused pass reads its input around each tile and chunk (halo), so it
         // must not write into the array it reads: the pass that starts from w
         // may not also be the one that writes w back.
@@ -722,10 +725,12 @@ extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const 
     double *gD = reinterpret_cast<double *>(base + L.gD);
 
     // forward recompute, storing W^0 .. W^{s-1}: 3D grids fuse three stages
-    // per pass and write the two intermediate states as well
+    // per pass (two for a remainder of two) and write the intermediate states
+    // as well
     HIP_TRY(launch_real_to_complex(N, w_n, S(0), st), "adjoint: W^0");
     for (int l = 0; l + 1 < s;) {
-        const int k = (kg.ndim == 3 && s - 1 - l >= 3) ? 3 : 1;
+        const int left = s - 1 - l;
+        const int k = (kg.ndim == 3 && left >= 2) ? (left >= 3 ? 3 : 2) : 1;
         PassArgs pa{};
         pa.k = k;
         pa.D = D;
@@ -789,7 +794,8 @@ int run_superstep_emb(const KGrid &kg, const PassCfg &cfg, const double *w, cons
     int l = 0, pass = 0;
     const double *in = nullptr, *ein = nullptr;
     while (l < s) {
-        const int kk = (k >= 2 && s - l >= k) ? k : 1;
+        int kk = (k >= 2 && s - l >= k) ? k : 1;
+        if (kk == 1 && k > 2 && s - l >= 2 && tblock_supported(kg, s - l)) kk = s - l;
         PassArgs pa{};
         pa.k = kk;
         pa.zchunk = cfg.zchunk;
