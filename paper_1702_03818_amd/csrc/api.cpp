@@ -575,7 +575,7 @@ std::vector<PassCfg> tune_candidates(const KGrid &kg)
     } else if (kg.ndim == 2) {
         for (int k : {2, 3, 4, 6, 8}) {
             add(k, 0);
-            add(k, 1);
+            if (kg.op != FRKC2_OP_BRUSS2) add(k, 1);   // the Brusselator has one tile
         }
     }
     return out;

@@ -66,9 +66,11 @@ int launch_euler_axpy(long long n, double *W, const double *F, double tr, double
                       hipStream_t st, double *emb = nullptr);
 int launch_zero(long long n, double *p, hipStream_t st);   // fill kernel (graph-safe)
 
-// Two-species Brusselator (bruss.hip): one stage per pass; reaction part of
-// the Gershgorin bound into partials[kReduceBlocks].
+// Two-species Brusselator (bruss.hip): one stage per pass, or p.k = 2..4
+// stages per pass (no embedded variant); reaction part of the Gershgorin
+// bound into partials[kReduceBlocks].
 int launch_bruss(const KGrid &g, const PassArgs &p, hipStream_t st);
+int launch_bruss_tb(const KGrid &g, const PassArgs &p, hipStream_t st);
 int launch_bruss_react_max(const KGrid &g, const double *w, double *partials, hipStream_t st);
 int launch_max_partials(double *partials, hipStream_t st);   // max of kReduceBlocks partials
 

@@ -133,7 +133,7 @@ int launch_bc(const KGrid &g, int k, int shape, const TbArgs &a, bool ir, bool o
 
 bool tblock_supported(const KGrid &g, int k)
 {
-    if (g.op == FRKC2_OP_BRUSS2) return false;
+    if (g.op == FRKC2_OP_BRUSS2) return k >= 2 && k <= 4;
     if (g.ndim == 3) return k == 2 || k == 3;
     if (g.ndim == 2) return k == 2 || k == 3 || k == 4 || k == 6 || k == 8;
     return false;
@@ -142,6 +142,7 @@ bool tblock_supported(const KGrid &g, int k)
 int launch_tblock(const KGrid &g, const PassArgs &p, int shape, hipStream_t st)
 {
     if (!tblock_supported(g, p.k)) return (int)hipErrorInvalidValue;
+    if (g.op == FRKC2_OP_BRUSS2) return launch_bruss_tb(g, p, st);
     if (g.ndim == 3 && (shape == 3 || shape == 4)) {
         PassArgs q = p;
         q.cols = (shape == 4) ? 32 : 64;
