@@ -381,12 +381,9 @@ def adaptive_leg(F, wl, torch, prob, D, rho, info):
             "fixed_step_stages": S_STAGES * SUPERSTEPS}
 
 
-def brusselator_leg(F, wl, torch):
-    """The paper's two-species Brusselator (Sec. 3.1). Throughput: 5 supersteps (s = 100,
-    T = 0.9 betabar / rho of the current state) on a 2048^2 grid. Accuracy: error-controlled
-    runs on the paper's 200^2 grid from its initial data to t = 1 at several tolerances, with
-    the accepted steps, the stages and the max error against a tol = 1e-8 run (the paper's
-    steps-to-error comparison, FRKC2 alone)."""
+def brusselator_throughput(F, wl, torch):
+    """2048^2 Brusselator supersteps (s = 100, T = 0.9 betabar / rho of the current state), the
+    default passes of 4 fused stages and one stage per pass."""
     big = wl.brusselator(2048)
     n = big.npoints
 
@@ -414,6 +411,16 @@ def brusselator_leg(F, wl, torch):
            "bytes_per_point_stage": 16,
            "achieved_gbs": 16 * n * S_STAGES / (ms * 1e-3) / 1e9,
            "one_stage_passes": {"ms_per_superstep": ms1, "value": n * S_STAGES / (ms1 * 1e-3)}}
+    return thr
+
+
+def brusselator_leg(F, wl, torch):
+    """The paper's two-species Brusselator (Sec. 3.1). Throughput: 5 supersteps (s = 100,
+    T = 0.9 betabar / rho of the current state) on a 2048^2 grid. Accuracy: error-controlled
+    runs on the paper's 200^2 grid from its initial data to t = 1 at several tolerances, with
+    the accepted steps, the stages and the max error against a tol = 1e-8 run (the paper's
+    steps-to-error comparison, FRKC2 alone)."""
+    thr = brusselator_throughput(F, wl, torch)
     p = wl.brusselator(200)
     runs = []
     ref = torch.tensor(p.w0.reshape(-1), dtype=torch.float64, device="cuda")
@@ -497,6 +504,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the error-control leg")
     ap.add_argument("--no-bruss", action="store_true", help="skip the Brusselator leg")
+    ap.add_argument("--bruss-throughput", action="store_true",
+                    help="run only the 2048^2 Brusselator throughput measurement (for profiling)")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 1D heat and 2D porous-medium legs")
     ap.add_argument("--tblock", type=int, default=0, choices=(0, 1, 2, 3),
@@ -537,6 +546,9 @@ def main():
     from paper_1702_03818_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.bruss_throughput:
+        print(json.dumps({"brusselator": brusselator_throughput(F, wl, torch)}))
+        return
     log("generating the 3D workload (n=%d)" % args.n)
     prob = wl.diffusion3d(n=args.n)
     N = prob.npoints
