@@ -75,7 +75,9 @@ typedef enum { FRKC2_BC_PERIODIC = 0, FRKC2_BC_DIRICHLET0 = 1 } frkc2_bc;
  *           fma(-4, vi, qi)), R_w = (fma(3, vr, -qr), fma(3, vi, -qi)) and
  *           f = fma(acc, 1/h^2, R) per component. Gershgorin bound:
  *           (2/h^2)(4d) + max_c max(|2vw - 4| + v^2, v^2 + |3 - 2vw|).
- *           One stage per pass; not available to the batched and adjoint calls.
+ *           frkc2_step fuses 2, 3 or 4 stages per pass (default 4; the
+ *           embedded passes of frkc2_integrate run one stage each); not
+ *           available to the batched and adjoint calls.
  *  ADVDIFF  f = d lap u - v . grad u with central differences (Sec. 2.1:
  *           damping makes the schemes usable for problems with a small
  *           hyperbolic part): a LAPLACE stencil whose face coefficients are

@@ -260,6 +260,23 @@ __global__ __launch_bounds__(256) void bruss_react_max(const double *s, long lon
     }
 }
 
+// 4 wavefronts of 8 rows: 64 x 32 tiles, about 130 VGPRs, three workgroups
+// per CU (8 wavefronts x 8 rows, 16 x 4 and a 128-VGPR cap measured no
+// faster at 2048^2).
+constexpr int kTbWaves = 4, kTbRows = 8;
+
+template <int K>
+int launch_bruss_tb_k(const BrussTbArgs &a, unsigned nblk, bool ir, bool orl, hipStream_t st)
+{
+    constexpr int NW = kTbWaves, R = kTbRows;
+    const dim3 grid(nblk), block(kTBX * NW);
+    if (ir && orl) hipLaunchKernelGGL((bruss_tb<K, true, true, NW, R>), grid, block, 0, st, a);
+    else if (ir) hipLaunchKernelGGL((bruss_tb<K, true, false, NW, R>), grid, block, 0, st, a);
+    else if (orl) hipLaunchKernelGGL((bruss_tb<K, false, true, NW, R>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((bruss_tb<K, false, false, NW, R>), grid, block, 0, st, a);
+    return (int)hipGetLastError();
+}
+
 }  // namespace
 
 int launch_bruss(const KGrid &g, const PassArgs &p, hipStream_t st)
@@ -297,23 +314,6 @@ int launch_bruss(const KGrid &g, const PassArgs &p, hipStream_t st)
     } else {
         hipLaunchKernelGGL((bruss_stage<false, false, false>), grid, block, 0, st, a);
     }
-    return (int)hipGetLastError();
-}
-
-// 4 wavefronts of 8 rows: 64 x 32 tiles, about 130 VGPRs, three workgroups
-// per CU (8 wavefronts x 8 rows, 16 x 4 and a 128-VGPR cap measured no
-// faster at 2048^2).
-constexpr int kTbWaves = 4, kTbRows = 8;
-
-template <int K>
-int launch_bruss_tb_k(const BrussTbArgs &a, unsigned nblk, bool ir, bool orl, hipStream_t st)
-{
-    constexpr int NW = kTbWaves, R = kTbRows;
-    const dim3 grid(nblk), block(kTBX * NW);
-    if (ir && orl) hipLaunchKernelGGL((bruss_tb<K, true, true, NW, R>), grid, block, 0, st, a);
-    else if (ir) hipLaunchKernelGGL((bruss_tb<K, true, false, NW, R>), grid, block, 0, st, a);
-    else if (orl) hipLaunchKernelGGL((bruss_tb<K, false, true, NW, R>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((bruss_tb<K, false, false, NW, R>), grid, block, 0, st, a);
     return (int)hipGetLastError();
 }
 
