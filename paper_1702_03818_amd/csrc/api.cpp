@@ -781,15 +781,17 @@ constexpr double kErrFloor = 1e-12;  // error estimates below this count as this
 
 // One superstep from the real state w that also carries the embedded
 // first-order solution; W^L (complex) and What^L are left in the workspace.
-// 3D grids fuse cfg.k stages per pass with the full-width tiles, other grids
-// and tile shapes run one stage per pass.
+// 3D grids fuse cfg.k stages per pass with the full-width tiles, the
+// Brusselator with its own tiles; other grids and tile shapes run one stage
+// per pass.
 int run_superstep_emb(const KGrid &kg, const PassCfg &cfg, const double *w, const double *D,
                       double Tn, const double *are, const double *aim, int s,
                       double *const buf[2], double *const emb[2], const double **WL,
                       const double **EL, hipStream_t st)
 {
-    const bool fused = kg.ndim == 3 && (cfg.tile == 3 || cfg.tile == 4) && cfg.k >= 2 &&
-                       tblock_supported(kg, cfg.k);
+    const bool bruss = kg.op == FRKC2_OP_BRUSS2;
+    const bool fused = (bruss || (kg.ndim == 3 && (cfg.tile == 3 || cfg.tile == 4))) &&
+                       cfg.k >= 2 && tblock_supported(kg, cfg.k);
     const int k = fused ? cfg.k : 1;
     int l = 0, pass = 0;
     const double *in = nullptr, *ein = nullptr;
@@ -812,7 +814,9 @@ int run_superstep_emb(const KGrid &kg, const PassCfg &cfg, const double *w, cons
             pa.tr[i] = Tn * are[l + i];
             pa.ti[i] = Tn * aim[l + i];
         }
-        const int rc = (kk == 1) ? launch_pass(kg, pa, 1, st) : launch_tb3d(kg, pa, st);
+        const int rc = (kk == 1) ? launch_pass(kg, pa, 1, st)
+                       : bruss   ? launch_bruss_tb(kg, pa, st)
+                                 : launch_tb3d(kg, pa, st);
         if (rc != 0) return rc;
         in = buf[pass & 1];
         ein = emb[pass & 1];

@@ -125,7 +125,9 @@ __global__ __launch_bounds__(kBBX *kBBY) void bruss_stage(BrussArgs a)
 // at least m cells inside the tile hold stage m values (lane 0, lane 63 and the
 // tile's outer rows take shifted-in or repeated values), so the centre is
 // exact after K stages. bruss_point() does the arithmetic, so the result
-// equals K single-stage passes bit for bit.
+// equals K single-stage passes bit for bit. With EMB each thread also carries
+// the embedded first-order solution of its points (real, advanced by Re tau
+// Re f per stage as in bruss_stage; it needs no neighbours).
 constexpr int kTBX = 64;
 
 struct BrussTbArgs {
@@ -133,6 +135,8 @@ struct BrussTbArgs {
     const double2 *in_c;
     double *out_re;
     double2 *out_c;
+    const double *emb_in;       // embedded solution in (complex input) and out
+    double *emb_out;
     int nx, ny, ntx;
     long long n;
     double inv_h2, d;
@@ -157,7 +161,7 @@ __device__ __forceinline__ double2 lane_shift2(double2 v)
     return make_double2(lane_shift<SHR>(v.x), lane_shift<SHR>(v.y));
 }
 
-template <int K, bool IN_REAL, bool OUT_REAL, int NW, int R>
+template <int K, bool IN_REAL, bool OUT_REAL, bool EMB, int NW, int R>
 __global__ __launch_bounds__(kTBX *NW) void bruss_tb(BrussTbArgs a)
 {
     constexpr int TY = NW * R, OX = kTBX - 2 * K, OY = TY - 2 * K;
@@ -168,6 +172,7 @@ __global__ __launch_bounds__(kTBX *NW) void bruss_tb(BrussTbArgs a)
     const int tx = threadIdx.x & (kTBX - 1), wv = threadIdx.x >> 6, r0 = wv * R;
     const int xs = bx * OX - K + tx, ys = by * OY - K + r0;
     double2 v[R], w[R];
+    double ev[EMB ? R : 1], ew[EMB ? R : 1];   // embedded solution (real), EMB only
     {
         const long long gx = wrap(xs, a.nx);
 #pragma unroll
@@ -179,6 +184,10 @@ __global__ __launch_bounds__(kTBX *NW) void bruss_tb(BrussTbArgs a)
             } else {
                 v[j] = a.in_c[i];
                 w[j] = a.in_c[a.n + i];
+            }
+            if (EMB) {
+                ev[j] = IN_REAL ? v[j].x : a.emb_in[i];
+                ew[j] = IN_REAL ? w[j].x : a.emb_in[a.n + i];
             }
         }
     }
@@ -208,6 +217,10 @@ __global__ __launch_bounds__(kTBX *NW) void bruss_tb(BrussTbArgs a)
                 bruss_point(vo, wo, lane_shift2<true>(vo), lane_shift2<false>(vo), vu, vd,
                             lane_shift2<true>(wo), lane_shift2<false>(wo), wu2, wd2, a.d,
                             a.inv_h2, a.tr[m], a.ti[m], v[j], w[j], fvr, fwr);
+                if (EMB) {
+                    ev[j] = fma(a.tr[m], fvr, ev[j]);
+                    ew[j] = fma(a.tr[m], fwr, ew[j]);
+                }
             }
             vu = vo;
             wu2 = wo;
@@ -225,6 +238,10 @@ __global__ __launch_bounds__(kTBX *NW) void bruss_tb(BrussTbArgs a)
             } else {
                 a.out_c[i] = v[j];
                 a.out_c[a.n + i] = w[j];
+            }
+            if (EMB) {
+                a.emb_out[i] = ev[j];
+                a.emb_out[a.n + i] = ew[j];
             }
         }
     }
@@ -270,10 +287,18 @@ int launch_bruss_tb_k(const BrussTbArgs &a, unsigned nblk, bool ir, bool orl, hi
 {
     constexpr int NW = kTbWaves, R = kTbRows;
     const dim3 grid(nblk), block(kTBX * NW);
-    if (ir && orl) hipLaunchKernelGGL((bruss_tb<K, true, true, NW, R>), grid, block, 0, st, a);
-    else if (ir) hipLaunchKernelGGL((bruss_tb<K, true, false, NW, R>), grid, block, 0, st, a);
-    else if (orl) hipLaunchKernelGGL((bruss_tb<K, false, true, NW, R>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((bruss_tb<K, false, false, NW, R>), grid, block, 0, st, a);
+    if (a.emb_out) {
+        if (ir) hipLaunchKernelGGL((bruss_tb<K, true, false, true, NW, R>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((bruss_tb<K, false, false, true, NW, R>), grid, block, 0, st, a);
+    } else if (ir && orl) {
+        hipLaunchKernelGGL((bruss_tb<K, true, true, false, NW, R>), grid, block, 0, st, a);
+    } else if (ir) {
+        hipLaunchKernelGGL((bruss_tb<K, true, false, false, NW, R>), grid, block, 0, st, a);
+    } else if (orl) {
+        hipLaunchKernelGGL((bruss_tb<K, false, true, false, NW, R>), grid, block, 0, st, a);
+    } else {
+        hipLaunchKernelGGL((bruss_tb<K, false, false, false, NW, R>), grid, block, 0, st, a);
+    }
     return (int)hipGetLastError();
 }
 
@@ -319,8 +344,10 @@ int launch_bruss(const KGrid &g, const PassArgs &p, hipStream_t st)
 
 int launch_bruss_tb(const KGrid &g, const PassArgs &p, hipStream_t st)
 {
-    if (g.op != FRKC2_OP_BRUSS2 || g.ndim != 2 || p.k < 2 || p.k > 4 || p.emb_out)
+    if (g.op != FRKC2_OP_BRUSS2 || g.ndim != 2 || p.k < 2 || p.k > 4)
         return (int)hipErrorInvalidValue;
+    // the embedded variant writes complex W and reads emb_in after the first stage
+    if (p.emb_out && (p.out_re || (!p.in_re && !p.emb_in))) return (int)hipErrorInvalidValue;
     if ((p.in_re != nullptr) == (p.in_c != nullptr) ||
         (p.out_re != nullptr) == (p.out_c != nullptr))
         return (int)hipErrorInvalidValue;
@@ -329,6 +356,8 @@ int launch_bruss_tb(const KGrid &g, const PassArgs &p, hipStream_t st)
     a.in_c = reinterpret_cast<const double2 *>(p.in_c);
     a.out_re = p.out_re;
     a.out_c = reinterpret_cast<double2 *>(p.out_c);
+    a.emb_in = p.emb_in;
+    a.emb_out = p.emb_out;
     a.nx = g.nx;
     a.ny = g.nz;   // 2D grids keep their second dimension in nz
     a.n = g.npts();

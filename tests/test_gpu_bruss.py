@@ -1,7 +1,8 @@
 """GPU parity of the two-species Brusselator (Sec. 3.1): Gershgorin bound, supersteps with the
 bound recomputed per superstep (one stage per pass and 2..4 fused stages per pass, on square,
 non-square and tiny periodic grids that the 64 x 32 tiles wrap around several times), the
-imaginary-part diagnostic and error-controlled integration, bit for bit against the oracle."""
+imaginary-part diagnostic and error-controlled integration (the embedded solution through the
+same fused passes), bit for bit against the oracle."""
 import numpy as np
 import pytest
 
@@ -80,6 +81,27 @@ def test_integrate_matches_oracle():
     st, trace = F.frkc2_integrate(p, w, None, t_span=t_span, T0=T0, tol=tol,
                                   trace_cap=len(trace_ref) + 4)
     torch.cuda.synchronize()
+    assert np.array_equal(trace, np.array(trace_ref))
+    assert st["T_next"] == T_ref
+    assert np.array_equal(w.cpu().numpy(), w_ref)
+
+
+@pytest.mark.parametrize("grid,k", [((57, 131), 2), ((131, 57), 3), ((64, 40), 4), ((5, 3), 4),
+                                    ((200, 200), 1)])
+def test_integrate_fused_depths_match_oracle(grid, k):
+    """Error control with the embedded solution carried through fused passes of k stages
+    (k = 1: one stage per pass), on non-square and tiny periodic grids."""
+    p = rect(*grid)
+    t_span, T0, tol = 1.0, 0.05, 1e-2      # steps of s = 4 .. 70 stages
+    w_ref, trace_ref, T_ref = adaptive.integrate(p, t_span, T0, tol)
+    F.frkc2_set_option(F.OPT_TBLOCK, k)
+    try:
+        w = dev(p.w0)
+        st, trace = F.frkc2_integrate(p, w, None, t_span=t_span, T0=T0, tol=tol,
+                                      trace_cap=len(trace_ref) + 4)
+        torch.cuda.synchronize()
+    finally:
+        F.frkc2_set_option(F.OPT_TBLOCK, 0)
     assert np.array_equal(trace, np.array(trace_ref))
     assert st["T_next"] == T_ref
     assert np.array_equal(w.cpu().numpy(), w_ref)
