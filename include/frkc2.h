@@ -75,9 +75,8 @@ typedef enum { FRKC2_BC_PERIODIC = 0, FRKC2_BC_DIRICHLET0 = 1 } frkc2_bc;
  *           fma(-4, vi, qi)), R_w = (fma(3, vr, -qr), fma(3, vi, -qi)) and
  *           f = fma(acc, 1/h^2, R) per component. Gershgorin bound:
  *           (2/h^2)(4d) + max_c max(|2vw - 4| + v^2, v^2 + |3 - 2vw|).
- *           frkc2_step fuses 2, 3 or 4 stages per pass (default 4; the
- *           embedded passes of frkc2_integrate run one stage each); not
- *           available to the batched and adjoint calls.
+ *           frkc2_step and frkc2_integrate fuse 2, 3 or 4 stages per pass
+ *           (default 4); not available to the batched and adjoint calls.
  *  ADVDIFF  f = d lap u - v . grad u with central differences (Sec. 2.1:
  *           damping makes the schemes usable for problems with a small
  *           hyperbolic part): a LAPLACE stencil whose face coefficients are
@@ -283,9 +282,9 @@ int frkc2_reduce(int op, const double *x, const double *y, size_t n, double *res
  *                (t, T, s, err, accepted 1/0), the first trace_cap attempts
  *   stats        host or NULL
  * Synchronises st once per attempt (the accept decision is taken on the
- * host). 3D grids fuse stages per HBM pass as frkc2_step does (full-width
- * tiles; the embedded solution adds 16 B per point and pass); other grids run
- * one stage per pass. Results are identical, bit for bit, to the same
+ * host). 3D grids (full-width tiles) and the Brusselator fuse stages per HBM
+ * pass as frkc2_step does (the embedded solution adds 16 B per point and
+ * species and pass); other grids run one stage per pass. Results are identical, bit for bit, to the same
  * procedure evaluated on the CPU in the library's arithmetic order. Errors:
  * FRKC2_EINVAL (arguments, checked before any HIP call), FRKC2_ENOMEM
  * (workspace), FRKC2_ENONFINITE (non-finite error estimate), FRKC2_ETIMEOUT,
