@@ -552,8 +552,8 @@ std::vector<PassCfg> tune_candidates(const KGrid &kg)
 {
     std::vector<PassCfg> out;
     std::vector<int> zcs{0};
-    for (int zc : {8, 16, 32, 64, 128})
-        if (zc < kg.nz) zcs.push_back(zc);
+    for (int zc : {8, 16, 32, 64, 128})   // the Brusselator's tiles have no chunk length
+        if (zc < kg.nz && kg.op != FRKC2_OP_BRUSS2) zcs.push_back(zc);
     auto add = [&](int k, int tile) {
         if (k >= 2 && !tblock_supported(kg, k)) return;
         for (int zc : zcs) {
