@@ -504,8 +504,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the error-control leg")
     ap.add_argument("--no-bruss", action="store_true", help="skip the Brusselator leg")
-    ap.add_argument("--bruss-throughput", action="store_true",
-                    help="run only the 2048^2 Brusselator throughput measurement (for profiling)")
+    ap.add_argument("--only", choices=("bruss-throughput", "batched", "adjoint", "porous2d"),
+                    help="run only this measurement and print its JSON (for profiling)")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 1D heat and 2D porous-medium legs")
     ap.add_argument("--tblock", type=int, default=0, choices=(0, 1, 2, 3),
@@ -546,8 +546,10 @@ def main():
     from paper_1702_03818_amd import workloads as wl
 
     torch.cuda.set_device(0)
-    if args.bruss_throughput:
-        print(json.dumps({"brusselator": brusselator_throughput(F, wl, torch)}))
+    if args.only:
+        legs = {"bruss-throughput": brusselator_throughput, "batched": batched_leg,
+                "adjoint": adjoint_leg, "porous2d": porous2d_leg}
+        print(json.dumps({args.only: legs[args.only](F, wl, torch)}), flush=True)
         return
     log("generating the 3D workload (n=%d)" % args.n)
     prob = wl.diffusion3d(n=args.n)
