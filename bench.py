@@ -504,7 +504,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the error-control leg")
     ap.add_argument("--no-bruss", action="store_true", help="skip the Brusselator leg")
-    ap.add_argument("--only", choices=("bruss-throughput", "batched", "adjoint", "porous2d"),
+    ap.add_argument("--only", choices=("bruss-throughput", "batched", "adjoint", "porous2d", "heat1d"),
                     help="run only this measurement and print its JSON (for profiling)")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 1D heat and 2D porous-medium legs")
@@ -548,7 +548,7 @@ def main():
     torch.cuda.set_device(0)
     if args.only:
         legs = {"bruss-throughput": brusselator_throughput, "batched": batched_leg,
-                "adjoint": adjoint_leg, "porous2d": porous2d_leg}
+                "adjoint": adjoint_leg, "porous2d": porous2d_leg, "heat1d": heat1d_leg}
         print(json.dumps({args.only: legs[args.only](F, wl, torch)}), flush=True)
         return
     log("generating the 3D workload (n=%d)" % args.n)

@@ -510,6 +510,10 @@ extern "C" int frkc2_step(const frkc2_grid *g, double *w, const double *D, doubl
         const bool last_step = (step == nsteps - 1);
         const bool want_stats = stats && last_step;
         if (stage1d_lds_fits(kg) && !want_stats) {
+            // A linear operator keeps T, and so every stepsize, for the rest of
+            // the call: its remaining supersteps (all but a last one that
+            // reports statistics) run in one launch, the state staying in LDS.
+            const int run = nonlinear(kg) ? 1 : (stats ? nsteps - 1 : nsteps) - step;
             tau_host.resize(2 * (size_t)s);
             for (int l = 0; l < s; ++l) {
                 tau_host[2 * l] = Tn * are[l];
@@ -518,7 +522,8 @@ extern "C" int frkc2_step(const frkc2_grid *g, double *w, const double *D, doubl
             HIP_TRY(hipMemcpyAsync(tau_dev, tau_host.data(), sizeof(double) * 2 * s,
                                    hipMemcpyHostToDevice, st),
                     "stepsize upload");
-            HIP_TRY(launch_stage1d_lds(kg, w, w, D, tau_dev, s, 1, st), "1D stage launch");
+            HIP_TRY(launch_stage1d_lds(kg, w, w, D, tau_dev, s, run, st), "1D stage launch");
+            step += run - 1;
             continue;
         }
         const double *last_out = nullptr;

@@ -133,6 +133,44 @@ def test_rho_bound_matches_oracle(kind, n):
     assert got == stage.rho_bound(p, p.w0)
 
 
+@pytest.mark.parametrize("bc,op,adaptive", [(wl.BC_PERIODIC, wl.OP_LAPLACE, True),
+                                             (wl.BC_DIRICHLET0, wl.OP_VARCOEF, False),
+                                             (wl.BC_PERIODIC, wl.OP_POROUS2, True)])
+def test_1d_many_supersteps_with_stats(bc, op, adaptive):
+    """A linear 1D operator runs all supersteps but a statistics-reporting last one in one
+    LDS-resident launch (the porous one, whose T follows the state, one launch per superstep):
+    the state, T and the imaginary-part ratio of the last superstep against the oracle."""
+    n = 300
+    rng = np.random.default_rng(44)
+    D = wl.lognormal_D((n,), 1.0, rng) if op == wl.OP_VARCOEF else None
+    h = 1.0 / (n + (1 if bc == wl.BC_DIRICHLET0 else 0))
+    p = wl.Problem(1, (n, 1, 1), h, bc, op, 1.0, D)
+    p.w0 = wl.random_state(p.shape, 45, smooth=1.0)
+    if op == wl.OP_POROUS2:
+        p.w0 = 1.0 + 0.3 * p.w0
+    s, nsteps = 12, 7
+    c = frkc2_coeffs(s, 0.01)
+    if adaptive:
+        ref, Ts = stage.run(p, s, nsteps, cfl=0.5, coeffs=c)
+    else:
+        T = 0.5 * c.beta_bar / stage.rho_bound(p)
+        ref, Ts = stage.run(p, s, nsteps, T=T, coeffs=c)
+    w = dev(p.w0)
+    kw = dict(cfl=0.5) if adaptive else dict(T=T)
+    st = F.frkc2_step(p, w, dev(D) if D is not None else None, s=s, nsteps=nsteps, stats=True, **kw)
+    torch.cuda.synchronize()
+    assert st["T_last"] == Ts[-1]
+    assert np.array_equal(host(w), ref)
+    # ||Im W^L|| / ||W^L|| of the last superstep: roundoff for the linear operators, O(T^2)
+    # for the porous one; the sums are reduced in another order, hence the tolerance
+    prev, _ = (stage.run(p, s, nsteps - 1, cfl=0.5, coeffs=c) if adaptive
+               else stage.run(p, s, nsteps - 1, T=T, coeffs=c))
+    wr, wi = stage.superstep(p, prev, Ts[-1] * c.a_re, Ts[-1] * c.a_im, want_imag=True)
+    assert np.array_equal(wr.reshape(-1), ref.reshape(-1))
+    im_ref = float(np.sqrt(np.sum(wi * wi) / np.sum(wr * wr + wi * wi)))
+    assert abs(st["im_ratio"] - im_ref) <= 1e-10 * im_ref + 1e-300
+
+
 def test_heat1d_full_config():
     """1D heat, N = 1024, s = 16, 20 supersteps (LDS-resident kernel): oracle and Fourier solution."""
     p = wl.heat1d()
