@@ -282,9 +282,10 @@ int frkc2_reduce(int op, const double *x, const double *y, size_t n, double *res
  *                (t, T, s, err, accepted 1/0), the first trace_cap attempts
  *   stats        host or NULL
  * Synchronises st once per attempt (the accept decision is taken on the
- * host). 3D grids (full-width tiles) and the Brusselator fuse stages per HBM
- * pass as frkc2_step does (the embedded solution adds 16 B per point and
- * species and pass); other grids run one stage per pass. Results are identical, bit for bit, to the same
+ * host). 3D grids (full-width tiles), 2D grids (rows of 256, depth 2..4) and
+ * the Brusselator fuse stages per HBM pass as frkc2_step does (the embedded
+ * solution adds 16 B per point and species and pass); other depths, tile
+ * shapes and 1D grids run one stage per pass. Results are identical, bit for bit, to the same
  * procedure evaluated on the CPU in the library's arithmetic order. Errors:
  * FRKC2_EINVAL (arguments, checked before any HIP call), FRKC2_ENOMEM
  * (workspace), FRKC2_ENONFINITE (non-finite error estimate), FRKC2_ETIMEOUT,

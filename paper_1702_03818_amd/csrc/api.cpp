@@ -786,23 +786,22 @@ constexpr double kErrFloor = 1e-12;  // error estimates below this count as this
 
 // One superstep from the real state w that also carries the embedded
 // first-order solution; W^L (complex) and What^L are left in the workspace.
-// 3D grids fuse cfg.k stages per pass with the full-width tiles, the
-// Brusselator with its own tiles; other grids and tile shapes run one stage
-// per pass.
+// Fused passes of cfg.k stages where the tile has an embedded variant (3D
+// full-width tiles, the Brusselator, 2D rows of 256 with k <= 4); other grids
+// and tile shapes run one stage per pass.
 int run_superstep_emb(const KGrid &kg, const PassCfg &cfg, const double *w, const double *D,
                       double Tn, const double *are, const double *aim, int s,
                       double *const buf[2], double *const emb[2], const double **WL,
                       const double **EL, hipStream_t st)
 {
-    const bool bruss = kg.op == FRKC2_OP_BRUSS2;
-    const bool fused = (bruss || (kg.ndim == 3 && (cfg.tile == 3 || cfg.tile == 4))) &&
-                       cfg.k >= 2 && tblock_supported(kg, cfg.k);
+    const bool fused = cfg.k >= 2 && tblock_emb_supported(kg, cfg.k, cfg.tile);
     const int k = fused ? cfg.k : 1;
     int l = 0, pass = 0;
     const double *in = nullptr, *ein = nullptr;
     while (l < s) {
         int kk = (k >= 2 && s - l >= k) ? k : 1;
-        if (kk == 1 && k > 2 && s - l >= 2 && tblock_supported(kg, s - l)) kk = s - l;
+        if (kk == 1 && k > 2 && s - l >= 2 && tblock_emb_supported(kg, s - l, cfg.tile))
+            kk = s - l;
         PassArgs pa{};
         pa.k = kk;
         pa.zchunk = cfg.zchunk;
@@ -820,8 +819,7 @@ int run_superstep_emb(const KGrid &kg, const PassCfg &cfg, const double *w, cons
             pa.ti[i] = Tn * aim[l + i];
         }
         const int rc = (kk == 1) ? launch_pass(kg, pa, 1, st)
-                       : bruss   ? launch_bruss_tb(kg, pa, st)
-                                 : launch_tb3d(kg, pa, st);
+                                 : launch_tblock(kg, pa, cfg.tile, st);
         if (rc != 0) return rc;
         in = buf[pass & 1];
         ein = emb[pass & 1];

@@ -76,6 +76,9 @@ int launch_max_partials(double *partials, hipStream_t st);   // max of kReduceBl
 
 // Temporally blocked passes (tblock.hip): p.k stages in one HBM pass.
 bool tblock_supported(const KGrid &g, int k);
+// ... and with the embedded solution (p.emb_out): 3D full-width tiles
+// (launch_tb3d), the Brusselator, 2D rows of 256 with k = 2..4.
+bool tblock_emb_supported(const KGrid &g, int k, int shape);
 int launch_tblock(const KGrid &g, const PassArgs &p, int shape, hipStream_t st);
 // 3D passes with 64-column output tiles and halo wavefronts (tb3d.hip), k = 2, 3.
 int launch_tb3d(const KGrid &g, const PassArgs &p, hipStream_t st);

@@ -17,6 +17,8 @@ struct TbArgs {
     const double2 *in_c;
     double *out_re;
     double2 *out_c;
+    const double *emb_in;       // EMB: embedded first-order solution in (complex input) and out
+    double *emb_out;
     const double *D;
     int nx, ny, nz;
     int zchunk, ntx, nty;
@@ -51,11 +53,16 @@ struct TbLds {
 
 // NDIM 3: threads BXE x TY, each owning R rows (ty + r*TY) of an extended
 // tile BXE x (TY*R). NDIM 2: one row, TY = R = 1, "z" is the second grid
-// dimension.
-template <int OP, int BC, int NDIM, int BXE, int TY, int R, int K, bool IN_REAL, bool OUT_REAL>
+// dimension. EMB (2D only): each level also advances the embedded first-order
+// solution of the error estimate, What <- What + Re tau Re f(W) at the same
+// point (no neighbours), carried in a register ring beside the level windows
+// and written with the last level.
+template <int OP, int BC, int NDIM, int BXE, int TY, int R, int K, bool IN_REAL, bool OUT_REAL,
+          bool EMB = false>
 __device__ __forceinline__ void tb_tile(const TbArgs &a, int bx, int by, int bz, double2 *sLp,
                                         double *sDp)
 {
+    static_assert(!EMB || (NDIM == 2 && K > 1 && !OUT_REAL), "embedded variant: 2D rows, complex out");
     constexpr int BYE = TY * R;
     constexpr bool SKIP_ROWS = (BXE == 64);         // one extended row per wavefront
     constexpr int SX = BXE + 2;
@@ -106,6 +113,11 @@ __device__ __forceinline__ void tb_tile(const TbArgs &a, int bx, int by, int bz,
         const long long i = bc_index_nb<BC>(dm, x, gy, gz, g);
         return IN_REAL ? make_double2(a.in_re[i], 0.0) : a.in_c[i];
     };
+    auto LE = [&](int gy, int gz) {   // embedded solution in (EMB with complex input)
+        bool g;
+        const long long i = bc_index_nb<BC>(dm, x, gy, gz, g);
+        return (EMB && !IN_REAL) ? a.emb_in[i] : 0.0;
+    };
     auto LD = [&](int gy, int gz) {
         bool g;
         const long long i = bc_index_nb<BC>(dm, x, gy, gz, g);
@@ -130,6 +142,11 @@ __device__ __forceinline__ void tb_tile(const TbArgs &a, int bx, int by, int bz,
     // tiles skip levels per row and keep the shifting windows.
     constexpr bool RING = (NDIM == 2) && (K > 1);
     double2 WR[RING ? K - 1 : 1][RING ? NR : 1][R];
+    // EMB: embedded solution of level 0 (read beside W; the real input itself
+    // on a first pass) and of levels 1..K-1, in the same ring slots
+    constexpr bool ER0 = EMB && !IN_REAL;
+    double E0[ER0 ? NR : 1][R];
+    double ER[EMB ? K - 1 : 1][EMB ? NR : 1][R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int gy = (NDIM == 3) ? yr[r] : 0;
@@ -137,12 +154,18 @@ __device__ __forceinline__ void tb_tile(const TbArgs &a, int bx, int by, int bz,
         for (int q = 0; q < NR; ++q) {
             L0[q][r] = make_double2(0.0, 0.0);
             D0[q][r] = 0.0;
+            if (ER0) E0[q][r] = 0.0;
+            if (EMB) {
+#pragma unroll
+                for (int m = 0; m + 1 < K; ++m) ER[m][q][r] = 0.0;
+            }
         }
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             const int tq = min(t_begin + q, t_end - 1);
             L0[q][r] = LW(gy, tq);
             D0[q][r] = LD(gy, tq);
+            if (ER0) E0[q][r] = LE(gy, tq);
         }
 #pragma unroll
         for (int m = 0; m + 1 < K; ++m) wm[m][r] = wc[m][r] = wp[m][r] = make_double2(0.0, 0.0);
@@ -168,6 +191,7 @@ __device__ __forceinline__ void tb_tile(const TbArgs &a, int bx, int by, int bz,
             const int tn = min(t + PF, t_end - 1);  // nothing past the last plane is used
             L0[rs(PF)][r] = LW(gy, tn);
             D0[rs(PF)][r] = LD(gy, tn);
+            if (ER0) E0[rs(PF)][r] = LE(gy, tn);
         }
         // plane t of level 0 is consumed from here on: zero its Dirichlet
         // ghosts once, in its ring slot
@@ -238,7 +262,15 @@ __device__ __forceinline__ void tb_tile(const TbArgs &a, int bx, int by, int bz,
                 face<OP>(acc_r, acc_i, c, zp, dc, dzp, false, qr_c, qi_c, a.fc[5]);
                 double2 v = euler(c, acc_r, acc_i, a.inv_h2, a.tr[m - 1], a.ti[m - 1]);
                 v = keep(v, col_ghost[r] || pghost);
+                double eh = 0.0;
+                if (EMB) {
+                    // level m-1's embedded value at this point: plane t-m
+                    const double base = (m == 1) ? (IN_REAL ? c.x : E0[ER0 ? rs(-1) : 0][r])
+                                                 : ER[(m - 2) % (K - 1)][rs(-1)][r];
+                    eh = fma(a.tr[m - 1], acc_r * a.inv_h2, base);
+                }
                 if (m < K) {
+                    if (EMB) ER[(m - 1) % (K - 1)][rs(0)][r] = eh;
                     if (RING) {
                         WR[(m - 1) % (K - 1)][rs(0)][r] = v;
                     } else {
@@ -251,6 +283,7 @@ __device__ __forceinline__ void tb_tile(const TbArgs &a, int bx, int by, int bz,
                     const long long i = x + (long long)a.nx * (gy + (long long)a.ny * p);
                     if (OUT_REAL) a.out_re[i] = v.x;
                     else a.out_c[i] = v;
+                    if (EMB) a.emb_out[i] = eh;
                 }
             }
         }

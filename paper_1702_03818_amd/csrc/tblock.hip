@@ -40,7 +40,8 @@ namespace {
 
 using namespace dev;
 
-template <int OP, int BC, int NDIM, int BXE, int TY, int R, int K, bool IN_REAL, bool OUT_REAL>
+template <int OP, int BC, int NDIM, int BXE, int TY, int R, int K, bool IN_REAL, bool OUT_REAL,
+          bool EMB = false>
 __global__ __launch_bounds__(BXE *TY) void tb_stage(TbArgs a)
 {
     using S = TbLds<OP, NDIM, BXE, TY, R, K>;
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(BXE *TY) void tb_stage(TbArgs a)
     lb /= a.ntx;
     const int by = lb % a.nty;
     const int bz = lb / a.nty;
-    tb_tile<OP, BC, NDIM, BXE, TY, R, K, IN_REAL, OUT_REAL>(a, bx, by, bz, sL, sD);
+    tb_tile<OP, BC, NDIM, BXE, TY, R, K, IN_REAL, OUT_REAL, EMB>(a, bx, by, bz, sL, sD);
 }
 
 int choose_zchunk(long long tiles, int nz, int target_blocks)
@@ -62,7 +63,7 @@ int choose_zchunk(long long tiles, int nz, int target_blocks)
 }
 
 template <int OP, int BC, int NDIM, int BXE, int TY, int R, int K>
-int launch_k(const TbArgs &a0, bool ir, bool orl, hipStream_t st)
+int launch_k(const TbArgs &a0, bool ir, bool orl, bool emb, hipStream_t st)
 {
     TbArgs a = a0;
     constexpr int BXO = BXE - 2 * K;
@@ -75,6 +76,18 @@ int launch_k(const TbArgs &a0, bool ir, bool orl, hipStream_t st)
     const long long nblk = tiles * ((a.nz + a.zchunk - 1) / a.zchunk);
     if (nblk > 0x7fffffffLL) return (int)hipErrorInvalidValue;
     dim3 grid((unsigned)nblk), block(BXE * TY);
+    if (emb) {   // 2D rows of 256, K <= 4 only (tblock_emb_supported)
+        if constexpr (NDIM == 2 && BXE == 256 && K <= 4) {
+            if (ir)
+                hipLaunchKernelGGL((tb_stage<OP, BC, NDIM, BXE, TY, R, K, true, false, true>), grid,
+                                   block, 0, st, a);
+            else
+                hipLaunchKernelGGL((tb_stage<OP, BC, NDIM, BXE, TY, R, K, false, false, true>), grid,
+                                   block, 0, st, a);
+            return (int)hipGetLastError();
+        }
+        return (int)hipErrorInvalidValue;
+    }
     if (ir && orl)
         hipLaunchKernelGGL((tb_stage<OP, BC, NDIM, BXE, TY, R, K, true, true>), grid, block, 0, st, a);
     else if (ir)
@@ -92,41 +105,44 @@ int launch_k(const TbArgs &a0, bool ir, bool orl, hipStream_t st)
 //  3D shape 2: 64 x 32 (K = 2) or 64 x 24 (K = 3) with 512 threads
 //  2D shape 0: rows of 256 extended columns; shape 1: rows of 512.
 template <int OP, int BC, int K>
-int launch_shape(int ndim, int shape, const TbArgs &a, bool ir, bool orl, hipStream_t st)
+int launch_shape(int ndim, int shape, const TbArgs &a, bool ir, bool orl, bool emb, hipStream_t st)
 {
     if (ndim == 3) {
+        if (emb) return (int)hipErrorInvalidValue;
         if constexpr (K == 2) {
-            if (shape == 1) return launch_k<OP, BC, 3, 64, 16, 2, K>(a, ir, orl, st);
-            if (shape == 2) return launch_k<OP, BC, 3, 64, 8, 4, K>(a, ir, orl, st);
+            if (shape == 1) return launch_k<OP, BC, 3, 64, 16, 2, K>(a, ir, orl, false, st);
+            if (shape == 2) return launch_k<OP, BC, 3, 64, 8, 4, K>(a, ir, orl, false, st);
         }
         if constexpr (K == 3) {
-            if (shape == 2) return launch_k<OP, BC, 3, 64, 8, 3, K>(a, ir, orl, st);
+            if (shape == 2) return launch_k<OP, BC, 3, 64, 8, 3, K>(a, ir, orl, false, st);
         }
-        if constexpr (K <= 3) return launch_k<OP, BC, 3, 64, 16, 1, K>(a, ir, orl, st);
+        if constexpr (K <= 3) return launch_k<OP, BC, 3, 64, 16, 1, K>(a, ir, orl, false, st);
         else return (int)hipErrorInvalidValue;
     }
-    if (shape == 1) return launch_k<OP, BC, 2, 512, 1, 1, K>(a, ir, orl, st);
-    return launch_k<OP, BC, 2, 256, 1, 1, K>(a, ir, orl, st);
+    if (shape == 1) return launch_k<OP, BC, 2, 512, 1, 1, K>(a, ir, orl, emb, st);
+    return launch_k<OP, BC, 2, 256, 1, 1, K>(a, ir, orl, emb, st);
 }
 
 template <int OP, int BC>
-int launch_kk(int ndim, int k, int shape, const TbArgs &a, bool ir, bool orl, hipStream_t st)
+int launch_kk(int ndim, int k, int shape, const TbArgs &a, bool ir, bool orl, bool emb,
+              hipStream_t st)
 {
     switch (k) {
-    case 2: return launch_shape<OP, BC, 2>(ndim, shape, a, ir, orl, st);
-    case 3: return launch_shape<OP, BC, 3>(ndim, shape, a, ir, orl, st);
-    case 4: return launch_shape<OP, BC, 4>(ndim, shape, a, ir, orl, st);
-    case 6: return launch_shape<OP, BC, 6>(ndim, shape, a, ir, orl, st);
-    case 8: return launch_shape<OP, BC, 8>(ndim, shape, a, ir, orl, st);
+    case 2: return launch_shape<OP, BC, 2>(ndim, shape, a, ir, orl, emb, st);
+    case 3: return launch_shape<OP, BC, 3>(ndim, shape, a, ir, orl, emb, st);
+    case 4: return launch_shape<OP, BC, 4>(ndim, shape, a, ir, orl, emb, st);
+    case 6: return launch_shape<OP, BC, 6>(ndim, shape, a, ir, orl, emb, st);
+    case 8: return launch_shape<OP, BC, 8>(ndim, shape, a, ir, orl, emb, st);
     default: return (int)hipErrorInvalidValue;
     }
 }
 
 template <int OP>
-int launch_bc(const KGrid &g, int k, int shape, const TbArgs &a, bool ir, bool orl, hipStream_t st)
+int launch_bc(const KGrid &g, int k, int shape, const TbArgs &a, bool ir, bool orl, bool emb,
+              hipStream_t st)
 {
-    if (g.bc == PER) return launch_kk<OP, PER>(g.ndim, k, shape, a, ir, orl, st);
-    return launch_kk<OP, DIR>(g.ndim, k, shape, a, ir, orl, st);
+    if (g.bc == PER) return launch_kk<OP, PER>(g.ndim, k, shape, a, ir, orl, emb, st);
+    return launch_kk<OP, DIR>(g.ndim, k, shape, a, ir, orl, emb, st);
 }
 
 }  // namespace
@@ -137,6 +153,13 @@ bool tblock_supported(const KGrid &g, int k)
     if (g.ndim == 3) return k == 2 || k == 3;
     if (g.ndim == 2) return k == 2 || k == 3 || k == 4 || k == 6 || k == 8;
     return false;
+}
+
+bool tblock_emb_supported(const KGrid &g, int k, int shape)
+{
+    if (g.op == FRKC2_OP_BRUSS2) return tblock_supported(g, k);
+    if (g.ndim == 3) return (shape == 3 || shape == 4) && tblock_supported(g, k);
+    return g.ndim == 2 && shape == 0 && k >= 2 && k <= 4;
 }
 
 int launch_tblock(const KGrid &g, const PassArgs &p, int shape, hipStream_t st)
@@ -153,6 +176,8 @@ int launch_tblock(const KGrid &g, const PassArgs &p, int shape, hipStream_t st)
     a.in_c = reinterpret_cast<const double2 *>(p.in_c);
     a.out_re = p.out_re;
     a.out_c = reinterpret_cast<double2 *>(p.out_c);
+    a.emb_in = p.emb_in;
+    a.emb_out = p.emb_out;
     a.D = p.D;
     a.nx = g.nx;
     a.ny = g.ny;
@@ -165,11 +190,13 @@ int launch_tblock(const KGrid &g, const PassArgs &p, int shape, hipStream_t st)
         a.ti[i] = p.ti[i];
     }
     for (int k = 0; k < 6; ++k) a.fc[k] = g.fc[k];
-    const bool ir = p.in_re != nullptr, orl = p.out_re != nullptr;
-    if (g.op == LAP) return launch_bc<LAP>(g, p.k, shape, a, ir, orl, st);
-    if (g.op == ADV) return launch_bc<ADV>(g, p.k, shape, a, ir, orl, st);
-    if (g.op == VAR) return launch_bc<VAR>(g, p.k, shape, a, ir, orl, st);
-    return launch_bc<POR>(g, p.k, shape, a, ir, orl, st);
+    const bool ir = p.in_re != nullptr, orl = p.out_re != nullptr, emb = p.emb_out != nullptr;
+    if (emb && (orl || !tblock_emb_supported(g, p.k, shape) || (!ir && !p.emb_in)))
+        return (int)hipErrorInvalidValue;
+    if (g.op == LAP) return launch_bc<LAP>(g, p.k, shape, a, ir, orl, emb, st);
+    if (g.op == ADV) return launch_bc<ADV>(g, p.k, shape, a, ir, orl, emb, st);
+    if (g.op == VAR) return launch_bc<VAR>(g, p.k, shape, a, ir, orl, emb, st);
+    return launch_bc<POR>(g, p.k, shape, a, ir, orl, emb, st);
 }
 
 }  // namespace frkc2

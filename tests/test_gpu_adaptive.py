@@ -1,6 +1,6 @@
 """GPU parity of the error-controlled integration (Sec. 3): every attempt (start time, T, s,
 error estimate, accept flag), the proposed next T and the final state equal the oracle's
-bit for bit."""
+bit for bit, with the embedded solution in one-stage passes and in fused 3D and 2D passes."""
 import numpy as np
 import pytest
 
@@ -82,6 +82,33 @@ def test_integrate_launch_configurations(k, tile, zchunk):
         p = problem("3d-lap-per", (65, 5, 12))
         rho = stage.rho_bound(p, p.w0)
         run_both(p, 1500.0 / rho, 800.0 / rho, 1e-3)
+    finally:
+        F.frkc2_set_option(F.OPT_TBLOCK, 0)
+        F.frkc2_set_option(F.OPT_TILE, 0)
+        F.frkc2_set_option(F.OPT_ZCHUNK, 0)
+
+
+@pytest.mark.parametrize("k,tile,zchunk", [(2, 1, 0), (3, 1, 0), (4, 1, 0), (4, 1, 9), (4, 2, 0),
+                                          (6, 1, 0), (1, 0, 0)])
+def test_integrate_2d_launch_configurations(k, tile, zchunk):
+    """The embedded solution in fused 2D rows of 256 (K = 2..4, a forced chunk length); rows
+    of 512 and K = 6 fall back to one-stage embedded passes. Every 2D operator, both
+    boundaries, ragged sizes."""
+    F.frkc2_set_option(F.OPT_TBLOCK, k)
+    F.frkc2_set_option(F.OPT_TILE, tile)
+    F.frkc2_set_option(F.OPT_ZCHUNK, zchunk)
+    try:
+        # (kind, grid, t_span and first T in units of 1/rho)
+        for kind, n, span, T0 in (("2d-por-per", (64, 64, 1), 1500.0, 800.0),
+                                  ("2d-var-dir", (300, 37, 1), 1500.0, 800.0),
+                                  ("2d-lap-per", (517, 23, 1), 1500.0, 800.0),
+                                  ("2d-por-dir", (41, 90, 1), 300.0, 50.0),
+                                  ("2d-var-per", (3, 250, 1), 1500.0, 800.0)):
+            p = problem(kind, n)
+            if p.op == wl.OP_POROUS2:
+                p.w0 = 1.0 + 0.4 * p.w0 / np.max(np.abs(p.w0))
+            rho = stage.rho_bound(p, p.w0)
+            run_both(p, span / rho, T0 / rho, 1e-3)
     finally:
         F.frkc2_set_option(F.OPT_TBLOCK, 0)
         F.frkc2_set_option(F.OPT_TILE, 0)
