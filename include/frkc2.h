@@ -284,8 +284,9 @@ int frkc2_reduce(int op, const double *x, const double *y, size_t n, double *res
  * Synchronises st once per attempt (the accept decision is taken on the
  * host). 3D grids (full-width tiles), 2D grids (rows of 256, depth 2..4) and
  * the Brusselator fuse stages per HBM pass as frkc2_step does (the embedded
- * solution adds 16 B per point and species and pass); other depths, tile
- * shapes and 1D grids run one stage per pass. Results are identical, bit for bit, to the same
+ * solution adds 16 B per point and species and pass); 1D grids of up to 4096
+ * points run each attempt's superstep in one LDS-resident launch; other
+ * depths, tile shapes and longer 1D grids run one stage per pass. Results are identical, bit for bit, to the same
  * procedure evaluated on the CPU in the library's arithmetic order. Errors:
  * FRKC2_EINVAL (arguments, checked before any HIP call), FRKC2_ENOMEM
  * (workspace), FRKC2_ENONFINITE (non-finite error estimate), FRKC2_ETIMEOUT,

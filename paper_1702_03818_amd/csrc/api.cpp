@@ -792,8 +792,26 @@ constexpr double kErrFloor = 1e-12;  // error estimates below this count as this
 int run_superstep_emb(const KGrid &kg, const PassCfg &cfg, const double *w, const double *D,
                       double Tn, const double *are, const double *aim, int s,
                       double *const buf[2], double *const emb[2], const double **WL,
-                      const double **EL, hipStream_t st)
+                      const double **EL, double *tau_dev, hipStream_t st)
 {
+    if (stage1d_lds_fits(kg)) {
+        // a 1D grid that fits in LDS: the whole superstep in one launch, the
+        // stepsizes from a device table (tau_dev, 2 s doubles)
+        static thread_local std::vector<double> tau_host;
+        tau_host.resize(2 * (size_t)s);
+        for (int l = 0; l < s; ++l) {
+            tau_host[2 * l] = Tn * are[l];
+            tau_host[2 * l + 1] = Tn * aim[l];
+        }
+        int rc = (int)hipMemcpyAsync(tau_dev, tau_host.data(), sizeof(double) * 2 * s,
+                                     hipMemcpyHostToDevice, st);
+        if (rc != 0) return rc;
+        rc = launch_stage1d_lds_emb(kg, w, buf[0], emb[0], D, tau_dev, s, st);
+        if (rc != 0) return rc;
+        *WL = buf[0];
+        *EL = emb[0];
+        return 0;
+    }
     const bool fused = cfg.k >= 2 && tblock_emb_supported(kg, cfg.k, cfg.tile);
     const int k = fused ? cfg.k : 1;
     int l = 0, pass = 0;
@@ -1012,7 +1030,8 @@ extern "C" int frkc2_integrate(const frkc2_grid *g, double *w, const double *D, 
         stats, [&](double *rho) { return rho_bound_impl(kg, w, D, partials, rho, st); },
         [&](double Tn, int s, const double *are, const double *aim, const double **WL,
             const double **EL) -> int {
-            HIP_TRY(run_superstep_emb(kg, cfg, w, D, Tn, are, aim, s, buf, emb, WL, EL, st),
+            HIP_TRY(run_superstep_emb(kg, cfg, w, D, Tn, are, aim, s, buf, emb, WL, EL,
+                                      partials + 2 * (kReduceBlocks + 8), st),
                     "embedded superstep launch");
             return FRKC2_OK;
         });

@@ -58,6 +58,9 @@ int launch_pass(const KGrid &g, const PassArgs &a, int tblock_hint, hipStream_t 
 int launch_stage1d_lds(const KGrid &g, const double *w_in, double *w_out, const double *D,
                        const double *tau, int s, int nsteps, hipStream_t st);
 bool stage1d_lds_fits(const KGrid &g);
+// One superstep with the embedded solution: W^L (complex) to out_c, What^L to emb_out.
+int launch_stage1d_lds_emb(const KGrid &g, const double *w_in, double *out_c, double *emb_out,
+                           const double *D, const double *tau, int s, hipStream_t st);
 int launch_finalize(const KGrid &g, const double *in_c, double *out_re, double *partials,
                     hipStream_t st);
 int launch_real_to_complex(long long n, const double *in, double *out_c, hipStream_t st);

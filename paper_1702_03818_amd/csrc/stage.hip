@@ -55,11 +55,12 @@ constexpr int k1dThreads = 1024;
 constexpr int k1dMaxPts = 4096;
 constexpr int k1dPerThread = k1dMaxPts / k1dThreads;
 
-template <int OP, int BC>
+template <int OP, int BC, bool EMB>
 __global__ __launch_bounds__(k1dThreads) void stage1d_lds(const double *w_in, double *w_out,
                                                           const double *D, const double2 *tau,
                                                           int n, int s, int nsteps,
-                                                          double inv_h2, double fcl, double fcr)
+                                                          double inv_h2, double fcl, double fcr,
+                                                          double2 *out_c, double *emb_out)
 {
     extern __shared__ double2 s1[];
     double2 *sW = s1;
@@ -69,11 +70,22 @@ __global__ __launch_bounds__(k1dThreads) void stage1d_lds(const double *w_in, do
         sW[i] = make_double2(w_in[i], 0.0);
         if (OP == VAR) sD[i] = 0.5 * D[i];   // D/2, as the face rule takes it
     }
+    // EMB (one superstep): the embedded first-order solution of each thread's
+    // points, What <- What + Re tau Re f(W) per stage, in registers; W^L is
+    // then written complex to out_c and What^L to emb_out.
+    double ev[EMB ? k1dPerThread : 1];
+    if (EMB) {
+#pragma unroll
+        for (int p = 0; p < k1dPerThread; ++p) {
+            const int i = tid + p * k1dThreads;
+            ev[p] = (i < n) ? w_in[i] : 0.0;
+        }
+    }
     __syncthreads();
     for (int step = 0; step < nsteps; ++step) {
         for (int l = 0; l < s; ++l) {
             const double tr = tau[l].x, ti = tau[l].y;
-            const bool last = (l == s - 1);
+            const bool last = (l == s - 1) && !EMB;
             double2 nv[k1dPerThread];
 #pragma unroll
             for (int p = 0; p < k1dPerThread; ++p) {
@@ -97,6 +109,7 @@ __global__ __launch_bounds__(k1dThreads) void stage1d_lds(const double *w_in, do
                 face<OP>(acc_r, acc_i, c, wr, dc, (OP == VAR) ? sD[ir] : 0.0, gr, qr_c, qi_c,
                          fcr);
                 const double2 u = euler(c, acc_r, acc_i, inv_h2, tr, ti);
+                if (EMB) ev[p] = fma(tr, acc_r * inv_h2, ev[p]);
                 // a superstep keeps Re W^L; the next one starts from a real state
                 nv[p] = make_double2(u.x, last ? 0.0 : u.y);
             }
@@ -110,7 +123,18 @@ __global__ __launch_bounds__(k1dThreads) void stage1d_lds(const double *w_in, do
             __syncthreads();
         }
     }
-    for (int i = tid; i < n; i += k1dThreads) w_out[i] = sW[i].x;
+    if (EMB) {
+#pragma unroll
+        for (int p = 0; p < k1dPerThread; ++p) {
+            const int i = tid + p * k1dThreads;
+            if (i < n) {
+                out_c[i] = sW[i];
+                emb_out[i] = ev[p];
+            }
+        }
+    } else {
+        for (int i = tid; i < n; i += k1dThreads) w_out[i] = sW[i].x;
+    }
 }
 
 // w = Re W and per-block partial sums of (Im W)^2 and |W|^2.
@@ -276,37 +300,62 @@ int launch_pass(const KGrid &g, const PassArgs &a, int /*tblock_hint*/, hipStrea
 bool stage1d_lds_fits(const KGrid &g) { return g.ndim == 1 && g.nx <= k1dMaxPts; }
 
 namespace {
-template <int OP, int BC>
-int launch_1d_t(const KGrid &g, const double *w_in, double *w_out, const double *D,
-                const double *tau, int s, int nsteps, hipStream_t st)
+struct Launch1d {
+    const double *w_in;
+    double *w_out;              // Re W^L (nsteps supersteps), or
+    double2 *out_c;             // ... with emb_out: W^L complex and What^L (one superstep)
+    double *emb_out;
+    const double *D;
+    const double *tau;
+    int s, nsteps;
+};
+
+template <int OP, int BC, bool EMB>
+int launch_1d_t(const KGrid &g, const Launch1d &q, hipStream_t st)
 {
     const size_t shm = (size_t)g.nx * (sizeof(double2) + sizeof(double));
-    auto kern = stage1d_lds<OP, BC>;
+    auto kern = stage1d_lds<OP, BC, EMB>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return (int)e;
-    hipLaunchKernelGGL(kern, dim3(1), dim3(k1dThreads), shm, st, w_in, w_out, D,
-                       reinterpret_cast<const double2 *>(tau), g.nx, s, nsteps, g.inv_h2,
-                       g.fc[0], g.fc[1]);
+    hipLaunchKernelGGL(kern, dim3(1), dim3(k1dThreads), shm, st, q.w_in, q.w_out, q.D,
+                       reinterpret_cast<const double2 *>(q.tau), g.nx, q.s, q.nsteps, g.inv_h2,
+                       g.fc[0], g.fc[1], q.out_c, q.emb_out);
     return (int)hipGetLastError();
 }
 template <int OP>
-int launch_1d_bc(const KGrid &g, const double *w_in, double *w_out, const double *D,
-                 const double *tau, int s, int nsteps, hipStream_t st)
+int launch_1d_bc(const KGrid &g, const Launch1d &q, hipStream_t st)
 {
-    if (g.bc == PER) return launch_1d_t<OP, PER>(g, w_in, w_out, D, tau, s, nsteps, st);
-    return launch_1d_t<OP, DIR>(g, w_in, w_out, D, tau, s, nsteps, st);
+    if (q.emb_out) {
+        if (g.bc == PER) return launch_1d_t<OP, PER, true>(g, q, st);
+        return launch_1d_t<OP, DIR, true>(g, q, st);
+    }
+    if (g.bc == PER) return launch_1d_t<OP, PER, false>(g, q, st);
+    return launch_1d_t<OP, DIR, false>(g, q, st);
+}
+int launch_1d(const KGrid &g, const Launch1d &q, hipStream_t st)
+{
+    if (!stage1d_lds_fits(g)) return (int)hipErrorInvalidValue;
+    if (g.op == LAP) return launch_1d_bc<LAP>(g, q, st);
+    if (g.op == ADV) return launch_1d_bc<ADV>(g, q, st);
+    if (g.op == VAR) return launch_1d_bc<VAR>(g, q, st);
+    return launch_1d_bc<POR>(g, q, st);
 }
 }  // namespace
 
 int launch_stage1d_lds(const KGrid &g, const double *w_in, double *w_out, const double *D,
                        const double *tau, int s, int nsteps, hipStream_t st)
 {
-    if (!stage1d_lds_fits(g)) return (int)hipErrorInvalidValue;
-    if (g.op == LAP) return launch_1d_bc<LAP>(g, w_in, w_out, D, tau, s, nsteps, st);
-    if (g.op == ADV) return launch_1d_bc<ADV>(g, w_in, w_out, D, tau, s, nsteps, st);
-    if (g.op == VAR) return launch_1d_bc<VAR>(g, w_in, w_out, D, tau, s, nsteps, st);
-    return launch_1d_bc<POR>(g, w_in, w_out, D, tau, s, nsteps, st);
+    return launch_1d(g, Launch1d{w_in, w_out, nullptr, nullptr, D, tau, s, nsteps}, st);
+}
+
+int launch_stage1d_lds_emb(const KGrid &g, const double *w_in, double *out_c, double *emb_out,
+                           const double *D, const double *tau, int s, hipStream_t st)
+{
+    if (!out_c || !emb_out) return (int)hipErrorInvalidValue;
+    return launch_1d(g, Launch1d{w_in, nullptr, reinterpret_cast<double2 *>(out_c), emb_out, D,
+                                 tau, s, 1},
+                     st);
 }
 
 int launch_finalize(const KGrid &g, const double *in_c, double *out_re, double *partials,

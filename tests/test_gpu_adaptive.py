@@ -113,3 +113,16 @@ def test_integrate_2d_launch_configurations(k, tile, zchunk):
         F.frkc2_set_option(F.OPT_TBLOCK, 0)
         F.frkc2_set_option(F.OPT_TILE, 0)
         F.frkc2_set_option(F.OPT_ZCHUNK, 0)
+
+
+@pytest.mark.parametrize("kind,n", [("1d-lap-per", (4096, 1, 1)), ("1d-var-dir", (777, 1, 1)),
+                                    ("1d-por-per", (300, 1, 1)), ("1d-lap-per", (1, 1, 1)),
+                                    ("1d-var-dir", (5000, 1, 1))])
+def test_integrate_1d(kind, n):
+    """1D grids that fit in LDS run each attempt's superstep, embedded solution included, in
+    one launch; a grid of 5000 points runs one pass per stage. Same attempts and state."""
+    p = problem(kind, n)
+    if p.op == wl.OP_POROUS2:
+        p.w0 = 1.0 + 0.4 * p.w0 / np.max(np.abs(p.w0))
+    rho = stage.rho_bound(p, p.w0)
+    run_both(p, 1500.0 / rho, 800.0 / rho, 1e-3)
