@@ -120,11 +120,11 @@ __global__ __launch_bounds__(kBBX *kBBY) void bruss_stage(BrussArgs a)
 // through all K stages: x neighbours come from the adjacent lanes (DPP
 // wavefront shifts), y neighbours from the thread's own rows, except the two
 // rows beyond its strip, which the wavefronts above and below publish in LDS
-// once per stage (two slots by stage parity, one barrier per stage). Every
-// point of the tile is updated at every stage; after stage m only the points
-// at least m cells inside the tile hold stage m values (lane 0, lane 63 and the
-// tile's outer rows take shifted-in or repeated values), so the centre is
-// exact after K stages. bruss_point() does the arithmetic, so the result
+// once per stage (two slots by stage parity, one barrier per stage). Stage m
+// updates every column of the rows m .. NW R - 1 - m (rows outside are left as
+// they are; the test is uniform over a wavefront); only the points at least m
+// cells inside the tile then hold stage m values (lanes 0 and 63 take
+// shifted-in values), so the centre is exact after K stages. bruss_point() does the arithmetic, so the result
 // equals K single-stage passes bit for bit. With EMB each thread also carries
 // the embedded first-order solution of its points (real, advanced by Re tau
 // Re f per stage as in bruss_stage; it needs no neighbours).
