@@ -400,7 +400,7 @@ int frkc2_autotune(const frkc2_grid *g, const double *w, const double *D, int s,
  * frkc2_set_option -- tuning knobs (process-wide, not thread-safe to change
  * while other threads call the library):
  *   FRKC2_OPT_TBLOCK  stages fused per HBM pass of frkc2_step: 1, or 2 and 3
- *                     (3D), 2, 3, 4, 6 and 8 (2D), 2, 3 and 4 (BRUSS2: 64x32
+ *                     (3D), 2, 3, 4, 6 and 8 (2D), 2, 3 and 4 (BRUSS2: 64x40
  *                     tiles of both species, its own shape, TILE and ZCHUNK
  *                     do not apply); an unsupported depth runs one stage per
  *                     pass; 0 = automatic (the entry frkc2_autotune stored for

@@ -277,10 +277,10 @@ __global__ __launch_bounds__(256) void bruss_react_max(const double *s, long lon
     }
 }
 
-// 4 wavefronts of 8 rows: 64 x 32 tiles, about 130 VGPRs, three workgroups
-// per CU (8 wavefronts x 8 rows, 16 x 4 and a 128-VGPR cap measured no
-// faster at 2048^2).
-constexpr int kTbWaves = 4, kTbRows = 8;
+// 4 wavefronts of 10 rows: 64 x 40 tiles, about 150 VGPRs, three workgroups
+// per CU (8 and 12 rows, 8 wavefronts x 8 rows, 16 x 4 and a 128-VGPR cap
+// measured 2-20 % slower at 2048^2).
+constexpr int kTbWaves = 4, kTbRows = 10;
 
 template <int K>
 int launch_bruss_tb_k(const BrussTbArgs &a, unsigned nblk, bool ir, bool orl, hipStream_t st)
