@@ -171,6 +171,37 @@ def test_1d_many_supersteps_with_stats(bc, op, adaptive):
     assert abs(st["im_ratio"] - im_ref) <= 1e-10 * im_ref + 1e-300
 
 
+@pytest.mark.parametrize("kind,n,s,k", [("3d-var-dir", (40, 23, 17), 514, 0),
+                                        ("3d-lap-per", (33, 9, 20), 512, 3),
+                                        ("3d-var-dir", (40, 23, 17), 2, 0),
+                                        ("2d-por-per", (130, 70, 1), 514, 0),
+                                        ("2d-var-dir", (200, 31, 1), 512, 3),
+                                        ("1d-var-dir", (1000, 1, 1), 514, 0)])
+def test_stage_count_limits(kind, n, s, k):
+    """The smallest and largest stage counts (s = 2, 512, 514; stepsizes with the shrink
+    count the ordering needs there), default and forced fused depths, one superstep at
+    T = 0.9 betabar / rho (the porous medium at 0.5: its nonlinearity diverges at 0.9 and
+    s = 514, in the oracle too), against the oracle bit for bit."""
+    p = problem(kind, n)
+    cfl = 0.9
+    if p.op == wl.OP_POROUS2:
+        p.w0 = 1.0 + 0.4 * p.w0 / np.max(np.abs(p.w0))
+        cfl = 0.5
+    c = frkc2_coeffs(s, 0.01)
+    T = cfl * c.beta_bar / stage.rho_bound(p, p.w0)
+    ref, _ = stage.run(p, s, 1, T=T, coeffs=c)
+    assert np.isfinite(ref).all()
+    F.frkc2_set_option(F.OPT_TBLOCK, k)
+    try:
+        w = dev(p.w0)
+        F.frkc2_step(p, w, dev(p.D) if p.D is not None else None, T=T, s=s, nsteps=1)
+        torch.cuda.synchronize()
+    finally:
+        F.frkc2_set_option(F.OPT_TBLOCK, 0)
+    got = host(w)
+    assert np.array_equal(got, ref), "%d values differ" % int(np.sum(got != ref))
+
+
 def test_heat1d_full_config():
     """1D heat, N = 1024, s = 16, 20 supersteps (LDS-resident kernel): oracle and Fourier solution."""
     p = wl.heat1d()
