@@ -72,3 +72,39 @@ def test_random_batch_matches_oracle(seed, count):
                     rep, j, p.n, s, int(np.sum(got != cur[j])))
     finally:
         F.frkc2_batched_release()
+
+
+def test_batch_stage_count_limits():
+    """A batch mixing the smallest and largest stage counts (s = 2, 512, 514) over 2D and 3D
+    problems, three replays, each problem against the oracle bit for bit."""
+    rng = np.random.default_rng(77)
+    probs = []
+    for i, (ndim, n, s) in enumerate([(3, (37, 11, 9), 514), (3, (20, 30, 5), 2),
+                                      (2, (150, 1, 40), 512), (2, (33, 1, 7), 514),
+                                      (3, (9, 9, 30), 512), (2, (64, 1, 64), 2)]):
+        bc = i % 2
+        shape = n[::-1] if ndim == 3 else (n[2], n[0])
+        D = wl.lognormal_D(shape, 2.0, rng)
+        h = 1.0 / (max(n) + (1 if bc == wl.BC_DIRICHLET0 else 0))
+        grid_n = n if ndim == 3 else (n[0], n[2], 1)
+        p = wl.Problem(ndim, grid_n, h, bc, wl.OP_VARCOEF, 1.0, D)
+        p.w0 = wl.random_state(p.shape, 500 + i, smooth=1.0)
+        c = frkc2_coeffs(s, 0.01)
+        T = 0.9 * c.beta_bar / stage.rho_bound(p)
+        probs.append((p, s, T, c))
+    ws = [dev(p.w0) for p, _, _, _ in probs]
+    Ds = [dev(p.D) for p, _, _, _ in probs]
+    args = F.BatchedArgs([p for p, _, _, _ in probs], ws, Ds, [T for _, _, T, _ in probs],
+                         [s for _, s, _, _ in probs])
+    cur = [p.w0.reshape(-1).copy() for p, _, _, _ in probs]
+    try:
+        for rep in range(3):
+            F.frkc2_step_batched(args)
+            torch.cuda.synchronize()
+            assert F.frkc2_batched_status() == 0
+            for j, ((p, s, T, c), w) in enumerate(zip(probs, ws)):
+                cur[j] = stage.superstep(p, cur[j], T * c.a_re, T * c.a_im).reshape(-1)
+                got = w.cpu().numpy()
+                assert np.array_equal(got, cur[j]), "replay %d problem %d s=%d" % (rep, j, s)
+    finally:
+        F.frkc2_batched_release()
