@@ -44,7 +44,7 @@ def _prob(kind):
 
 
 @pytest.mark.parametrize("kind", ["3d-var-dir", "3d-var-per", "2d-var-dir", "3d-lap-dir"])
-@pytest.mark.parametrize("s", [2, 6, 8, 16, 64])   # 3D: 3-stage forward passes + 0..2 single
+@pytest.mark.parametrize("s", [2, 6, 8, 16, 64, 512, 514])   # 3D: 3-stage forward passes + 0..2 single
 def test_adjoint_matches_oracle(kind, s):
     p = _prob(kind)
     c = frkc2_coeffs(s, 0.01)
