@@ -202,6 +202,23 @@ def test_stage_count_limits(kind, n, s, k):
     assert np.array_equal(got, ref), "%d values differ" % int(np.sum(got != ref))
 
 
+@pytest.mark.parametrize("kind,n", [("1d-lap-per", (4096, 1, 1)), ("1d-lap-per", (4097, 1, 1)),
+                                    ("1d-var-dir", (4096, 1, 1)), ("1d-por-per", (4097, 1, 1))])
+def test_1d_lds_size_limit(kind, n):
+    """4096 points run in the LDS-resident kernel, 4097 in one pass per stage: both against
+    the oracle bit for bit (three supersteps)."""
+    p = problem(kind, n)
+    if p.op == wl.OP_POROUS2:
+        p.w0 = 1.0 + 0.4 * p.w0 / np.max(np.abs(p.w0))
+    c = frkc2_coeffs(16, 0.01)
+    T = 0.5 * c.beta_bar / stage.rho_bound(p, p.w0)
+    ref, _ = stage.run(p, 16, 3, T=T, coeffs=c)
+    w = dev(p.w0)
+    F.frkc2_step(p, w, dev(p.D) if p.D is not None else None, T=T, s=16, nsteps=3)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(w), ref)
+
+
 def test_heat1d_full_config():
     """1D heat, N = 1024, s = 16, 20 supersteps (LDS-resident kernel): oracle and Fourier solution."""
     p = wl.heat1d()
