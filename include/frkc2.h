@@ -75,7 +75,7 @@ typedef enum { FRKC2_BC_PERIODIC = 0, FRKC2_BC_DIRICHLET0 = 1 } frkc2_bc;
  *           fma(-4, vi, qi)), R_w = (fma(3, vr, -qr), fma(3, vi, -qi)) and
  *           f = fma(acc, 1/h^2, R) per component. Gershgorin bound:
  *           (2/h^2)(4d) + max_c max(|2vw - 4| + v^2, v^2 + |3 - 2vw|).
- *           frkc2_step and frkc2_integrate fuse 2, 3 or 4 stages per pass
+ *           frkc2_step and frkc2_integrate fuse 2 to 6 stages per pass
  *           (default 4); not available to the batched and adjoint calls.
  *  ADVDIFF  f = d lap u - v . grad u with central differences (Sec. 2.1:
  *           damping makes the schemes usable for problems with a small
@@ -400,7 +400,7 @@ int frkc2_autotune(const frkc2_grid *g, const double *w, const double *D, int s,
  * frkc2_set_option -- tuning knobs (process-wide, not thread-safe to change
  * while other threads call the library):
  *   FRKC2_OPT_TBLOCK  stages fused per HBM pass of frkc2_step: 1, or 2 and 3
- *                     (3D), 2, 3, 4, 6 and 8 (2D), 2, 3 and 4 (BRUSS2: 64x40
+ *                     (3D), 2, 3, 4, 6 and 8 (2D), 2 to 6 (BRUSS2: 64x40
  *                     tiles of both species, its own shape, TILE and ZCHUNK
  *                     do not apply); an unsupported depth runs one stage per
  *                     pass; 0 = automatic (the entry frkc2_autotune stored for

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kBBX *kBBY) void bruss_stage(BrussArgs a)
     }
 }
 
-// K stages (2..4) in one HBM pass. A workgroup of NW wavefronts works on a
+// K stages (2..6) in one HBM pass. A workgroup of NW wavefronts works on a
 // 64 x (NW R) extended tile of both species (periodic wrap) and writes its
 // (64 - 2K) x (NW R - 2K) centre. Lane x of wavefront r owns column x, rows
 // rR .. rR+R-1, and keeps their complex values of both species in registers
@@ -140,7 +140,7 @@ struct BrussTbArgs {
     int nx, ny, ntx;
     long long n;
     double inv_h2, d;
-    double tr[4], ti[4];
+    double tr[kMaxTBlock], ti[kMaxTBlock];
 };
 
 // The value of lane i - 1 (SHR) or i + 1 (SHL) of the wavefront; 0 at the end
@@ -344,7 +344,7 @@ int launch_bruss(const KGrid &g, const PassArgs &p, hipStream_t st)
 
 int launch_bruss_tb(const KGrid &g, const PassArgs &p, hipStream_t st)
 {
-    if (g.op != FRKC2_OP_BRUSS2 || g.ndim != 2 || p.k < 2 || p.k > 4)
+    if (g.op != FRKC2_OP_BRUSS2 || g.ndim != 2 || p.k < 2 || p.k > 6)
         return (int)hipErrorInvalidValue;
     // the embedded variant writes complex W and reads emb_in after the first stage
     if (p.emb_out && (p.out_re || (!p.in_re && !p.emb_in))) return (int)hipErrorInvalidValue;
@@ -375,7 +375,9 @@ int launch_bruss_tb(const KGrid &g, const PassArgs &p, hipStream_t st)
     const bool ir = p.in_re != nullptr, orl = p.out_re != nullptr;
     if (p.k == 2) return launch_bruss_tb_k<2>(a, (unsigned)nblk, ir, orl, st);
     if (p.k == 3) return launch_bruss_tb_k<3>(a, (unsigned)nblk, ir, orl, st);
-    return launch_bruss_tb_k<4>(a, (unsigned)nblk, ir, orl, st);
+    if (p.k == 4) return launch_bruss_tb_k<4>(a, (unsigned)nblk, ir, orl, st);
+    if (p.k == 5) return launch_bruss_tb_k<5>(a, (unsigned)nblk, ir, orl, st);
+    return launch_bruss_tb_k<6>(a, (unsigned)nblk, ir, orl, st);
 }
 
 int launch_bruss_react_max(const KGrid &g, const double *w, double *partials, hipStream_t st)

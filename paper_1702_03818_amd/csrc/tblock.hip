@@ -149,7 +149,7 @@ int launch_bc(const KGrid &g, int k, int shape, const TbArgs &a, bool ir, bool o
 
 bool tblock_supported(const KGrid &g, int k)
 {
-    if (g.op == FRKC2_OP_BRUSS2) return k >= 2 && k <= 4;
+    if (g.op == FRKC2_OP_BRUSS2) return k >= 2 && k <= 6;
     if (g.ndim == 3) return k == 2 || k == 3;
     if (g.ndim == 2) return k == 2 || k == 3 || k == 4 || k == 6 || k == 8;
     return false;
