@@ -187,9 +187,12 @@ int frkc2_rho_bound(const frkc2_grid *g, const double *w, const double *D, doubl
  *   s, nu   as for frkc2_coeffs
  *   ws      device workspace of at least frkc2_workspace_bytes(g, s, FRKC2_WS_STEP)
  *   stats   host, may be NULL; when given, the call synchronises st and fills it
- * Before the first superstep (and before every superstep for POROUS2) rho is
- * computed and the call fails with FRKC2_EUNSTABLE if T * rho > beta_bar;
- * those checks synchronise st. Otherwise asynchronous.
+ * Before the first superstep (and before every superstep for the
+ * state-dependent operators POROUS2 and BRUSS2) rho is computed and the call
+ * fails with FRKC2_EUNSTABLE if T * rho > beta_bar; those checks synchronise
+ * st. Otherwise asynchronous. A 1D grid of up to 4096 points runs each
+ * superstep in one LDS-resident launch, and for a linear operator (one T) all
+ * supersteps of the call but a last one that fills stats in one launch.
  */
 int frkc2_step(const frkc2_grid *g, double *w, const double *D, double T, double cfl, int s,
                double nu, int nsteps, void *ws, size_t ws_bytes, hipStream_t st,
@@ -286,8 +289,9 @@ int frkc2_reduce(int op, const double *x, const double *y, size_t n, double *res
  * the Brusselator fuse stages per HBM pass as frkc2_step does (the embedded
  * solution adds 16 B per point and species and pass); 1D grids of up to 4096
  * points run each attempt's superstep in one LDS-resident launch; other
- * depths, tile shapes and longer 1D grids run one stage per pass. Results are identical, bit for bit, to the same
- * procedure evaluated on the CPU in the library's arithmetic order. Errors:
+ * depths, tile shapes and longer 1D grids run one stage per pass. Results are
+ * identical, bit for bit, to the same procedure evaluated on the CPU in the
+ * library's arithmetic order. Errors:
  * FRKC2_EINVAL (arguments, checked before any HIP call), FRKC2_ENOMEM
  * (workspace), FRKC2_ENONFINITE (non-finite error estimate), FRKC2_ETIMEOUT,
  * FRKC2_EHIP.
