@@ -157,6 +157,8 @@ int frkc2_write_table(const char *path, double nu, int m_max);
 
 /*
  * frkc2_workspace_bytes -- device workspace needed by the calls below for grid g.
+ * A systems pattern of this library (the caller owns all device memory); no
+ * passage of the paper defines it.
  *   FRKC2_WS_STEP: frkc2_step and frkc2_rho_bound (two complex state buffers
  *   plus reduction scratch); FRKC2_WS_ADJOINT: frkc2_step_adjoint (s stored
  *   complex stages, two complex adjoint buffers, one real gradient buffer);
@@ -168,9 +170,17 @@ size_t frkc2_workspace_bytes(const frkc2_grid *g, int s, int flags);
 
 /*
  * frkc2_rho_bound -- Gershgorin bound on the spectral radius of the Jacobian
- * of f at the real state w: rho = (2/h^2) * max_c sum_f D_f (POROUS2: the face
- * value (w_c^2 + w_nb^2)/2). This is the rho of the stability requirement
- * T rho <= beta_bar (Sec. 2: |R(T lambda)| <= 1).
+ * of f at the real state w, the largest row sum |a_cc| + sum_nb |a_cn|. This
+ * is the rho of the stability requirement T rho <= beta_bar (Sec. 2:
+ * |R(T lambda)| <= 1 on the spectrum).
+ *   LAPLACE, VARCOEF: rho = (2/h^2) * max_c sum_f D_f.
+ *   POROUS2: the face value Q_f = (w_c^2 + w_nb^2)/2 depends on the state, so
+ *     with dw = w_nb - w_c the row is a_cc = sum_f (w_c dw - Q_f) / h^2 and
+ *     a_cn = (w_nb dw + Q_f) / h^2 (a Dirichlet ghost, fixed at 0, adds to
+ *     a_cc only): rho = (1/h^2) * max_c (|sum_f (w_c dw - Q_f)| +
+ *     sum_f |w_nb dw + Q_f|), per face in the order x-, x+, y-, y+, z-, z+.
+ *   BRUSS2: the diffusion rows plus the reaction rows (see the operator list).
+ *   ADVDIFF: (|sum_f c_f| + sum_f |c_f|) / h^2, computed on the host.
  *   w   device, N doubles (read for POROUS2 only; may be NULL otherwise)
  *   D   device, N doubles (VARCOEF only; NULL otherwise)
  *   rho host, receives the bound. Synchronises st.
@@ -199,7 +209,9 @@ int frkc2_step(const frkc2_grid *g, double *w, const double *D, double T, double
                frkc2_step_stats *stats);
 
 /*
- * frkc2_step_adjoint -- reverse-mode derivative of one superstep (VARCOEF or LAPLACE).
+ * frkc2_step_adjoint -- reverse-mode derivative of one superstep (VARCOEF or LAPLACE):
+ * the transpose of the Sec. 3 Euler-step recursion W^{l+1} = W^l + T a_l f(W^l),
+ * applied stage by stage in reverse order.
  * With w^{n+1} = S(w^n; D) the superstep from w_n with fixed T:
  *   lam_next  device, N doubles: dJ/dw^{n+1}
  *   lam_n     device, N doubles, out: dJ/dw^n = S^T lam_next
@@ -216,10 +228,11 @@ int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const double *D, 
                        void *ws, size_t ws_bytes, hipStream_t st);
 
 /*
- * frkc2_step_batched -- one superstep for each of nprob independent problems
- * (VARCOEF or LAPLACE, 2D or 3D, each with its own grid, T and s) in a single
- * HIP graph launch. The graph has concurrent branches: 3D problems (two
- * interleaved groups, one branch each)
+ * frkc2_step_batched -- one superstep (Sec. 3, Euler-step equation) for each of
+ * nprob independent problems (VARCOEF or LAPLACE, 2D or 3D, each with its own
+ * grid, T and s) in a single HIP graph launch. Batching is a systems pattern
+ * of this library; no passage of the paper defines it. The graph has
+ * concurrent branches: 3D problems (two interleaved groups, one branch each)
  * advance in pass levels (level L: stages 3L .. 3L+2 of every problem that has
  * them, fused in one HBM pass, then the remaining single stages), 2D problems
  * likewise with passes of 4 stages (s = 4: four single stages).
@@ -231,10 +244,15 @@ int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const double *D, 
  *   ws     device workspace of at least frkc2_batched_workspace_bytes(...),
  *          256-byte aligned; it holds the work tables and two complex
  *          buffers per problem and must not be shared by concurrent calls
- * The first call for a given set of arguments uploads the work tables into
- * ws (synchronising st) and captures the graph; later calls with identical
- * arguments only replay it (asynchronous). The graph stays cached for ws
- * until frkc2_batched_release(ws). Each problem's result is bit-identical to
+ * The first call for a given set of arguments checks every problem's
+ * stability (T rho <= betabar(s), rho the Gershgorin bound of frkc2_rho_bound;
+ * FRKC2_EUNSTABLE names the first problem that fails, before any state is
+ * touched), builds the work tables and captures the graph (synchronising st);
+ * later calls with identical arguments upload the tables again (about 1 MB
+ * for 512 problems, asynchronous, so ws need not keep its contents between
+ * calls) and replay the graph. The check is not repeated on replays: D must
+ * not change while the graph is cached. The graph stays cached for ws until
+ * frkc2_batched_release(ws). Each problem's result is bit-identical to
  * frkc2_step on it. frkc2_batched_status synchronises st and reports any
  * HIP error of the replays.
  */

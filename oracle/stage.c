@@ -47,6 +47,16 @@
  * and fully to the cell of a Dirichlet boundary face.
  */
 #include <math.h>
+
+/* FMA is the correctly rounded fused multiply-add of C99 (the arithmetic order
+ * above). Built with -DORACLE_UNFUSED it is the plain a*b + c (two roundings):
+ * that variant only measures how far the fused order moves results from the
+ * unfused one; it is not the reference the tests compare against. */
+#ifdef ORACLE_UNFUSED
+#define FMA(a, b, c) ((a) * (b) + (c))
+#else
+#define FMA(a, b, c) fma((a), (b), (c))
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -133,19 +143,19 @@ static void apply_bruss(const grid_t *g, const double *wr, const double *wi, dou
                 long q = neighbour(g, i, f);
                 double nr = (q < 0) ? 0.0 : ur[q];
                 double ni = (q < 0) ? 0.0 : ui[q];
-                acc[s][0] = fma(d, nr - ur[p], acc[s][0]);
-                acc[s][1] = fma(d, ni - ui[p], acc[s][1]);
+                acc[s][0] = FMA(d, nr - ur[p], acc[s][0]);
+                acc[s][1] = FMA(d, ni - ui[p], acc[s][1]);
             }
         }
         double vr = wr[p], vi = wi[p], xr = wr[N + p], xi = wi[N + p];
-        double pr = fma(vr, vr, -(vi * vi)), pi = 2.0 * (vr * vi);
-        double qr = fma(xr, pr, -(xi * pi)), qi = fma(xr, pi, xi * pr);
-        double rvr = fma(-4.0, vr, 1.0) + qr, rvi = fma(-4.0, vi, qi);
-        double rwr = fma(3.0, vr, -qr), rwi = fma(3.0, vi, -qi);
-        fr[p] = fma(acc[0][0], g->inv_h2, rvr);
-        fi[p] = fma(acc[0][1], g->inv_h2, rvi);
-        fr[N + p] = fma(acc[1][0], g->inv_h2, rwr);
-        fi[N + p] = fma(acc[1][1], g->inv_h2, rwi);
+        double pr = FMA(vr, vr, -(vi * vi)), pi = 2.0 * (vr * vi);
+        double qr = FMA(xr, pr, -(xi * pi)), qi = FMA(xr, pi, xi * pr);
+        double rvr = FMA(-4.0, vr, 1.0) + qr, rvi = FMA(-4.0, vi, qi);
+        double rwr = FMA(3.0, vr, -qr), rwi = FMA(3.0, vi, -qi);
+        fr[p] = FMA(acc[0][0], g->inv_h2, rvr);
+        fi[p] = FMA(acc[0][1], g->inv_h2, rvi);
+        fr[N + p] = FMA(acc[1][0], g->inv_h2, rwr);
+        fi[N + p] = FMA(acc[1][1], g->inv_h2, rwi);
     }
 }
 
@@ -170,14 +180,14 @@ static void apply_op(const grid_t *g, const double *D, const double *wr, const d
             double dr = nr - wr[p];
             double di = ni - wi[p];
             if (g->op == OP_POROUS2) {
-                double qr_c = fma(wr[p], wr[p], -(wi[p] * wi[p]));
+                double qr_c = FMA(wr[p], wr[p], -(wi[p] * wi[p]));
                 double qi_c = 2.0 * (wr[p] * wi[p]);
-                double qr_n = fma(nr, nr, -(ni * ni));
+                double qr_n = FMA(nr, nr, -(ni * ni));
                 double qi_n = 2.0 * (nr * ni);
                 double Dr = 0.5 * qr_c + 0.5 * qr_n;
                 double Di = 0.5 * qi_c + 0.5 * qi_n;
-                acc_r = fma(Dr, dr, fma(-Di, di, acc_r));
-                acc_i = fma(Dr, di, fma(Di, dr, acc_i));
+                acc_r = FMA(Dr, dr, FMA(-Di, di, acc_r));
+                acc_i = FMA(Dr, di, FMA(Di, dr, acc_i));
             } else {
                 double Df;
                 if (g->op == OP_LAPLACE) {
@@ -188,8 +198,8 @@ static void apply_op(const grid_t *g, const double *D, const double *wr, const d
                     double Dn = (q < 0) ? D[p] : D[q];
                     Df = 0.5 * D[p] + 0.5 * Dn;
                 }
-                acc_r = fma(Df, dr, acc_r);
-                acc_i = fma(Df, di, acc_i);
+                acc_r = FMA(Df, dr, acc_r);
+                acc_i = FMA(Df, di, acc_i);
             }
         }
         fr[p] = acc_r * g->inv_h2;
@@ -242,11 +252,11 @@ int oracle_superstep(int ndim, const long *n, int bc, int op, double inv_h2, dou
         double tr = tau_re[l], ti = tau_im[l];
 #pragma omp parallel for schedule(static)
         for (long p = 0; p < N; ++p) {
-            double nr = fma(tr, fr[p], fma(-ti, fi[p], wr[p]));
-            double ni = fma(tr, fi[p], fma(ti, fr[p], wi[p]));
+            double nr = FMA(tr, fr[p], FMA(-ti, fi[p], wr[p]));
+            double ni = FMA(tr, fi[p], FMA(ti, fr[p], wi[p]));
             wr[p] = nr;
             wi[p] = ni;
-            if (emb_out) emb_out[p] = fma(tr, fr[p], emb_out[p]);
+            if (emb_out) emb_out[p] = FMA(tr, fr[p], emb_out[p]);
         }
     }
     memcpy(w, wr, sizeof(double) * N);
@@ -266,11 +276,11 @@ void oracle_euler_update(long N, double *wr, double *wi, const double *fr, const
 {
 #pragma omp parallel for schedule(static)
     for (long p = 0; p < N; ++p) {
-        double nr = fma(tr, fr[p], fma(-ti, fi[p], wr[p]));
-        double ni = fma(tr, fi[p], fma(ti, fr[p], wi[p]));
+        double nr = FMA(tr, fr[p], FMA(-ti, fi[p], wr[p]));
+        double ni = FMA(tr, fi[p], FMA(ti, fr[p], wi[p]));
         wr[p] = nr;
         wi[p] = ni;
-        if (emb) emb[p] = fma(tr, fr[p], emb[p]);
+        if (emb) emb[p] = FMA(tr, fr[p], emb[p]);
     }
 }
 
@@ -342,11 +352,22 @@ int oracle_adjoint(int ndim, const long *n, int bc, int op, double inv_h2, doubl
 }
 
 /*
- * Gershgorin bound on the spectral radius of the Jacobian of f at real w:
- * rho = (2*inv_h2) * max_c sum_faces D_f, with D_f of the operator (op 2: the
- * face value (w_c^2 + w_nb^2)/2 of the current state). Op 3 adds the
- * reaction rows: rho = (2*inv_h2) * (4d) + max_c max(|2vw - 4| + v^2,
- * v^2 + |3 - 2vw|) (diagonal and coupling entries of each row).
+ * Gershgorin bound on the spectral radius of the Jacobian of f at real w
+ * (the rho of the stability requirement T rho <= betabar, Sec. 2):
+ *  ops 0, 1: the operator is linear, the row of cell c has diagonal
+ *            -sum_f D_f / h^2 and off-diagonal entries D_f / h^2, so
+ *            rho = (2*inv_h2) * max_c sum_faces D_f.
+ *  op 2:     f_c = sum_f Q_f (w_nb - w_c) / h^2 with Q_f = (w_c^2 + w_nb^2)/2
+ *            depends on w through Q_f as well, so the Jacobian row is
+ *            d f_c / d w_c  = sum_f (w_c (w_nb - w_c) - Q_f) / h^2,
+ *            d f_c / d w_nb = (w_nb (w_nb - w_c) + Q_f) / h^2
+ *            (a Dirichlet ghost, w_nb = 0, is no unknown: it adds to the
+ *            diagonal only), and rho = inv_h2 * max_c (|diag| + sum |off|),
+ *            evaluated per face as dw = w_nb - w_c, Q = 0.5*(w_c*w_c + w_nb*w_nb),
+ *            diag = diag + (w_c*dw - Q), off = off + fabs(w_nb*dw + Q).
+ *  op 3:     adds the reaction rows: rho = (2*inv_h2) * (4d) + max_c
+ *            max(|2vw - 4| + v^2, v^2 + |3 - 2vw|) (diagonal and coupling
+ *            entries of each row).
  */
 double oracle_rho_bound(int ndim, const long *n, int bc, int op, double inv_h2, double d_const,
                         const double *D, const double *w)
@@ -367,7 +388,7 @@ double oracle_rho_bound(int ndim, const long *n, int bc, int op, double inv_h2, 
     for (long p = 0; p < N; ++p) {
         long i[3];
         coords(&g, p, i);
-        double sum = 0.0;
+        double sum = 0.0, diag = 0.0;
         for (int f = 0; f < 2 * ndim; ++f) {
             long q = neighbour(&g, i, f);
             double Df;
@@ -377,10 +398,15 @@ double oracle_rho_bound(int ndim, const long *n, int bc, int op, double inv_h2, 
                 Df = 0.5 * D[p] + 0.5 * ((q < 0) ? D[p] : D[q]);
             } else {
                 double un = (q < 0) ? 0.0 : w[q];
-                Df = 0.5 * (w[p] * w[p] + un * un);
+                double dw = un - w[p];
+                double Q = 0.5 * (w[p] * w[p] + un * un);
+                diag = diag + (w[p] * dw - Q);
+                if (q >= 0) sum = sum + fabs(un * dw + Q);
+                continue;
             }
             sum = sum + Df;
         }
+        if (op == OP_POROUS2) sum = fabs(diag) + sum;
         if (sum > m) m = sum;
     }
     if (op == OP_BRUSS2) {
@@ -395,6 +421,7 @@ double oracle_rho_bound(int ndim, const long *n, int bc, int op, double inv_h2, 
         }
         return (2.0 * inv_h2) * m + r;
     }
+    if (op == OP_POROUS2) return inv_h2 * m;
     return (2.0 * inv_h2) * m;
 }
 

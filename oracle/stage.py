@@ -22,48 +22,67 @@ from .coeffs import frkc2_coeffs
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
+# The same source with every fused multiply-add evaluated as a*b + c (two
+# roundings): used only to measure how far the fused order moves results.
+_LIB_UNFUSED = os.path.join(_HERE, "_build", "liboracle_unfused.so")
 _lib = None
+_lib_unfused = None
 
 
 def build(force: bool = True) -> str:
-    """Compile stage.c with gcc (FP64, no contraction, OpenMP over points)."""
+    """Compile stage.c with gcc (FP64, no contraction, OpenMP over points), and its unfused
+    variant."""
     os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-                               "-fPIC", "-shared", "-o", tmp,
-                               os.path.join(_HERE, "stage.c"), "-lm"])
-        os.replace(tmp, _LIB_PATH)
+    for path, extra in ((_LIB_PATH, []), (_LIB_UNFUSED, ["-DORACLE_UNFUSED"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                                   "-fopenmp", "-fPIC", "-shared"] + extra +
+                                  ["-o", tmp, os.path.join(_HERE, "stage.c"), "-lm"])
+            os.replace(tmp, path)
     return _LIB_PATH
 
 
-def _load():
-    global _lib
+def _load(unfused: bool = False):
+    global _lib, _lib_unfused
+    if unfused and _lib_unfused is None:
+        _load()
+        lib = ctypes.CDLL(_LIB_UNFUSED)
+        _declare(lib)
+        _lib_unfused = lib
+    if unfused:
+        return _lib_unfused
     if _lib is None:
         src = os.path.join(_HERE, "stage.c")
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(src) > os.path.getmtime(_LIB_PATH):
+        stale = any(not os.path.exists(p) or os.path.getmtime(src) > os.path.getmtime(p)
+                    for p in (_LIB_PATH, _LIB_UNFUSED))
+        if stale:
             build(force=True)
         lib = ctypes.CDLL(_LIB_PATH)
-        dp = ctypes.POINTER(ctypes.c_double)
-        lp = ctypes.POINTER(ctypes.c_long)
-        common = [ctypes.c_int, lp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                  dp, ctypes.c_int, dp, dp]
-        lib.oracle_superstep.argtypes = common + [dp, dp, dp, dp]
-        lib.oracle_superstep.restype = ctypes.c_int
-        lib.oracle_adjoint.argtypes = common + [dp, dp, dp, dp]
-        lib.oracle_adjoint.restype = ctypes.c_int
-        lib.oracle_rho_bound.argtypes = [ctypes.c_int, lp, ctypes.c_int, ctypes.c_int,
-                                         ctypes.c_double, ctypes.c_double, dp, dp]
-        lib.oracle_rho_bound.restype = ctypes.c_double
-        lib.oracle_set_faces.argtypes = [dp]
-        lib.oracle_set_faces.restype = None
-        lib.oracle_euler_update.argtypes = [ctypes.c_long, dp, dp, dp, dp, ctypes.c_double,
-                                            ctypes.c_double, dp]
-        lib.oracle_euler_update.restype = None
-        lib.oracle_threads.argtypes = []
-        lib.oracle_threads.restype = ctypes.c_int
+        _declare(lib)
         _lib = lib
     return _lib
+
+
+def _declare(lib):
+    dp = ctypes.POINTER(ctypes.c_double)
+    lp = ctypes.POINTER(ctypes.c_long)
+    common = [ctypes.c_int, lp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+              dp, ctypes.c_int, dp, dp]
+    lib.oracle_superstep.argtypes = common + [dp, dp, dp, dp]
+    lib.oracle_superstep.restype = ctypes.c_int
+    lib.oracle_adjoint.argtypes = common + [dp, dp, dp, dp]
+    lib.oracle_adjoint.restype = ctypes.c_int
+    lib.oracle_rho_bound.argtypes = [ctypes.c_int, lp, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_double, dp, dp]
+    lib.oracle_rho_bound.restype = ctypes.c_double
+    lib.oracle_set_faces.argtypes = [dp]
+    lib.oracle_set_faces.restype = None
+    lib.oracle_euler_update.argtypes = [ctypes.c_long, dp, dp, dp, dp, ctypes.c_double,
+                                        ctypes.c_double, dp]
+    lib.oracle_euler_update.restype = None
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = ctypes.c_int
 
 
 def _dp(a):
@@ -83,10 +102,10 @@ def face_coefficients(prob):
     return fc
 
 
-def _grid_args(prob):
+def _grid_args(prob, lib=None):
     n = (ctypes.c_long * 3)(*[int(v) for v in prob.n])
     inv_h2 = 1.0 / (prob.h * prob.h)
-    lib = _load()
+    lib = lib if lib is not None else _load()
     if prob.op == 4:
         _grid_args.fc = face_coefficients(prob)
         lib.oracle_set_faces(_dp(_grid_args.fc))
@@ -104,10 +123,11 @@ def threads() -> int:
     return int(_load().oracle_threads())
 
 
-def superstep(prob, w, tau_re, tau_im, D=None, want_imag=False):
-    """One superstep from real w with stepsizes tau (execution order). Returns Re W^s (and Im W^s)."""
-    lib = _load()
-    n, inv_h2 = _grid_args(prob)
+def superstep(prob, w, tau_re, tau_im, D=None, want_imag=False, unfused=False):
+    """One superstep from real w with stepsizes tau (execution order). Returns Re W^s (and Im W^s).
+    unfused=True runs the variant that rounds every multiply-add twice (a*b + c)."""
+    lib = _load(unfused)
+    n, inv_h2 = _grid_args(prob, lib)
     wr = _f64(w).copy()
     wi = np.empty_like(wr) if want_imag else None
     Dd = _f64(D if D is not None else prob.D) if (prob.D is not None or D is not None) else None
@@ -164,10 +184,11 @@ def run(prob, s, nsteps, T=None, cfl=None, nu=0.01, w=None, coeffs=None):
     return cur, Ts
 
 
-def adjoint(prob, w_n, lam_next, tau_re, tau_im, grad_logD=None, D=None):
-    """Adjoint of one superstep: returns lam_n and grad_logD (accumulated in place)."""
-    lib = _load()
-    n, inv_h2 = _grid_args(prob)
+def adjoint(prob, w_n, lam_next, tau_re, tau_im, grad_logD=None, D=None, unfused=False):
+    """Adjoint of one superstep: returns lam_n and grad_logD (accumulated in place).
+    unfused=True runs the variant that rounds every multiply-add twice."""
+    lib = _load(unfused)
+    n, inv_h2 = _grid_args(prob, lib)
     Dd = D if D is not None else prob.D
     Dd = _f64(Dd) if Dd is not None else None
     wn = _f64(w_n)

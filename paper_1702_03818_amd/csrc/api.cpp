@@ -188,7 +188,9 @@ AdjLayout adj_layout(long long N, int s)
     return L;
 }
 
-// Gershgorin bound (2/h^2) max_c sum_f D_f; synchronises st.
+// Gershgorin bound on the Jacobian of f: (2/h^2) max_c sum_f D_f for the linear
+// operators, (1/h^2) max_c (|diag| + sum |off|) of the state-dependent rows for
+// POROUS2, plus the reaction rows for BRUSS2; synchronises st.
 int rho_bound_impl(const KGrid &kg, const double *w, const double *D, double *partials,
                    double *rho, hipStream_t st)
 {
@@ -214,7 +216,7 @@ int rho_bound_impl(const KGrid &kg, const double *w, const double *D, double *pa
                 "rho bound copy");
         HIP_TRY(hipStreamSynchronize(st), "rho bound");
     }
-    *rho = (2.0 * kg.inv_h2) * m;
+    *rho = (kg.op == FRKC2_OP_POROUS2) ? kg.inv_h2 * m : (2.0 * kg.inv_h2) * m;
     if (kg.op == FRKC2_OP_BRUSS2) {
         // reaction rows of the Jacobian (diagonal and species coupling)
         double r = 0.0;
@@ -447,11 +449,14 @@ extern "C" int frkc2_rho_bound(const frkc2_grid *g, const double *w, const doubl
     return rho_bound_impl(kg, w, D, static_cast<double *>(ws), rho, st);
 }
 
-extern "C" int frkc2_step(const frkc2_grid *g, double *w, const double *D, double T, double cfl,
-                          int s, double nu, int nsteps, void *ws, size_t ws_bytes, hipStream_t st,
-                          frkc2_step_stats *stats)
+namespace frkc2 {
+
+size_t step_workspace_bytes(long long nstate) { return step_layout(nstate).total; }
+
+// Argument checks of frkc2_step (no HIP call).
+int step_validate(const frkc2_grid *g, const double *w, const double *D, double T, double cfl,
+                  int s, double nu, int nsteps, KGrid &kg)
 {
-    KGrid kg;
     if (!make_kgrid(g, kg)) return FRKC2_EINVAL;
     if (!w) {
         set_error("w is NULL");
@@ -472,6 +477,19 @@ extern "C" int frkc2_step(const frkc2_grid *g, double *w, const double *D, doubl
         set_error("exactly one of T and cfl must be positive and finite (T=%g, cfl=%g)", T, cfl);
         return FRKC2_EINVAL;
     }
+    return FRKC2_OK;
+}
+
+// frkc2_step's body; ws is the caller's workspace or the library's static
+// scratch (frkc2_step_noalloc).
+int step_core(const frkc2_grid *g, double *w, const double *D, double T, double cfl, int s,
+              double nu, int nsteps, void *ws, size_t ws_bytes, hipStream_t st,
+              frkc2_step_stats *stats)
+{
+    KGrid kg;
+    const int vrc = step_validate(g, w, D, T, cfl, s, nu, nsteps, kg);
+    if (vrc < 0) return vrc;
+    const bool adaptive = cfl > 0.0 && std::isfinite(cfl);
     const long long N = kg.nstate();
     const StepLayout L = step_layout(N);
     if (!ws || ws_bytes < L.total || !aligned16(ws)) {
@@ -547,6 +565,15 @@ extern "C" int frkc2_step(const frkc2_grid *g, double *w, const double *D, doubl
         HIP_TRY(hipStreamSynchronize(st), "step");
     }
     return crc;
+}
+
+}  // namespace frkc2
+
+extern "C" int frkc2_step(const frkc2_grid *g, double *w, const double *D, double T, double cfl,
+                          int s, double nu, int nsteps, void *ws, size_t ws_bytes, hipStream_t st,
+                          frkc2_step_stats *stats)
+{
+    return step_core(g, w, D, T, cfl, s, nu, nsteps, ws, ws_bytes, st, stats);
 }
 
 namespace {

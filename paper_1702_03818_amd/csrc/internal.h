@@ -35,6 +35,15 @@ struct KGrid {
 
 bool make_kgrid(const frkc2_grid *g, KGrid &k);
 
+// frkc2_step's argument checks (no HIP call), frkc2_step on a given workspace
+// (api.cpp), and the workspace it needs for a state of nstate values.
+int step_validate(const frkc2_grid *g, const double *w, const double *D, double T, double cfl,
+                  int s, double nu, int nsteps, KGrid &kg);
+int step_core(const frkc2_grid *g, double *w, const double *D, double T, double cfl, int s,
+              double nu, int nsteps, void *ws, size_t ws_bytes, hipStream_t st,
+              frkc2_step_stats *stats);
+size_t step_workspace_bytes(long long nstate);
+
 // One pass of k consecutive stages over the whole grid.
 struct PassArgs {
     const double *in_re;        // real input (first pass) or nullptr

@@ -8,9 +8,14 @@
 // the result) does not depend on the device or the run.
 //
 // The Gershgorin bound (stability requirement T rho <= betabar of Sec. 2,
-// |R(T lambda)| <= 1 on the spectrum) is rho = (2/h^2) max_c sum_f D_f with the
-// operator's own face diffusivity, faces in the order x-, x+, y-, y+, z-, z+.
-// A maximum is exact in any order.
+// |R(T lambda)| <= 1 on the spectrum) is the largest row sum |a_cc| + sum |a_cn|
+// of the Jacobian of f, faces in the order x-, x+, y-, y+, z-, z+. For the
+// linear operators the row sum is 2 sum_f D_f / h^2 with the operator's face
+// diffusivity. For div(u^2 grad u) the face value Q_f = (w_c^2 + w_nb^2)/2
+// depends on the state, so the row is diag = sum_f (w_c dw - Q_f),
+// off_nb = w_nb dw + Q_f with dw = w_nb - w_c (over h^2; a Dirichlet ghost adds
+// to the diagonal only); rho_pass1 yields max_c (|diag| + sum |off|) and the
+// host multiplies by 1/h^2. A maximum is exact in any order.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -75,7 +80,8 @@ __global__ __launch_bounds__(kThreads) void reduce_pass2(double *partials, int n
     if (threadIdx.x == 0) partials[nb] = r;
 }
 
-// per-cell sum of face diffusivities, then max
+// per-cell Jacobian row sum (without the 1/h^2 factor; linear operators also
+// without their factor 2), then max
 template <int OP, int BC, int NDIM>
 __global__ __launch_bounds__(kThreads) void rho_pass1(const double *w, const double *D, int nx,
                                                       int ny, int nz, double d_const,
@@ -88,7 +94,7 @@ __global__ __launch_bounds__(kThreads) void rho_pass1(const double *w, const dou
         const int x = (int)(p % nx);
         const int y = (int)((p / nx) % ny);
         const int z = (int)(p / ((long long)nx * ny));
-        double sum = 0.0;
+        double sum = 0.0, diag = 0.0;
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
             const int d = f >> 1;
@@ -109,11 +115,17 @@ __global__ __launch_bounds__(kThreads) void rho_pass1(const double *w, const dou
             } else if (OP == FRKC2_OP_VARCOEF) {
                 Df = 0.5 * D[p] + 0.5 * (ghost ? D[p] : D[q]);
             } else {
+                const double wc = w[p];
                 const double un = ghost ? 0.0 : w[q];
-                Df = 0.5 * (w[p] * w[p] + un * un);
+                const double dw = un - wc;
+                const double Q = 0.5 * (wc * wc + un * un);
+                diag = diag + (wc * dw - Q);
+                if (!ghost) sum = sum + fabs(un * dw + Q);
+                continue;
             }
             sum = sum + Df;
         }
+        if (OP == FRKC2_OP_POROUS2) sum = fabs(diag) + sum;
         m = m > sum ? m : sum;
     }
     const double r = block_reduce<R_MAX>(m);
