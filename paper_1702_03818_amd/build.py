@@ -1,8 +1,9 @@
 """Build libfrkc2.so in-tree for gfx950.
 
 HIP sources are compiled by hipcc for gfx950 only, FP64 with contraction
-disabled (-ffp-contract=off: the stencil arithmetic order is fixed and no
-multiply-add is fused) and without packed FP32 operations. The host
+disabled (-ffp-contract=off: the stencil arithmetic order is fixed; the only
+fused multiply-adds are the explicit fma() calls of that order) and without
+packed FP32 operations. The host
 stepsize generator uses binary128 from libquadmath and is compiled by g++.
 
     python -m paper_1702_03818_amd.build

@@ -28,6 +28,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t probs[2], tau, bufs, total;             // index 0: 3D list, 1: 2D list
+    size_t partials;                               // reduction scratch of the rho check
     size_t pass3;                                  // 3D pass tables: kGroups3 * 2 * levels3 rows of n3 + 1
     int levels3;                                   // pass levels of the 3D list
     size_t pass2;                                  // 2D pass tables: 2 * levels2 rows of n2 + 1
@@ -92,6 +93,8 @@ Layout layout(int nprob, const std::vector<KGrid> &kg, const int *s)
     o = align_up(o + sizeof(long long) * 2 * (size_t)L.levels2 * (cnt[1] + 1));
     L.tau = o;
     o = align_up(o + sizeof(double) * 2 * sum_s);
+    L.partials = o;
+    o = align_up(o + sizeof(double) * (kReduceBlocks + 2));
     L.bufs = o;
     L.buf_off.resize(nprob);
     for (int i = 0; i < nprob; ++i) {
@@ -129,6 +132,30 @@ int hip_err(hipError_t e, const char *what)
 {
     set_error("batched: %s: HIP error %d (%s)", what, (int)e, hipGetErrorString(e));
     return FRKC2_EHIP;
+}
+
+// Upload the work tables (host copies kept in E) into ws on st, asynchronously.
+// Every call uploads them, replays included, so that ws need not keep its
+// contents between calls (a caller's allocator may hand the memory to other
+// tensors in between).
+hipError_t upload_tables(const GraphEntry &E, const Layout &L, char *base, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    if (!E.pass3.empty())
+        e = hipMemcpyAsync(base + L.pass3, E.pass3.data(), sizeof(long long) * E.pass3.size(),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !E.pass2.empty())
+        e = hipMemcpyAsync(base + L.pass2, E.pass2.data(), sizeof(long long) * E.pass2.size(),
+                           hipMemcpyHostToDevice, st);
+    for (int d = 0; d < 2 && e == hipSuccess; ++d) {
+        if (E.probs[d].empty()) continue;
+        e = hipMemcpyAsync(base + L.probs[d], E.probs[d].data(),
+                           sizeof(BatchProblem) * E.probs[d].size(), hipMemcpyHostToDevice, st);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + L.tau, E.tau.data(), sizeof(double) * E.tau.size(),
+                           hipMemcpyHostToDevice, st);
+    return e;
 }
 
 void drop(GraphEntry &E)
@@ -194,13 +221,51 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
 
     std::lock_guard<std::mutex> lk(g_mu);
     GraphEntry &E = g_graphs[ws];
+    char *base = static_cast<char *>(ws);
     if (E.exec && E.key == key) {
-        hipError_t e = hipGraphLaunch(E.exec, st);
+        hipError_t e = upload_tables(E, L, base, st);
+        if (e == hipSuccess) e = hipGraphLaunch(E.exec, st);
         return e == hipSuccess ? FRKC2_OK : hip_err(e, "graph launch");
     }
     drop(E);
+    // ---- stability of every problem (Sec. 2: T rho <= betabar(s)), checked
+    // when the graph is built; replays assume the same D, as the graph does ----
+    {
+        double *partials = reinterpret_cast<double *>(base + L.partials);
+        std::vector<double> rmax(nprob, 0.0);
+        for (int i = 0; i < nprob; ++i) {
+            if (kg[i].op == FRKC2_OP_LAPLACE) {
+                double sum = 0.0;
+                for (int f = 0; f < 2 * kg[i].ndim; ++f) sum = sum + kg[i].d_const;
+                rmax[i] = sum;
+                continue;
+            }
+            int rc = launch_rho(kg[i], w[i], D[i], partials, st);
+            hipError_t e = (hipError_t)rc;
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(&rmax[i], partials + kReduceBlocks, sizeof(double),
+                                   hipMemcpyDeviceToHost, st);
+            if (e != hipSuccess) return hip_err(e, "rho check");
+        }
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_err(e, "rho check");
+        for (int i = 0; i < nprob; ++i) {
+            frkc2_coeff_info info;
+            int crc = coeffs_cached(s[i], nu, nullptr, nullptr, &info);
+            if (crc < 0) return crc;
+            const double rho = (2.0 * kg[i].inv_h2) * rmax[i];
+            if (!std::isfinite(rho)) {
+                set_error("batched: problem %d has a non-finite Gershgorin bound", i);
+                return FRKC2_ENONFINITE;
+            }
+            if (T[i] * rho > info.beta_bar) {
+                set_error("batched: problem %d: T*rho = %g exceeds beta_bar = %g", i, T[i] * rho,
+                          info.beta_bar);
+                return FRKC2_EUNSTABLE;
+            }
+        }
+    }
     // ---- work tables: 3D and 2D lists, each sorted by decreasing s (stable) ----
-    char *base = static_cast<char *>(ws);
     std::vector<int> order(nprob);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return s[a] > s[b]; });
@@ -299,21 +364,7 @@ extern "C" int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *co
             sg[j + 1] = sg[j] + (lv >= P.nfull && lv < P.npass ? P.ntiles : 0);
         }
     }
-    hipError_t e = hipSuccess;
-    if (!E.pass3.empty())
-        e = hipMemcpyAsync(base + L.pass3, E.pass3.data(), sizeof(long long) * E.pass3.size(),
-                           hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && !E.pass2.empty())
-        e = hipMemcpyAsync(base + L.pass2, E.pass2.data(), sizeof(long long) * E.pass2.size(),
-                           hipMemcpyHostToDevice, st);
-    for (int d = 0; d < 2 && e == hipSuccess; ++d) {
-        if (E.probs[d].empty()) continue;
-        e = hipMemcpyAsync(base + L.probs[d], E.probs[d].data(),
-                           sizeof(BatchProblem) * E.probs[d].size(), hipMemcpyHostToDevice, st);
-    }
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(base + L.tau, E.tau.data(), sizeof(double) * E.tau.size(),
-                           hipMemcpyHostToDevice, st);
+    hipError_t e = upload_tables(E, L, base, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_err(e, "table upload");
 

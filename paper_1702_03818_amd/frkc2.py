@@ -189,6 +189,14 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _forget(k):
+    """Drop a cached workspace; the library's batched graph keyed on its address goes first
+    (torch may hand the same address to the next buffer)."""
+    buf = _ws_cache.pop(k, None)
+    if buf is not None and k[1] == "batched" and _lib is not None:
+        _lib.frkc2_batched_release(ctypes.c_void_p(buf.data_ptr()))
+
+
 def workspace(nbytes: int, device=None, key="default"):
     """A cached uint8 device buffer of at least nbytes (grown on demand)."""
     torch = _torch()
@@ -196,14 +204,15 @@ def workspace(nbytes: int, device=None, key="default"):
     k = (dev.index, key)
     buf = _ws_cache.get(k)
     if buf is None or buf.numel() < nbytes:
-        _ws_cache.pop(k, None)
+        _forget(k)
         buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=dev)
         _ws_cache[k] = buf
     return buf
 
 
 def release_workspaces():
-    _ws_cache.clear()
+    for k in list(_ws_cache):
+        _forget(k)
 
 
 # ---- the ABI ----

@@ -108,3 +108,56 @@ def test_batch_stage_count_limits():
                 assert np.array_equal(got, cur[j]), "replay %d problem %d s=%d" % (rep, j, s)
     finally:
         F.frkc2_batched_release()
+
+
+def test_replay_after_workspace_reuse():
+    """The workspace's memory is handed to other data between two calls with identical
+    arguments (overwritten directly, and through release_workspaces and a new allocation of
+    the same size, which torch's allocator tends to place at the same address): the second
+    call must still give the plain path's bits (the library uploads its tables every call)."""
+    probs = _batch(3, 10)
+    ws = [dev(p.w0) for p, _, _, _ in probs]
+    Ds = [dev(p.D) if p.D is not None else None for p, _, _, _ in probs]
+    plain = [dev(p.w0) for p, _, _, _ in probs]
+    args = F.BatchedArgs([p for p, _, _, _ in probs], ws, Ds, [T for _, _, T, _ in probs],
+                         [s for _, s, _, _ in probs])
+    need = F.frkc2_batched_workspace_bytes([p for p, _, _, _ in probs], [s for _, s, _, _ in probs])
+    try:
+        F.frkc2_step_batched(args)
+        buf = F.workspace(need, key="batched")
+        buf.fill_(0xA5)                      # tables and buffers overwritten in place
+        F.frkc2_step_batched(args)
+        F.release_workspaces()
+        junk = torch.full((need,), 0x5A, dtype=torch.uint8, device="cuda")
+        del junk
+        F.frkc2_step_batched(args)
+        torch.cuda.synchronize()
+        assert F.frkc2_batched_status() == 0
+        for (p, s, T, c), w, D, wp in zip(probs, ws, Ds, plain):
+            F.frkc2_step(p, wp, D, T=T, s=s, nsteps=3)
+            torch.cuda.synchronize()
+            assert torch.equal(w, wp), "problem %s s=%d" % (p.n, s)
+    finally:
+        F.frkc2_batched_release()
+
+
+def test_unstable_problem_is_refused():
+    """T rho > betabar(s) for one problem of a batch: FRKC2_EUNSTABLE naming it, no state
+    touched."""
+    probs = _batch(4, 6)
+    p, s, T, c = probs[3]
+    probs[3] = (p, s, 1.01 * c.beta_bar / stage.rho_bound(p), c)
+    ws = [dev(p.w0) for p, _, _, _ in probs]
+    Ds = [dev(p.D) if p.D is not None else None for p, _, _, _ in probs]
+    args = F.BatchedArgs([p for p, _, _, _ in probs], ws, Ds, [T for _, _, T, _ in probs],
+                         [s for _, s, _, _ in probs])
+    try:
+        with pytest.raises(F.Frkc2Error) as e:
+            F.frkc2_step_batched(args)
+        assert e.value.status == -4
+        assert "problem 3" in str(e.value)
+        torch.cuda.synchronize()
+        for (p, _, _, _), w in zip(probs, ws):
+            assert np.array_equal(w.cpu().numpy(), p.w0.reshape(-1))
+    finally:
+        F.frkc2_batched_release()
