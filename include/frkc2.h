@@ -209,6 +209,27 @@ int frkc2_step(const frkc2_grid *g, double *w, const double *D, double T, double
                frkc2_step_stats *stats);
 
 /*
+ * frkc2_step_noalloc -- frkc2_step for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc. Same arguments and results as frkc2_step (bit for bit),
+ * without ws: the two complex state buffers, reduction partials and stepsize
+ * table come from a static device array of the library, one per GPU, of
+ * FRKC2_NOALLOC_MAX_VALUES * 32 bytes + 64 KiB (64 MiB + 64 KiB), held from
+ * the first call on that GPU until the process ends. The call itself performs
+ * no hipMalloc, hipFree or other device allocation.
+ *   States of more than FRKC2_NOALLOC_MAX_VALUES values (2^21, e.g. 128^3)
+ *   are refused with FRKC2_ENOMEM before any HIP call.
+ *   Every call on one GPU shares that GPU's array, which keeps the last
+ *   call's contents (nothing in it has to start at zero: every buffer is
+ *   written before it is read). Calls that overlap on one GPU (other streams,
+ *   other threads) race on it; the caller serialises them.
+ * Errors: those of frkc2_step (FRKC2_ENOMEM means the size limit above).
+ */
+#define FRKC2_NOALLOC_MAX_VALUES 2097152
+int frkc2_step_noalloc(const frkc2_grid *g, double *w, const double *D, double T, double cfl,
+                       int s, double nu, int nsteps, hipStream_t st, frkc2_step_stats *stats);
+
+/*
  * frkc2_step_adjoint -- reverse-mode derivative of one superstep (VARCOEF or LAPLACE):
  * the transpose of the Sec. 3 Euler-step recursion W^{l+1} = W^l + T a_l f(W^l),
  * applied stage by stage in reverse order.

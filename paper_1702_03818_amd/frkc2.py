@@ -24,6 +24,7 @@ FRKC2_WQBOUND = 1
 STATUS_NAMES = {0: "OK", 1: "WQBOUND", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP",
                 -4: "EUNSTABLE", -5: "ENONFINITE", -6: "ETIMEOUT"}
 WS_STEP = 0
+NOALLOC_MAX_VALUES = 2097152   # largest state frkc2_step_noalloc accepts (2^21 values)
 WS_ADJOINT = 1
 WS_ADAPT = 2
 RED_SUMSQ, RED_SUM, RED_MAXSQ, RED_SUMSQDIFF, RED_DOT = 0, 1, 2, 3, 4
@@ -85,6 +86,9 @@ _SIGS = {
     "frkc2_step": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_int, ctypes.c_double, ctypes.c_int, _VP, ctypes.c_size_t,
                                   _VP, ctypes.POINTER(StepStats)]),
+    "frkc2_step_noalloc": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                          ctypes.c_int, _VP, ctypes.POINTER(StepStats)]),
     "frkc2_step_adjoint": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, ctypes.c_double,
                                           ctypes.c_int, ctypes.c_double, _VP, _VP, _VP, _VP,
                                           ctypes.c_size_t, _VP]),
@@ -258,6 +262,20 @@ def frkc2_step(grid, w, D=None, T=0.0, cfl=0.0, s=16, nu=0.01, nsteps=1, stream=
                                float(nu), int(nsteps), ctypes.c_void_p(buf.data_ptr()),
                                buf.numel(), _stream_ptr(stream),
                                ctypes.byref(st) if st is not None else None))
+    if stats:
+        return {f: getattr(st, f) for f, _ in StepStats._fields_}
+    return rc
+
+
+def frkc2_step_noalloc(grid, w, D=None, T=0.0, cfl=0.0, s=16, nu=0.01, nsteps=1, stream=None,
+                       stats=False):
+    """frkc2_step on the library's static scratch: no workspace, no device allocation."""
+    lib = load()
+    g = make_grid(grid)
+    st = StepStats() if stats else None
+    rc = _check(lib.frkc2_step_noalloc(ctypes.byref(g), _ptr(w), _ptr(D), float(T), float(cfl),
+                                       int(s), float(nu), int(nsteps), _stream_ptr(stream),
+                                       ctypes.byref(st) if st is not None else None))
     if stats:
         return {f: getattr(st, f) for f, _ in StepStats._fields_}
     return rc

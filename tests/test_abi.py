@@ -291,3 +291,25 @@ def test_user_workspace_and_integrate_validation():
     assert call(nu=1.0) == -1
     assert call(max_attempts=0) == -1
     assert call() == -2            # arguments fine, no workspace
+
+
+def _noalloc(g, w=1, D=1, T=1e-3, cfl=0.0, s=16, nu=0.01, nsteps=1):
+    lib = F.load()
+    p = lambda v: ctypes.c_void_p(4096 * 16) if v else None  # never dereferenced: validation fails first
+    return lib.frkc2_step_noalloc(ctypes.byref(g), p(w), p(D), T, cfl, s, nu, nsteps, None, None)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(w=0), -1), (dict(D=0), -1), (dict(s=7), -1), (dict(nsteps=-1), -1), (dict(T=0.0), -1),
+])
+def test_step_noalloc_validation(kw, expect):
+    assert _noalloc(grid(), **kw) == expect
+    assert F.frkc2_last_error()
+
+
+def test_step_noalloc_size_limit():
+    """States beyond the static scratch (2^21 values) are refused before any HIP call."""
+    assert F.NOALLOC_MAX_VALUES == 2 ** 21
+    assert _noalloc(grid(n=(129, 128, 128))) == -2
+    assert "static scratch" in F.frkc2_last_error()
+    assert _noalloc(grid(ndim=2, n=(1449, 1449, 1), op=0)) == -2
