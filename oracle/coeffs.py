@@ -162,19 +162,22 @@ def _R_abs_hp(ar, ai, x: float):
         return p
 
 
-def real_extent(ar: np.ndarray, ai: np.ndarray, L: int) -> float:
+def real_extent(ar: np.ndarray, ai: np.ndarray, L: int, beta0: float | None = None) -> float:
     """Largest double b with |R(-x)| <= 1 on [0, b] (Sec. 2: extent beta).
 
     A scan in FP64 log-magnitudes, dense where C_L oscillates fastest (eight
     points per half-period in z, then a few points past z = -1), finds the first
     sample above 1; bisection on doubles with the DPS-digit predicate
-    |R(-b)| <= 1 + 1e-20 then locates the crossing.
+    |R(-b)| <= 1 + 1e-20 then locates the crossing. beta0 is the extent the
+    scan is laid out on (default: the undamped N = 2 extent 2 (L^2 - 1)/3).
     """
-    beta0 = 2.0 * (L * L - 1) / 3.0
+    if beta0 is None:
+        beta0 = 2.0 * (L * L - 1) / 3.0
     ks = np.arange(1, 8 * L + 1)
     zs = np.cos(ks * np.pi / (8 * L))
     xs = list((zs - 1.0) * (beta0 / 2.0))
     xs += [-beta0 * (1.0 + 1e-3 * j) for j in range(1, 41)]
+    xs += [-beta0 * (1.04 + 0.05 * j) for j in range(1, 21)]   # reached only past 1.04 beta0
     xs = np.array(xs)
     lr = 2.0 * log_abs_R_half(ar, ai, xs)
     bad = np.nonzero(lr > 1e-12)[0]

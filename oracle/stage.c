@@ -425,6 +425,99 @@ double oracle_rho_bound(int ndim, const long *n, int bc, int op, double inv_h2, 
     return (2.0 * inv_h2) * m;
 }
 
+/*
+ * One superstep of s stages on a complex state (Sec. 3, Euler-step equation with
+ * complex W^0): (wr, wi) in, W^s out, every stage as in oracle_superstep. The A flows
+ * of the split scheme of Sec. 4.1 start from complex states.
+ */
+int oracle_superstep_c(int ndim, const long *n, int bc, int op, double inv_h2, double d_const,
+                       const double *D, int s, const double *tau_re, const double *tau_im,
+                       double *wr, double *wi)
+{
+    grid_t g;
+    if (make_grid(&g, ndim, n, bc, op, inv_h2, d_const)) return -1;
+    long N = nstate(&g);
+    double *fr = malloc(sizeof(double) * N), *fi = malloc(sizeof(double) * N);
+    if (!fr || !fi) { free(fr); free(fi); return -2; }
+    for (int l = 0; l < s; ++l) {
+        apply_op(&g, D, wr, wi, fr, fi);
+        double tr = tau_re[l], ti = tau_im[l];
+#pragma omp parallel for schedule(static)
+        for (long p = 0; p < N; ++p) {
+            double nr = FMA(tr, fr[p], FMA(-ti, fi[p], wr[p]));
+            double ni = FMA(tr, fi[p], FMA(ti, fr[p], wi[p]));
+            wr[p] = nr;
+            wi[p] = ni;
+        }
+    }
+    free(fr); free(fi);
+    return 0;
+}
+
+/*
+ * Reaction flow of the two-species Brusselator (Sec. 3.1) over a complex time tau, the
+ * B flow of the split scheme of Sec. 4.1: dY/ds = tau f_B(Y), s in [0, 1], with
+ * f_B(v, w) = (1 - 4v + v^2 w, 3v - v^2 w) continued to complex v, w, by nsub classical
+ * Runge-Kutta steps of length 1/nsub in s. The caller passes c = tau/nsub, c/2 and c/6
+ * (re, im). Arithmetic in this order, no multiply-add fused:
+ *   f:  v2 = (vr*vr - vi*vi, 2*(vr*vi)), q = v2 w = (v2r*wr - v2i*wi, v2r*wi + v2i*wr),
+ *       fv = ((1 - 4*vr) + qr, qi - 4*vi), fw = (3*vr - qr, 3*vi - qi);
+ *   y + c k = (yr + (cr*kr - ci*ki), yi + (cr*ki + ci*kr)) per species;
+ *   k1 = f(y), k2 = f(y + (c/2) k1), k3 = f(y + (c/2) k2), k4 = f(y + c k3),
+ *   y <- y + (c/6) (((k1 + 2 k2) + 2 k3) + k4).
+ * State: v at [0, N), w at [N, 2N), real parts in zr, imaginary parts in zi.
+ */
+typedef struct { double vr, vi, wr, wi; } bz_t;
+
+static bz_t bz_f(bz_t y)
+{
+    double v2r = y.vr * y.vr - y.vi * y.vi;
+    double v2i = 2.0 * (y.vr * y.vi);
+    double qr = v2r * y.wr - v2i * y.wi;
+    double qi = v2r * y.wi + v2i * y.wr;
+    bz_t f;
+    f.vr = (1.0 - 4.0 * y.vr) + qr;
+    f.vi = qi - 4.0 * y.vi;
+    f.wr = 3.0 * y.vr - qr;
+    f.wi = 3.0 * y.vi - qi;
+    return f;
+}
+
+static bz_t bz_axpy(bz_t y, double cr, double ci, bz_t k)
+{
+    bz_t o;
+    o.vr = y.vr + (cr * k.vr - ci * k.vi);
+    o.vi = y.vi + (cr * k.vi + ci * k.vr);
+    o.wr = y.wr + (cr * k.wr - ci * k.wi);
+    o.wi = y.wi + (cr * k.wi + ci * k.wr);
+    return o;
+}
+
+void oracle_react_flow(long N, double *zr, double *zi, double cr, double ci, double c2r,
+                       double c2i, double c6r, double c6i, int nsub)
+{
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < N; ++p) {
+        bz_t y = {zr[p], zi[p], zr[N + p], zi[N + p]};
+        for (int j = 0; j < nsub; ++j) {
+            bz_t k1 = bz_f(y);
+            bz_t k2 = bz_f(bz_axpy(y, c2r, c2i, k1));
+            bz_t k3 = bz_f(bz_axpy(y, c2r, c2i, k2));
+            bz_t k4 = bz_f(bz_axpy(y, cr, ci, k3));
+            bz_t S;
+            S.vr = ((k1.vr + 2.0 * k2.vr) + 2.0 * k3.vr) + k4.vr;
+            S.vi = ((k1.vi + 2.0 * k2.vi) + 2.0 * k3.vi) + k4.vi;
+            S.wr = ((k1.wr + 2.0 * k2.wr) + 2.0 * k3.wr) + k4.wr;
+            S.wi = ((k1.wi + 2.0 * k2.wi) + 2.0 * k3.wi) + k4.wi;
+            y = bz_axpy(y, c6r, c6i, S);
+        }
+        zr[p] = y.vr;
+        zi[p] = y.vi;
+        zr[N + p] = y.wr;
+        zi[N + p] = y.wi;
+    }
+}
+
 /* Threads the OpenMP loops above use (1 when built without OpenMP). */
 #ifdef _OPENMP
 #include <omp.h>

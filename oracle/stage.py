@@ -83,6 +83,10 @@ def _declare(lib):
     lib.oracle_euler_update.restype = None
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_superstep_c.argtypes = common + [dp, dp]
+    lib.oracle_superstep_c.restype = ctypes.c_int
+    lib.oracle_react_flow.argtypes = [ctypes.c_long, dp, dp] + [ctypes.c_double] * 6 + [ctypes.c_int]
+    lib.oracle_react_flow.restype = None
 
 
 def _dp(a):
@@ -209,3 +213,29 @@ def euler_update(wr, wi, fr, fi, tr, ti, emb=None):
         assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
     _load().oracle_euler_update(wr.size, _dp(wr), _dp(wi), _dp(fr), _dp(fi), float(tr), float(ti),
                                 _dp(emb))
+
+
+def superstep_complex(prob, wr, wi, tau_re, tau_im, op=None, D=None):
+    """s stages on the complex state (wr, wi) in place (contiguous float64), the operator of
+    prob (or op; op 0 with prob.d_const is the diffusion flow of the split scheme)."""
+    lib = _load()
+    n, inv_h2 = _grid_args(prob)
+    for a in (wr, wi):
+        assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    opv = prob.op if op is None else op
+    Dd = D if D is not None else (prob.D if opv == 1 else None)
+    Dd = _f64(Dd) if Dd is not None else None
+    tr, ti = _f64(tau_re), _f64(tau_im)
+    rc = lib.oracle_superstep_c(prob.ndim, n, prob.bc, opv, inv_h2, prob.d_const, _dp(Dd),
+                                len(tr), _dp(tr), _dp(ti), _dp(wr), _dp(wi))
+    if rc != 0:
+        raise RuntimeError("oracle_superstep_c failed (%d)" % rc)
+
+
+def react_flow(N, zr, zi, taus, nsub):
+    """Brusselator reaction flow over a complex time (in place; v then w in zr, zi); taus =
+    (c, c/2, c/6) as (re, im) pairs, c = tau / nsub."""
+    for a in (zr, zi):
+        assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"] and a.size == 2 * N
+    (cr, ci), (c2r, c2i), (c6r, c6i) = taus
+    _load().oracle_react_flow(int(N), _dp(zr), _dp(zi), cr, ci, c2r, c2i, c6r, c6i, int(nsub))
