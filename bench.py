@@ -444,6 +444,69 @@ def brusselator_leg(F, wl, torch):
             "steps_to_error": runs}
 
 
+def fourth_order_leg(F, wl, torch, steps=(10, 20, 40, 80, 160, 320), m_ref=2560):
+    """Steps to error on the Brusselator (Sec. 3.1 problem, 200^2, t = 0 .. 1): fixed-step
+    FRKC4s (the split fourth-order scheme of Sec. 4.1, nsub = 4 reaction substeps) against
+    fixed-step FRKC2 with the same number of steps. Each run uses the smallest stage count
+    whose extent covers its step (FRKC4s: (T/4) rho_A <= 0.9 betabar_4(s), rho_A = 8 d / h^2;
+    FRKC2: T rho <= 0.7 betabar(s) with rho the Gershgorin bound of the initial state).
+    Errors are max norms against FRKC4s with m_ref steps (a self-convergence reference)."""
+    p = wl.brusselator(200)
+    rho_a = 8 * p.d_const / (p.h * p.h)
+    w0 = torch.tensor(p.w0.reshape(-1), dtype=torch.float64, device="cuda")
+    rho2 = F.frkc2_rho_bound(p, w0, None)
+
+    def s4_for(T):
+        s = 4
+        while F.frkc4_coeffs(s, NU)[2]["beta_bar"] * 0.9 < 0.25 * T * rho_a:
+            s += 4
+        return s
+
+    def s2_for(T):
+        s = 2
+        while F.frkc2_coeffs(s, NU)[2]["beta_bar"] * 0.7 < T * rho2:
+            s += 2
+        return s
+
+    def run4(m):
+        T = 1.0 / m
+        s = s4_for(T)
+        w = w0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F.frkc4s_step(p, w, T, s, nsub=4, nu=NU, nsteps=m)
+        torch.cuda.synchronize()
+        return w, s, time.perf_counter() - t0
+
+    ref, s_ref, t_ref = run4(m_ref)
+    out = {"grid": [200, 200], "t_end": 1.0, "nsub": 4,
+           "reference": {"scheme": "FRKC4s", "steps": m_ref, "s": s_ref, "wall_s": t_ref},
+           "frkc4s": [], "frkc2": []}
+    for m in steps:
+        w, s, dt = run4(m)
+        err = float(torch.max(torch.abs(w - ref)))
+        out["frkc4s"].append({"steps": m, "s": s, "diffusion_stages": m * 4 * s,
+                              "max_error": err, "wall_ms": dt * 1e3})
+        T = 1.0 / m
+        s2 = s2_for(T)
+        w = w0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F.frkc2_step(p, w, None, T=T, s=s2, nsteps=m)
+        torch.cuda.synchronize()
+        dt2 = time.perf_counter() - t0
+        err2 = float(torch.max(torch.abs(w - ref)))
+        out["frkc2"].append({"steps": m, "s": s2, "stages": m * s2, "max_error": err2,
+                             "wall_ms": dt2 * 1e3})
+        log("fourth order: %d steps: FRKC4s s=%d error %.2e; FRKC2 s=%d error %.2e"
+            % (m, s, err, s2, err2))
+    e = [r["max_error"] for r in out["frkc4s"]]
+    out["frkc4s_order"] = [float(np.log2(e[i] / e[i + 1])) for i in range(len(e) - 1)]
+    e2 = [r["max_error"] for r in out["frkc2"]]
+    out["frkc2_order"] = [float(np.log2(e2[i] / e2[i + 1])) for i in range(len(e2) - 1)]
+    return out
+
+
 def adjoint_leg(F, wl, torch, reps=3):
     """3D 128^3 variable D, s = 64, 8 supersteps, J = sum (w - target)^2: forward alone
     and forward + adjoint through the autograd function."""
@@ -504,7 +567,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the error-control leg")
     ap.add_argument("--no-bruss", action="store_true", help="skip the Brusselator leg")
-    ap.add_argument("--only", choices=("bruss-throughput", "batched", "adjoint", "porous2d", "heat1d"),
+    ap.add_argument("--only", choices=("bruss-throughput", "batched", "adjoint", "porous2d", "heat1d",
+                                       "fourth-order"),
                     help="run only this measurement and print its JSON (for profiling)")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 1D heat and 2D porous-medium legs")
@@ -548,7 +612,8 @@ def main():
     torch.cuda.set_device(0)
     if args.only:
         legs = {"bruss-throughput": brusselator_throughput, "batched": batched_leg,
-                "adjoint": adjoint_leg, "porous2d": porous2d_leg, "heat1d": heat1d_leg}
+                "adjoint": adjoint_leg, "porous2d": porous2d_leg, "heat1d": heat1d_leg,
+                "fourth-order": fourth_order_leg}
         print(json.dumps({args.only: legs[args.only](F, wl, torch)}), flush=True)
         return
     log("generating the 3D workload (n=%d)" % args.n)
@@ -703,6 +768,8 @@ def main():
     out["adjoint"] = None if args.no_adjoint else adjoint_leg(F, wl, torch)
     torch.cuda.empty_cache()
     out["brusselator"] = None if args.no_bruss else brusselator_leg(F, wl, torch)
+    torch.cuda.empty_cache()
+    out["fourth_order"] = None if args.no_bruss else fourth_order_leg(F, wl, torch)
     torch.cuda.empty_cache()
     out["heat1d"] = None if args.no_small else heat1d_leg(F, wl, torch)
     out["porous2d"] = None if args.no_small else porous2d_leg(F, wl, torch)

@@ -141,6 +141,24 @@ typedef struct {
 int frkc2_coeffs(int s, double nu, double *a_re, double *a_im, frkc2_coeff_info *info);
 
 /*
+ * frkc4_coeffs -- the s ordered stepsizes of the fourth-order (N = 4) FRKC
+ * polynomial (Sec. 2: B = d0 + 2 sum_{k=1..4} d_k C_{kM}, L = 4M, the d_k from
+ * the linear order conditions R^(n)(0) = 1, n = 1..4), in the internal-stability
+ * order of Sec. 2.2; the linear flows of the split scheme FRKC4s (Sec. 4.1).
+ * Readings: R(x) = P(C_M(z))/P(1), z = 1 + x/(M^2 alpha_M), P of degree 4 fixed
+ * by the order conditions for a given alpha_M; damping nu (Sec. 2.1) sets
+ * alpha_M so that P(-1) = 1 - 4 nu (the marginal real-axis points get
+ * |R| = 1 - 4 nu; nu = 0 gives the largest extent, |P| <= 1 on [-1, 1]); the
+ * 2M stepsizes from the roots of P with positive imaginary part are ordered
+ * greedily and followed by their conjugates. M = 1 is classical RK4.
+ *   s       multiple of 4, 4 <= s <= 512
+ *   nu      0 <= nu < 0.25
+ *   a_re, a_im, info  as for frkc2_coeffs (info->mu_re holds alpha_M, mu_im 0)
+ * Host only; cached per (s, nu). Returns FRKC2_OK, FRKC2_WQBOUND or FRKC2_EINVAL.
+ */
+int frkc4_coeffs(int s, double nu, double *a_re, double *a_im, frkc2_coeff_info *info);
+
+/*
  * frkc2_write_table -- the stepsize table in the layout of the paper's public
  * code (Sec. 3.1, "FRKC2 public code"): for M = 1 .. m_max (s = 2M stages),
  * line 3M-2 holds betabar and the realised Q, line 3M-1 the real parts and
@@ -405,6 +423,34 @@ int frkc2_integrate_user(long long n, double *w, frkc2_user_f f, frkc2_user_rho 
                          double rho_const, void *user, double t_span, double T0, double tol,
                          double nu, int max_attempts, void *ws, size_t ws_bytes, hipStream_t st,
                          double *trace, int trace_cap, frkc2_adapt_stats *stats);
+
+/*
+ * frkc4s_step -- nsteps steps of the fourth-order split scheme FRKC4s (Sec. 4.1,
+ * "Complex splitting") on the two-species Brusselator (g->op = FRKC2_OP_BRUSS2,
+ * periodic 2D, d = g->d_const): w' = A w + f_B(w) with A = d lap per species and
+ * f_B the reaction of Sec. 3.1. One step of length T is
+ *   w <- Re[ e^{b1 T B} e^{T/4 A} e^{b2 T B} e^{T/4 A} e^{b3 T B} e^{T/4 A}
+ *            e^{b2 T B} e^{T/4 A} e^{b1 T B} w ],
+ * b1 = (3 + i)/30, b2 = (4 - 2i)/15, b3 = (4 + 3i)/15 (the symmetric
+ * composition with four equal real A steps; consistency and the third-order
+ * conditions leave this conjugate pair, the paper prints no coefficients).
+ * Each A flow is one superstep of s stages of the fourth-order polynomial
+ * (frkc4_coeffs) on the complex state, per species, fused as frkc2_step
+ * fuses stages; each B flow integrates dY/dsig = (b T) f_B(Y), sig in [0, 1], by
+ * nsub classical Runge-Kutta steps per grid point (arithmetic order in
+ * frkc4.hip). The first B flow starts from (w, 0); the step keeps Re.
+ *   w      device, 2N doubles (v then w), in/out
+ *   T      step length, > 0; (T/4) rho <= betabar_4(s) is required,
+ *          rho = 8 d / h^2 (FRKC2_EUNSTABLE otherwise)
+ *   s      multiple of 4, 4..512; nu as for frkc4_coeffs
+ *   nsub   1..64
+ *   ws     frkc4s_workspace_bytes(g) bytes, 16-byte aligned
+ * Asynchronous. Errors: FRKC2_EINVAL (arguments, checked before any HIP call),
+ * FRKC2_EUNSTABLE, FRKC2_ENOMEM, FRKC2_EHIP.
+ */
+size_t frkc4s_workspace_bytes(const frkc2_grid *g);
+int frkc4s_step(const frkc2_grid *g, double *w, double T, int s, int nsub, double nu, int nsteps,
+                void *ws, size_t ws_bytes, hipStream_t st);
 
 /*
  * frkc2_autotune -- pick the launch configuration of frkc2_step's passes for

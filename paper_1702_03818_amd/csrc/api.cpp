@@ -719,6 +719,144 @@ extern "C" int frkc2_autotune(const frkc2_grid *g, const double *w, const double
     return crc;
 }
 
+namespace {
+
+// One linear flow of s stages on the complex state Z (Sec. 3 Euler steps with
+// complex W^0): passes as run_superstep schedules them, the first reading Z,
+// the last writing Z, the ones between ping-ponging buf. A fused pass reads a
+// halo around its tiles, so a single pass may not read and write Z: the
+// first pass then takes one stage less.
+int run_flow_c(const KGrid &kg, const PassCfg &cfg, double *Z, double Tn, const double *are,
+               const double *aim, int s, double *const buf[2], hipStream_t st)
+{
+    const int k = cfg.k;
+    int l = 0, pass = 0;
+    const double *in = Z;
+    while (l < s) {
+        int kk = (k >= 2 && s - l >= k) ? k : 1;
+        if (kk == 1 && k > 2 && s - l >= 2 && tblock_supported(kg, s - l)) kk = s - l;
+        if (l == 0 && kk == s && s > 1) {
+            kk = s - 1;
+            while (kk >= 2 && !tblock_supported(kg, kk)) --kk;
+        }
+        PassArgs pa{};
+        pa.k = kk;
+        pa.zchunk = cfg.zchunk;
+        pa.in_c = in;
+        const bool last = (l + kk == s);
+        double *out = last ? Z : buf[pass & 1];
+        pa.out_c = out;
+        for (int i = 0; i < kk; ++i) {
+            pa.tr[i] = Tn * are[l + i];
+            pa.ti[i] = Tn * aim[l + i];
+        }
+        const int rc = (kk == 1) ? launch_pass(kg, pa, 1, st) : launch_tblock(kg, pa, cfg.tile, st);
+        if (rc != 0) return rc;
+        in = out;
+        l += kk;
+        ++pass;
+    }
+    return 0;
+}
+
+// The B steps of the split scheme: b1 = (3 + i)/30, b2 = (4 - 2i)/15,
+// b3 = (4 + 3i)/15, in the order b1 b2 b3 b2 b1.
+const double kSplitB[5][2] = {{3.0 / 30.0, 1.0 / 30.0}, {4.0 / 15.0, -2.0 / 15.0},
+                              {4.0 / 15.0, 3.0 / 15.0}, {4.0 / 15.0, -2.0 / 15.0},
+                              {3.0 / 30.0, 1.0 / 30.0}};
+
+struct SplitLayout {
+    size_t Z, bufA, bufB, total;
+};
+
+SplitLayout split_layout(long long N)
+{
+    SplitLayout L;
+    L.Z = 0;
+    L.bufA = align_up((size_t)N * 32);
+    L.bufB = L.bufA + align_up((size_t)N * 16);
+    L.total = L.bufB + align_up((size_t)N * 16) + kScratch;
+    return L;
+}
+
+bool split_grid(const frkc2_grid *g, KGrid &kb, KGrid &ka)
+{
+    if (!make_kgrid(g, kb)) return false;
+    if (kb.op != FRKC2_OP_BRUSS2) {
+        set_error("frkc4s_step: the split scheme runs the Brusselator (op BRUSS2)");
+        return false;
+    }
+    frkc2_grid gl = *g;
+    gl.op = FRKC2_OP_LAPLACE;
+    return make_kgrid(&gl, ka);
+}
+
+}  // namespace
+
+extern "C" size_t frkc4s_workspace_bytes(const frkc2_grid *g)
+{
+    KGrid kb, ka;
+    if (!split_grid(g, kb, ka)) return 0;
+    return split_layout(ka.npts()).total;
+}
+
+extern "C" int frkc4s_step(const frkc2_grid *g, double *w, double T, int s, int nsub, double nu,
+                           int nsteps, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    KGrid kb, ka;
+    if (!split_grid(g, kb, ka)) return FRKC2_EINVAL;
+    if (!w) {
+        set_error("frkc4s_step: w is NULL");
+        return FRKC2_EINVAL;
+    }
+    if (!(T > 0.0) || !std::isfinite(T) || nsub < 1 || nsub > 64 || nsteps < 0) {
+        set_error("frkc4s_step: need T > 0 finite, 1 <= nsub <= 64, nsteps >= 0");
+        return FRKC2_EINVAL;
+    }
+    const double *are, *aim;
+    frkc2_coeff_info info;
+    const int crc = coeffs4_cached(s, nu, &are, &aim, &info);
+    if (crc < 0) return crc;
+    // stability of the linear flows of length T/4 (Sec. 2): Gershgorin bound of
+    // the periodic Laplacian, 2 (4 d) / h^2, exact
+    double dsum = 0.0;
+    for (int f = 0; f < 2 * ka.ndim; ++f) dsum = dsum + ka.d_const;
+    const double rho = (2.0 * ka.inv_h2) * dsum;
+    const double TA = T * 0.25;
+    if (TA * rho > info.beta_bar) {
+        set_error("frkc4s_step: (T/4)*rho = %g exceeds beta_bar(%d) = %g", TA * rho, s,
+                  info.beta_bar);
+        return FRKC2_EUNSTABLE;
+    }
+    const long long N = ka.npts();
+    const SplitLayout L = split_layout(N);
+    if (!ws || ws_bytes < L.total || !aligned16(ws)) {
+        set_error("frkc4s_step: workspace needs %zu bytes (got %zu), 16-byte aligned", L.total,
+                  ws_bytes);
+        return FRKC2_ENOMEM;
+    }
+    char *base = static_cast<char *>(ws);
+    double *Z = reinterpret_cast<double *>(base + L.Z);
+    double *buf[2] = {reinterpret_cast<double *>(base + L.bufA),
+                      reinterpret_cast<double *>(base + L.bufB)};
+    const PassCfg cfg = pass_cfg(ka);
+    for (int step = 0; step < nsteps; ++step) {
+        HIP_TRY(launch_real_to_complex(2 * N, w, Z, st), "split: state upload");
+        for (int j = 0; j < 5; ++j) {
+            const double tr = kSplitB[j][0] * T, ti = kSplitB[j][1] * T;
+            const double cr = tr / (double)nsub, ci = ti / (double)nsub;
+            const double c[6] = {cr, ci, cr / 2.0, ci / 2.0, cr / 6.0, ci / 6.0};
+            HIP_TRY(launch_react_flow(Z, N, c, nsub, st), "split: reaction flow");
+            if (j == 4) break;
+            for (int sp = 0; sp < 2; ++sp)
+                HIP_TRY(run_flow_c(ka, cfg, Z + 2 * N * sp, TA, are, aim, s, buf, st),
+                        "split: diffusion flow");
+        }
+        HIP_TRY(launch_take_real(Z, w, 2 * N, st), "split: real part");
+    }
+    return crc;
+}
+
 extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const double *D,
                                   double T, int s, double nu, const double *lam_next,
                                   double *lam_n, double *grad_logD, void *ws, size_t ws_bytes,

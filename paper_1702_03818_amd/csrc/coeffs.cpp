@@ -133,15 +133,16 @@ bool stable_q(const std::vector<double> &ar, const std::vector<double> &ai, doub
 // Largest double b with |R(-x)| <= 1 on [0, b]: scan dense where C_L
 // oscillates fastest (8 samples per half period in z, then past z = -1), then
 // bisect on doubles with the binary128 test.
-double real_extent(const std::vector<double> &ar, const std::vector<double> &ai, int L)
+double real_extent(const std::vector<double> &ar, const std::vector<double> &ai, int L,
+                   double beta0)
 {
-    double beta0 = 2.0 * (double)(L * L - 1) / 3.0;
     std::vector<double> xs;
     for (int k = 1; k <= 8 * L; ++k) {
         double zk = std::cos((double)k * M_PI / (double)(8 * L));
         xs.push_back((zk - 1.0) * (beta0 / 2.0));
     }
     for (int j = 1; j <= 40; ++j) xs.push_back(-beta0 * (1.0 + 1e-3 * j));
+    for (int j = 1; j <= 20; ++j) xs.push_back(-beta0 * (1.04 + 0.05 * j));   // past 1.04 beta0
     size_t i = 0;
     for (; i < xs.size(); ++i)
         if (2.0 * log_abs_half(ar, ai, xs[i]) > 1e-12) break;
@@ -237,7 +238,7 @@ Entry compute(int s, double nu)
         ar[i] = (double)aq[i].re;
         ai[i] = (double)aq[i].im;
     }
-    double beta = real_extent(ar, ai, L);
+    double beta = real_extent(ar, ai, L, 2.0 * (double)(L * L - 1) / 3.0);
     double bound = 10.0 * (double)L * (double)L;
     double best_q = INFINITY, best_bb = 0.0;
     int best_n = 0;
@@ -272,7 +273,247 @@ Entry compute(int s, double nu)
     return e;
 }
 
+// ---- Fourth order (N = 4), the A flows of the split scheme (Sec. 4.1) ----
+//
+// R(x) = P(C_M(z)) / P(1), z = 1 + x / (M^2 alpha_M), P of degree 4 in y = C_M(z).
+// For a given alpha_M the four order conditions R^(n)(0) = 1 fix the
+// derivatives p_k = P^(k)(1) / P(1) (chain rule for P(g(x)) with
+// g^(n)(0) = C_M^(n)(1) / (M^2 alpha_M)^n, C_M^(n)(1) = prod_{j<n} (M^2 - j^2)/(2j+1)).
+// |R| <= 1 on [-2 M^2 alpha_M, 0] iff |P| <= 1 on [-1, 1]; alpha_M is taken
+// with P(-1) = 1 - 4 nu (damping: the marginal real-axis points keep
+// |R| = 1 - 4 nu). Stepsizes from the roots: C_M(zeta) = y for each root y
+// of P, zeta = cos((acos(y) + 2 pi j)/M), a = 1/(M^2 alpha_M (1 - zeta)).
+
+void taylor_p4(int M, q_t alpha, q_t p[4])
+{
+    q_t c[4], v = 1;
+    for (int j = 0; j < 4; ++j) {
+        v = v * ((q_t)M * (q_t)M - (q_t)(j * j)) / (q_t)(2 * j + 1);
+        c[j] = v;
+    }
+    const q_t sc = (q_t)M * (q_t)M * alpha;
+    q_t g[4];
+    q_t pw = sc;
+    for (int k = 0; k < 4; ++k) {
+        g[k] = c[k] / pw;
+        pw = pw * sc;
+    }
+    const q_t g1 = g[0];
+    p[0] = 1 / g1;
+    p[1] = (1 - p[0] * g[1]) / (g1 * g1);
+    p[2] = (1 - 3 * p[1] * g1 * g[1] - p[0] * g[2]) / (g1 * g1 * g1);
+    p[3] = (1 - 6 * p[2] * g1 * g1 * g[1] - p[1] * (3 * g[1] * g[1] + 4 * g1 * g[2]) - p[0] * g[3]) /
+           (g1 * g1 * g1 * g1);
+}
+
+// coefficients of y^0 .. y^4 of P(y) = 1 + sum_k p_k (y - 1)^k / k!
+void poly4(int M, q_t alpha, q_t coef[5])
+{
+    q_t p[4];
+    taylor_p4(M, alpha, p);
+    for (int j = 0; j < 5; ++j) coef[j] = 0;
+    coef[0] = 1;
+    q_t fact = 1;
+    for (int k = 1; k <= 4; ++k) {
+        fact *= k;
+        q_t binom = 1;   // C(k, j)
+        for (int j = 0; j <= k; ++j) {
+            const q_t sign = ((k - j) % 2) ? -1 : 1;
+            coef[j] += p[k - 1] / fact * binom * sign;
+            binom = binom * (q_t)(k - j) / (q_t)(j + 1);
+        }
+    }
+}
+
+q_t p_minus1(int M, q_t alpha)
+{
+    q_t p[4];
+    taylor_p4(M, alpha, p);
+    q_t v = 1, fact = 1, pw = 1;
+    for (int k = 1; k <= 4; ++k) {
+        fact *= k;
+        pw *= -2;
+        v += p[k - 1] * pw / fact;
+    }
+    return v;
+}
+
+// alpha_M with P(-1) = 1 - 4 nu by bisection on [0.5, 3]; < 0 if not bracketed
+q_t alpha4(int M, double nu)
+{
+    const q_t target = 1 - 4 * (q_t)nu;
+    q_t lo = 0.5Q, hi = 3;
+    if (!(p_minus1(M, lo) - target < 0 && p_minus1(M, hi) - target > 0)) return -1;
+    for (int it = 0; it < 200; ++it) {
+        q_t mid = (lo + hi) / 2;
+        if (p_minus1(M, mid) - target < 0) lo = mid; else hi = mid;
+    }
+    return (lo + hi) / 2;
+}
+
+qc poly_eval(const q_t c[5], qc z)
+{
+    qc v = {c[4], 0};
+    for (int j = 3; j >= 0; --j) v = v * z + qc{c[j], 0};
+    return v;
+}
+
+qc poly_deriv(const q_t c[5], qc z)
+{
+    qc v = {4 * c[4], 0};
+    for (int j = 3; j >= 1; --j) v = v * z + qc{(q_t)j * c[j], 0};
+    return v;
+}
+
+// the four roots of c4 y^4 + ... + c0: Weierstrass (Durand-Kerner) iteration,
+// then Newton steps on each root
+void quartic_roots(const q_t c[5], qc r[4])
+{
+    const qc seed = {0.4Q, 0.9Q};
+    qc z = {1, 0};
+    for (int i = 0; i < 4; ++i) {
+        r[i] = z;
+        z = z * seed;
+    }
+    for (int it = 0; it < 500; ++it) {
+        q_t change = 0;
+        for (int i = 0; i < 4; ++i) {
+            qc den = {c[4], 0};
+            for (int j = 0; j < 4; ++j)
+                if (j != i) den = den * (r[i] - r[j]);
+            qc d = poly_eval(c, r[i]) / den;
+            r[i] = r[i] - d;
+            change += fabsq(d.re) + fabsq(d.im);
+        }
+        if (change < 1e-33Q) break;
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int it = 0; it < 4; ++it) r[i] = r[i] - poly_eval(c, r[i]) / poly_deriv(c, r[i]);
+}
+
+qc q_cos(qc t) { return {cosq(t.re) * coshq(t.im), -sinq(t.re) * sinhq(t.im)}; }
+qc q_sin(qc t) { return {sinq(t.re) * coshq(t.im), cosq(t.re) * sinhq(t.im)}; }
+
+// principal acos(y): the double-precision value refined by Newton on cos(t) = y
+qc q_acos(qc y)
+{
+    std::complex<double> t0 = std::acos(std::complex<double>((double)y.re, (double)y.im));
+    qc t = {(q_t)t0.real(), (q_t)t0.imag()};
+    for (int it = 0; it < 8; ++it) {
+        qc s = q_sin(t);
+        t = t + (q_cos(t) - y) / s;   // t - (cos t - y) / (-sin t)
+    }
+    return t;
+}
+
+// stepsizes from the two roots of P with Im y > 0 (sorted by real, then imaginary part)
+std::vector<qc> half_group4(int M, double nu, q_t &alpha)
+{
+    std::vector<qc> a;
+    alpha = alpha4(M, nu);
+    if (!(alpha > 0)) return a;
+    q_t c[5];
+    poly4(M, alpha, c);
+    qc r[4];
+    quartic_roots(c, r);
+    std::vector<qc> up;
+    for (int i = 0; i < 4; ++i)
+        if (r[i].im > 0) up.push_back(r[i]);
+    if (up.size() != 2) return a;
+    if (up[1].re < up[0].re || (up[1].re == up[0].re && up[1].im < up[0].im)) std::swap(up[0], up[1]);
+    const q_t sc = (q_t)M * (q_t)M * alpha;
+    for (const qc &y : up) {
+        const qc th0 = q_acos(y);
+        for (int j = 0; j < M; ++j) {
+            const qc th = {(th0.re + 2 * M_PIq * (q_t)j) / (q_t)M, th0.im / (q_t)M};
+            const qc sh = q_sin(qc{th.re / 2, th.im / 2});
+            const qc om = (q_t)2 * (sh * sh);
+            a.push_back(qc{1, 0} / (sc * om));
+        }
+    }
+    return a;
+}
+
+Entry compute4(int s, double nu)
+{
+    const int L = s, M = s / 4;
+    Entry e;
+    q_t alpha;
+    std::vector<qc> aq = half_group4(M, nu, alpha);
+    if (aq.empty()) {
+        e.info.beta = -1.0;
+        e.status = FRKC2_EINVAL;
+        return e;
+    }
+    std::vector<double> ar(aq.size()), ai(aq.size());
+    for (size_t i = 0; i < aq.size(); ++i) {
+        ar[i] = (double)aq[i].re;
+        ai[i] = (double)aq[i].im;
+    }
+    const double alpha_d = (double)alpha;
+    double beta = real_extent(ar, ai, L, 2.0 * (double)M * (double)M * alpha_d);
+    double bound = 10.0 * (double)L * (double)L;
+    double best_q = INFINITY, best_bb = 0.0;
+    int best_n = 0;
+    std::vector<std::complex<double>> best_seq;
+    for (int n = 1; n <= kShrinkMax; ++n) {
+        double beta_bar = (1.0 - n * kShrinkC) * beta;
+        std::vector<int> ord = greedy(ar, ai, beta_bar, L);
+        std::vector<std::complex<double>> seq;
+        for (int j : ord) seq.emplace_back(ar[j], ai[j]);
+        for (int j : ord) seq.emplace_back(ar[j], -ai[j]);
+        double q = realised_q(seq, beta, L);
+        if (q < best_q) {
+            best_q = q;
+            best_n = n;
+            best_bb = beta_bar;
+            best_seq = seq;
+        }
+        if (q <= bound) break;
+    }
+    for (auto &c : best_seq) {
+        e.re.push_back(c.real());
+        e.im.push_back(c.imag());
+    }
+    e.info.beta = beta;
+    e.info.beta_bar = best_bb;
+    e.info.q_realised = best_q;
+    e.info.mu_re = alpha_d;
+    e.info.mu_im = 0.0;
+    e.info.n_shrink = best_n;
+    e.info.q_bound_met = best_q <= bound;
+    e.status = e.info.q_bound_met ? FRKC2_OK : FRKC2_WQBOUND;
+    return e;
+}
+
+std::map<std::pair<int, double>, Entry> g_cache4;
+
 }  // namespace
+
+int coeffs4_cached(int s, double nu, const double **re, const double **im, frkc2_coeff_info *info)
+{
+    if (s < 4 || s > kMaxStages4 || (s % 4) != 0) {
+        set_error("frkc4_coeffs: s must be a multiple of 4 with 4 <= s <= %d (got %d)",
+                  kMaxStages4, s);
+        return FRKC2_EINVAL;
+    }
+    if (!(nu >= 0.0 && nu < 0.25)) {
+        set_error("frkc4_coeffs: nu must lie in [0, 0.25) (got %g)", nu);
+        return FRKC2_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_pair(s, nu);
+    auto it = g_cache4.find(key);
+    if (it == g_cache4.end()) it = g_cache4.emplace(key, compute4(s, nu)).first;
+    if (it->second.info.beta <= 0.0) {
+        set_error("frkc4_coeffs: construction failed for s=%d", s);
+        return FRKC2_EINVAL;
+    }
+    if (re) *re = it->second.re.data();
+    if (im) *im = it->second.im.data();
+    if (info) *info = it->second.info;
+    return it->second.status;
+}
 
 int coeffs_cached(int s, double nu, const double **re, const double **im, frkc2_coeff_info *info)
 {
@@ -304,6 +545,16 @@ extern "C" int frkc2_coeffs(int s, double nu, double *a_re, double *a_im, frkc2_
 {
     const double *re = nullptr, *im = nullptr;
     int rc = frkc2::coeffs_cached(s, nu, &re, &im, info);
+    if (rc < 0) return rc;
+    if (a_re) std::memcpy(a_re, re, sizeof(double) * (size_t)s);
+    if (a_im) std::memcpy(a_im, im, sizeof(double) * (size_t)s);
+    return rc;
+}
+
+extern "C" int frkc4_coeffs(int s, double nu, double *a_re, double *a_im, frkc2_coeff_info *info)
+{
+    const double *re = nullptr, *im = nullptr;
+    int rc = frkc2::coeffs4_cached(s, nu, &re, &im, info);
     if (rc < 0) return rc;
     if (a_re) std::memcpy(a_re, re, sizeof(double) * (size_t)s);
     if (a_im) std::memcpy(a_im, im, sizeof(double) * (size_t)s);

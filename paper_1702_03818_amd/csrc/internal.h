@@ -16,6 +16,9 @@ void set_error(const char *fmt, ...);
 
 // Cached ordered stepsizes (host pointers valid for the process lifetime).
 int coeffs_cached(int s, double nu, const double **re, const double **im, frkc2_coeff_info *info);
+// ... of the fourth-order polynomial (s = 4M stages; info.mu_re holds alpha_M).
+constexpr int kMaxStages4 = 512;
+int coeffs4_cached(int s, double nu, const double **re, const double **im, frkc2_coeff_info *info);
 
 // Grid description as the kernels see it. For ndim = 1 and 2 the last used
 // dimension is the "march" dimension: (nx, ny, nz) = (n0, 1, 1) in 1D,
@@ -109,6 +112,11 @@ int launch_rho(const KGrid &g, const double *w, const double *D, double *partial
 int launch_err_max(const double *Wc, const double *E, long long n, double tol, double *partials,
                    hipStream_t st);
 int launch_take_real(const double *Wc, double *w, long long n, hipStream_t st);
+
+// Brusselator reaction flow over a complex time (frkc4.hip), in place on the
+// complex state (v then w, n points each); c = {c, c/2, c/6} as (re, im) pairs,
+// c = tau / nsub.
+int launch_react_flow(double *Zc, long long n, const double c[6], int nsub, hipStream_t st);
 
 // Adjoint (adjoint.hip).
 struct AdjArgs {

@@ -81,6 +81,11 @@ USER_RHO = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong, ct
 
 _SIGS = {
     "frkc2_coeffs": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, _DP, _DP, ctypes.POINTER(CoeffInfo)]),
+    "frkc4_coeffs": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, _DP, _DP, ctypes.POINTER(CoeffInfo)]),
+    "frkc4s_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid)]),
+    "frkc4s_step": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, ctypes.c_double, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_double, ctypes.c_int, _VP,
+                                   ctypes.c_size_t, _VP]),
     "frkc2_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), ctypes.c_int, ctypes.c_int]),
     "frkc2_rho_bound": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, _DP, _VP, ctypes.c_size_t, _VP]),
     "frkc2_step": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, ctypes.c_double, ctypes.c_double,
@@ -231,6 +236,31 @@ def frkc2_coeffs(s: int, nu: float = 0.01):
                                  ctypes.byref(info)))
     d = {f: getattr(info, f) for f, _ in CoeffInfo._fields_}
     return re, im, d, rc
+
+
+def frkc4_coeffs(s: int, nu: float = 0.01):
+    """Fourth-order stepsizes: returns (a_re, a_im, info dict, status). Host only."""
+    lib = load()
+    re = np.zeros(s)
+    im = np.zeros(s)
+    info = CoeffInfo()
+    rc = _check(lib.frkc4_coeffs(int(s), float(nu), re.ctypes.data_as(_DP), im.ctypes.data_as(_DP),
+                                 ctypes.byref(info)))
+    d = {f: getattr(info, f) for f, _ in CoeffInfo._fields_}
+    return re, im, d, rc
+
+
+def frkc4s_step(grid, w, T, s, nsub=4, nu=0.01, nsteps=1, stream=None, ws=None):
+    """nsteps steps of the split fourth-order scheme on the Brusselator state w (in place)."""
+    lib = load()
+    g = make_grid(grid)
+    need = lib.frkc4s_workspace_bytes(ctypes.byref(g))
+    if need == 0:
+        _check(-1)
+    buf = ws if ws is not None else workspace(need, key="split")
+    return _check(lib.frkc4s_step(ctypes.byref(g), _ptr(w), float(T), int(s), int(nsub), float(nu),
+                                  int(nsteps), ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                  _stream_ptr(stream)))
 
 
 def frkc2_workspace_bytes(grid, s: int, flags: int = WS_STEP) -> int:

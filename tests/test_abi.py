@@ -19,7 +19,7 @@ def header_functions():
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     src = open(os.path.join(root, HEADER)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(frkc2_\w+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(frkc(?:2|4s?)_\w+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_function():
@@ -313,3 +313,47 @@ def test_step_noalloc_size_limit():
     assert _noalloc(grid(n=(129, 128, 128))) == -2
     assert "static scratch" in F.frkc2_last_error()
     assert _noalloc(grid(ndim=2, n=(1449, 1449, 1), op=0)) == -2
+
+
+@pytest.mark.parametrize("nu", [0.0, 0.01, 0.05])
+def test_frkc4_coeffs_bitwise_equal_to_oracle(nu):
+    """Fourth-order stepsizes: library (binary128 bisection, Weierstrass roots, Newton acos)
+    and oracle (50-digit mpmath) round to the same doubles, the same order and extent."""
+    from oracle import frkc4
+    for s in list(range(4, 68, 4)) + [100, 128, 200, 256, 512]:
+        re_, im_, info, rc = F.frkc4_coeffs(s, nu)
+        o = frkc4.frkc4_coeffs(s, nu)
+        assert np.array_equal(re_, o.a_re) and np.array_equal(im_, o.a_im), s
+        assert info["beta"] == o.beta and info["beta_bar"] == o.beta_bar, s
+        assert info["n_shrink"] == o.n_shrink and bool(info["q_bound_met"]) == o.q_bound_met
+        assert info["mu_re"] == o.alpha
+
+
+@pytest.mark.parametrize("s,nu", [(0, 0.01), (6, 0.01), (516, 0.01), (8, -0.1), (8, 0.25)])
+def test_frkc4_coeffs_rejects(s, nu):
+    with pytest.raises(F.Frkc2Error) as e:
+        F.frkc4_coeffs(s, nu)
+    assert e.value.status == -1
+
+
+def _split(g, w=1, T=1e-3, s=8, nsub=4, nu=0.01, nsteps=1, ws=1, ws_bytes=1 << 40):
+    lib = F.load()
+    p = lambda v: ctypes.c_void_p(4096 * 16) if v else None  # never dereferenced: validation fails first
+    return lib.frkc4s_step(ctypes.byref(g), p(w), T, s, nsub, nu, nsteps, p(ws), ws_bytes, None)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(w=0), -1), (dict(T=0.0), -1), (dict(s=6), -1), (dict(s=516), -1), (dict(nsub=0), -1),
+    (dict(nsub=65), -1), (dict(nsteps=-1), -1), (dict(nu=0.3), -1), (dict(ws=0), -2),
+    (dict(ws_bytes=1024), -2), (dict(T=1.0, s=4), -4),
+])
+def test_frkc4s_validation(kw, expect):
+    g = F.make_grid(dict(ndim=2, n=(64, 64, 1), h=1 / 64, bc=0, op=3, d_const=0.02))
+    assert _split(g, **kw) == expect
+    assert F.frkc2_last_error()
+
+
+def test_frkc4s_needs_brusselator():
+    g = grid(op=1)
+    assert _split(g) == -1
+    assert F.load().frkc4s_workspace_bytes(ctypes.byref(g)) == 0
