@@ -95,7 +95,7 @@ def _short(name):
     return name.replace("frkc2::(anonymous namespace)::", "")
 
 
-def summarize_trace(directory, command, k, tile, out_md):
+def summarize_trace(directory, command, k, tile, out_md, pattern=None, title=None, note=None):
     """Per-(kernel, grid) durations from a rocprofv3 --kernel-trace run, as markdown."""
     groups = {}
     for r in _csv_rows(directory, "kernel_trace.csv"):
@@ -105,16 +105,18 @@ def summarize_trace(directory, command, k, tile, out_md):
         d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
         groups.setdefault(key, []).append(d)
     total = sum(sum(v) for v in groups.values())
-    pat = kernel_pattern(k, tile)
+    pat = pattern or kernel_pattern(k, tile)
     dom = max((key for key in groups if pat in key[0]), key=lambda kk: len(groups[kk]))
-    lines = ["# Kernel trace: 3D variable-D 256^3, s = 100 (bench step)", "",
+    what = ("Dominant kernel (interior pass, k = %d, tile %d)" % (k, tile)) if pattern is None \
+        else "Kernel"
+    lines = ["# Kernel trace: %s" % (title or "3D variable-D 256^3, s = 100 (bench step)"), "",
              "Command (from /tmp, with the repository as the working copy):", "",
-             "    " + command, "",
+             "    " + command, ""] + ([note, ""] if note else []) + [
              "Durations per (kernel, grid size in threads) from rocprofv3 `kernel_trace.csv`, "
              "microseconds.", "",
-             "Dominant kernel (interior pass, k = %d, tile %d): `%s` at grid %d: %d launches, "
-             "average %.2f us." % (k, tile, _short(dom[0]), dom[1], len(groups[dom]),
-                                   sum(groups[dom]) / len(groups[dom])), "",
+             "%s: `%s` at grid %d: %d launches, average %.2f us." % (
+                 what, _short(dom[0]), dom[1], len(groups[dom]),
+                 sum(groups[dom]) / len(groups[dom])), "",
              "| Kernel | grid | calls | total ms | average us | min us | max us | % |",
              "|---|---|---|---|---|---|---|---|"]
     for key, v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:25]:
@@ -185,6 +187,71 @@ def summarize_counters(fetch_dir, write_dir, fetch_cmd, write_cmd, k, tile, zchu
     return t
 
 
+SQ_DERIVED_NOTE = (
+    "Counters are summed over the GPU per dispatch and averaged over the dispatches of the "
+    "kernel. SQ_BUSY_CU_CYCLES counts cycles summed over CUs; SQ_ACTIVE_INST_VALU and the "
+    "wait counters count 4-cycle units per wavefront; the LDS bandwidth counters count "
+    "64-byte units. Derived: VALU busy per SIMD = 4 ACTIVE_INST_VALU / (4 BUSY_CU_CYCLES); "
+    "LDS bytes per CU-cycle = 64 (LOAD_BANDWIDTH + STORE_BANDWIDTH) / BUSY_CU_CYCLES against "
+    "128 per cycle; FP64 share = (ADD + MUL + FMA F64) / INSTS_VALU.")
+
+
+def summarize_sq(dirs, pattern, commands, title, out_md):
+    """SQ counters of one kernel from rocprofv3 --pmc runs (one directory per pass)."""
+    vals, grid, name = {}, None, None
+    for d in dirs:
+        per = {}
+        for r in _csv_rows(d, "counter_collection.csv"):
+            if pattern not in r["Kernel_Name"]:
+                continue
+            key = (r["Kernel_Name"], int(r["Grid_Size"]))
+            per.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(
+                float(r["Counter_Value"]))
+        if not per:
+            raise SystemExit("no dispatch of %s under %s" % (pattern, d))
+        key = max(per, key=lambda k: len(next(iter(per[k].values()))))
+        name, grid = key
+        for c, v in per[key].items():
+            vals[c] = sum(v) / len(v)
+    g = vals.get
+    derived = {}
+    if g("SQ_BUSY_CU_CYCLES"):
+        bc = g("SQ_BUSY_CU_CYCLES")
+        if g("SQ_ACTIVE_INST_VALU") is not None:
+            derived["VALU busy per SIMD"] = g("SQ_ACTIVE_INST_VALU") / bc
+        if g("SQ_INSTS_LDS_LOAD_BANDWIDTH") is not None:
+            lb = 64 * (g("SQ_INSTS_LDS_LOAD_BANDWIDTH") + g("SQ_INSTS_LDS_STORE_BANDWIDTH", 0.0))
+            derived["LDS bytes per CU-cycle (of 128)"] = lb / bc
+        if g("SQ_LDS_BANK_CONFLICT") is not None:
+            derived["LDS bank-conflict cycles per CU-cycle"] = g("SQ_LDS_BANK_CONFLICT") / bc
+    if g("SQ_INSTS_VALU") and g("SQ_INSTS_VALU_FMA_F64") is not None:
+        derived["FP64 share of VALU instructions"] = (
+            g("SQ_INSTS_VALU_FMA_F64") + g("SQ_INSTS_VALU_ADD_F64") + g("SQ_INSTS_VALU_MUL_F64")) / g(
+            "SQ_INSTS_VALU")
+    if g("SQ_WAVES") and g("SQ_INSTS_VALU"):
+        derived["VALU instructions per wavefront"] = g("SQ_INSTS_VALU") / g("SQ_WAVES")
+        if g("SQ_INSTS_SALU") is not None:
+            derived["SALU instructions per wavefront"] = g("SQ_INSTS_SALU") / g("SQ_WAVES")
+        if g("SQ_INSTS_LDS") is not None:
+            derived["LDS instructions per wavefront"] = g("SQ_INSTS_LDS") / g("SQ_WAVES")
+    if g("SQ_WAVE_CYCLES") and g("SQ_WAIT_INST_LDS") is not None:
+        derived["share of wave time waiting to issue LDS"] = g("SQ_WAIT_INST_LDS") / g("SQ_WAVE_CYCLES")
+    lines = ["# SQ counters: %s" % title, "",
+             "Commands (from /tmp, with the repository as the working copy), one per counter pass:",
+             ""] + ["    " + c for c in commands] + [
+             "", "Kernel `%s`, grid %d threads." % (_short(name), grid), "",
+             "| Counter | per dispatch |", "|---|---|"]
+    for c in sorted(vals):
+        lines.append("| %s | %.4g |" % (c, vals[c]))
+    lines += ["", "| Derived | value |", "|---|---|"]
+    for k, v in derived.items():
+        lines.append("| %s | %.3f |" % (k, v))
+    lines += ["", SQ_DERIVED_NOTE]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return vals, derived
+
+
 def kernel_name(k, tile):
     """The dominant kernel of a superstep at fused depth k and tile shape (option numbering)."""
     if k == 1:
@@ -211,12 +278,35 @@ def pass_schedule(s, k, supported=(2, 3)):
     return out
 
 
-def cpu_baseline(prob, T, c_lib, min_seconds=10.0, max_supersteps=8):
-    """Oracle supersteps (s = 100) on the full 256^3 grid, timed on the host cores: repeated
-    until about min_seconds of CPU work (bounded by max_supersteps)."""
+def cpu_baseline(prob, T, c_lib, min_seconds=8.0, max_supersteps=4):
+    """The oracle (plain C stage loops, OpenMP over points) timed on the host cores, at all
+    cores and at one thread, on a bounded sample of each configuration (about 40 s of CPU
+    work in all). The headline value is the 256^3 variable-D workload at all cores:
+    consecutive supersteps (s = 100) until about min_seconds. Per configuration the sample is
+    stated next to it; rates are grid-point-stage updates per second (the adjoint: forward
+    point-stages whose reverse sweep, stage recompute included, completes per second)."""
     from oracle import frkc2_coeffs as ocoeffs
     from oracle import stage as ostage
+    from paper_1702_03818_amd import workloads as wl
+    all_cores = ostage.threads()
     c = ocoeffs(S_STAGES, NU)
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    def both(fn, work_all, work_one, fn_one=None):
+        out = {}
+        for name, nthr, f, work in (("all_cores", all_cores, fn, work_all),
+                                    ("one_thread", 1, fn_one or fn, work_one)):
+            ostage.set_threads(nthr)
+            dt = timed(f)
+            out[name] = {"threads": nthr, "seconds": dt, "value": work / dt}
+        ostage.set_threads(all_cores)
+        return out
+
+    # C2 headline: whole supersteps at all cores
     w = prob.w0
     n = 0
     t0 = time.perf_counter()
@@ -227,24 +317,86 @@ def cpu_baseline(prob, T, c_lib, min_seconds=10.0, max_supersteps=8):
         if dt >= min_seconds or n >= max_supersteps:
             break
     ups = prob.npoints * S_STAGES * n / dt
-    # the 1D heat run in full (20 supersteps of s = 16 on 1024 points), median of 3
-    from paper_1702_03818_amd import workloads as wl
+    cfg = {}
+    # C2 at one thread: the first 5 stages of a superstep on the full grid
+    ostage.set_threads(1)
+    d1 = timed(lambda: ostage.superstep(prob, prob.w0, T * c.a_re[:5], T * c.a_im[:5]))
+    ostage.set_threads(all_cores)
+    cfg["C2_diffusion3d_256"] = {
+        "all_cores": {"threads": all_cores, "seconds": dt, "value": ups,
+                      "sample": "%d whole supersteps (s = 100)" % n},
+        "one_thread": {"threads": 1, "seconds": d1, "value": prob.npoints * 5 / d1,
+                       "sample": "the first 5 stages of one superstep, full grid"}}
+    # C1: the whole 1D heat run (20 supersteps of s = 16 on 1024 points), median of 3
     p1 = wl.heat1d()
     c16 = ocoeffs(16, NU)
     T1 = CFL * c16.beta_bar / (4.0 / (p1.h * p1.h))
-    t1 = []
-    for _ in range(3):
-        t0 = time.perf_counter()
-        ostage.run(p1, 16, 20, T=T1, coeffs=c16)
-        t1.append(time.perf_counter() - t0)
-    ms1 = sorted(t1)[1] * 1e3
-    return {"value": ups, "unit": "grid-point-stage updates/s", "cores": ostage.threads(),
+
+    def heat():
+        ts = []
+        for _ in range(3):
+            ts.append(timed(lambda: ostage.run(p1, 16, 20, T=T1, coeffs=c16)))
+        return sorted(ts)[1]
+    r = {}
+    for name, nthr in (("all_cores", all_cores), ("one_thread", 1)):
+        ostage.set_threads(nthr)
+        sec = heat()
+        r[name] = {"threads": nthr, "seconds": sec, "ms": sec * 1e3,
+                   "value": p1.npoints * 16 * 20 / sec}
+    ostage.set_threads(all_cores)
+    r["sample"] = "the whole run (20 supersteps, s = 16, 1024 points), median of 3"
+    cfg["C1_heat1d_1024"] = r
+    # C3: the first 5 stages of one s = 400 superstep of the 4096^2 porous medium
+    p3 = wl.porous2d()
+    c400 = ocoeffs(400, NU)
+    T3 = 0.002 * c400.beta_bar / ostage.rho_bound(p3, p3.w0)
+    r = both(lambda: ostage.superstep(p3, p3.w0, T3 * c400.a_re[:5], T3 * c400.a_im[:5]),
+             p3.npoints * 5, p3.npoints * 5)
+    r["sample"] = "the first 5 stages of one s = 400 superstep, full 4096^2 grid"
+    cfg["C3_porous2d_4096"] = r
+    del p3
+    # C4: whole supersteps of sampled problems of the 512-problem batch
+    batch = wl.batched()
+    sample_all = batch[::32]
+    sample_one = batch[::128]
+
+    def run_batch(sample):
+        def f():
+            for p, s in sample:
+                cs = ocoeffs(s, NU)
+                Tb = CFL * cs.beta_bar / ostage.rho_bound(p)
+                ostage.superstep(p, p.w0, Tb * cs.a_re, Tb * cs.a_im)
+        return f
+    for p, s in sample_all:   # stepsizes and bounds outside the timed region
+        ocoeffs(s, NU)
+    r = both(run_batch(sample_all), sum(p.npoints * s for p, s in sample_all),
+             sum(p.npoints * s for p, s in sample_one), run_batch(sample_one))
+    r["sample"] = ("one superstep of every 32nd problem (%d problems) at all cores, of every "
+                   "128th (%d) at one thread" % (len(sample_all), len(sample_one)))
+    cfg["C4_batched_512"] = r
+    del batch
+    # C5: the adjoint of one superstep of the 128^3 problem (s = 64; one thread: 16 stages)
+    p5, target = wl.adjoint3d()
+    c64 = ocoeffs(64, NU)
+    T5 = CFL * c64.beta_bar / ostage.rho_bound(p5)
+    lam = 2 * (p5.w0.reshape(-1) - target.reshape(-1))
+
+    def adj(k):
+        return lambda: ostage.adjoint(p5, p5.w0, lam, T5 * c64.a_re[:k], T5 * c64.a_im[:k],
+                                      grad_logD=np.zeros(p5.npoints))
+    r = both(adj(64), p5.npoints * 64, p5.npoints * 16, adj(16))
+    r["sample"] = ("the adjoint of one superstep (forward recompute with the stage store, then "
+                   "the reverse stages and the log-D gradient): s = 64 at all cores, the first "
+                   "16 stages at one thread")
+    cfg["C5_adjoint3d_128"] = r
+    return {"value": ups, "unit": "grid-point-stage updates/s", "cores": all_cores,
             "kind": "oracle",
             "sample": "%d consecutive supersteps (s=100) of the same 256^3 variable-D problem, "
                       "%.1f s" % (n, dt),
-            "heat1d": {"cpu_ms": ms1, "value": p1.npoints * 16 * 20 / (ms1 * 1e-3),
-                       "sample": "the whole 1D heat run (20 supersteps, s = 16, 1024 points), "
-                                 "median of 3"}}
+            "configs": cfg,
+            "heat1d": {"cpu_ms": cfg["C1_heat1d_1024"]["all_cores"]["ms"],
+                       "value": cfg["C1_heat1d_1024"]["all_cores"]["value"],
+                       "sample": cfg["C1_heat1d_1024"]["sample"]}}
 
 
 def batched_leg(F, wl, torch, reps=3):
@@ -582,15 +734,31 @@ def main():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the HBM traffic summary under profiles/ from rocprofv3 --pmc "
                          "FETCH_SIZE and WRITE_SIZE runs of this script (no GPU needed)")
+    ap.add_argument("--summarize-sq", nargs="+", metavar=("OUT_MD", "DIR"),
+                    help="write the SQ-counter summary of one kernel (--sq-kernel, --sq-title) "
+                         "from rocprofv3 --pmc directories (one per pass) and exit")
+    ap.add_argument("--trace-kernel", default=None, help="with --summarize-trace: kernel name part")
+    ap.add_argument("--trace-title", default=None)
+    ap.add_argument("--trace-note", default=None)
+    ap.add_argument("--trace-out", default=None, help="with --summarize-trace: output file")
+    ap.add_argument("--sq-kernel", default="tb3d_stage<1, 1, 3, false, false, false, false, 64>")
+    ap.add_argument("--sq-title", default="3D variable-D interior pass, 256^3, s = 100, k = 3")
     ap.add_argument("--command", action="append", default=[],
                     help="with --summarize-*: the command line(s) that produced the data")
     args = ap.parse_args()
+    if args.summarize_sq:
+        summarize_sq(args.summarize_sq[1:], args.sq_kernel, args.command, args.sq_title,
+                     args.summarize_sq[0])
+        return
     if args.summarize_trace or args.summarize_counters:
         k = args.tblock or 2
         tile = args.tile or (4 if k >= 2 else 1)
         if args.summarize_trace:
-            avg = summarize_trace(args.summarize_trace, args.command[0], k, tile,
-                                  os.path.join(ROOT, "profiles", "kernel_trace_stage3d_256.md"))
+            out_md = os.path.join(ROOT, "profiles", "kernel_trace_stage3d_256.md")
+            if args.trace_out:
+                out_md = args.trace_out
+            avg = summarize_trace(args.summarize_trace, args.command[0], k, tile, out_md,
+                                  args.trace_kernel, args.trace_title, args.trace_note)
             print("dominant kernel average %.2f us" % avg)
         else:
             t = summarize_counters(args.summarize_counters[0], args.summarize_counters[1],
@@ -667,8 +835,26 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     copy_gbs = 5 * 2 * copy_bytes / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del src, dst
     log("copy bandwidth %.1f GB/s" % copy_gbs)
+    # The library's hand-written streaming copy (16 B per lane, four accesses in
+    # flight, plain or nontemporal, 1..16 workgroups per CU): the best of these is
+    # the measured HBM ceiling the stage kernels are compared with.
+    stream = {}
+    for bpc in (1, 2, 4, 8, 16):
+        for nt in (False, True):
+            F.frkc2_stream_copy(src, dst, bpc, nt)
+            e0.record()
+            for _ in range(5):
+                F.frkc2_stream_copy(src, dst, bpc, nt)
+            e1.record()
+            torch.cuda.synchronize()
+            stream[(bpc, nt)] = 5 * 2 * copy_bytes / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    best_stream = max(stream, key=stream.get)
+    stream_gbs = stream[best_stream]
+    assert torch.equal(dst, src)
+    del src, dst
+    log("streaming copy ceiling %.1f GB/s (%d workgroups per CU, %s)"
+        % (stream_gbs, best_stream[0], "nontemporal" if best_stream[1] else "plain"))
 
     for i in range(args.warmup):
         step()
@@ -717,7 +903,10 @@ def main():
             "kernel": kernel_name(kdepth, tile),
             "stages_per_pass": kdepth, "tile": tile, "zchunk": zchunk,
             "autotuned": tune is not None, "bytes_per_point_per_pass": 40,
-            "algorithmic_bytes_per_launch": 40 * N, "avg_launch_ms": avg_launch_ms}
+            "algorithmic_bytes_per_launch": 40 * N, "avg_launch_ms": avg_launch_ms,
+            "measured_ceiling": stream_gbs, "frac_of_measured_ceiling": achieved / stream_gbs,
+            "measured_ceiling_note": "best of the library's streaming copy (frkc2_stream_copy) "
+                                     "over workgroups per CU and nontemporal accesses, 1 GiB"}
     # Update-rate caps: HBM at the pass schedule's minimal bytes per point-stage, and FP64
     # at the stage's flops per point (variable D, fused order: per face 2 subtractions,
     # 1 add and 2 fma; then 2 multiplies and 4 fma; an fma counts 2 flops: 52 flops).
@@ -756,6 +945,10 @@ def main():
         "roofline": roof,
         "one_stage_per_pass": k1_ref,
         "diagnostics": {"copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                        "stream_ceiling_gbs": stream_gbs,
+                        "stream_config": {"workgroups_per_cu": best_stream[0],
+                                          "nontemporal": best_stream[1]},
+                        "frac_of_stream_ceiling": achieved / stream_gbs,
                         "im_ratio": last[0]["im_ratio"], "l2_norm": float(np.sqrt(last[1])),
                         "q_realised": info["q_realised"], "n_shrink": info["n_shrink"]},
     }

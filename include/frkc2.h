@@ -518,6 +518,17 @@ int frkc2_autotune(const frkc2_grid *g, const double *w, const double *D, int s,
 #define FRKC2_OPT_ZCHUNK 5
 int frkc2_set_option(int key, int value);
 
+/*
+ * frkc2_stream_copy -- a measurement helper, not part of the method: copies
+ * `bytes` (a multiple of 16) from src to dst (device, 16-byte aligned, not
+ * overlapping) with 128-bit accesses per lane, blocks_per_cu workgroups of
+ * 256 threads per CU (1..64), plain (nontemporal = 0) or nontemporal accesses.
+ * Timed by the caller, it gives the HBM streaming ceiling the stage kernels'
+ * bandwidth is compared with. Asynchronous.
+ */
+int frkc2_stream_copy(const void *src, void *dst, size_t bytes, int blocks_per_cu, int nontemporal,
+                      hipStream_t st);
+
 /* Thread-local description of the last error. */
 const char *frkc2_last_error(void);
 

@@ -530,3 +530,13 @@ int oracle_threads(void)
     return 1;
 #endif
 }
+
+/* Threads for the OpenMP loops that follow (the CPU baseline times 1 and all). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -83,6 +83,8 @@ def _declare(lib):
     lib.oracle_euler_update.restype = None
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
     lib.oracle_superstep_c.argtypes = common + [dp, dp]
     lib.oracle_superstep_c.restype = ctypes.c_int
     lib.oracle_react_flow.argtypes = [ctypes.c_long, dp, dp] + [ctypes.c_double] * 6 + [ctypes.c_int]
@@ -125,6 +127,11 @@ def _f64(a):
 def threads() -> int:
     """OpenMP threads the oracle's loops use."""
     return int(_load().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads for the oracle's loops from now on."""
+    _load().oracle_set_threads(int(n))
 
 
 def superstep(prob, w, tau_re, tau_im, D=None, want_imag=False, unfused=False):

@@ -144,14 +144,15 @@ struct BrussTbArgs {
 };
 
 // The value of lane i - 1 (SHR) or i + 1 (SHL) of the wavefront; 0 at the end
-// lane.
+// lane (the DPP move's bound control writes 0 where the source lane is out of
+// the wavefront, so no destination has to be cleared first).
 template <bool SHR>
 __device__ __forceinline__ double lane_shift(double v)
 {
     constexpr int ctrl = SHR ? 0x138 : 0x130;   // DPP wave_shr:1 / wave_shl:1
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, ctrl, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, ctrl, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctrl, 0xF, 0xF, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 

@@ -125,6 +125,7 @@ _SIGS = {
                                       ctypes.POINTER(TuneResult)]),
     "frkc2_write_table": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_double, ctypes.c_int]),
     "frkc2_set_option": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    "frkc2_stream_copy": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, _VP]),
     "frkc2_last_error": (ctypes.c_char_p, []),
     "frkc2_version": (ctypes.c_char_p, []),
 }
@@ -520,6 +521,17 @@ def frkc2_reduce(op: int, x, y=None, stream=None) -> float:
 def frkc2_write_table(path, nu: float = 0.01, m_max: int = 257):
     """Write the stepsize table (betabar, Q / Re a / Im a per M) in the public-code layout."""
     return _check(load().frkc2_write_table(os.fsencode(path), float(nu), int(m_max)))
+
+
+def frkc2_stream_copy(src, dst, blocks_per_cu=4, nontemporal=False, stream=None):
+    """Streaming copy of src into dst (device tensors of equal byte size), the HBM ceiling."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst sizes differ")
+    return _check(load().frkc2_stream_copy(ctypes.c_void_p(src.data_ptr()),
+                                           ctypes.c_void_p(dst.data_ptr()), nbytes,
+                                           int(blocks_per_cu), int(bool(nontemporal)),
+                                           _stream_ptr(stream)))
 
 
 def frkc2_set_option(key: int, value: int):
