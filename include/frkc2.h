@@ -272,9 +272,12 @@ int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const double *D, 
  * grid, T and s) in a single HIP graph launch. Batching is a systems pattern
  * of this library; no passage of the paper defines it. The graph has
  * concurrent branches: 3D problems (two interleaved groups, one branch each)
- * advance in pass levels (level L: stages 3L .. 3L+2 of every problem that has
- * them, fused in one HBM pass, then the remaining single stages), 2D problems
- * likewise with passes of 4 stages (s = 4: four single stages).
+ * advance in pass levels (level L: stages k3 L .. k3 L + k3 - 1 of every
+ * problem that has them, fused in one HBM pass, then the remaining single
+ * stages), 2D problems likewise with passes of k2 stages (s = k: k single
+ * stages); k3 = 3, k2 = 4 and the fused 3D tiles' width come from
+ * frkc2_batched_autotune or the FRKC2_OPT_BATCH_* options (built-in: 3, the
+ * width with less modelled work, 4).
  *   grids  host array of nprob grids
  *   w      host array of nprob device pointers (in/out states, real)
  *   D      host array of nprob device pointers (NULL entries for LAPLACE)
@@ -301,6 +304,45 @@ int frkc2_step_batched(int nprob, const frkc2_grid *grids, double *const *w,
                        void *ws, size_t ws_bytes, hipStream_t st);
 int frkc2_batched_status(void *ws, hipStream_t st);   /* synchronises st */
 int frkc2_batched_release(void *ws);                  /* frees the graph cached for ws */
+
+/*
+ * frkc2_batched_autotune -- pick the launch configuration of
+ * frkc2_step_batched for a problem set by timing. A batch runs its 3D problems
+ * in fused passes of k3 stages (2 or 3) over tiles of 32 or 64 output columns
+ * and its 2D problems in fused passes of k2 stages (2, 3, 4 or 6); which is
+ * fastest depends on the mix of sizes and stage counts. Candidates: the
+ * built-in configuration, every (k3, width) with its k2 (widths 32, 64 and
+ * 1, one per problem, as FRKC2_OPT_BATCH_COLS numbers them), then every k2
+ * with the best (k3, width); each
+ * runs one warm-up and `reps` timed supersteps of the whole batch (graph
+ * replays, HIP events on st). The fastest (the built-in one unless a
+ * candidate beats it by more than 2 %) is stored for problem sets of the same
+ * dimensions, extents, boundaries, operators and s, in the same order, and
+ * used by the graphs frkc2_step_batched builds for them while the
+ * FRKC2_OPT_BATCH_* options are 0.
+ *   nprob .. ws_bytes  as for frkc2_step_batched (the same stability check)
+ *   reps               timed supersteps per candidate, 1..100
+ *   res                host; receives the choice, the number of
+ *                      configurations timed and the average superstep time
+ *                      of the choice and of the built-in configuration
+ * Every timed superstep advances the states w in place, (reps + 1) per
+ * candidate: pass copies of the states to keep them. Every configuration
+ * gives the same bits. Synchronises st; drops the graph cached for ws.
+ * Errors: FRKC2_EINVAL (arguments), FRKC2_EUNSTABLE, FRKC2_ENONFINITE,
+ * FRKC2_ENOMEM (workspace), FRKC2_EHIP.
+ */
+typedef struct {
+    int k3;             /* stages per fused 3D pass */
+    int cols3;          /* output columns of the fused 3D tiles (1: per problem) */
+    int k2;             /* stages per fused 2D pass */
+    int candidates;     /* configurations timed */
+    double ms_best;     /* average superstep time of the choice */
+    double ms_default;  /* ... and of the built-in configuration */
+} frkc2_batch_tune_result;
+int frkc2_batched_autotune(int nprob, const frkc2_grid *grids, double *const *w,
+                           const double *const *D, const double *T, const int *s, double nu,
+                           int reps, void *ws, size_t ws_bytes, hipStream_t st,
+                           frkc2_batch_tune_result *res);
 
 /*
  * frkc2_reduce -- deterministic FP64 reductions over n elements (device x, y).
@@ -508,14 +550,26 @@ int frkc2_autotune(const frkc2_grid *g, const double *w, const double *D, int s,
  *                     rounds of one workgroup per CU; otherwise halve from the
  *                     whole depth until >= 512 workgroups for 3D fused passes,
  *                     >= 2048 otherwise)
- *   FRKC2_OPT_CLEAR_TUNED  forget every configuration frkc2_autotune stored
- *                     (value ignored)
+ *   FRKC2_OPT_CLEAR_TUNED  forget every configuration frkc2_autotune and
+ *                     frkc2_batched_autotune stored (value ignored)
+ *   FRKC2_OPT_BATCH_K3, FRKC2_OPT_BATCH_COLS, FRKC2_OPT_BATCH_K2  the launch
+ *                     configuration of every frkc2_step_batched graph built
+ *                     afterwards: stages per fused 3D pass (2 or 3), output
+ *                     columns of its tiles (32 or 64 for all 3D problems, or
+ *                     1: each problem the width with less modelled work for
+ *                     it, the two widths on separate graph branches), stages
+ *                     per fused 2D pass (2, 3, 4 or 6); 0 = automatic (what
+ *                     frkc2_batched_autotune stored for the problem set, else
+ *                     the built-in configuration of frkc2_step_batched)
  * Results are identical, bit for bit, for every setting.
  */
 #define FRKC2_OPT_TBLOCK 1
 #define FRKC2_OPT_TILE 3
 #define FRKC2_OPT_CLEAR_TUNED 4
 #define FRKC2_OPT_ZCHUNK 5
+#define FRKC2_OPT_BATCH_K3 6
+#define FRKC2_OPT_BATCH_COLS 7
+#define FRKC2_OPT_BATCH_K2 8
 int frkc2_set_option(int key, int value);
 
 /*

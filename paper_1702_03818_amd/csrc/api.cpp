@@ -404,10 +404,15 @@ extern "C" int frkc2_set_option(int key, int value)
         return FRKC2_OK;
     }
     if (key == FRKC2_OPT_CLEAR_TUNED) {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned.clear();
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tuned.clear();
+        }
+        batched_clear_tuned();
         return FRKC2_OK;
     }
+    if (key == FRKC2_OPT_BATCH_K3 || key == FRKC2_OPT_BATCH_COLS || key == FRKC2_OPT_BATCH_K2)
+        return batched_set_option(key, value);
     set_error("unknown option %d", key);
     return FRKC2_EINVAL;
 }

@@ -108,44 +108,44 @@ struct Pass3Args {
     int nprob, level;
 };
 
-template <int OP, int BC, bool IR, bool OR, int W>
+template <int OP, int BC, bool IR, bool OR, int W, int KB>
 __device__ void run_fused(const BatchProblem &P, Tb3Args &a, long long c, double2 *sL, double *sD)
 {
     const int bx = (int)(c % P.ntx3);
     const long long r = c / P.ntx3;
-    tb3d_tile<OP, BC, kBatchK, IR, OR, false, false, W>(a, bx, (int)(r % P.nty3),
-                                                       (int)(r / P.nty3), sL, sD);
+    tb3d_tile<OP, BC, KB, IR, OR, false, false, W>(a, bx, (int)(r % P.nty3), (int)(r / P.nty3),
+                                                   sL, sD);
 }
 
-template <int OP, int BC, int W>
+template <int OP, int BC, int W, int KB>
 __device__ void fused_io_w(const BatchProblem &P, Tb3Args &a, long long c, bool ir, bool orl,
                            double2 *sL, double *sD)
 {
-    if (ir) run_fused<OP, BC, true, false, W>(P, a, c, sL, sD);
-    else if (orl) run_fused<OP, BC, false, true, W>(P, a, c, sL, sD);
-    else run_fused<OP, BC, false, false, W>(P, a, c, sL, sD);
+    if (ir) run_fused<OP, BC, true, false, W, KB>(P, a, c, sL, sD);
+    else if (orl) run_fused<OP, BC, false, true, W, KB>(P, a, c, sL, sD);
+    else run_fused<OP, BC, false, false, W, KB>(P, a, c, sL, sD);
 }
 
 
-template <int OP, int BC>
+template <int OP, int BC, int KB>
 __device__ void row_io(const TbArgs &a, int bx, int bz, bool ir, bool orl, double2 *sL, double *sD)
 {
-    if (ir) tb_tile<OP, BC, 2, kBXE2, 1, 1, kBatchK2, true, false>(a, bx, 0, bz, sL, sD);
-    else if (orl) tb_tile<OP, BC, 2, kBXE2, 1, 1, kBatchK2, false, true>(a, bx, 0, bz, sL, sD);
-    else tb_tile<OP, BC, 2, kBXE2, 1, 1, kBatchK2, false, false>(a, bx, 0, bz, sL, sD);
+    if (ir) tb_tile<OP, BC, 2, kBXE2, 1, 1, KB, true, false>(a, bx, 0, bz, sL, sD);
+    else if (orl) tb_tile<OP, BC, 2, kBXE2, 1, 1, KB, false, true>(a, bx, 0, bz, sL, sD);
+    else tb_tile<OP, BC, 2, kBXE2, 1, 1, KB, false, false>(a, bx, 0, bz, sL, sD);
 }
 
 // One pass level of the 3D problems. FUSED: each active problem's pass of
-// kBatchK stages (stages kBatchK*level ..), as tb3d_tile items; otherwise its
+// KB stages (stages KB*level ..), as tb3d_tile items; otherwise its
 // single-stage pass (the stages left after the fused ones), as 64 x 16
 // plane-march items. A problem's first pass reads w, its last writes w, the
 // passes between ping-pong the workspace buffers.
-template <bool FUSED, int W>
+template <bool FUSED, int W, int KB>
 __global__ __launch_bounds__(1024) void batched_pass3(Pass3Args t)
 {
     using S1 = TileShape<VAR, DIR, 3, kPBX, kPBY>;
-    constexpr int NL = FUSED ? Tb3Lds<VAR, kBatchK, W>::L : S1::LDS_W;
-    constexpr int ND = FUSED ? Tb3Lds<VAR, kBatchK, W>::D : S1::LDS_D;
+    constexpr int NL = FUSED ? Tb3Lds<VAR, KB, W>::L : S1::LDS_W;
+    constexpr int ND = FUSED ? Tb3Lds<VAR, KB, W>::D : S1::LDS_D;
     __shared__ double2 sL[NL];
     __shared__ double sD[ND];
     long long first, hi, step;
@@ -201,21 +201,21 @@ __global__ __launch_bounds__(1024) void batched_pass3(Pass3Args t)
             ta.inv_h2 = P.inv_h2;
             ta.d_const = P.d_const;
             for (int k = 0; k < 6; ++k) ta.fc[k] = P.d_const;
-            const int l0 = kBatchK * L;
+            const int l0 = KB * L;
 #pragma unroll
-            for (int i = 0; i < kBatchK; ++i) {
+            for (int i = 0; i < KB; ++i) {
                 ta.tr[i] = uni(P.tau[2 * (l0 + i)]);
                 ta.ti[i] = uni(P.tau[2 * (l0 + i) + 1]);
             }
             if (var) {
-                if (per) fused_io_w<VAR, PER, W>(P, ta, c, ir, orl, sL, sD);
-                else fused_io_w<VAR, DIR, W>(P, ta, c, ir, orl, sL, sD);
+                if (per) fused_io_w<VAR, PER, W, KB>(P, ta, c, ir, orl, sL, sD);
+                else fused_io_w<VAR, DIR, W, KB>(P, ta, c, ir, orl, sL, sD);
             } else {
-                if (per) fused_io_w<LAP, PER, W>(P, ta, c, ir, orl, sL, sD);
-                else fused_io_w<LAP, DIR, W>(P, ta, c, ir, orl, sL, sD);
+                if (per) fused_io_w<LAP, PER, W, KB>(P, ta, c, ir, orl, sL, sD);
+                else fused_io_w<LAP, DIR, W, KB>(P, ta, c, ir, orl, sL, sD);
             }
         } else {
-            const int l = kBatchK * P.nfull + (L - P.nfull);
+            const int l = KB * P.nfull + (L - P.nfull);
             PlaneArgs pa{};
             pa.in_re = P.w;
             pa.in_c = reinterpret_cast<const double2 *>(in_c);
@@ -246,14 +246,14 @@ __global__ __launch_bounds__(1024) void batched_pass3(Pass3Args t)
 }
 
 // One pass level of the 2D problems. FUSED: each active problem's pass of
-// kBatchK2 stages (stages kBatchK2*level ..), as row items of tb_tile.h (64
+// KB stages (stages KB*level ..), as row items of tb_tile.h (64
 // extended columns marching up to 128 rows); otherwise its single-stage pass,
 // as 64-column plane-march items. Buffers as in the 3D pass kernel.
-template <bool FUSED>
+template <bool FUSED, int KB>
 __global__ __launch_bounds__(64) void batched_pass2(Pass3Args t)
 {
     using S1 = TileShape<VAR, DIR, 2, kBX2, 1>;
-    using S2 = TbLds<VAR, 2, kBXE2, 1, 1, kBatchK2>;
+    using S2 = TbLds<VAR, 2, kBXE2, 1, 1, KB>;
     __shared__ double2 sL[FUSED ? S2::L : S1::LDS_W];
     __shared__ double sD[FUSED ? S2::D : S1::LDS_D];
     long long first, hi, step;
@@ -308,22 +308,22 @@ __global__ __launch_bounds__(64) void batched_pass2(Pass3Args t)
             ta.inv_h2 = P.inv_h2;
             ta.d_const = P.d_const;
             for (int k = 0; k < 6; ++k) ta.fc[k] = P.d_const;
-            const int l0 = kBatchK2 * L;
+            const int l0 = KB * L;
 #pragma unroll
-            for (int i = 0; i < kBatchK2; ++i) {
+            for (int i = 0; i < KB; ++i) {
                 ta.tr[i] = uni(P.tau[2 * (l0 + i)]);
                 ta.ti[i] = uni(P.tau[2 * (l0 + i) + 1]);
             }
             const int bx = (int)(c % P.ntx3), bz = (int)(c / P.ntx3);
             if (var) {
-                if (per) row_io<VAR, PER>(ta, bx, bz, ir, orl, sL, sD);
-                else row_io<VAR, DIR>(ta, bx, bz, ir, orl, sL, sD);
+                if (per) row_io<VAR, PER, KB>(ta, bx, bz, ir, orl, sL, sD);
+                else row_io<VAR, DIR, KB>(ta, bx, bz, ir, orl, sL, sD);
             } else {
-                if (per) row_io<LAP, PER>(ta, bx, bz, ir, orl, sL, sD);
-                else row_io<LAP, DIR>(ta, bx, bz, ir, orl, sL, sD);
+                if (per) row_io<LAP, PER, KB>(ta, bx, bz, ir, orl, sL, sD);
+                else row_io<LAP, DIR, KB>(ta, bx, bz, ir, orl, sL, sD);
             }
         } else {
-            const int l = kBatchK2 * P.nfull + (L - P.nfull);
+            const int l = KB * P.nfull + (L - P.nfull);
             PlaneArgs pa{};
             pa.in_re = P.w;
             pa.in_c = reinterpret_cast<const double2 *>(in_c);
@@ -357,44 +357,84 @@ __global__ __launch_bounds__(64) void batched_pass2(Pass3Args t)
 
 void batched_tile(int ndim, int *bx, int *by) { *bx = ndim == 3 ? kPBX : kBX2; *by = ndim == 3 ? kPBY : 1; }
 
-void batched_tile3(int cols, int *bx, int *by)
+void batched_tile3(int cols, int k, int *bx, int *by)
 {
     *bx = cols;
-    *by = (cols == 32) ? Tb3Shape<kBatchK, 32>::BYO : Tb3Shape<kBatchK, 64>::BYO;
+    if (k == 2) *by = (cols == 32) ? Tb3Shape<2, 32>::BYO : Tb3Shape<2, 64>::BYO;
+    else *by = (cols == 32) ? Tb3Shape<3, 32>::BYO : Tb3Shape<3, 64>::BYO;
 }
 
-int launch_batched_pass3(bool fused, int cols, const BatchProblem *probs,
+bool batched_cfg_supported(int k3, int cols3, int k2)
+{
+    return (k3 == 2 || k3 == 3) && (cols3 == 32 || cols3 == 64) &&
+           (k2 == 2 || k2 == 3 || k2 == 4 || k2 == 6);
+}
+
+namespace {
+
+template <bool FUSED, int W, int KB>
+void launch3(const Pass3Args &t, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((batched_pass3<FUSED, W, KB>), dim3(grid), dim3(1024), 0, st, t);
+}
+
+template <bool FUSED, int KB>
+void launch2(const Pass3Args &t, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((batched_pass2<FUSED, KB>), dim3(grid), dim3(64), 0, st, t);
+}
+
+}  // namespace
+
+int launch_batched_pass3(bool fused, int cols, int k, const BatchProblem *probs,
                          const long long *item_prefix, long long items, int nprob, int level,
                          int grid, hipStream_t st)
 {
-    // the single-stage kernel does not depend on the width: one instance
     Pass3Args t{probs, item_prefix, items, nprob, level};
-    if (!fused) hipLaunchKernelGGL((batched_pass3<false, 64>), dim3(grid), dim3(1024), 0, st, t);
-    else if (cols == 32) hipLaunchKernelGGL((batched_pass3<true, 32>), dim3(grid), dim3(1024), 0, st, t);
-    else hipLaunchKernelGGL((batched_pass3<true, 64>), dim3(grid), dim3(1024), 0, st, t);
+    // the single-stage items do not depend on the width
+    if (k == 2) {
+        if (!fused) launch3<false, 64, 2>(t, grid, st);
+        else if (cols == 32) launch3<true, 32, 2>(t, grid, st);
+        else launch3<true, 64, 2>(t, grid, st);
+    } else if (k == 3) {
+        if (!fused) launch3<false, 64, 3>(t, grid, st);
+        else if (cols == 32) launch3<true, 32, 3>(t, grid, st);
+        else launch3<true, 64, 3>(t, grid, st);
+    } else {
+        return (int)hipErrorInvalidValue;
+    }
     return (int)hipGetLastError();
 }
 
-int batched_row2() { return kBXE2 - 2 * kBatchK2; }
+int batched_row2(int k) { return kBXE2 - 2 * k; }
 
-int launch_batched_pass2(bool fused, const BatchProblem *probs, const long long *item_prefix,
-                         long long items, int nprob, int level, int grid, hipStream_t st)
+int launch_batched_pass2(bool fused, int k, const BatchProblem *probs,
+                         const long long *item_prefix, long long items, int nprob, int level,
+                         int grid, hipStream_t st)
 {
     Pass3Args t{probs, item_prefix, items, nprob, level};
-    if (fused) hipLaunchKernelGGL((batched_pass2<true>), dim3(grid), dim3(64), 0, st, t);
-    else hipLaunchKernelGGL((batched_pass2<false>), dim3(grid), dim3(64), 0, st, t);
+    switch (k) {
+    case 2: fused ? launch2<true, 2>(t, grid, st) : launch2<false, 2>(t, grid, st); break;
+    case 3: fused ? launch2<true, 3>(t, grid, st) : launch2<false, 3>(t, grid, st); break;
+    case 4: fused ? launch2<true, 4>(t, grid, st) : launch2<false, 4>(t, grid, st); break;
+    case 6: fused ? launch2<true, 6>(t, grid, st) : launch2<false, 6>(t, grid, st); break;
+    default: return (int)hipErrorInvalidValue;
+    }
     return (int)hipGetLastError();
 }
 
 int batched_grid_size(int ndim)
 {
+    // every pass kernel of a dimension has the same workgroup size and fits the
+    // same number of workgroups per CU (one for 3D: its LDS; the 2D rows are
+    // bound by waves per CU), so one query per dimension serves all
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     hipError_t e = (ndim == 3)
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_pass3<true, 64>, 1024, 0)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_pass2<true>, 64, 0);
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_pass3<true, 64, 3>, 1024, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_pass2<true, 4>, 64, 0);
     if (e != hipSuccess) return 0;
     return cus * (per > 0 ? per : 1);
 }

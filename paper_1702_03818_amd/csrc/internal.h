@@ -101,7 +101,7 @@ int launch_tb3d(const KGrid &g, const PassArgs &p, hipStream_t st);
 // pass time on this grid (rounds of workgroups x steps x step cost).
 int tb3d_pick_cols(const KGrid &g, int k);
 // Steps x step cost of all fused-tile items of one batched 3D problem.
-int tb3d_work(int cols, int nx, int ny, int nz, int zc);
+long long tb3d_work(int k, int cols, int nx, int ny, int nz, int zc);
 
 // Reductions (reduce.hip). partials must hold kReduceBlocks doubles + 2.
 constexpr int kReduceBlocks = 512;
@@ -142,26 +142,38 @@ struct BatchProblem {           // one problem's descriptor in device memory
     int nx, ny, nz, ndim, bc, op;   // kernel layout: 3D (n0, n1, n2), 2D (n0, 1, n1)
     int s, ntiles;                  // stages, tiles per one-stage pass
     int zchunk, ntx, nty;           // one-stage tile grid: ntx * nty * ceil(nz / zchunk)
-    int nfull, npass;               // passes of kBatchK (3D) / kBatchK2 (2D) stages, then single stages
+    int nfull, npass;               // fused passes of k3 (3D) / k2 (2D) stages, then single stages
     int zc3, ntx3, nty3, ntiles3;   // fused-pass tile grid (3D: full-width tiles; 2D: rows)
     int cols3;                      // 3D: its output columns per tile (64 or 32)
     double inv_h2, d_const;
 };
-constexpr int kBatchK = 3;          // stages per fused 3D pass of the batch
-constexpr int kBatchK2 = 4;         // stages per fused 2D pass of the batch
+// Launch configuration of a batch: stages per fused 3D pass (2, 3), output
+// columns of the fused 3D tiles (32, 64, or kColsPerProblem), stages per fused
+// 2D pass (2, 3, 4, 6). Every configuration gives the same bits.
+constexpr int kColsPerProblem = 1;  // BatchCfg::cols3: each 3D problem its modelled width
+struct BatchCfg {
+    int k3 = 3, cols3 = 64, k2 = 4;
+};
+bool batched_cfg_supported(int k3, int cols3, int k2);
 void batched_tile(int ndim, int *bx, int *by);
-void batched_tile3(int cols, int *bx, int *by);
-int batched_row2();                 // output columns of a fused 2D row item
+void batched_tile3(int cols, int k, int *bx, int *by);
+int batched_row2(int k);            // output columns of a fused 2D row item of k stages
 int batched_grid_size(int ndim);
-// 2D pass level: fused == true runs the kBatchK2-stage passes of level
-// `level`, otherwise the single-stage passes; item_prefix spans all nprob 2D
-// problems.
-int launch_batched_pass2(bool fused, const BatchProblem *probs, const long long *item_prefix,
-                         long long items, int nprob, int level, int grid, hipStream_t st);
-// 3D pass level: fused == true runs the kBatchK-stage passes of level `level`,
-// otherwise the single-stage passes; item_prefix spans all nprob 3D problems.
-int launch_batched_pass3(bool fused, int cols, const BatchProblem *probs,
-                         const long long *item_prefix,
-                         long long items, int nprob, int level, int grid, hipStream_t st);
+// 2D pass level: fused == true runs the k-stage passes of level `level`,
+// otherwise the single-stage passes; item_prefix spans all nprob 2D problems.
+int launch_batched_pass2(bool fused, int k, const BatchProblem *probs,
+                         const long long *item_prefix, long long items, int nprob, int level,
+                         int grid, hipStream_t st);
+// 3D pass level: fused == true runs the k-stage passes (cols output columns)
+// of level `level`, otherwise the single-stage passes; item_prefix spans all
+// nprob 3D problems.
+int launch_batched_pass3(bool fused, int cols, int k, const BatchProblem *probs,
+                         const long long *item_prefix, long long items, int nprob, int level,
+                         int grid, hipStream_t st);
+// frkc2_set_option's batch keys (FRKC2_OPT_BATCH_*: a configuration forced
+// for every batch, 0 = automatic), and forgetting what frkc2_batched_autotune
+// stored.
+int batched_set_option(int key, int value);
+void batched_clear_tuned();
 
 }  // namespace frkc2

@@ -207,14 +207,22 @@ int tb3d_pick_cols(const KGrid &g, int k)
     return tb3d_cost<3, 32>(g) < tb3d_cost<3, 64>(g) ? 32 : 64;
 }
 
-int tb3d_work(int cols, int nx, int ny, int nz, int zc)
+namespace {
+template <int K, int W>
+long long tb3d_work_kw(int nx, int ny, int nz, int zc)
+{
+    using S = Tb3Shape<K, W>;
+    const long long tiles = (long long)((nx + W - 1) / W) * ((ny + S::BYO - 1) / S::BYO);
+    const int chunks = (nz + zc - 1) / zc;
+    return tiles * ((long long)nz + 2LL * K * chunks) * S::STEP_COST;
+}
+}  // namespace
+
+long long tb3d_work(int k, int cols, int nx, int ny, int nz, int zc)
 {
     // steps x step cost of all tiles of a grid with chunk zc (batched items)
-    const int bxo = cols, byo = (cols == 32) ? Tb3Shape<kBatchK, 32>::BYO : Tb3Shape<kBatchK, 64>::BYO;
-    const int cost = (cols == 32) ? Tb3Shape<kBatchK, 32>::STEP_COST : Tb3Shape<kBatchK, 64>::STEP_COST;
-    const long long tiles = (long long)((nx + bxo - 1) / bxo) * ((ny + byo - 1) / byo);
-    const int chunks = (nz + zc - 1) / zc;
-    return (int)std::min<long long>(tiles * ((long long)nz + 2LL * kBatchK * chunks) * cost, 0x7fffffff);
+    if (k == 2) return cols == 32 ? tb3d_work_kw<2, 32>(nx, ny, nz, zc) : tb3d_work_kw<2, 64>(nx, ny, nz, zc);
+    return cols == 32 ? tb3d_work_kw<3, 32>(nx, ny, nz, zc) : tb3d_work_kw<3, 64>(nx, ny, nz, zc);
 }
 
 }  // namespace frkc2

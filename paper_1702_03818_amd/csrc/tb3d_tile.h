@@ -161,7 +161,12 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
     // 1..K-1: planes (q-1, q, q+1) around the plane the next level computes.
     constexpr int PF = EMB ? 1 : 2;                 // EMB: registers for the What rings
     constexpr int NR = PF + 3;
-    const int t_begin = z0 - K, t_end = z1 + K;     // level 0 planes z0-K .. z1+K-1
+    // Steps z0-K .. z0-1 only fill the levels below the chunk. At a Dirichlet
+    // lower end those planes are ghosts, 0 at every level, which the rings
+    // and LDS hold from the start: the march begins at plane 0, with the
+    // ghost plane's D put in place (below).
+    const bool lead_ghost = dir && z0 == 0;
+    const int t_begin = lead_ghost ? 0 : z0 - K, t_end = z1 + K;   // level 0 planes
     double2 L0[NR];
     double D0[NR];
     constexpr bool ER = EMB && !IN_REAL;            // embedded input read from memory
@@ -194,6 +199,13 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
 
     if (dir) {
         for (int i = tid; i < 2 * K * PL; i += 1024) sLp[i] = make_double2(0.0, 0.0);
+        if (VC && lead_ghost) {
+            // planes -1 and -2 in the register ring, plane -1 in the LDS ring,
+            // as the skipped steps would have left them (clamped loads)
+            D0[NR - 1] = LD(-1);
+            D0[NR - 2] = LD(-2);
+            sD[dslot(-1)][slot] = D0[NR - 1];
+        }
         __syncthreads();
     }
 

@@ -32,6 +32,9 @@ OPT_TBLOCK = 1
 OPT_TILE = 3
 OPT_CLEAR_TUNED = 4
 OPT_ZCHUNK = 5
+OPT_BATCH_K3 = 6
+OPT_BATCH_COLS = 7
+OPT_BATCH_K2 = 8
 
 
 class Frkc2Error(RuntimeError):
@@ -71,6 +74,12 @@ class TuneResult(ctypes.Structure):
                 ("ms_default", ctypes.c_double)]
 
 
+class BatchTuneResult(ctypes.Structure):
+    _fields_ = [("k3", ctypes.c_int), ("cols3", ctypes.c_int), ("k2", ctypes.c_int),
+                ("candidates", ctypes.c_int), ("ms_best", ctypes.c_double),
+                ("ms_default", ctypes.c_double)]
+
+
 _lib = None
 _VP = ctypes.c_void_p
 USER_F = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong,
@@ -103,6 +112,11 @@ _SIGS = {
                                           ctypes.POINTER(_VP), ctypes.POINTER(_VP), _DP,
                                           ctypes.POINTER(ctypes.c_int), ctypes.c_double, _VP,
                                           ctypes.c_size_t, _VP]),
+    "frkc2_batched_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Grid),
+                                              ctypes.POINTER(_VP), ctypes.POINTER(_VP), _DP,
+                                              ctypes.POINTER(ctypes.c_int), ctypes.c_double,
+                                              ctypes.c_int, _VP, ctypes.c_size_t, _VP,
+                                              ctypes.POINTER(BatchTuneResult)]),
     "frkc2_batched_status": (ctypes.c_int, [_VP, _VP]),
     "frkc2_batched_release": (ctypes.c_int, [_VP]),
     "frkc2_reduce": (ctypes.c_int, [ctypes.c_int, _VP, _VP, ctypes.c_size_t, _DP, _VP,
@@ -495,6 +509,22 @@ def frkc2_step_batched(args: BatchedArgs, nu=0.01, stream=None, ws=None):
     return _check(lib.frkc2_step_batched(args.n, args.grids, args.w, args.D, args.T, args.s,
                                          float(nu), ctypes.c_void_p(buf.data_ptr()), buf.numel(),
                                          _stream_ptr(stream)))
+
+
+def frkc2_batched_autotune(args: BatchedArgs, nu=0.01, reps=2, stream=None, ws=None):
+    """Time the batch's launch configurations on this problem set and keep the fastest for it.
+    Every timed superstep advances the states in args (pass copies to keep them). Returns the
+    result fields as a dict."""
+    lib = load()
+    need = lib.frkc2_batched_workspace_bytes(args.n, args.grids, args.s)
+    if need == 0:
+        _check(-1)
+    buf = ws if ws is not None else workspace(need, key="batched")
+    r = BatchTuneResult()
+    _check(lib.frkc2_batched_autotune(args.n, args.grids, args.w, args.D, args.T, args.s,
+                                      float(nu), int(reps), ctypes.c_void_p(buf.data_ptr()),
+                                      buf.numel(), _stream_ptr(stream), ctypes.byref(r)))
+    return {f: getattr(r, f) for f, _ in BatchTuneResult._fields_}
 
 
 def frkc2_batched_status(ws=None, stream=None):

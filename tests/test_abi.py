@@ -140,6 +140,50 @@ def test_set_option_validation():
     assert F.frkc2_set_option(F.OPT_TILE, 0) == 0
 
 
+@pytest.mark.parametrize("key,good,bad", [("OPT_BATCH_K3", (0, 2, 3), (1, 4, -1)),
+                                          ("OPT_BATCH_COLS", (0, 1, 32, 64), (2, 16, 48, 128)),
+                                          ("OPT_BATCH_K2", (0, 2, 3, 4, 6), (1, 5, 8))])
+def test_batch_option_validation(key, good, bad):
+    lib = F.load()
+    for v in bad:
+        assert lib.frkc2_set_option(getattr(F, key), v) == -1
+    for v in good:
+        assert lib.frkc2_set_option(getattr(F, key), v) == 0
+    assert lib.frkc2_set_option(getattr(F, key), 0) == 0
+
+
+def test_batched_autotune_validation():
+    """Argument errors come back before any HIP call."""
+    lib = F.load()
+    g = (F.Grid * 1)(grid(n=(8, 8, 8), op=0))
+    s = (ctypes.c_int * 1)(8)
+    w = (ctypes.c_void_p * 1)(None)
+    D = (ctypes.c_void_p * 1)(None)
+    T = (ctypes.c_double * 1)(0.001)
+    r = F.BatchTuneResult()
+    assert lib.frkc2_batched_autotune(1, g, w, D, T, s, 0.01, 2, None, 0, None,
+                                      ctypes.byref(r)) == -1          # w[0] NULL
+    w2 = (ctypes.c_void_p * 1)(16)
+    for reps in (0, 101):
+        assert lib.frkc2_batched_autotune(1, g, w2, D, T, s, 0.01, reps, None, 0, None,
+                                          ctypes.byref(r)) == -1
+    assert lib.frkc2_batched_autotune(1, g, w2, D, T, s, 0.01, 2, None, 0, None, None) == -1
+    s_bad = (ctypes.c_int * 1)(7)
+    assert lib.frkc2_batched_autotune(1, g, w2, D, T, s_bad, 0.01, 2, None, 0, None,
+                                      ctypes.byref(r)) == -1
+    assert lib.frkc2_batched_autotune(1, g, w2, D, T, s, 0.01, 2, None, 0, None,
+                                      ctypes.byref(r)) == -2          # no workspace
+
+
+def test_batched_workspace_covers_every_depth():
+    """The work tables are sized for the most pass levels any supported depth gives."""
+    lib = F.load()
+    g3 = (F.Grid * 1)(grid(n=(8, 8, 8), op=0))
+    small = lib.frkc2_batched_workspace_bytes(1, g3, (ctypes.c_int * 1)(2))
+    big = lib.frkc2_batched_workspace_bytes(1, g3, (ctypes.c_int * 1)(514))
+    assert 0 < small < big
+
+
 def test_grid_from_problem():
     p = wl.heat1d()
     g = F.make_grid(p)

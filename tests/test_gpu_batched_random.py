@@ -1,8 +1,10 @@
 """Seeded random batches: mixed 2D/3D problems with ragged sizes, both boundaries and linear
-operators, and stage counts that exercise every pass structure of the batch (s = 2 and 4 run
-single stages only, larger s fused passes of three (3D) or four (2D) stages with 0..3 single
-stages after them), with eager host work and synchronisation between graph replays; each
-problem against the oracle, bit for bit, after every replay."""
+operators, and stage counts that exercise every pass structure of the batch (s = k runs single
+stages only, larger s fused passes of k stages with 0..k-1 single stages after them), with
+eager host work and synchronisation between graph replays; each problem against the oracle,
+bit for bit, after every replay, under the built-in launch configuration, forced ones (3D
+depth 2 or 3, width 32, 64 or one per problem, 2D depth 2, 3, 4 or 6) and the one the batch
+autotuner picks."""
 import numpy as np
 import pytest
 
@@ -71,6 +73,65 @@ def test_random_batch_matches_oracle(seed, count):
                 assert np.array_equal(got, cur[j]), "replay %d problem %d %s s=%d: %d values differ" % (
                     rep, j, p.n, s, int(np.sum(got != cur[j])))
     finally:
+        F.frkc2_batched_release()
+
+
+def _run_and_check(probs, reps):
+    ws = [dev(p.w0) for p, _, _, _ in probs]
+    Ds = [dev(p.D) if p.D is not None else None for p, _, _, _ in probs]
+    args = F.BatchedArgs([p for p, _, _, _ in probs], ws, Ds, [T for _, _, T, _ in probs],
+                         [s for _, s, _, _ in probs])
+    cur = [p.w0.reshape(-1).copy() for p, _, _, _ in probs]
+    for rep in range(reps):
+        F.frkc2_step_batched(args)
+        torch.cuda.synchronize()
+        assert F.frkc2_batched_status() == 0
+        for j, ((p, s, T, c), w) in enumerate(zip(probs, ws)):
+            cur[j] = stage.superstep(p, cur[j], T * c.a_re, T * c.a_im).reshape(-1)
+            got = w.cpu().numpy()
+            assert np.array_equal(got, cur[j]), "replay %d problem %d %s s=%d: %d values differ" % (
+                rep, j, p.n, s, int(np.sum(got != cur[j])))
+
+
+@pytest.mark.parametrize("k3,cols,k2", [(2, 32, 2), (2, 64, 3), (3, 32, 6), (3, 64, 4),
+                                        (2, 64, 6), (3, 32, 2), (2, 32, 4), (3, 64, 3),
+                                        (3, 1, 4), (2, 1, 3)])
+def test_batch_configurations_match_oracle(k3, cols, k2):
+    """Every launch configuration gives the oracle's bits, over two replays."""
+    probs = _batch(5, 20)
+    try:
+        for key, v in ((F.OPT_BATCH_K3, k3), (F.OPT_BATCH_COLS, cols), (F.OPT_BATCH_K2, k2)):
+            assert F.frkc2_set_option(key, v) == 0
+        _run_and_check(probs, 2)
+    finally:
+        for key in (F.OPT_BATCH_K3, F.OPT_BATCH_COLS, F.OPT_BATCH_K2):
+            F.frkc2_set_option(key, 0)
+        F.frkc2_batched_release()
+
+
+def test_batched_autotune_then_step():
+    """The autotuner times the candidates on copies of the states (which it advances), stores
+    its choice for the problem set, and the graph built with it gives the oracle's bits; the
+    same for a batch of 3D problems only and one of 2D problems only."""
+    full = _batch(6, 16)
+    subsets = [full, [q for q in full if q[0].ndim == 3], [q for q in full if q[0].ndim == 2]]
+    try:
+        for probs in subsets:
+            assert probs
+            tw = [dev(p.w0) for p, _, _, _ in probs]
+            Ds = [dev(p.D) if p.D is not None else None for p, _, _, _ in probs]
+            targs = F.BatchedArgs([p for p, _, _, _ in probs], tw, Ds,
+                                  [T for _, _, T, _ in probs], [s for _, s, _, _ in probs])
+            r = F.frkc2_batched_autotune(targs, reps=1)
+            assert r["k3"] in (2, 3) and r["cols3"] in (1, 32, 64) and r["k2"] in (2, 3, 4, 6)
+            has3 = any(p.ndim == 3 for p, _, _, _ in probs)
+            has2 = any(p.ndim == 2 for p, _, _, _ in probs)
+            assert r["candidates"] == 1 + 5 * has3 + 3 * has2
+            assert 0 < r["ms_best"] <= r["ms_default"]
+            assert all(bool(torch.isfinite(w).all()) for w in tw)
+            _run_and_check(probs, 2)
+    finally:
+        F.frkc2_set_option(F.OPT_CLEAR_TUNED, 0)
         F.frkc2_batched_release()
 
 
