@@ -260,7 +260,10 @@ int frkc2_step_noalloc(const frkc2_grid *g, double *w, const double *D, double T
  * stages), then the transposed stages run in reverse order:
  * lam <- lam + conj(tau_l) A lam (A is symmetric), with the face-diffusivity
  * derivative -Re(tau_l conj(lam_nb - lam_c)(W_nb - W_c))/h^2 of each stage
- * accumulated per cell. Asynchronous.
+ * accumulated per cell. On request two reverse stages share an HBM pass on
+ * 3D grids (FRKC2_OPT_ADJ_STAGES), with the same bits. lam_n may alias
+ * lam_next.
+ * Asynchronous.
  */
 int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const double *D, double T, int s,
                        double nu, const double *lam_next, double *lam_n, double *grad_logD,
@@ -552,6 +555,11 @@ int frkc2_autotune(const frkc2_grid *g, const double *w, const double *D, int s,
  *                     >= 2048 otherwise)
  *   FRKC2_OPT_CLEAR_TUNED  forget every configuration frkc2_autotune and
  *                     frkc2_batched_autotune stored (value ignored)
+ *   FRKC2_OPT_ADJ_STAGES  reverse stages per pass of frkc2_step_adjoint: 0 =
+ *                     automatic (one), 1, or 2 (3D grids; others run one;
+ *                     two move 44 instead of 72 bytes per cell and stage but
+ *                     take longer at 128^3, their extra arithmetic and
+ *                     barriers being the limit)
  *   FRKC2_OPT_BATCH_K3, FRKC2_OPT_BATCH_COLS, FRKC2_OPT_BATCH_K2  the launch
  *                     configuration of every frkc2_step_batched graph built
  *                     afterwards: stages per fused 3D pass (2 or 3), output
@@ -567,6 +575,7 @@ int frkc2_autotune(const frkc2_grid *g, const double *w, const double *D, int s,
 #define FRKC2_OPT_TILE 3
 #define FRKC2_OPT_CLEAR_TUNED 4
 #define FRKC2_OPT_ZCHUNK 5
+#define FRKC2_OPT_ADJ_STAGES 9
 #define FRKC2_OPT_BATCH_K3 6
 #define FRKC2_OPT_BATCH_COLS 7
 #define FRKC2_OPT_BATCH_K2 8

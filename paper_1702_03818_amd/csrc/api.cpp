@@ -26,6 +26,7 @@ thread_local char g_err[512] = "";
 int g_tblock = 0;
 int g_tile = 0;
 int g_zchunk = 0;
+int g_adj_stages = 0;   // reverse stages per pass of the adjoint: 0 automatic, 1, 2
 
 constexpr size_t kAlign = 256;
 constexpr size_t kScratch = 64 * 1024;   // reduction partials + stepsize table
@@ -409,6 +410,14 @@ extern "C" int frkc2_set_option(int key, int value)
             g_tuned.clear();
         }
         batched_clear_tuned();
+        return FRKC2_OK;
+    }
+    if (key == FRKC2_OPT_ADJ_STAGES) {
+        if (value < 0 || value > 2) {
+            set_error("adjoint stages per pass must be 0 (automatic), 1 or 2");
+            return FRKC2_EINVAL;
+        }
+        g_adj_stages = value;
         return FRKC2_OK;
     }
     if (key == FRKC2_OPT_BATCH_K3 || key == FRKC2_OPT_BATCH_COLS || key == FRKC2_OPT_BATCH_K2)
@@ -927,19 +936,33 @@ extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const 
     }
     const bool vc = kg.op == FRKC2_OP_VARCOEF;
     if (vc) HIP_TRY(launch_zero(N, gD, st), "adjoint: zero gD");
-    for (int r = 0; r < s; ++r) {
+    // reverse stage r (stage l = s-1-r): lambda^{l+1} -> lambda^l; pass q
+    // writes buffer q & 1. On request, 3D grids run two stages per pass (s is
+    // even) in the same per-cell arithmetic; measured slower than one per
+    // pass, so not the default. One pass of two would read lam_next and write
+    // lam_n, so it needs the two to be distinct.
+    const bool pairs = kg.ndim == 3 && g_adj_stages == 2 && !(s == 2 && lam_n == lam_next);
+    auto rev = [&](int r, int q_in, int q_out) {
         const int l = s - 1 - r;
         AdjArgs a{};
         if (r == 0) a.lam_in_re = lam_next;
-        else a.lam_in_c = lam[(r - 1) & 1];
+        else a.lam_in_c = lam[q_in & 1];
         if (r == s - 1) a.lam_out_re = lam_n;
-        else a.lam_out_c = lam[r & 1];
+        else a.lam_out_c = lam[q_out & 1];
         a.W = S(l);
         a.D = D;
         a.gD = vc ? gD : nullptr;
         a.tr = T * are[l];
         a.ti = T * aim[l];
-        HIP_TRY(launch_adjoint_stage(kg, a, st), "adjoint stage");
+        return a;
+    };
+    if (pairs) {
+        for (int r = 0, q = 0; r < s; r += 2, ++q)
+            HIP_TRY(launch_adjoint_pair(kg, rev(r, q - 1, q), rev(r + 1, q - 1, q), st),
+                    "adjoint pair");
+    } else {
+        for (int r = 0; r < s; ++r)
+            HIP_TRY(launch_adjoint_stage(kg, rev(r, r - 1, r), st), "adjoint stage");
     }
     if (vc && grad_logD) HIP_TRY(launch_grad_finish(N, D, gD, grad_logD, st), "adjoint: gradient");
     return crc;

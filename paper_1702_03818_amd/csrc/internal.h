@@ -130,6 +130,10 @@ struct AdjArgs {
     double tr, ti;
 };
 int launch_adjoint_stage(const KGrid &g, const AdjArgs &a, hipStream_t st);
+// Reverse stages a1 (stage l) then a2 (stage l-1) in one pass, 3D LAPLACE or
+// VARCOEF: lam in from a1, lam out to a2 (they must not alias), W^l = a1.W,
+// W^{l-1} = a2.W, D and gD from a1.
+int launch_adjoint_pair(const KGrid &g, const AdjArgs &a1, const AdjArgs &a2, hipStream_t st);
 int launch_grad_finish(long long n, const double *D, const double *gD, double *grad_logD,
                        hipStream_t st);
 

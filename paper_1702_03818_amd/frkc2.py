@@ -33,6 +33,7 @@ OPT_TILE = 3
 OPT_CLEAR_TUNED = 4
 OPT_ZCHUNK = 5
 OPT_BATCH_K3 = 6
+OPT_ADJ_STAGES = 9
 OPT_BATCH_COLS = 7
 OPT_BATCH_K2 = 8
 

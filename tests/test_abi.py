@@ -140,7 +140,8 @@ def test_set_option_validation():
     assert F.frkc2_set_option(F.OPT_TILE, 0) == 0
 
 
-@pytest.mark.parametrize("key,good,bad", [("OPT_BATCH_K3", (0, 2, 3), (1, 4, -1)),
+@pytest.mark.parametrize("key,good,bad", [("OPT_ADJ_STAGES", (0, 1, 2), (3, -1)),
+                                          ("OPT_BATCH_K3", (0, 2, 3), (1, 4, -1)),
                                           ("OPT_BATCH_COLS", (0, 1, 32, 64), (2, 16, 48, 128)),
                                           ("OPT_BATCH_K2", (0, 2, 3, 4, 6), (1, 5, 8))])
 def test_batch_option_validation(key, good, bad):
