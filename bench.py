@@ -95,13 +95,15 @@ def _short(name):
     return name.replace("frkc2::(anonymous namespace)::", "")
 
 
-def summarize_trace(directory, command, k, tile, out_md, pattern=None, title=None, note=None):
-    """Per-(kernel, grid) durations from a rocprofv3 --kernel-trace run, as markdown."""
+def summarize_trace(directory, command, k, tile, out_md, pattern=None, title=None, note=None,
+                    by_kernel=False):
+    """Per-(kernel, grid) durations from a rocprofv3 --kernel-trace run, as markdown (per
+    kernel over all grid sizes with by_kernel)."""
     groups = {}
     for r in _csv_rows(directory, "kernel_trace.csv"):
         grid = int(r["Grid_Size"]) if "Grid_Size" in r else (
             int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]))
-        key = (r["Kernel_Name"], grid)
+        key = (r["Kernel_Name"], "various" if by_kernel else grid)
         d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
         groups.setdefault(key, []).append(d)
     total = sum(sum(v) for v in groups.values())
@@ -113,14 +115,14 @@ def summarize_trace(directory, command, k, tile, out_md, pattern=None, title=Non
              "Command (from /tmp, with the repository as the working copy):", "",
              "    " + command, ""] + ([note, ""] if note else []) + [
              "Durations per (kernel, grid size in threads) from rocprofv3 `kernel_trace.csv`, "
-             "microseconds.", "",
-             "%s: `%s` at grid %d: %d launches, average %.2f us." % (
+             "microseconds%s." % (", over all grid sizes of a kernel" if by_kernel else ""), "",
+             "%s: `%s` at grid %s: %d launches, average %.2f us." % (
                  what, _short(dom[0]), dom[1], len(groups[dom]),
                  sum(groups[dom]) / len(groups[dom])), "",
              "| Kernel | grid | calls | total ms | average us | min us | max us | % |",
              "|---|---|---|---|---|---|---|---|"]
     for key, v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:25]:
-        lines.append("| `%s` | %d | %d | %.2f | %.2f | %.2f | %.2f | %.2f |" % (
+        lines.append("| `%s` | %s | %d | %.2f | %.2f | %.2f | %.2f | %.2f |" % (
             _short(key[0]), key[1], len(v), sum(v) * 1e-3, sum(v) / len(v), min(v), max(v),
             100 * sum(v) / total))
     with open(out_md, "w") as f:
@@ -751,6 +753,8 @@ def main():
     ap.add_argument("--trace-title", default=None)
     ap.add_argument("--trace-note", default=None)
     ap.add_argument("--trace-out", default=None, help="with --summarize-trace: output file")
+    ap.add_argument("--trace-by-kernel", action="store_true",
+                    help="with --summarize-trace: one row per kernel over all grid sizes")
     ap.add_argument("--sq-kernel", default="tb3d_stage<1, 1, 3, false, false, false, false, 64>")
     ap.add_argument("--sq-title", default="3D variable-D interior pass, 256^3, s = 100, k = 3")
     ap.add_argument("--command", action="append", default=[],
@@ -768,7 +772,8 @@ def main():
             if args.trace_out:
                 out_md = args.trace_out
             avg = summarize_trace(args.summarize_trace, args.command[0], k, tile, out_md,
-                                  args.trace_kernel, args.trace_title, args.trace_note)
+                                  args.trace_kernel, args.trace_title, args.trace_note,
+                                  args.trace_by_kernel)
             print("dominant kernel average %.2f us" % avg)
         else:
             t = summarize_counters(args.summarize_counters[0], args.summarize_counters[1],
