@@ -334,6 +334,19 @@ int frkc2_batched_release(void *ws);                  /* frees the graph cached 
  * Errors: FRKC2_EINVAL (arguments), FRKC2_EUNSTABLE, FRKC2_ENONFINITE,
  * FRKC2_ENOMEM (workspace), FRKC2_EHIP.
  */
+/*
+ * frkc2_batched_config -- the launch configuration frkc2_step_batched would
+ * build a graph with for this problem set now: the FRKC2_OPT_BATCH_* options
+ * where set, else what frkc2_batched_autotune stored for the set, else the
+ * built-in one. Host only, no GPU use.
+ *   nprob, grids, s  as for frkc2_step_batched
+ *   k3, cols3, k2    host, out: stages per fused 3D pass, output columns of
+ *                    its tiles (1: per problem), stages per fused 2D pass
+ * Errors: FRKC2_EINVAL.
+ */
+int frkc2_batched_config(int nprob, const frkc2_grid *grids, const int *s, int *k3, int *cols3,
+                         int *k2);
+
 typedef struct {
     int k3;             /* stages per fused 3D pass */
     int cols3;          /* output columns of the fused 3D tiles (1: per problem) */

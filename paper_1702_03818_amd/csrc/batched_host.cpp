@@ -730,6 +730,23 @@ extern "C" int frkc2_batched_autotune(int nprob, const frkc2_grid *grids, double
     return FRKC2_OK;
 }
 
+extern "C" int frkc2_batched_config(int nprob, const frkc2_grid *grids, const int *s, int *k3,
+                                    int *cols3, int *k2)
+{
+    std::vector<KGrid> kg;
+    if (!validate(nprob, grids, s, kg)) return FRKC2_EINVAL;
+    if (!k3 || !cols3 || !k2) {
+        set_error("batched config: output pointers must be non-NULL");
+        return FRKC2_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    const BatchCfg c = resolve_cfg(nprob, kg, s);
+    *k3 = c.k3;
+    *cols3 = c.cols3;
+    *k2 = c.k2;
+    return FRKC2_OK;
+}
+
 extern "C" int frkc2_batched_status(void *ws, hipStream_t st)
 {
     if (!ws) {

@@ -118,6 +118,11 @@ _SIGS = {
                                               ctypes.POINTER(ctypes.c_int), ctypes.c_double,
                                               ctypes.c_int, _VP, ctypes.c_size_t, _VP,
                                               ctypes.POINTER(BatchTuneResult)]),
+    "frkc2_batched_config": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Grid),
+                                            ctypes.POINTER(ctypes.c_int),
+                                            ctypes.POINTER(ctypes.c_int),
+                                            ctypes.POINTER(ctypes.c_int),
+                                            ctypes.POINTER(ctypes.c_int)]),
     "frkc2_batched_status": (ctypes.c_int, [_VP, _VP]),
     "frkc2_batched_release": (ctypes.c_int, [_VP]),
     "frkc2_reduce": (ctypes.c_int, [ctypes.c_int, _VP, _VP, ctypes.c_size_t, _DP, _VP,
@@ -526,6 +531,18 @@ def frkc2_batched_autotune(args: BatchedArgs, nu=0.01, reps=2, stream=None, ws=N
                                       float(nu), int(reps), ctypes.c_void_p(buf.data_ptr()),
                                       buf.numel(), _stream_ptr(stream), ctypes.byref(r)))
     return {f: getattr(r, f) for f, _ in BatchTuneResult._fields_}
+
+
+def frkc2_batched_config(grids, s_list):
+    """(k3, cols3, k2) a graph built now for this problem set would use (host only)."""
+    lib = load()
+    n = len(grids)
+    garr = (Grid * n)(*[make_grid(g) for g in grids])
+    sarr = (ctypes.c_int * n)(*[int(v) for v in s_list])
+    k3, c3, k2 = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib.frkc2_batched_config(n, garr, sarr, ctypes.byref(k3), ctypes.byref(c3),
+                                    ctypes.byref(k2)))
+    return k3.value, c3.value, k2.value
 
 
 def frkc2_batched_status(ws=None, stream=None):

@@ -169,6 +169,29 @@ def porous2d(seed: int = 3, n: int = 4096, sigma_cells: float = 64.0) -> Problem
                    np.ascontiguousarray(u0))
 
 
+def _batch_draw(rng, side2d, side3d, m_range):
+    """Dimension, side and M of one batched problem: the first draws of its generator."""
+    dim = 2 if rng.random() < 0.5 else 3
+    lo, hi = side2d if dim == 2 else side3d
+    side = int(rng.integers(lo, hi + 1))
+    M = int(rng.integers(m_range[0], m_range[1] + 1))
+    return dim, side, M
+
+
+def batched_shapes(seed: int = 4, count: int = 512, side2d=(32, 512), side3d=(32, 128),
+                   m_range=(4, 100)) -> list[tuple[Problem, int]]:
+    """The problems of batched() without their fields (D and u0 left None): the grids and
+    stage counts only, for host-side checks that need no data."""
+    out = []
+    for child in np.random.SeedSequence(seed).spawn(count):
+        rng = np.random.Generator(np.random.PCG64(child))
+        dim, side, M = _batch_draw(rng, side2d, side3d, m_range)
+        _, h = _nodes(side, BC_DIRICHLET0)
+        n = (side, side, side) if dim == 3 else (side, side, 1)
+        out.append((Problem(dim, n, h, BC_DIRICHLET0, OP_VARCOEF, 1.0, None, None), 2 * M))
+    return out
+
+
 def batched(seed: int = 4, count: int = 512, side2d=(32, 512), side3d=(32, 128),
             m_range=(4, 100)) -> list[tuple[Problem, int]]:
     """`count` independent Dirichlet variable-D problems and their stage counts.
@@ -181,10 +204,7 @@ def batched(seed: int = 4, count: int = 512, side2d=(32, 512), side3d=(32, 128),
     out = []
     for child in np.random.SeedSequence(seed).spawn(count):
         rng = np.random.Generator(np.random.PCG64(child))
-        dim = 2 if rng.random() < 0.5 else 3
-        lo, hi = side2d if dim == 2 else side3d
-        side = int(rng.integers(lo, hi + 1))
-        M = int(rng.integers(m_range[0], m_range[1] + 1))
+        dim, side, M = _batch_draw(rng, side2d, side3d, m_range)
         shape = (side,) * dim
         D = lognormal_D(shape, max(2.0, side / 32.0), rng)
         xs, h = _nodes(side, BC_DIRICHLET0)

@@ -402,3 +402,44 @@ def test_frkc4s_needs_brusselator():
     g = grid(op=1)
     assert _split(g) == -1
     assert F.load().frkc4s_workspace_bytes(ctypes.byref(g)) == 0
+
+
+def test_batched_shapes_match_the_batch():
+    """batched_shapes draws the same grids and stage counts as batched (first 6 problems)."""
+    full = wl.batched(count=6)
+    shapes = wl.batched_shapes(count=6)
+    for (p, s), (q, t) in zip(full, shapes):
+        assert (p.ndim, p.n, p.h, s) == (q.ndim, q.n, q.h, t)
+
+
+def test_batched_config_query():
+    """The configuration a graph would be built with: built-in (depths 3 and 4, the width
+    with less modelled work: 32 columns for the 512-problem batch, 64 for one 256^3 grid),
+    then the options, which override it per key; host only."""
+    batch = wl.batched_shapes()
+    grids = [p for p, _ in batch]
+    ss = [s for _, s in batch]
+    assert F.frkc2_batched_config(grids, ss) == (3, 32, 4)
+    big = wl.Problem(3, (256, 256, 256), 1.0 / 257, wl.BC_DIRICHLET0, wl.OP_VARCOEF)
+    assert F.frkc2_batched_config([big], [100]) == (3, 64, 4)
+    try:
+        assert F.frkc2_set_option(F.OPT_BATCH_K2, 6) == 0
+        assert F.frkc2_batched_config(grids, ss) == (3, 32, 6)
+        assert F.frkc2_set_option(F.OPT_BATCH_COLS, 1) == 0
+        assert F.frkc2_batched_config(grids, ss) == (3, 1, 6)
+        assert F.frkc2_set_option(F.OPT_BATCH_K3, 2) == 0
+        assert F.frkc2_batched_config(grids, ss) == (2, 1, 6)
+        assert F.frkc2_set_option(F.OPT_BATCH_COLS, 0) == 0
+        k3, cols, k2 = F.frkc2_batched_config(grids, ss)
+        assert (k3, k2) == (2, 6) and cols in (32, 64)
+    finally:
+        for key in (F.OPT_BATCH_K3, F.OPT_BATCH_COLS, F.OPT_BATCH_K2):
+            F.frkc2_set_option(key, 0)
+    assert F.frkc2_batched_config(grids, ss) == (3, 32, 4)
+    lib = F.load()
+    one = (F.Grid * 1)(F.make_grid(big))
+    sarr = (ctypes.c_int * 1)(100)
+    v = ctypes.c_int()
+    assert lib.frkc2_batched_config(0, one, sarr, ctypes.byref(v), ctypes.byref(v),
+                                    ctypes.byref(v)) == -1
+    assert lib.frkc2_batched_config(1, one, sarr, None, ctypes.byref(v), ctypes.byref(v)) == -1

@@ -124,6 +124,10 @@ def test_batched_autotune_then_step():
                                   [T for _, _, T, _ in probs], [s for _, s, _, _ in probs])
             r = F.frkc2_batched_autotune(targs, reps=1)
             assert r["k3"] in (2, 3) and r["cols3"] in (1, 32, 64) and r["k2"] in (2, 3, 4, 6)
+            # the stored choice is what graphs for this problem set are built with
+            assert F.frkc2_batched_config([p for p, _, _, _ in probs],
+                                          [s for _, s, _, _ in probs]) == (r["k3"], r["cols3"],
+                                                                           r["k2"])
             has3 = any(p.ndim == 3 for p, _, _, _ in probs)
             has2 = any(p.ndim == 2 for p, _, _, _ in probs)
             assert r["candidates"] == 1 + 5 * has3 + 3 * has2
