@@ -374,6 +374,8 @@ double oracle_rho_bound(int ndim, const long *n, int bc, int op, double inv_h2, 
 {
     grid_t g;
     if (make_grid(&g, ndim, n, bc, op, inv_h2, d_const)) return -1.0;
+    /* the state-dependent bounds need the state, the variable one its D */
+    if (((op == OP_POROUS2 || op == OP_BRUSS2) && !w) || (op == OP_VARCOEF && !D)) return -1.0;
     if (op == OP_ADVDIFF) {
         /* |a_ii| + sum_j |a_ij| with a_ii = -sum_f fc_f / h^2, a_ij = fc_f / h^2 */
         double sum = 0.0, asum = 0.0;

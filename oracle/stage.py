@@ -168,13 +168,21 @@ def superstep_embedded(prob, w, tau_re, tau_im, D=None):
 
 
 def rho_bound(prob, w=None, D=None) -> float:
+    """Gershgorin bound of f's Jacobian; the porous and Brusselator bounds depend on the
+    state w (prob.w0 if w is None)."""
     lib = _load()
     n, inv_h2 = _grid_args(prob)
     Dd = D if D is not None else prob.D
     Dd = _f64(Dd) if Dd is not None else None
+    if w is None and prob.op in (2, 3):
+        w = prob.w0
     ww = _f64(w) if w is not None else None
-    return lib.oracle_rho_bound(prob.ndim, n, prob.bc, prob.op, inv_h2, prob.d_const,
-                                _dp(Dd), _dp(ww))
+    r = lib.oracle_rho_bound(prob.ndim, n, prob.bc, prob.op, inv_h2, prob.d_const,
+                             _dp(Dd), _dp(ww))
+    if r < 0:
+        raise ValueError("rho_bound: invalid grid, or a state (porous, Brusselator) or D "
+                         "(variable coefficient) missing")
+    return r
 
 
 def run(prob, s, nsteps, T=None, cfl=None, nu=0.01, w=None, coeffs=None):

@@ -186,6 +186,40 @@ def test_porous_complex_stages_limit_T():
     assert diverged
 
 
+def _max_stable_cfl(p, s, steps=3, iters=10):
+    """Largest cfl (bisection on [0, 1]) for which `steps` supersteps stay bounded."""
+    c = frkc2_coeffs(s, 0.01)
+
+    def ok(cfl):
+        with np.errstate(all="ignore"):
+            try:
+                w, _ = stage.run(p, s, steps, cfl=cfl, coeffs=c)
+            except ZeroDivisionError:
+                return False
+        return bool(np.isfinite(w).all() and np.abs(w).max() < 1.6)
+
+    if ok(1.0):
+        return 1.0, c
+    lo, hi = 0.0, 1.0
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if ok(mid) else (lo, mid)
+    return lo, c
+
+
+def test_porous_stable_step_saturates_in_s():
+    """Characterisation (not a pin) of the porous operator with complex stages: small s run
+    at the full T rho = betabar(s); from s ~ 64 on the longest stable step no longer grows
+    with s (T rho ~ 500 on 32^2, ~1000 on 64^2 and 128^2), so larger s buy no longer steps."""
+    p = wl.porous2d(n=32, sigma_cells=4.0)
+    cfl16, _ = _max_stable_cfl(p, 16)
+    assert cfl16 == 1.0
+    cfl64, c64 = _max_stable_cfl(p, 64)
+    cfl100, c100 = _max_stable_cfl(p, 100)
+    t64, t100 = cfl64 * c64.beta_bar, cfl100 * c100.beta_bar
+    assert 300 < t64 and t100 < 1.5 * t64 and cfl100 < 0.2
+
+
 def test_superstep_linearity():
     """Linear f: S(alpha u + v) = alpha S(u) + S(v)."""
     p = wl.diffusion3d(n=10, nblobs=2)
