@@ -452,7 +452,7 @@ extern "C" int frkc2_rho_bound(const frkc2_grid *g, const double *w, const doubl
         return FRKC2_EINVAL;
     }
     if ((kg.op == FRKC2_OP_POROUS2 || kg.op == FRKC2_OP_BRUSS2) && !w) {
-        set_error("POROUS2 needs w");
+        set_error("the POROUS2 and BRUSS2 bounds need the state w");
         return FRKC2_EINVAL;
     }
     const bool host_only = kg.op == FRKC2_OP_LAPLACE || kg.op == FRKC2_OP_ADVDIFF;
