@@ -291,7 +291,7 @@ int default_depth(const KGrid &kg) { return (kg.ndim == 3) ? 3 : (kg.ndim == 2 ?
 // prefers for this grid.
 int default_tile(const KGrid &kg)
 {
-    if (kg.ndim != 3) return 0;
+    if (kg.ndim != 3 || !tb3d_plane_ok(kg)) return 0;
     return tb3d_pick_cols(kg, default_depth(kg)) == 32 ? 4 : 3;
 }
 
@@ -914,7 +914,7 @@ extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const 
     HIP_TRY(launch_real_to_complex(N, w_n, S(0), st), "adjoint: W^0");
     for (int l = 0; l + 1 < s;) {
         const int left = s - 1 - l;
-        const int k = (kg.ndim == 3 && left >= 2) ? (left >= 3 ? 3 : 2) : 1;
+        const int k = (kg.ndim == 3 && tb3d_plane_ok(kg) && left >= 2) ? (left >= 3 ? 3 : 2) : 1;
         PassArgs pa{};
         pa.k = k;
         pa.D = D;

@@ -113,8 +113,8 @@ __device__ void run_fused(const BatchProblem &P, Tb3Args &a, long long c, double
 {
     const int bx = (int)(c % P.ntx3);
     const long long r = c / P.ntx3;
-    tb3d_tile<OP, BC, KB, IR, OR, false, false, W>(a, bx, (int)(r % P.nty3), (int)(r / P.nty3),
-                                                   sL, sD);
+    tb3d_tile<OP, BC, KB, IR, OR, false, false, W, false, false>(a, bx, (int)(r % P.nty3),
+                                                                 (int)(r / P.nty3), sL, sD);
 }
 
 template <int OP, int BC, int W, int KB>
@@ -144,8 +144,8 @@ template <bool FUSED, int W, int KB>
 __global__ __launch_bounds__(1024) void batched_pass3(Pass3Args t)
 {
     using S1 = TileShape<VAR, DIR, 3, kPBX, kPBY>;
-    constexpr int NL = FUSED ? Tb3Lds<VAR, KB, W>::L : S1::LDS_W;
-    constexpr int ND = FUSED ? Tb3Lds<VAR, KB, W>::D : S1::LDS_D;
+    constexpr int NL = FUSED ? Tb3Lds<VAR, KB, W, true>::L : S1::LDS_W;
+    constexpr int ND = FUSED ? Tb3Lds<VAR, KB, W, true>::D : S1::LDS_D;
     __shared__ double2 sL[NL];
     __shared__ double sD[ND];
     long long first, hi, step;

@@ -111,6 +111,39 @@ __device__ __forceinline__ double load_r_nb(const Dims &d, const double *v, int 
     return ghost ? 0.0 : r;
 }
 
+// Buffer accesses: a resource (scalar registers) whose base is the given
+// pointer and whose extent is `bytes`, addressed by a 32-bit byte offset per
+// lane. An offset at or past the extent reads 0 and drops a store. The third
+// word is the CDNA raw-buffer format (no swizzle, no stride).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, 0x00020000);
+}
+
+__device__ __forceinline__ double buf_load_f64(const double *base, int bytes, unsigned off)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(buf_rsrc(base, bytes), off, 0, 0);
+    return __builtin_bit_cast(double, v);
+}
+
+__device__ __forceinline__ double2 buf_load_c(const double2 *base, int bytes, unsigned off)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(buf_rsrc(base, bytes), off, 0, 0);
+    return __builtin_bit_cast(double2, v);
+}
+
+__device__ __forceinline__ void buf_store_f64(double *base, int bytes, unsigned off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(HIP_vector_base<unsigned, 2>::Native_vec_, v),
+                                          buf_rsrc(base, bytes), off, 0, 0);
+}
+
+__device__ __forceinline__ void buf_store_c(double2 *base, int bytes, unsigned off, double2 v)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(HIP_vector_base<unsigned, 4>::Native_vec_, v),
+                                           buf_rsrc(base, bytes), off, 0, 0);
+}
+
 // W^2 of a complex value in the fixed order the library and its CPU check
 // share: (fma(re, re, -(im*im)), 2*(re*im)).
 __device__ __forceinline__ void csq(double2 c, double &qr, double &qi)

@@ -44,8 +44,8 @@ template <int OP, int BC, int K, bool IN_REAL, bool OUT_REAL, bool EMB = false, 
           int W = 64>
 __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
 {
-    __shared__ double2 sL[Tb3Lds<OP, K, W>::L];
-    __shared__ double sD[Tb3Lds<OP, K, W>::D];
+    __shared__ double2 sL[Tb3Lds<OP, K, W, EMB>::L];
+    __shared__ double sD[Tb3Lds<OP, K, W, EMB>::D];   // the D ring where EMB turns the faces off
     int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int bx = lb % a.ntx;
     lb /= a.ntx;
@@ -169,9 +169,11 @@ double tb3d_cost(const KGrid &g)
 
 }  // namespace
 
+bool tb3d_plane_ok(const KGrid &g) { return (long long)g.nx * g.ny <= (1LL << 27); }
+
 int launch_tb3d(const KGrid &g, const PassArgs &p, hipStream_t st)
 {
-    if (g.ndim != 3 || (p.k != 2 && p.k != 3)) return (int)hipErrorInvalidValue;
+    if (g.ndim != 3 || (p.k != 2 && p.k != 3) || !tb3d_plane_ok(g)) return (int)hipErrorInvalidValue;
     Tb3Args a{};
     a.in_re = p.in_re;
     a.in_c = reinterpret_cast<const double2 *>(p.in_c);

@@ -69,12 +69,15 @@ struct Tb3Shape {
     static constexpr int STEP_COST = (K == 3) ? (W == 64 ? 8 : 10) : 7;
 };
 
-// LDS of one tile: level planes (double2) and the diffusivity ring (double).
-template <int OP, int K, int W = 64>
+// LDS of one tile: level planes (double2), double-buffered by step parity,
+// and for the diffusion operator D/2 (double): one plane double-buffered
+// where the faces live in registers, a ring of K + 2 planes where the
+// levels read their D neighbours themselves (DRING).
+template <int OP, int K, int W = 64, bool DRING = false>
 struct Tb3Lds {
     static constexpr int PL = Tb3Shape<K, W>::SX * Tb3Shape<K, W>::SY;
     static constexpr int L = 2 * K * PL;
-    static constexpr int D = (OP == FRKC2_OP_VARCOEF) ? (K + 2) * PL : 1;
+    static constexpr int D = (OP == FRKC2_OP_VARCOEF) ? (DRING ? K + 2 : 2) * PL : 1;
 };
 
 // EMB: also advance the embedded first-order solution of the error estimate
@@ -82,8 +85,13 @@ struct Tb3Lds {
 // pointwise recursion carried in registers next to the level windows.
 // ST: also write the intermediate levels 1..K-1 of the output columns (the
 // stage states the adjoint's reverse sweep reads).
+// FACES: the diffusion operator's faces from a register ring (below); off
+// where the registers are taken (the embedded solution; the batch's kernels,
+// which hold the code of two operators), with the D ring of Tb3Lds<..., true>.
+// BUF: global accesses through buffer resources (below); off in the batch's
+// kernels, which address through 64-bit lane pointers.
 template <int OP, int BC, int K, bool IN_REAL, bool OUT_REAL, bool EMB = false, bool ST = false,
-          int W = 64>
+          int W = 64, bool FACES = !EMB, bool BUF = true>
 __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int bz, double2 *sLp,
                                           double *sDp)
 {
@@ -92,8 +100,11 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
     constexpr int SX = S::SX;                       // padding cells around each plane
     constexpr int PL = Tb3Lds<OP, K, W>::PL;
     constexpr bool VC = (OP == VAR);
-    constexpr int ND = K + 2;                       // D ring: planes t-K-1 .. t
-    // level m plane, by step parity; D ring
+    // Diffusivity faces D_f = D_c/2 + D_nb/2: from a register ring (FR), or
+    // per level from D/2 planes in LDS (DR)
+    constexpr bool FR = VC && FACES, DR = VC && !FACES;
+    constexpr int ND = DR ? K + 2 : 2;              // D/2 planes in LDS
+    // level m plane by step parity; D/2 planes
     double2 (*sL)[K][PL] = reinterpret_cast<double2 (*)[K][PL]>(sLp);
     double (*sD)[VC ? PL : 1] = reinterpret_cast<double (*)[VC ? PL : 1]>(sDp);
 
@@ -135,36 +146,63 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
                          y < a.ny;
     const int slot = (ly + 1) * SX + lx + 1;
 
-    // Global addresses: a fixed column offset per lane (clamped into the grid
-    // for Dirichlet, wrapped for periodic) plus a uniform plane offset.
+    // Global accesses: buffer loads and stores whose resource (scalar
+    // registers) starts at the plane and spans its bytes, plus the lane's
+    // column offset in bytes (clamped into the grid for Dirichlet, wrapped for
+    // periodic) in one 32-bit vector register, so no lane holds a 64-bit
+    // pointer. The host sends planes of more than 2^27 points elsewhere, so
+    // every offset and extent fits 31 bits.
+    // (Without BUF: a 64-bit pointer per lane to its column plus a uniform
+    // plane offset.)
     const int cx = (BC == PER) ? wrap(x, a.nx) : min(max(x, 0), a.nx - 1);
     const int cy = (BC == PER) ? wrap(y, a.ny) : min(max(y, 0), a.ny - 1);
-    const long long ixy = cx + (long long)a.nx * cy;
+    const unsigned oxy = (unsigned)cx + (unsigned)a.nx * (unsigned)cy;
+    const unsigned o8 = 8u * oxy, o16 = 16u * oxy;
     const long long pst = (long long)a.nx * a.ny;
+    const int pb8 = (int)(8 * pst), pb16 = (int)(16 * pst);   // plane extents in bytes
     auto zoff = [&](int gz) {
         return pst * ((BC == PER) ? wrap(gz, a.nz) : min(max(gz, 0), a.nz - 1));
     };
-    const double2 *pWc = IN_REAL ? nullptr : a.in_c + ixy;
-    const double *pWr = IN_REAL ? a.in_re + ixy : nullptr;
-    const double *pD = VC ? a.D + ixy : nullptr;
-    const double *pE = (EMB && !IN_REAL) ? a.emb_in + ixy : nullptr;
+    const double2 *pWc = (BUF || IN_REAL) ? nullptr : a.in_c + oxy;
+    const double *pWr = (BUF || !IN_REAL) ? nullptr : a.in_re + oxy;
+    const double *pD = (BUF || !VC) ? nullptr : a.D + oxy;
+    const double *pE = (BUF || !(EMB && !IN_REAL)) ? nullptr : a.emb_in + oxy;
     auto LW = [&](int gz) {
-        return IN_REAL ? make_double2(pWr[zoff(gz)], 0.0) : pWc[zoff(gz)];
+        if constexpr (!BUF) return IN_REAL ? make_double2(pWr[zoff(gz)], 0.0) : pWc[zoff(gz)];
+        if (IN_REAL) {
+            const double v = buf_load_f64(a.in_re + zoff(gz), pb8, o8);
+            return make_double2(v, 0.0);
+        }
+        return buf_load_c(a.in_c + zoff(gz), pb16, o16);
     };
-    auto LD = [&](int gz) { return VC ? 0.5 * pD[zoff(gz)] : 0.0; };   // D/2 (face rule)
-    auto LE = [&](int gz) { return (EMB && !IN_REAL) ? pE[zoff(gz)] : 0.0; };
+    // D as loaded: with the face ring it is halved (the face rule takes D/2)
+    // when its plane enters use, so the multiply never waits on a load still
+    // in flight; with the per-level reads (HL) as it is loaded
+    constexpr bool HL = !FACES;
+    auto LD = [&](int gz) {
+        if constexpr (!VC) return 0.0;
+        const double d = BUF ? buf_load_f64(a.D + zoff(gz), pb8, o8) : pD[zoff(gz)];
+        return HL ? 0.5 * d : d;
+    };
+    auto LE = [&](int gz) {
+        if constexpr (!(EMB && !IN_REAL)) return 0.0;
+        return BUF ? buf_load_f64(a.emb_in + zoff(gz), pb8, o8) : pE[zoff(gz)];
+    };
     auto pout = [&](int p) { return dir && (p < 0 || p >= a.nz); };
-    auto dslot = [](int p) { return ((p % ND) + ND) % ND; };
 
     // Level 0 ring: plane p in slot (p - t_begin) % NR with its D; at step t
     // planes t-2 .. t are in use and the next PF planes in flight. Windows of levels
     // 1..K-1: planes (q-1, q, q+1) around the plane the next level computes.
-    constexpr int PF = EMB ? 1 : 2;                 // EMB: registers for the What rings
+    // Planes loaded ahead: one for the diffusion operator, whose face ring
+    // takes the registers (two measured no faster where they fit), and with
+    // the embedded solution (its rings)
+    constexpr int PF = (EMB || (VC && FACES)) ? 1 : 2;
     constexpr int NR = PF + 3;
+    static_assert(K < NR, "the face rings hold K + 1 planes");
     // Steps z0-K .. z0-1 only fill the levels below the chunk. At a Dirichlet
     // lower end those planes are ghosts, 0 at every level, which the rings
     // and LDS hold from the start: the march begins at plane 0, with the
-    // ghost plane's D put in place (below).
+    // ghost plane's D in place (below).
     const bool lead_ghost = dir && z0 == 0;
     const int t_begin = lead_ghost ? 0 : z0 - K, t_end = z1 + K;   // level 0 planes
     double2 L0[NR];
@@ -176,11 +214,30 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
     // t-m; the window of level m+1 at step t is the slots of steps t-2..t.
     // The step loop is unrolled by NR, so every index is static.
     double2 WR[K - 1][NR];
+    // FR: the faces, the operand of every face term, formed once per plane
+    // instead of once per level. At step t the lane forms the four x/y faces
+    // of plane t-1 from the neighbours' D/2 in LDS, and the z face between
+    // planes t-1 and t, into the slot of step t; level m (plane t-m) then
+    // finds its x/y faces in the slot of step t-m+1, its z- face in the slot
+    // of step t-m and its z+ face in the slot of step t-m+1. The sums are the
+    // ones the per-level form computes, so every result keeps its bits.
+    double FX[FR ? NR : 1][4];
+    double FZ[FR ? NR : 1];
+    double dhp = 0.0;                               // D/2 of plane t-1
+    // DR: D/2 of planes t-2 .. t in registers (the D ring, halved as loaded),
+    // older planes in the LDS ring
+    static_assert(!DR || HL, "the per-level reads take D/2 from the load ring");
+    double (&DH)[NR] = D0;
+    auto dslot = [](int p) { return ((p % ND) + ND) % ND; };
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
         L0[q] = make_double2(0.0, 0.0);
         D0[q] = 0.0;
         if (ER) E0[q] = 0.0;
+        if constexpr (FR) {
+            FX[q][0] = FX[q][1] = FX[q][2] = FX[q][3] = 0.0;
+            FZ[q] = 0.0;
+        }
     }
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
@@ -200,11 +257,16 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
     if (dir) {
         for (int i = tid; i < 2 * K * PL; i += 1024) sLp[i] = make_double2(0.0, 0.0);
         if (VC && lead_ghost) {
-            // planes -1 and -2 in the register ring, plane -1 in the LDS ring,
-            // as the skipped steps would have left them (clamped loads)
-            D0[NR - 1] = LD(-1);
-            D0[NR - 2] = LD(-2);
-            sD[dslot(-1)][slot] = D0[NR - 1];
+            // the ghost planes (clamped loads: plane 0's D) as the steps
+            // before plane 0 leave them, in registers and in LDS
+            if constexpr (FR) {
+                dhp = 0.5 * LD(-1);
+                sD[1][slot] = dhp;
+            } else {
+                DH[NR - 1] = LD(-1);
+                DH[NR - 2] = LD(-2);
+                sD[dslot(-1)][slot] = DH[NR - 1];
+            }
         }
         __syncthreads();
     }
@@ -230,16 +292,24 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
             D0[rs(PF)] = LD(tn);
             if (ER) E0[rs(PF)] = LE(tn);
         }
+        // D/2 of plane t, loaded PF steps ago
+        const double dht = VC ? (HL ? D0[rs(0)] : 0.5 * D0[rs(0)]) : 0.0;
         zero_if(pout(t), L0[rs(0)]);
         const int rb = (t - 1) & 1, wb = t & 1;     // LDS buffers read / written at step t
-        // LDS operands of level m: x/y neighbours of level m-1 and their D,
-        // and the cell's own D where the register ring no longer holds it.
-        // Every lane reads them (all slots are in range). With RA, level
-        // m+1's operands are read before level m is computed, so their
+        if constexpr (FR) {
+            const double *Dp = sD[rb];              // D/2 of plane t-1
+            FX[rs(0)][0] = dhp + Dp[slot - 1];
+            FX[rs(0)][1] = dhp + Dp[slot + 1];
+            FX[rs(0)][2] = dhp + Dp[slot - SX];
+            FX[rs(0)][3] = dhp + Dp[slot + SX];
+            FZ[rs(0)] = dhp + dht;
+        }
+        // x/y neighbours of level m-1 at plane t-m, written at step t-1.
+        // With RA, level m+1's are read before level m is computed, so their
         // latency overlaps the work.
         struct Nb {
             double2 w[4];
-            double d[4], dc, dzm, dzp;
+            double d[4], dc, dzm, dzp;              // DR: D/2 of neighbours and cell
         };
         auto readw = [&](int m, Nb &n) {
             const double2 *L = sL[rb][m - 1];
@@ -247,44 +317,38 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
             n.w[1] = L[slot + 1];
             n.w[2] = L[slot - SX];
             n.w[3] = L[slot + SX];
-        };
-        auto readd = [&](int m, Nb &n) {
-            const int p = t - m;
-            n.dc = n.dzm = n.dzp = 0.0;
-            n.d[0] = n.d[1] = n.d[2] = n.d[3] = 0.0;
-            if (VC) {
+            if constexpr (DR) {
+                // plane p = t-m: the x/y neighbours from its LDS plane; the
+                // cell and its z neighbours from the registers while they hold
+                // them (planes t-2 .. t), else from LDS
+                const int p = t - m;
                 const double *Dp = sD[dslot(p)];
                 n.d[0] = Dp[slot - 1];
                 n.d[1] = Dp[slot + 1];
                 n.d[2] = Dp[slot - SX];
                 n.d[3] = Dp[slot + SX];
                 if (m == 1) {
-                    n.dzm = D0[rs(-2)];
-                    n.dc = D0[rs(-1)];
-                    n.dzp = D0[rs(0)];
+                    n.dzm = DH[rs(-2)];
+                    n.dc = DH[rs(-1)];
+                    n.dzp = DH[rs(0)];
                 } else {
-                    n.dc = (m == 2) ? D0[rs(-2)] : Dp[slot];
+                    n.dc = (m == 2) ? DH[rs(-2)] : Dp[slot];
                     n.dzm = sD[dslot(p - 1)][slot];
-                    n.dzp = (m == 2) ? D0[rs(-1)] : (m == 3 ? D0[rs(-2)] : sD[dslot(p + 1)][slot]);
+                    n.dzp = (m == 2) ? DH[rs(-1)] : DH[rs(-2)];
                 }
             }
         };
-        // (For K = 3, or with the embedded solution, the operands of two levels
-        // do not fit the registers of four wavefronts per SIMD: there each
-        // level reads its own; reading only the next level's W neighbours
-        // ahead, or writing each level's plane as soon as it is computed,
-        // measured no faster.)
+        // (With the embedded solution the operands of two levels do not fit
+        // the registers of four wavefronts per SIMD: there each level reads
+        // its own.)
         constexpr bool RA = (K <= 2) && !EMB;
+        static_assert(K <= 3, "the register D/2 ring covers three levels");
         Nb cur;
         readw(1, cur);
-        readd(1, cur);
 #pragma unroll
         for (int m = 1; m <= K; ++m) {
             Nb nxt = cur;
-            if (RA && m < K) {
-                readw(m + 1, nxt);
-                readd(m + 1, nxt);
-            }
+            if (RA && m < K) readw(m + 1, nxt);
             const int p = t - m;
             if (m > wneed) {
                 // keep the slot written every step (the value is never read)
@@ -305,17 +369,27 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
                 if (OP == POR) {
                     csqh(c, qr_c, qi_c);
                 }
+                double acc_r = 0.0, acc_i = 0.0;
                 // A Dirichlet ghost holds W = 0 and the D of the boundary cell
                 // it faces (loads are clamped), so every face takes the plain
                 // mean, which there equals D_c bit for bit.
-                const double dc = cur.dc;
-                double acc_r = 0.0, acc_i = 0.0;
-                face<OP>(acc_r, acc_i, c, cur.w[0], dc, cur.d[0], false, qr_c, qi_c, a.fc[0]);
-                face<OP>(acc_r, acc_i, c, cur.w[1], dc, cur.d[1], false, qr_c, qi_c, a.fc[1]);
-                face<OP>(acc_r, acc_i, c, cur.w[2], dc, cur.d[2], false, qr_c, qi_c, a.fc[2]);
-                face<OP>(acc_r, acc_i, c, cur.w[3], dc, cur.d[3], false, qr_c, qi_c, a.fc[3]);
-                face<OP>(acc_r, acc_i, c, zm, dc, cur.dzm, false, qr_c, qi_c, a.fc[4]);
-                face<OP>(acc_r, acc_i, c, zp, dc, cur.dzp, false, qr_c, qi_c, a.fc[5]);
+                if constexpr (FR) {
+                    const double *fx = FX[rs(1 - m)];
+                    face<LAP>(acc_r, acc_i, c, cur.w[0], 0.0, 0.0, false, 0.0, 0.0, fx[0]);
+                    face<LAP>(acc_r, acc_i, c, cur.w[1], 0.0, 0.0, false, 0.0, 0.0, fx[1]);
+                    face<LAP>(acc_r, acc_i, c, cur.w[2], 0.0, 0.0, false, 0.0, 0.0, fx[2]);
+                    face<LAP>(acc_r, acc_i, c, cur.w[3], 0.0, 0.0, false, 0.0, 0.0, fx[3]);
+                    face<LAP>(acc_r, acc_i, c, zm, 0.0, 0.0, false, 0.0, 0.0, FZ[rs(-m)]);
+                    face<LAP>(acc_r, acc_i, c, zp, 0.0, 0.0, false, 0.0, 0.0, FZ[rs(1 - m)]);
+                } else {
+                    const double dc = cur.dc;
+                    face<OP>(acc_r, acc_i, c, cur.w[0], dc, cur.d[0], false, qr_c, qi_c, a.fc[0]);
+                    face<OP>(acc_r, acc_i, c, cur.w[1], dc, cur.d[1], false, qr_c, qi_c, a.fc[1]);
+                    face<OP>(acc_r, acc_i, c, cur.w[2], dc, cur.d[2], false, qr_c, qi_c, a.fc[2]);
+                    face<OP>(acc_r, acc_i, c, cur.w[3], dc, cur.d[3], false, qr_c, qi_c, a.fc[3]);
+                    face<OP>(acc_r, acc_i, c, zm, dc, cur.dzm, false, qr_c, qi_c, a.fc[4]);
+                    face<OP>(acc_r, acc_i, c, zp, dc, cur.dzp, false, qr_c, qi_c, a.fc[5]);
+                }
                 double2 v = euler(c, acc_r, acc_i, a.inv_h2, a.tr[m - 1], a.ti[m - 1]);
                 zero_if(pout(p), v);
                 double eh = 0.0;
@@ -328,20 +402,26 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
                 if (m < K) {
                     WR[m - 1][rs(0)] = v;
                     if (EMB) ehn[m - 1] = eh;
-                    if (ST && out_col && p >= z0 && p < z1)
-                        a.lvl_out[(m - 1) * a.lvl_stride + ixy + pst * p] = v;
+                    if (ST && out_col && p >= z0 && p < z1) {
+                        double2 *lv = a.lvl_out + (m - 1) * a.lvl_stride + pst * p;
+                        if constexpr (BUF) buf_store_c(lv, pb16, o16, v);
+                        else lv[oxy] = v;
+                    }
                 } else if (out_col && p >= z0 && p < z1) {
-                    // an output column is inside the grid: ixy is its own offset
-                    const long long i = ixy + pst * p;
-                    if (OUT_REAL) a.out_re[i] = v.x;
-                    else a.out_c[i] = v;
-                    if (EMB) a.emb_out[i] = eh;
+                    // an output column is inside the grid: oxy is its own offset
+                    if constexpr (BUF) {
+                        if (OUT_REAL) buf_store_f64(a.out_re + pst * p, pb8, o8, v.x);
+                        else buf_store_c(a.out_c + pst * p, pb16, o16, v);
+                        if (EMB) buf_store_f64(a.emb_out + pst * p, pb8, o8, eh);
+                    } else {
+                        const long long i = oxy + pst * p;
+                        if (OUT_REAL) a.out_re[i] = v.x;
+                        else a.out_c[i] = v;
+                        if (EMB) a.emb_out[i] = eh;
+                    }
                 }
             }
-            if (!RA && m < K) {
-                readw(m + 1, nxt);
-                readd(m + 1, nxt);
-            }
+            if (!RA && m < K) readw(m + 1, nxt);
             cur = nxt;
         }
         // All LDS writes of the step come after all its reads, so the reads
@@ -357,7 +437,11 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
 #pragma unroll
             for (int m = 0; m + 1 < K; ++m) ehc[m] = ehn[m];
         }
-        if (VC) sD[dslot(t)][slot] = D0[rs(0)];
+        if constexpr (FR) {
+            sD[wb][slot] = dht;
+            dhp = dht;
+        }
+        if constexpr (DR) sD[dslot(t)][slot] = dht;
         __syncthreads();   // step t's planes are visible to step t+1, whose
                            // writes go to the other buffer
     }

@@ -166,6 +166,7 @@ int launch_tblock(const KGrid &g, const PassArgs &p, int shape, hipStream_t st)
 {
     if (!tblock_supported(g, p.k)) return (int)hipErrorInvalidValue;
     if (g.op == FRKC2_OP_BRUSS2) return launch_bruss_tb(g, p, st);
+    if (g.ndim == 3 && (shape == 3 || shape == 4) && !tb3d_plane_ok(g)) shape = 0;
     if (g.ndim == 3 && (shape == 3 || shape == 4)) {
         PassArgs q = p;
         q.cols = (shape == 4) ? 32 : 64;
