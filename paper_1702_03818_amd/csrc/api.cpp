@@ -344,6 +344,9 @@ int run_superstep(const KGrid &kg, const PassCfg &cfg, double *w, const double *
             pa.tr[i] = Tn * are[l + i];
             pa.ti[i] = Tn * aim[l + i];
         }
+        // consecutive fused passes march in opposite directions, so that each
+        // starts on the planes the one before touched last (still cached)
+        pa.rev = pass & 1;
         const int rc = (kk == 1) ? launch_pass(kg, pa, 1, st) : launch_tblock(kg, pa, cfg.tile, st);
         if (rc != 0) return rc;
         in = out;

@@ -63,6 +63,8 @@ struct PassArgs {
     double *lvl_out;            // 3D fused passes: levels 1..k-1 also written to
     long long lvl_stride;       // lvl_out + (m-1)*lvl_stride complex values (non-null selects it)
     int cols;                   // 3D fused passes: output columns per tile, 64 (0) or 32
+    int rev;                    // 3D full-width fused passes: march each chunk downwards
+                                // (same bits; alternate passes reuse the cached planes)
 };
 
 // Launchers (stage.hip). Return hipError_t as int.

@@ -87,13 +87,18 @@ __global__ __launch_bounds__(kThreads) void rho_pass1(const double *w, const dou
                                                       int ny, int nz, double d_const,
                                                       double *partials)
 {
-    const long long n = (long long)nx * ny * nz;
+    // Work items of kThreads consecutive points of one x row, so that the
+    // row and its y, z follow from one (uniform) division per item
+    const int cpr = (nx + kThreads - 1) / kThreads;
+    const long long items = (long long)cpr * ny * nz;
     double m = 0.0;
-    for (long long p = blockIdx.x * (long long)kThreads + threadIdx.x; p < n;
-         p += (long long)gridDim.x * kThreads) {
-        const int x = (int)(p % nx);
-        const int y = (int)((p / nx) % ny);
-        const int z = (int)(p / ((long long)nx * ny));
+    for (long long it = blockIdx.x; it < items; it += gridDim.x) {
+        const long long r = it / cpr;
+        const int x = (int)(it - r * cpr) * kThreads + (int)threadIdx.x;
+        if (x >= nx) continue;
+        const int y = (int)(r % ny);
+        const int z = (int)(r / ny);
+        const long long p = x + (long long)nx * r;
         double sum = 0.0, diag = 0.0;
 #pragma unroll
         for (int f = 0; f < 6; ++f) {

@@ -41,7 +41,7 @@ using namespace dev;
 // tb3d_stage: one workgroup per tile, the block index remapped so that each
 // XCD receives a contiguous range of tiles.
 template <int OP, int BC, int K, bool IN_REAL, bool OUT_REAL, bool EMB = false, bool ST = false,
-          int W = 64>
+          int W = 64, bool REV = false>
 __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
 {
     __shared__ double2 sL[Tb3Lds<OP, K, W, EMB>::L];
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(1024) void tb3d_stage(Tb3Args a)
     lb /= a.ntx;
     const int by = lb % a.nty;
     const int bz = lb / a.nty;
-    tb3d_tile<OP, BC, K, IN_REAL, OUT_REAL, EMB, ST, W>(a, bx, by, bz, sL, sD);
+    tb3d_tile<OP, BC, K, IN_REAL, OUT_REAL, EMB, ST, W, !EMB, true, REV>(a, bx, by, bz, sL, sD);
 }
 
 // Chunk length: one workgroup fills a CU (its LDS), so the launch runs in
@@ -96,7 +96,7 @@ int choose_zchunk3(long long tiles, int nz, int K)
 }
 
 template <int OP, int BC, int K, int W>
-int launch3_k(const Tb3Args &a0, bool ir, bool orl, hipStream_t st)
+int launch3_k(const Tb3Args &a0, bool ir, bool orl, bool rev, hipStream_t st)
 {
     Tb3Args a = a0;
     a.ntx = (a.nx + W - 1) / W;
@@ -122,6 +122,17 @@ int launch3_k(const Tb3Args &a0, bool ir, bool orl, hipStream_t st)
             hipLaunchKernelGGL((tb3d_stage<OP, BC, K, false, false, true, false, W>), grid, block, 0, st, a);
         return (int)hipGetLastError();
     }
+    if (rev) {
+        if (ir && orl)
+            hipLaunchKernelGGL((tb3d_stage<OP, BC, K, true, true, false, false, W, true>), grid, block, 0, st, a);
+        else if (ir)
+            hipLaunchKernelGGL((tb3d_stage<OP, BC, K, true, false, false, false, W, true>), grid, block, 0, st, a);
+        else if (orl)
+            hipLaunchKernelGGL((tb3d_stage<OP, BC, K, false, true, false, false, W, true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((tb3d_stage<OP, BC, K, false, false, false, false, W, true>), grid, block, 0, st, a);
+        return (int)hipGetLastError();
+    }
     if (ir && orl)
         hipLaunchKernelGGL((tb3d_stage<OP, BC, K, true, true, false, false, W>), grid, block, 0, st, a);
     else if (ir)
@@ -134,24 +145,24 @@ int launch3_k(const Tb3Args &a0, bool ir, bool orl, hipStream_t st)
 }
 
 template <int OP, int BC>
-int launch3_kk(int k, int cols, const Tb3Args &a, bool ir, bool orl, hipStream_t st)
+int launch3_kk(int k, int cols, const Tb3Args &a, bool ir, bool orl, bool rev, hipStream_t st)
 {
     if (cols == 32) {
-        if (k == 2) return launch3_k<OP, BC, 2, 32>(a, ir, orl, st);
-        if (k == 3) return launch3_k<OP, BC, 3, 32>(a, ir, orl, st);
+        if (k == 2) return launch3_k<OP, BC, 2, 32>(a, ir, orl, rev, st);
+        if (k == 3) return launch3_k<OP, BC, 3, 32>(a, ir, orl, rev, st);
         return (int)hipErrorInvalidValue;
     }
-    if (k == 2) return launch3_k<OP, BC, 2, 64>(a, ir, orl, st);
-    if (k == 3) return launch3_k<OP, BC, 3, 64>(a, ir, orl, st);
+    if (k == 2) return launch3_k<OP, BC, 2, 64>(a, ir, orl, rev, st);
+    if (k == 3) return launch3_k<OP, BC, 3, 64>(a, ir, orl, rev, st);
     return (int)hipErrorInvalidValue;
 }
 
 template <int OP>
-int launch3_bc(const KGrid &g, int k, int cols, const Tb3Args &a, bool ir, bool orl,
+int launch3_bc(const KGrid &g, int k, int cols, const Tb3Args &a, bool ir, bool orl, bool rev,
                hipStream_t st)
 {
-    if (g.bc == PER) return launch3_kk<OP, PER>(k, cols, a, ir, orl, st);
-    return launch3_kk<OP, DIR>(k, cols, a, ir, orl, st);
+    if (g.bc == PER) return launch3_kk<OP, PER>(k, cols, a, ir, orl, rev, st);
+    return launch3_kk<OP, DIR>(k, cols, a, ir, orl, rev, st);
 }
 
 // Predicted time of a pass in units of one time step of the 64-column tile:
@@ -196,11 +207,12 @@ int launch_tb3d(const KGrid &g, const PassArgs &p, hipStream_t st)
     }
     for (int k = 0; k < 6; ++k) a.fc[k] = g.fc[k];
     const bool ir = p.in_re != nullptr, orl = p.out_re != nullptr;
+    const bool rev = p.rev != 0;
     const int cols = (p.cols == 32) ? 32 : 64;
-    if (g.op == LAP) return launch3_bc<LAP>(g, p.k, cols, a, ir, orl, st);
-    if (g.op == ADV) return launch3_bc<ADV>(g, p.k, cols, a, ir, orl, st);
-    if (g.op == VAR) return launch3_bc<VAR>(g, p.k, cols, a, ir, orl, st);
-    return launch3_bc<POR>(g, p.k, cols, a, ir, orl, st);
+    if (g.op == LAP) return launch3_bc<LAP>(g, p.k, cols, a, ir, orl, rev, st);
+    if (g.op == ADV) return launch3_bc<ADV>(g, p.k, cols, a, ir, orl, rev, st);
+    if (g.op == VAR) return launch3_bc<VAR>(g, p.k, cols, a, ir, orl, rev, st);
+    return launch3_bc<POR>(g, p.k, cols, a, ir, orl, rev, st);
 }
 
 int tb3d_pick_cols(const KGrid &g, int k)

@@ -90,8 +90,13 @@ struct Tb3Lds {
 // which hold the code of two operators), with the D ring of Tb3Lds<..., true>.
 // BUF: global accesses through buffer resources (below); off in the batch's
 // kernels, which address through 64-bit lane pointers.
+// REV: march the chunk from its top plane down (with the face ring only).
+// Every point takes the same operands in the same order, so the results are
+// the same bits; consecutive passes that alternate the direction start on
+// the planes the previous pass touched last, which the last-level cache
+// (256 MB) still holds.
 template <int OP, int BC, int K, bool IN_REAL, bool OUT_REAL, bool EMB = false, bool ST = false,
-          int W = 64, bool FACES = !EMB, bool BUF = true>
+          int W = 64, bool FACES = !EMB, bool BUF = true, bool REV = false>
 __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int bz, double2 *sLp,
                                           double *sDp)
 {
@@ -103,6 +108,7 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
     // Diffusivity faces D_f = D_c/2 + D_nb/2: from a register ring (FR), or
     // per level from D/2 planes in LDS (DR)
     constexpr bool FR = VC && FACES, DR = VC && !FACES;
+    static_assert(!REV || (FACES && !EMB && !ST), "the reversed march: face ring, plain passes");
     constexpr int ND = DR ? K + 2 : 2;              // D/2 planes in LDS
     // level m plane by step parity; D/2 planes
     double2 (*sL)[K][PL] = reinterpret_cast<double2 (*)[K][PL]>(sLp);
@@ -160,7 +166,12 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
     const unsigned o8 = 8u * oxy, o16 = 16u * oxy;
     const long long pst = (long long)a.nx * a.ny;
     const int pb8 = (int)(8 * pst), pb16 = (int)(16 * pst);   // plane extents in bytes
-    auto zoff = [&](int gz) {
+    // The march runs over q = z0-K .. z1+K-1 (planes below, in and above the
+    // chunk); plane(q) is the plane it stands for: q itself, or its mirror in
+    // the chunk with REV.
+    auto plane = [&](int q) { return REV ? z0 + z1 - 1 - q : q; };
+    auto zoff = [&](int q) {
+        const int gz = plane(q);
         return pst * ((BC == PER) ? wrap(gz, a.nz) : min(max(gz, 0), a.nz - 1));
     };
     const double2 *pWc = (BUF || IN_REAL) ? nullptr : a.in_c + oxy;
@@ -188,7 +199,10 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
         if constexpr (!(EMB && !IN_REAL)) return 0.0;
         return BUF ? buf_load_f64(a.emb_in + zoff(gz), pb8, o8) : pE[zoff(gz)];
     };
-    auto pout = [&](int p) { return dir && (p < 0 || p >= a.nz); };
+    auto pout = [&](int q) {
+        const int p = plane(q);
+        return dir && (p < 0 || p >= a.nz);
+    };
 
     // Level 0 ring: plane p in slot (p - t_begin) % NR with its D; at step t
     // planes t-2 .. t are in use and the next PF planes in flight. Windows of levels
@@ -203,8 +217,8 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
     // lower end those planes are ghosts, 0 at every level, which the rings
     // and LDS hold from the start: the march begins at plane 0, with the
     // ghost plane's D in place (below).
-    const bool lead_ghost = dir && z0 == 0;
-    const int t_begin = lead_ghost ? 0 : z0 - K, t_end = z1 + K;   // level 0 planes
+    const bool lead_ghost = dir && (REV ? z1 == a.nz : z0 == 0);
+    const int t_begin = lead_ghost ? z0 : z0 - K, t_end = z1 + K;   // level 0 planes
     double2 L0[NR];
     double D0[NR];
     constexpr bool ER = EMB && !IN_REAL;            // embedded input read from memory
@@ -260,8 +274,8 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
             // the ghost planes (clamped loads: plane 0's D) as the steps
             // before plane 0 leave them, in registers and in LDS
             if constexpr (FR) {
-                dhp = 0.5 * LD(-1);
-                sD[1][slot] = dhp;
+                dhp = 0.5 * LD(t_begin - 1);
+                sD[(t_begin - 1) & 1][slot] = dhp;
             } else {
                 DH[NR - 1] = LD(-1);
                 DH[NR - 2] = LD(-2);
@@ -379,16 +393,28 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
                     face<LAP>(acc_r, acc_i, c, cur.w[1], 0.0, 0.0, false, 0.0, 0.0, fx[1]);
                     face<LAP>(acc_r, acc_i, c, cur.w[2], 0.0, 0.0, false, 0.0, 0.0, fx[2]);
                     face<LAP>(acc_r, acc_i, c, cur.w[3], 0.0, 0.0, false, 0.0, 0.0, fx[3]);
-                    face<LAP>(acc_r, acc_i, c, zm, 0.0, 0.0, false, 0.0, 0.0, FZ[rs(-m)]);
-                    face<LAP>(acc_r, acc_i, c, zp, 0.0, 0.0, false, 0.0, 0.0, FZ[rs(1 - m)]);
+                    // the face toward the lower plane first
+                    if (REV) {
+                        face<LAP>(acc_r, acc_i, c, zp, 0.0, 0.0, false, 0.0, 0.0, FZ[rs(1 - m)]);
+                        face<LAP>(acc_r, acc_i, c, zm, 0.0, 0.0, false, 0.0, 0.0, FZ[rs(-m)]);
+                    } else {
+                        face<LAP>(acc_r, acc_i, c, zm, 0.0, 0.0, false, 0.0, 0.0, FZ[rs(-m)]);
+                        face<LAP>(acc_r, acc_i, c, zp, 0.0, 0.0, false, 0.0, 0.0, FZ[rs(1 - m)]);
+                    }
                 } else {
                     const double dc = cur.dc;
                     face<OP>(acc_r, acc_i, c, cur.w[0], dc, cur.d[0], false, qr_c, qi_c, a.fc[0]);
                     face<OP>(acc_r, acc_i, c, cur.w[1], dc, cur.d[1], false, qr_c, qi_c, a.fc[1]);
                     face<OP>(acc_r, acc_i, c, cur.w[2], dc, cur.d[2], false, qr_c, qi_c, a.fc[2]);
                     face<OP>(acc_r, acc_i, c, cur.w[3], dc, cur.d[3], false, qr_c, qi_c, a.fc[3]);
-                    face<OP>(acc_r, acc_i, c, zm, dc, cur.dzm, false, qr_c, qi_c, a.fc[4]);
-                    face<OP>(acc_r, acc_i, c, zp, dc, cur.dzp, false, qr_c, qi_c, a.fc[5]);
+                    // the face toward the lower plane first, with its coefficient
+                    if (REV) {
+                        face<OP>(acc_r, acc_i, c, zp, dc, cur.dzp, false, qr_c, qi_c, a.fc[4]);
+                        face<OP>(acc_r, acc_i, c, zm, dc, cur.dzm, false, qr_c, qi_c, a.fc[5]);
+                    } else {
+                        face<OP>(acc_r, acc_i, c, zm, dc, cur.dzm, false, qr_c, qi_c, a.fc[4]);
+                        face<OP>(acc_r, acc_i, c, zp, dc, cur.dzp, false, qr_c, qi_c, a.fc[5]);
+                    }
                 }
                 double2 v = euler(c, acc_r, acc_i, a.inv_h2, a.tr[m - 1], a.ti[m - 1]);
                 zero_if(pout(p), v);
@@ -403,18 +429,19 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
                     WR[m - 1][rs(0)] = v;
                     if (EMB) ehn[m - 1] = eh;
                     if (ST && out_col && p >= z0 && p < z1) {
-                        double2 *lv = a.lvl_out + (m - 1) * a.lvl_stride + pst * p;
+                        double2 *lv = a.lvl_out + (m - 1) * a.lvl_stride + pst * plane(p);
                         if constexpr (BUF) buf_store_c(lv, pb16, o16, v);
                         else lv[oxy] = v;
                     }
                 } else if (out_col && p >= z0 && p < z1) {
                     // an output column is inside the grid: oxy is its own offset
+                    const long long po = pst * plane(p);
                     if constexpr (BUF) {
-                        if (OUT_REAL) buf_store_f64(a.out_re + pst * p, pb8, o8, v.x);
-                        else buf_store_c(a.out_c + pst * p, pb16, o16, v);
-                        if (EMB) buf_store_f64(a.emb_out + pst * p, pb8, o8, eh);
+                        if (OUT_REAL) buf_store_f64(a.out_re + po, pb8, o8, v.x);
+                        else buf_store_c(a.out_c + po, pb16, o16, v);
+                        if (EMB) buf_store_f64(a.emb_out + po, pb8, o8, eh);
                     } else {
-                        const long long i = oxy + pst * p;
+                        const long long i = oxy + po;
                         if (OUT_REAL) a.out_re[i] = v.x;
                         else a.out_c[i] = v;
                         if (EMB) a.emb_out[i] = eh;
@@ -425,13 +452,16 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
             cur = nxt;
         }
         // All LDS writes of the step come after all its reads, so the reads
-        // of every level can be issued early. A lane that does not need
-        // level m stores a value no needed cell reads; a ghost column stores
-        // nothing, so its cells keep the ghost value 0.
+        // of every level can be issued early. A wavefront stores the levels
+        // it computed (a lane of it that does not need level m stores a value
+        // no needed cell reads; the levels it skips no needed cell reads
+        // either); a ghost column stores nothing, so its cells keep the ghost
+        // value 0.
         if (!col_ghost) {
             sL[wb][0][slot] = L0[rs(0)];
 #pragma unroll
-            for (int m = 1; m < K; ++m) sL[wb][m][slot] = WR[m - 1][rs(0)];
+            for (int m = 1; m < K; ++m)
+                if (m <= wneed) sL[wb][m][slot] = WR[m - 1][rs(0)];
         }
         if (EMB) {
 #pragma unroll
