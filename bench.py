@@ -73,7 +73,8 @@ def kernel_pattern(k, tile):
     if k == 1:
         return "plane_stage<1, 1, 3, 64, 4, false, false>"
     if tile in (4, 5):
-        return "tb3d_stage<1, 1, %d, false, false, false, false, %d>" % (k, 64 if tile == 4 else 32)
+        # both march directions (the last template argument)
+        return "tb3d_stage<1, 1, %d, false, false, false, false, %d, " % (k, 64 if tile == 4 else 32)
     shape = {1: "64, 16, 1", 2: "64, 16, 2", 3: "64, 8, %d" % (4 if k == 2 else 3)}[tile]
     return "tb_stage<1, 1, 3, %s, %d, false, false>" % (shape, k)
 
@@ -109,6 +110,9 @@ def summarize_trace(directory, command, k, tile, out_md, pattern=None, title=Non
     total = sum(sum(v) for v in groups.values())
     pat = pattern or kernel_pattern(k, tile)
     dom = max((key for key in groups if pat in key[0]), key=lambda kk: len(groups[kk]))
+    # every kernel the pattern names at that grid size (e.g. both march directions)
+    dom_d = [d for key in groups if pat in key[0] and key[1] == dom[1] for d in groups[key]]
+    dom_names = sorted({_short(key[0]) for key in groups if pat in key[0] and key[1] == dom[1]})
     what = ("Dominant kernel (interior pass, k = %d, tile %d)" % (k, tile)) if pattern is None \
         else "Kernel"
     lines = ["# Kernel trace: %s" % (title or "3D variable-D 256^3, s = 100 (bench step)"), "",
@@ -116,9 +120,9 @@ def summarize_trace(directory, command, k, tile, out_md, pattern=None, title=Non
              "    " + command, ""] + ([note, ""] if note else []) + [
              "Durations per (kernel, grid size in threads) from rocprofv3 `kernel_trace.csv`, "
              "microseconds%s." % (", over all grid sizes of a kernel" if by_kernel else ""), "",
-             "%s: `%s` at grid %s: %d launches, average %.2f us." % (
-                 what, _short(dom[0]), dom[1], len(groups[dom]),
-                 sum(groups[dom]) / len(groups[dom])), "",
+             "%s: %s at grid %s: %d launches, average %.2f us." % (
+                 what, " and ".join("`%s`" % n for n in dom_names), dom[1], len(dom_d),
+                 sum(dom_d) / len(dom_d)), "",
              "| Kernel | grid | calls | total ms | average us | min us | max us | % |",
              "|---|---|---|---|---|---|---|---|"]
     for key, v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:25]:
@@ -127,7 +131,7 @@ def summarize_trace(directory, command, k, tile, out_md, pattern=None, title=Non
             100 * sum(v) / total))
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
-    return sum(groups[dom]) / len(groups[dom])
+    return sum(dom_d) / len(dom_d)
 
 
 def summarize_counters(fetch_dir, write_dir, fetch_cmd, write_cmd, k, tile, zchunk, out_md):
@@ -150,11 +154,14 @@ def summarize_counters(fetch_dir, write_dir, fetch_cmd, write_cmd, k, tile, zchu
     fg, fs = per["FETCH_SIZE"]
     wg, ws = per["WRITE_SIZE"]
     dom = max((key for key in fg if pat in key[0]), key=lambda kk: len(fg[kk]))
-    fetch = 1024.0 * fs * sum(fg[dom]) / len(fg[dom])
-    write = 1024.0 * ws * sum(wg[dom]) / len(wg[dom])
+    keys = [key for key in fg if pat in key[0] and key[1] == dom[1]]
+    fv_all = [v for key in keys for v in fg[key]]
+    wv_all = [v for key in keys for v in wg.get(key, [])]
+    fetch = 1024.0 * fs * sum(fv_all) / len(fv_all)
+    write = 1024.0 * ws * sum(wv_all) / len(wv_all)
     n = 256 ** 3
     alg = 40 * n
-    t = {"kernel": _short(dom[0]), "grid": dom[1],
+    t = {"kernel": " and ".join(sorted(_short(key[0]) for key in keys)), "grid": dom[1],
          "workload": "3D var-D 256^3, s = 100, k = %d (interior passes)" % k,
          "config": {"tblock": k, "tile": tile, "zchunk": zchunk},
          "sources_sha256": kernel_sources_sha256(k, tile),
@@ -179,10 +186,11 @@ def summarize_counters(fetch_dir, write_dir, fetch_cmd, write_cmd, k, tile, zchu
         lines.append("| `%s` | %d | %d | %.1f | %.1f | %.1f | %.1f |" % (
             _short(key[0]), key[1], len(fg[key]), fv, wv, fv * 1024 * fs / 1e6,
             wv * 1024 * ws / 1e6))
-    lines += ["", "Dominant kernel `%s` (grid %d): %.1f MB read and %.1f MB written per launch; "
+    lines += ["", "Dominant kernel %s (grid %d): %.1f MB read and %.1f MB written per launch; "
               "algorithmic %.1f MB read (16 B complex W + 8 B D per point) and %.1f MB written "
               "(16 B per point), so %.3f x the algorithmic bytes." % (
-                  _short(dom[0]), dom[1], fetch / 1e6, write / 1e6, 24 * n / 1e6, 16 * n / 1e6,
+                  " and ".join("`%s`" % _short(key[0]) for key in sorted(keys)), dom[1],
+                  fetch / 1e6, write / 1e6, 24 * n / 1e6, 16 * n / 1e6,
                   (fetch + write) / alg)]
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -212,8 +220,11 @@ def summarize_sq(dirs, pattern, commands, title, out_md):
         if not per:
             raise SystemExit("no dispatch of %s under %s" % (pattern, d))
         key = max(per, key=lambda k: len(next(iter(per[k].values()))))
-        name, grid = key
-        for c, v in per[key].items():
+        grid = key[1]
+        keys = sorted(k for k in per if k[1] == grid)   # e.g. both march directions
+        name = " and ".join(k[0] for k in keys)
+        for c in per[key]:
+            v = [x for k in keys for x in per[k].get(c, [])]
             vals[c] = sum(v) / len(v)
     g = vals.get
     derived = {}
@@ -241,7 +252,7 @@ def summarize_sq(dirs, pattern, commands, title, out_md):
     lines = ["# SQ counters: %s" % title, "",
              "Commands (from /tmp, with the repository as the working copy), one per counter pass:",
              ""] + ["    " + c for c in commands] + [
-             "", "Kernel `%s`, grid %d threads." % (_short(name), grid), "",
+             "", "Kernels (dispatches of all averaged) `%s`, grid %d threads." % (_short(name).replace(" and ", "` and `"), grid), "",
              "| Counter | per dispatch |", "|---|---|"]
     for c in sorted(vals):
         lines.append("| %s | %.4g |" % (c, vals[c]))
@@ -755,7 +766,7 @@ def main():
     ap.add_argument("--trace-out", default=None, help="with --summarize-trace: output file")
     ap.add_argument("--trace-by-kernel", action="store_true",
                     help="with --summarize-trace: one row per kernel over all grid sizes")
-    ap.add_argument("--sq-kernel", default="tb3d_stage<1, 1, 3, false, false, false, false, 64>")
+    ap.add_argument("--sq-kernel", default="tb3d_stage<1, 1, 3, false, false, false, false, 64, ")
     ap.add_argument("--sq-title", default="3D variable-D interior pass, 256^3, s = 100, k = 3")
     ap.add_argument("--command", action="append", default=[],
                     help="with --summarize-*: the command line(s) that produced the data")

@@ -82,24 +82,31 @@ __global__ __launch_bounds__(kThreads) void reduce_pass2(double *partials, int n
 
 // per-cell Jacobian row sum (without the 1/h^2 factor; linear operators also
 // without their factor 2), then max
+constexpr int kRhoThreads = 1024;   // a full CU of wavefronts over the grid's loads
+
 template <int OP, int BC, int NDIM>
-__global__ __launch_bounds__(kThreads) void rho_pass1(const double *w, const double *D, int nx,
+__global__ __launch_bounds__(kRhoThreads) void rho_pass1(const double *w, const double *D, int nx,
                                                       int ny, int nz, double d_const,
                                                       double *partials)
 {
     // Work items of kThreads consecutive points of one x row, so that the
     // row and its y, z follow from one (uniform) division per item
-    const int cpr = (nx + kThreads - 1) / kThreads;
+    const int cpr = (nx + kRhoThreads - 1) / kRhoThreads;
     const long long items = (long long)cpr * ny * nz;
     double m = 0.0;
     for (long long it = blockIdx.x; it < items; it += gridDim.x) {
         const long long r = it / cpr;
-        const int x = (int)(it - r * cpr) * kThreads + (int)threadIdx.x;
+        const int x = (int)(it - r * cpr) * kRhoThreads + (int)threadIdx.x;
         if (x >= nx) continue;
         const int y = (int)(r % ny);
         const int z = (int)(r / ny);
         const long long p = x + (long long)nx * r;
         double sum = 0.0, diag = 0.0;
+        // Every neighbour is loaded, with no branch around the loads (so they
+        // are all in flight together): a Dirichlet ghost at the clamped index,
+        // which is the cell itself, then set aside by a select.
+        const double Dc = (OP == FRKC2_OP_VARCOEF) ? D[p] : 0.0;
+        const double wc = (OP == FRKC2_OP_POROUS2) ? w[p] : 0.0;
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
             const int d = f >> 1;
@@ -107,21 +114,20 @@ __global__ __launch_bounds__(kThreads) void rho_pass1(const double *w, const dou
             if (NDIM == 2 && d == 1) continue;   // 2D grids march in z
             int j[3] = {x, y, z};
             const int nd[3] = {nx, ny, nz};
-            j[d] += (f & 1) ? 1 : -1;
-            bool ghost = false;
-            if (j[d] < 0 || j[d] >= nd[d]) {
-                if (BC == FRKC2_BC_DIRICHLET0) ghost = true;
-                else j[d] = (j[d] + nd[d]) % nd[d];
-            }
-            const long long q = ghost ? p : j[0] + (long long)nx * (j[1] + (long long)ny * j[2]);
+            const int jd = j[d] + ((f & 1) ? 1 : -1);
+            const bool out = jd < 0 || jd >= nd[d];
+            const bool ghost = (BC == FRKC2_BC_DIRICHLET0) && out;
+            j[d] = (BC == FRKC2_BC_DIRICHLET0) ? min(max(jd, 0), nd[d] - 1)
+                                               : (out ? (jd < 0 ? jd + nd[d] : jd - nd[d]) : jd);
+            const long long q = j[0] + (long long)nx * (j[1] + (long long)ny * j[2]);
             double Df;
             if (OP == FRKC2_OP_LAPLACE) {
                 Df = d_const;
             } else if (OP == FRKC2_OP_VARCOEF) {
-                Df = 0.5 * D[p] + 0.5 * (ghost ? D[p] : D[q]);
+                Df = 0.5 * Dc + 0.5 * D[q];   // a ghost's clamped D is D_c
             } else {
-                const double wc = w[p];
-                const double un = ghost ? 0.0 : w[q];
+                const double wq = w[q];
+                const double un = ghost ? 0.0 : wq;
                 const double dw = un - wc;
                 const double Q = 0.5 * (wc * wc + un * un);
                 diag = diag + (wc * dw - Q);
@@ -133,8 +139,19 @@ __global__ __launch_bounds__(kThreads) void rho_pass1(const double *w, const dou
         if (OP == FRKC2_OP_POROUS2) sum = fabs(diag) + sum;
         m = m > sum ? m : sum;
     }
-    const double r = block_reduce<R_MAX>(m);
-    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+    // block maximum (exact in any order): wavefronts, then their maxima
+    __shared__ double sm[kRhoThreads / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(m, off, 64);
+        m = m > o ? m : o;
+    }
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = sm[0];
+        for (int i = 1; i < kRhoThreads / 64; ++i) r = r > sm[i] ? r : sm[i];
+        partials[blockIdx.x] = r;
+    }
 }
 
 template <int OP>
@@ -151,7 +168,7 @@ template <int OP, int BC>
 int launch_rho_t(const KGrid &g, const double *w, const double *D, double *partials,
                  hipStream_t st)
 {
-    dim3 grid(kReduceBlocks), block(kThreads);
+    dim3 grid(kReduceBlocks), block(kRhoThreads);
     if (g.ndim == 3)
         hipLaunchKernelGGL((rho_pass1<OP, BC, 3>), grid, block, 0, st, w, D, g.nx, g.ny, g.nz,
                            g.d_const, partials);

@@ -167,13 +167,17 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(const double2 *in
     }
 }
 
-__global__ void finalize_sum(double *partials, int nb)
+__global__ __launch_bounds__(256) void finalize_sum(double *partials, int nb)
 {
+    // the partials staged in LDS by all threads, then summed in index order
+    __shared__ double s[2 * kReduceBlocks];
+    for (int i = threadIdx.x; i < 2 * nb; i += blockDim.x) s[i] = partials[i];
+    __syncthreads();
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         double a = 0.0, b = 0.0;
         for (int i = 0; i < nb; ++i) {
-            a = a + partials[2 * i];
-            b = b + partials[2 * i + 1];
+            a = a + s[2 * i];
+            b = b + s[2 * i + 1];
         }
         partials[2 * nb] = a;
         partials[2 * nb + 1] = b;
@@ -364,7 +368,7 @@ int launch_finalize(const KGrid &g, const double *in_c, double *out_re, double *
     const long long n = g.nstate();
     hipLaunchKernelGGL(finalize_kernel, dim3(kReduceBlocks), dim3(kFinThreads), 0, st,
                        reinterpret_cast<const double2 *>(in_c), out_re, n, partials);
-    hipLaunchKernelGGL(finalize_sum, dim3(1), dim3(64), 0, st, partials, kReduceBlocks);
+    hipLaunchKernelGGL(finalize_sum, dim3(1), dim3(256), 0, st, partials, kReduceBlocks);
     return (int)hipGetLastError();
 }
 
