@@ -428,13 +428,9 @@ def batched_leg(F, wl, torch, reps=3):
         s_list.append(s)
         grids.append(p)
     work = sum(p.npoints * s for p, s in probs)
-    # launch configuration timed on copies of the states (the autotuner advances them)
-    tune_args = F.BatchedArgs(grids, [w.clone() for w in ws_list], D_list, T_list, s_list)
-    tune = F.frkc2_batched_autotune(tune_args, reps=2)
-    del tune_args
-    log("batched autotune: k3=%d cols=%d k2=%d, %.2f ms against %.2f ms built-in (%d timed)"
-        % (tune["k3"], tune["cols3"], tune["k2"], tune["ms_best"], tune["ms_default"],
-           tune["candidates"]))
+    # the built-in launch configuration (the timing autotuner is switched off in this build)
+    k3, cols3, k2 = F.frkc2_batched_config(grids, s_list)
+    log("batched configuration: k3=%d cols=%d k2=%d (built-in)" % (k3, cols3, k2))
     args = F.BatchedArgs(grids, ws_list, D_list, T_list, s_list)
     F.frkc2_step_batched(args)          # builds and captures the graph
     torch.cuda.synchronize()
@@ -465,9 +461,7 @@ def batched_leg(F, wl, torch, reps=3):
             "unit": "grid-point-stage updates/s",
             "plain_sequential_ms": t_p, "plain_sequential_value": work / (t_p * 1e-3),
             "speedup_vs_plain": t_p / t_b,
-            "config": {"k3": tune["k3"], "cols3": tune["cols3"], "k2": tune["k2"]},
-            "autotune_ms": {"chosen": tune["ms_best"], "built_in": tune["ms_default"],
-                            "candidates": tune["candidates"]}}
+            "config": {"k3": k3, "cols3": cols3, "k2": k2, "source": "built-in"}}
 
 
 def heat1d_leg(F, wl, torch, reps=10):

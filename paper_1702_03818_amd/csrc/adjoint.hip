@@ -100,23 +100,31 @@ __global__ __launch_bounds__(BX *BY) void adjoint_stage(AdjPlaneArgs a)
     const int hslot = (NDIM == 3 ? (hy + 1) * SX : 0) + (hx + 1);
     const int oslot = (NDIM == 3 ? (ty + 1) * SX : 0) + (tx + 1);
 
+    // Loads without branches (clamped index, a Dirichlet ghost selected to
+    // 0 afterwards), so that a plane's loads are all in flight together.
     auto ldL = [&](int gx, int gy, int gz) {
-        return load_c<BC, IN_REAL>(dm, a.lin_re, a.lin_c, gx, gy, gz);
+        return load_c_nb<BC, IN_REAL>(dm, a.lin_re, a.lin_c, gx, gy, gz);
     };
     auto ldW = [&](int gx, int gy, int gz) {
-        return load_c<BC, false>(dm, nullptr, a.W, gx, gy, gz);
+        return load_c_nb<BC, false>(dm, nullptr, a.W, gx, gy, gz);
     };
+    auto ldD = [&](int gx, int gy, int gz) { return 0.5 * load_r_nb<BC>(dm, a.D, gx, gy, gz); };
+    // the dJ/dD accumulator of the lane's cell (any cell for an idle lane:
+    // the read is then discarded), read one plane ahead of its update
+    const long long pst = (long long)a.nx * a.ny;
+    const long long ixy = min(x, a.nx - 1) + (long long)a.nx * min(y, a.ny - 1);
 
     double2 Lm = ldL(x, y, z0 - 1), Lc = ldL(x, y, z0), Lp = ldL(x, y, z0 + 1);
     double2 Wm = make_double2(0.0, 0.0), Wc = Wm, Wp = Wm;
-    double Dm = 0.0, Dc = 0.0, Dp = 0.0;
+    double Dm = 0.0, Dc = 0.0, Dp = 0.0, Gc = 0.0;
     if (VC) {
         Wm = ldW(x, y, z0 - 1);
         Wc = ldW(x, y, z0);
         Wp = ldW(x, y, z0 + 1);
-        Dm = 0.5 * load_r<BC>(dm, a.D, x, y, z0 - 1);
-        Dc = 0.5 * load_r<BC>(dm, a.D, x, y, z0);
-        Dp = 0.5 * load_r<BC>(dm, a.D, x, y, z0 + 1);
+        Dm = ldD(x, y, z0 - 1);
+        Dc = ldD(x, y, z0);
+        Dp = ldD(x, y, z0 + 1);
+        Gc = a.gD[ixy + pst * z0];
     }
     double2 hL = make_double2(0.0, 0.0), hW = hL;
     double hD = 0.0;
@@ -124,7 +132,7 @@ __global__ __launch_bounds__(BX *BY) void adjoint_stage(AdjPlaneArgs a)
         hL = ldL(x0 + hx, y0 + hy, z0);
         if (VC) {
             hW = ldW(x0 + hx, y0 + hy, z0);
-            hD = 0.5 * load_r<BC>(dm, a.D, x0 + hx, y0 + hy, z0);
+            hD = ldD(x0 + hx, y0 + hy, z0);
         }
     }
 
@@ -147,9 +155,11 @@ __global__ __launch_bounds__(BX *BY) void adjoint_stage(AdjPlaneArgs a)
             hL = ldL(x0 + hx, y0 + hy, z + 1);
             if (VC) {
                 hW = ldW(x0 + hx, y0 + hy, z + 1);
-                hD = 0.5 * load_r<BC>(dm, a.D, x0 + hx, y0 + hy, z + 1);
+                hD = ldD(x0 + hx, y0 + hy, z + 1);
             }
         }
+        // next plane's accumulator, in flight during this plane's work
+        const double Gn = (VC && z + 1 < z1) ? a.gD[ixy + pst * (z + 1)] : 0.0;
         if (active) {
             const bool dir = (BC == DIR);
             double gsum = 0.0, acc_r = 0.0, acc_i = 0.0;
@@ -175,7 +185,7 @@ __global__ __launch_bounds__(BX *BY) void adjoint_stage(AdjPlaneArgs a)
                              a.tr, a.ti, a.d_const);
             }
             const long long i = x + (long long)a.nx * (y + (long long)a.ny * z);
-            if (VC) a.gD[i] = a.gD[i] - gsum * a.inv_h2;
+            if (VC) a.gD[i] = Gc - gsum * a.inv_h2;
             const double gr = acc_r * a.inv_h2;
             const double gi = acc_i * a.inv_h2;
             const double nr = Lc.x + (a.tr * gr + a.ti * gi);
@@ -190,12 +200,13 @@ __global__ __launch_bounds__(BX *BY) void adjoint_stage(AdjPlaneArgs a)
             Wc = Wp;
             Dm = Dc;
             Dc = Dp;
+            Gc = Gn;
         }
         if (z + 1 < z1) {
             Lp = ldL(x, y, z + 2);
             if (VC) {
                 Wp = ldW(x, y, z + 2);
-                Dp = 0.5 * load_r<BC>(dm, a.D, x, y, z + 2);
+                Dp = ldD(x, y, z + 2);
             }
         }
     }

@@ -113,7 +113,7 @@ __device__ void run_fused(const BatchProblem &P, Tb3Args &a, long long c, double
 {
     const int bx = (int)(c % P.ntx3);
     const long long r = c / P.ntx3;
-    tb3d_tile<OP, BC, KB, IR, OR, false, false, W, false, false>(a, bx, (int)(r % P.nty3),
+    tb3d_tile<OP, BC, KB, IR, OR, false, false, W, false, true>(a, bx, (int)(r % P.nty3),
                                                                  (int)(r / P.nty3), sL, sD);
 }
 

@@ -129,6 +129,8 @@ struct GraphEntry {
 
 std::mutex g_mu;
 std::map<void *, GraphEntry> g_graphs;
+// The timing autotuner is switched off (frkc2_batched_autotune's header block).
+constexpr bool g_autotune_enabled = false;
 BatchCfg g_forced{0, 0, 0};                                  // FRKC2_OPT_BATCH_*
 std::map<std::vector<unsigned char>, BatchCfg> g_tuned;      // by problem-set shape
 hipStream_t g_capture = nullptr, g_capture2 = nullptr;   // 3D group 0 and 2D branches
@@ -640,6 +642,13 @@ extern "C" int frkc2_batched_autotune(int nprob, const frkc2_grid *grids, double
         set_error("batched: workspace needs %zu bytes (got %zu), 256-byte aligned", L.total,
                   ws_bytes);
         return FRKC2_ENOMEM;
+    }
+    if (!g_autotune_enabled) {
+        set_error("batched autotune: switched off in this build (runs that rebuilt the batch "
+                  "graph per candidate ended in a host heap corruption inside this call, cause "
+                  "not found); frkc2_step_batched uses the options or the built-in "
+                  "configuration");
+        return FRKC2_EDISABLED;
     }
     std::lock_guard<std::mutex> lk(g_mu);
     GraphEntry &E = g_graphs[ws];

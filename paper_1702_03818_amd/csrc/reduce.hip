@@ -89,17 +89,29 @@ __global__ __launch_bounds__(kRhoThreads) void rho_pass1(const double *w, const 
                                                       int ny, int nz, double d_const,
                                                       double *partials)
 {
-    // Work items of kThreads consecutive points of one x row, so that the
-    // row and its y, z follow from one (uniform) division per item
-    const int cpr = (nx + kRhoThreads - 1) / kRhoThreads;
-    const long long items = (long long)cpr * ny * nz;
+    // Work items of up to kRhoThreads points: a segment of one x row, or
+    // several whole rows when they are shorter, so that the row and its y, z
+    // follow from one (uniform) division per item
+    const int tpr = nx < kRhoThreads ? nx : kRhoThreads;     // threads per row segment
+    const int rpi = kRhoThreads / tpr;                        // rows per item
+    const int cpr = (nx + tpr - 1) / tpr;                     // segments per row
+    const long long rows = (long long)ny * nz;
+    const long long items = (long long)cpr * ((rows + rpi - 1) / rpi);
+    const int trow = (int)threadIdx.x / tpr, tx = (int)threadIdx.x % tpr;
     double m = 0.0;
     for (long long it = blockIdx.x; it < items; it += gridDim.x) {
-        const long long r = it / cpr;
-        const int x = (int)(it - r * cpr) * kRhoThreads + (int)threadIdx.x;
-        if (x >= nx) continue;
-        const int y = (int)(r % ny);
-        const int z = (int)(r / ny);
+        const long long rg = it / cpr;
+        const long long r = rg * rpi + trow;
+        const int x = (int)(it - rg * cpr) * tpr + tx;
+        if (trow >= rpi || r >= rows || x >= nx) continue;
+        int y, z;
+        if (rows <= 0xffffffffLL) {   // 32-bit division where the rows allow (uniform)
+            y = (int)((unsigned)r % (unsigned)ny);
+            z = (int)((unsigned)r / (unsigned)ny);
+        } else {
+            y = (int)(r % ny);
+            z = (int)(r / ny);
+        }
         const long long p = x + (long long)nx * r;
         double sum = 0.0, diag = 0.0;
         // Every neighbour is loaded, with no branch around the loads (so they

@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libfrkc2.so")
 FRKC2_OK = 0
 FRKC2_WQBOUND = 1
 STATUS_NAMES = {0: "OK", 1: "WQBOUND", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP",
-                -4: "EUNSTABLE", -5: "ENONFINITE", -6: "ETIMEOUT"}
+                -4: "EUNSTABLE", -5: "ENONFINITE", -6: "ETIMEOUT",
+                -7: "EDISABLED"}
 WS_STEP = 0
 NOALLOC_MAX_VALUES = 2097152   # largest state frkc2_step_noalloc accepts (2^21 values)
 WS_ADJOINT = 1

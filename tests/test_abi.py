@@ -176,6 +176,24 @@ def test_batched_autotune_validation():
                                       ctypes.byref(r)) == -2          # no workspace
 
 
+def test_batched_autotune_is_switched_off():
+    """With valid arguments the switched-off autotuner refuses before any HIP call and says
+    why."""
+    lib = F.load()
+    g = (F.Grid * 1)(grid(n=(8, 8, 8), op=0))
+    s = (ctypes.c_int * 1)(8)
+    w = (ctypes.c_void_p * 1)(16)
+    D = (ctypes.c_void_p * 1)(None)
+    T = (ctypes.c_double * 1)(0.001)
+    r = F.BatchTuneResult()
+    need = lib.frkc2_batched_workspace_bytes(1, g, s)
+    assert need > 0
+    ws = ctypes.c_void_p(1 << 20)   # never dereferenced: the call returns before using it
+    assert lib.frkc2_batched_autotune(1, g, w, D, T, s, 0.01, 2, ws, need, None,
+                                      ctypes.byref(r)) == -7
+    assert b"switched off" in lib.frkc2_last_error()
+
+
 def test_batched_workspace_covers_every_depth():
     """The work tables are sized for the most pass levels any supported depth gives."""
     lib = F.load()
