@@ -679,7 +679,7 @@ def fourth_order_leg(F, wl, torch, steps=(10, 20, 40, 80, 160, 320), m_ref=2560)
 def adjoint_leg(F, wl, torch, reps=3):
     """3D 128^3 variable D, s = 64, 8 supersteps, J = sum (w - target)^2: forward alone
     and forward + adjoint through the autograd function."""
-    from paper_1702_03818_amd.autograd import superstep_fn
+    from paper_1702_03818_amd.autograd import _want_store, superstep_fn
     log("generating the adjoint workload")
     p, target = wl.adjoint3d()
     s, nsteps = 64, 8
@@ -695,15 +695,19 @@ def adjoint_leg(F, wl, torch, reps=3):
         F.frkc2_step(p, w, D, T=T, s=s, nsteps=nsteps)
         return w
 
-    def fwd_bwd():
+    def fwd_bwd(store):
         u = u0.clone().requires_grad_(True)
         ld = logD.clone().requires_grad_(True)
-        J = ((superstep_fn(u, ld, p, T, s, nsteps) - tgt) ** 2).sum()
+        J = ((superstep_fn(u, ld, p, T, s, nsteps, store_stages=store) - tgt) ** 2).sum()
         J.backward()
         return J
 
-    res = {}
-    for name, fn in (("forward", fwd), ("forward_backward", fwd_bwd)):
+    # the autograd function's automatic choice (the stage store when it fits a quarter of the
+    # free memory, as it does here: 8 x 64 x 128^3 complex states, 17.2 GB), then the
+    # per-superstep checkpoints that recompute the stages in the backward
+    res = {"stage_store": _want_store(p, s, nsteps, u0.device)}
+    for name, fn in (("forward", fwd), ("forward_backward", lambda: fwd_bwd(None)),
+                     ("forward_backward_checkpoints", lambda: fwd_bwd(False))):
         fn()
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -720,8 +724,9 @@ def adjoint_leg(F, wl, torch, reps=3):
                 "value_forward_backward": work / (res["forward_backward_ms"] * 1e-3),
                 "unit": "forward grid-point-stage updates/s",
                 "backward_over_forward": res["forward_backward_ms"] / res["forward_ms"]})
-    log("adjoint: forward %.2f ms, forward+backward %.2f ms"
-        % (res["forward_ms"], res["forward_backward_ms"]))
+    log("adjoint: forward %.2f ms, forward+backward %.2f ms (stage store %s), with "
+        "checkpoints %.2f ms" % (res["forward_ms"], res["forward_backward_ms"],
+                                 res["stage_store"], res["forward_backward_checkpoints_ms"]))
     return res
 
 

@@ -128,6 +128,8 @@ typedef struct {
 #define FRKC2_WS_STEP    0
 #define FRKC2_WS_ADJOINT 1
 #define FRKC2_WS_ADAPT   2
+#define FRKC2_WS_STAGES  3
+#define FRKC2_WS_ADJOINT_STORED 4
 
 /*
  * frkc2_coeffs -- the s ordered stepsizes a_l (Sec. 2, 2.1, 2.2).
@@ -182,8 +184,12 @@ int frkc2_write_table(const char *path, double nu, int m_max);
  *   plus reduction scratch); FRKC2_WS_ADJOINT: frkc2_step_adjoint (s stored
  *   complex stages, two complex adjoint buffers, one real gradient buffer);
  *   FRKC2_WS_ADAPT: frkc2_integrate (two complex and two real state buffers
- *   plus scratch; s is ignored).
- * Returns 0 for an invalid grid.
+ *   plus scratch; s is ignored); FRKC2_WS_STAGES: the stage store of
+ *   frkc2_step_store and frkc2_step_adjoint_stored (s complex states, each
+ *   slot rounded up to 256 bytes); FRKC2_WS_ADJOINT_STORED:
+ *   frkc2_step_adjoint_stored (two complex adjoint buffers, one real gradient
+ *   buffer, scratch; s is ignored).
+ * Returns 0 for an invalid grid (or an invalid s where s sets the size).
  */
 size_t frkc2_workspace_bytes(const frkc2_grid *g, int s, int flags);
 
@@ -269,6 +275,46 @@ int frkc2_step_noalloc(const frkc2_grid *g, double *w, const double *D, double T
 int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const double *D, double T, int s,
                        double nu, const double *lam_next, double *lam_n, double *grad_logD,
                        void *ws, size_t ws_bytes, hipStream_t st);
+
+/*
+ * frkc2_step_store -- one superstep (Sec. 3, Euler-step equation; VARCOEF or
+ * LAPLACE) that keeps its stage states for frkc2_step_adjoint_stored, so that
+ * the backward pass need not recompute them: memory (s complex states per
+ * superstep) for the recomputation's time.
+ *   w       device, N doubles, in/out: w^n on entry, w^{n+1} on return, with the
+ *           bits frkc2_step gives for the same T, s and nu
+ *   D       device, N doubles (VARCOEF only; NULL otherwise)
+ *   T       fixed superstep length, positive and finite
+ *   stages  device, caller-owned, at least frkc2_workspace_bytes(g, s,
+ *           FRKC2_WS_STAGES) bytes, 16-byte aligned; out: W^0 .. W^{s-1}, the
+ *           complex state before stage l at byte offset l * slot, slot =
+ *           16 N rounded up to 256, interleaved (re, im) per point in the
+ *           grid's x-fastest order
+ *   ws      device, reduction scratch of at least 65536 bytes (any
+ *           FRKC2_WS_STEP workspace serves); may be NULL for LAPLACE
+ * The stability requirement is checked as frkc2_step checks it (FRKC2_EUNSTABLE
+ * if T * rho > beta_bar; the check synchronises st for VARCOEF). Otherwise
+ * asynchronous.
+ */
+int frkc2_step_store(const frkc2_grid *g, double *w, const double *D, double T, int s, double nu,
+                     double *stages, size_t stages_bytes, void *ws, size_t ws_bytes,
+                     hipStream_t st);
+
+/*
+ * frkc2_step_adjoint_stored -- frkc2_step_adjoint with the forward stages taken
+ * from a store that frkc2_step_store filled for the same g, D, T, s and nu
+ * (the same bits as frkc2_step_adjoint from that superstep's w_n).
+ *   stages    device, the store as frkc2_step_store left it (read only)
+ *   lam_next, lam_n, grad_logD  as for frkc2_step_adjoint (lam_n may alias
+ *             lam_next)
+ *   ws        device, at least frkc2_workspace_bytes(g, s,
+ *             FRKC2_WS_ADJOINT_STORED) bytes, 16-byte aligned
+ * Asynchronous.
+ */
+int frkc2_step_adjoint_stored(const frkc2_grid *g, const double *stages, size_t stages_bytes,
+                              const double *D, double T, int s, double nu,
+                              const double *lam_next, double *lam_n, double *grad_logD, void *ws,
+                              size_t ws_bytes, hipStream_t st);
 
 /*
  * frkc2_step_batched -- one superstep (Sec. 3, Euler-step equation) for each of

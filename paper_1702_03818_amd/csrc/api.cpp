@@ -176,6 +176,8 @@ struct AdjLayout {
     size_t store, lamA, lamB, gD, scratch, total;
 };
 
+// s == 0: no stage store (frkc2_step_adjoint_stored, whose caller holds the
+// stages)
 AdjLayout adj_layout(long long N, int s)
 {
     AdjLayout L;
@@ -436,6 +438,11 @@ extern "C" size_t frkc2_workspace_bytes(const frkc2_grid *g, int s, int flags)
     if (flags == FRKC2_WS_ADJOINT) {
         if (s < 2 || s > kMaxStages || (s % 2)) return 0;
         return adj_layout(kg.npts(), s).total;
+    }
+    if (flags == FRKC2_WS_ADJOINT_STORED) return adj_layout(kg.npts(), 0).total;
+    if (flags == FRKC2_WS_STAGES) {
+        if (s < 2 || s > kMaxStages || (s % 2)) return 0;
+        return (size_t)s * align_up((size_t)kg.npts() * 16);
     }
     if (flags == FRKC2_WS_ADAPT) return adapt_layout(kg.nstate()).total;
     return step_layout(kg.nstate()).total;
@@ -874,19 +881,19 @@ extern "C" int frkc4s_step(const frkc2_grid *g, double *w, double T, int s, int 
     return crc;
 }
 
-extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const double *D,
-                                  double T, int s, double nu, const double *lam_next,
-                                  double *lam_n, double *grad_logD, void *ws, size_t ws_bytes,
-                                  hipStream_t st)
+namespace {
+
+// Argument checks shared by the adjoint entry points (no HIP call).
+int adjoint_validate(const frkc2_grid *g, const double *D, double T, int s, double nu,
+                     const double *lam_next, double *lam_n, KGrid &kg)
 {
-    KGrid kg;
     if (!make_kgrid(g, kg)) return FRKC2_EINVAL;
     if (nonlinear(kg) || kg.op == FRKC2_OP_ADVDIFF) {
         set_error("the adjoint supports the symmetric operators (LAPLACE, VARCOEF)");
         return FRKC2_EINVAL;
     }
-    if (!w_n || !lam_next || !lam_n || (kg.op == FRKC2_OP_VARCOEF && !D)) {
-        set_error("w_n, lam_next, lam_n (and D for VARCOEF) must be non-NULL");
+    if ((lam_next == nullptr) != (lam_n == nullptr) || (kg.op == FRKC2_OP_VARCOEF && !D)) {
+        set_error("lam_next and lam_n (and D for VARCOEF) must be non-NULL");
         return FRKC2_EINVAL;
     }
     if (!check_s_nu(s, nu)) return FRKC2_EINVAL;
@@ -894,28 +901,20 @@ extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const 
         set_error("T must be positive and finite");
         return FRKC2_EINVAL;
     }
-    const long long N = kg.npts();
-    const AdjLayout L = adj_layout(N, s);
-    if (!ws || ws_bytes < L.total || !aligned16(ws)) {
-        set_error("adjoint workspace needs %zu bytes (got %zu), 16-byte aligned", L.total,
-                  ws_bytes);
-        return FRKC2_ENOMEM;
-    }
-    const double *are, *aim;
-    int crc = coeffs_cached(s, nu, &are, &aim, nullptr);
-    if (crc < 0) return crc;
-    char *base = static_cast<char *>(ws);
-    const size_t cbytes = align_up((size_t)N * 16);
-    auto S = [&](int l) { return reinterpret_cast<double *>(base + L.store + (size_t)l * cbytes); };
-    double *lam[2] = {reinterpret_cast<double *>(base + L.lamA),
-                      reinterpret_cast<double *>(base + L.lamB)};
-    double *gD = reinterpret_cast<double *>(base + L.gD);
+    return FRKC2_OK;
+}
 
-    // forward recompute, storing W^0 .. W^{s-1}: 3D grids fuse three stages
-    // per pass (two for a remainder of two) and write the intermediate states
-    // as well
-    HIP_TRY(launch_real_to_complex(N, w_n, S(0), st), "adjoint: W^0");
-    for (int l = 0; l + 1 < s;) {
+// The forward stages W^0 .. W^{s-1} of the superstep from the real state w_n
+// (Sec. 3, Euler-step equation) into the slots S(0) .. S(s-1) of store (slot
+// stride cbytes): 3D grids fuse three stages per pass (two for a remainder of
+// two) and write the intermediate states as well.
+int store_stages(const KGrid &kg, const double *w_n, const double *D, double T,
+                 const double *are, const double *aim, int s, char *store, size_t cbytes,
+                 hipStream_t st)
+{
+    auto S = [&](int l) { return reinterpret_cast<double *>(store + (size_t)l * cbytes); };
+    int rc = launch_real_to_complex(kg.npts(), w_n, S(0), st);
+    for (int l = 0; rc == 0 && l + 1 < s;) {
         const int left = s - 1 - l;
         const int k = (kg.ndim == 3 && tb3d_plane_ok(kg) && left >= 2) ? (left >= 3 ? 3 : 2) : 1;
         PassArgs pa{};
@@ -931,19 +930,30 @@ extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const 
             pa.cols = tb3d_pick_cols(kg, 3);
             pa.lvl_out = S(l + 1);
             pa.lvl_stride = (long long)(cbytes / 16);
-            HIP_TRY(launch_tb3d(kg, pa, st), "adjoint: forward pass");
+            rc = launch_tb3d(kg, pa, st);
         } else {
-            HIP_TRY(launch_pass(kg, pa, 0, st), "adjoint: forward stage");
+            rc = launch_pass(kg, pa, 0, st);
         }
         l += k;
     }
+    return rc;
+}
+
+// The transposed stages in reverse order (stage l = s-1 .. 0) from lam_next to
+// lam_n, with W^l in the slots of store; lam[2] are complex scratch states,
+// gD the real per-cell accumulator (VARCOEF). Pass q writes lam[q & 1].
+int reverse_stages(const KGrid &kg, const char *store, size_t cbytes, const double *D, double T,
+                   const double *are, const double *aim, int s, const double *lam_next,
+                   double *lam_n, double *grad_logD, double *const lam[2], double *gD,
+                   hipStream_t st)
+{
     const bool vc = kg.op == FRKC2_OP_VARCOEF;
-    if (vc) HIP_TRY(launch_zero(N, gD, st), "adjoint: zero gD");
-    // reverse stage r (stage l = s-1-r): lambda^{l+1} -> lambda^l; pass q
-    // writes buffer q & 1. On request, 3D grids run two stages per pass (s is
-    // even) in the same per-cell arithmetic; measured slower than one per
-    // pass, so not the default. One pass of two would read lam_next and write
-    // lam_n, so it needs the two to be distinct.
+    int rc = vc ? launch_zero(kg.npts(), gD, st) : 0;
+    if (rc) return rc;
+    // On request, 3D grids run two stages per pass (s is even) in the same
+    // per-cell arithmetic; measured slower than one per pass, so not the
+    // default. One pass of two would read lam_next and write lam_n, so it needs
+    // the two to be distinct.
     const bool pairs = kg.ndim == 3 && g_adj_stages == 2 && !(s == 2 && lam_n == lam_next);
     auto rev = [&](int r, int q_in, int q_out) {
         const int l = s - 1 - r;
@@ -952,7 +962,7 @@ extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const 
         else a.lam_in_c = lam[q_in & 1];
         if (r == s - 1) a.lam_out_re = lam_n;
         else a.lam_out_c = lam[q_out & 1];
-        a.W = S(l);
+        a.W = reinterpret_cast<const double *>(store + (size_t)l * cbytes);
         a.D = D;
         a.gD = vc ? gD : nullptr;
         a.tr = T * are[l];
@@ -960,14 +970,137 @@ extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const 
         return a;
     };
     if (pairs) {
-        for (int r = 0, q = 0; r < s; r += 2, ++q)
-            HIP_TRY(launch_adjoint_pair(kg, rev(r, q - 1, q), rev(r + 1, q - 1, q), st),
-                    "adjoint pair");
+        for (int r = 0, q = 0; r < s && rc == 0; r += 2, ++q)
+            rc = launch_adjoint_pair(kg, rev(r, q - 1, q), rev(r + 1, q - 1, q), st);
     } else {
-        for (int r = 0; r < s; ++r)
-            HIP_TRY(launch_adjoint_stage(kg, rev(r, r - 1, r), st), "adjoint stage");
+        for (int r = 0; r < s && rc == 0; ++r) rc = launch_adjoint_stage(kg, rev(r, r - 1, r), st);
     }
-    if (vc && grad_logD) HIP_TRY(launch_grad_finish(N, D, gD, grad_logD, st), "adjoint: gradient");
+    if (rc == 0 && vc && grad_logD) rc = launch_grad_finish(kg.npts(), D, gD, grad_logD, st);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const double *D,
+                                  double T, int s, double nu, const double *lam_next,
+                                  double *lam_n, double *grad_logD, void *ws, size_t ws_bytes,
+                                  hipStream_t st)
+{
+    KGrid kg;
+    const int vrc = adjoint_validate(g, D, T, s, nu, lam_next, lam_n, kg);
+    if (vrc < 0) return vrc;
+    if (!w_n || !lam_next) {
+        set_error("w_n, lam_next, lam_n (and D for VARCOEF) must be non-NULL");
+        return FRKC2_EINVAL;
+    }
+    const long long N = kg.npts();
+    const AdjLayout L = adj_layout(N, s);
+    if (!ws || ws_bytes < L.total || !aligned16(ws)) {
+        set_error("adjoint workspace needs %zu bytes (got %zu), 16-byte aligned", L.total,
+                  ws_bytes);
+        return FRKC2_ENOMEM;
+    }
+    const double *are, *aim;
+    int crc = coeffs_cached(s, nu, &are, &aim, nullptr);
+    if (crc < 0) return crc;
+    char *base = static_cast<char *>(ws);
+    const size_t cbytes = align_up((size_t)N * 16);
+    double *lam[2] = {reinterpret_cast<double *>(base + L.lamA),
+                      reinterpret_cast<double *>(base + L.lamB)};
+    double *gD = reinterpret_cast<double *>(base + L.gD);
+    HIP_TRY(store_stages(kg, w_n, D, T, are, aim, s, base + L.store, cbytes, st),
+            "adjoint: forward recompute");
+    HIP_TRY(reverse_stages(kg, base + L.store, cbytes, D, T, are, aim, s, lam_next, lam_n,
+                           grad_logD, lam, gD, st),
+            "adjoint: reverse stages");
+    return crc;
+}
+
+extern "C" int frkc2_step_store(const frkc2_grid *g, double *w, const double *D, double T, int s,
+                                double nu, double *stages, size_t stages_bytes, void *ws,
+                                size_t ws_bytes, hipStream_t st)
+{
+    KGrid kg;
+    const int vrc = adjoint_validate(g, D, T, s, nu, nullptr, nullptr, kg);
+    if (vrc < 0) return vrc;
+    if (!w || !stages) {
+        set_error("w and stages (and D for VARCOEF) must be non-NULL");
+        return FRKC2_EINVAL;
+    }
+    const long long N = kg.npts();
+    const size_t cbytes = align_up((size_t)N * 16);
+    if (stages_bytes < (size_t)s * cbytes || !aligned16(stages)) {
+        set_error("the stage store needs %zu bytes (got %zu), 16-byte aligned",
+                  (size_t)s * cbytes, stages_bytes);
+        return FRKC2_ENOMEM;
+    }
+    const bool host_only = kg.op == FRKC2_OP_LAPLACE;
+    if (!host_only && (!ws || ws_bytes < kScratch || !aligned16(ws))) {
+        set_error("workspace needs at least %zu bytes, 16-byte aligned", kScratch);
+        return FRKC2_ENOMEM;
+    }
+    const double *are, *aim;
+    frkc2_coeff_info info;
+    int crc = coeffs_cached(s, nu, &are, &aim, &info);
+    if (crc < 0) return crc;
+    // stability as frkc2_step checks it (Sec. 2: T rho <= beta_bar)
+    double rho = 0.0;
+    const int rc = rho_bound_impl(kg, w, D, static_cast<double *>(ws), &rho, st);
+    if (rc < 0) return rc;
+    if (T * rho > info.beta_bar) {
+        set_error("T*rho = %g exceeds beta_bar = %g", T * rho, info.beta_bar);
+        return FRKC2_EUNSTABLE;
+    }
+    char *store = reinterpret_cast<char *>(stages);
+    HIP_TRY(store_stages(kg, w, D, T, are, aim, s, store, cbytes, st), "store: stages");
+    // the last stage from W^{s-1}, its real part into w
+    PassArgs pa{};
+    pa.k = 1;
+    pa.D = D;
+    pa.in_c = reinterpret_cast<const double *>(store + (size_t)(s - 1) * cbytes);
+    pa.out_re = w;
+    pa.tr[0] = T * are[s - 1];
+    pa.ti[0] = T * aim[s - 1];
+    HIP_TRY(launch_pass(kg, pa, 0, st), "store: last stage");
+    return crc;
+}
+
+extern "C" int frkc2_step_adjoint_stored(const frkc2_grid *g, const double *stages,
+                                         size_t stages_bytes, const double *D, double T, int s,
+                                         double nu, const double *lam_next, double *lam_n,
+                                         double *grad_logD, void *ws, size_t ws_bytes,
+                                         hipStream_t st)
+{
+    KGrid kg;
+    const int vrc = adjoint_validate(g, D, T, s, nu, lam_next, lam_n, kg);
+    if (vrc < 0) return vrc;
+    if (!stages || !lam_next) {
+        set_error("stages, lam_next, lam_n (and D for VARCOEF) must be non-NULL");
+        return FRKC2_EINVAL;
+    }
+    const long long N = kg.npts();
+    const size_t cbytes = align_up((size_t)N * 16);
+    if (stages_bytes < (size_t)s * cbytes || !aligned16(stages)) {
+        set_error("the stage store needs %zu bytes (got %zu), 16-byte aligned",
+                  (size_t)s * cbytes, stages_bytes);
+        return FRKC2_ENOMEM;
+    }
+    const AdjLayout L = adj_layout(N, 0);
+    if (!ws || ws_bytes < L.total || !aligned16(ws)) {
+        set_error("adjoint workspace needs %zu bytes (got %zu), 16-byte aligned", L.total,
+                  ws_bytes);
+        return FRKC2_ENOMEM;
+    }
+    const double *are, *aim;
+    int crc = coeffs_cached(s, nu, &are, &aim, nullptr);
+    if (crc < 0) return crc;
+    char *base = static_cast<char *>(ws);
+    double *lam[2] = {reinterpret_cast<double *>(base + L.lamA),
+                      reinterpret_cast<double *>(base + L.lamB)};
+    double *gD = reinterpret_cast<double *>(base + L.gD);
+    HIP_TRY(reverse_stages(kg, reinterpret_cast<const char *>(stages), cbytes, D, T, are, aim, s,
+                           lam_next, lam_n, grad_logD, lam, gD, st),
+            "adjoint: reverse stages");
     return crc;
 }
 

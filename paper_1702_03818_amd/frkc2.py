@@ -28,6 +28,8 @@ WS_STEP = 0
 NOALLOC_MAX_VALUES = 2097152   # largest state frkc2_step_noalloc accepts (2^21 values)
 WS_ADJOINT = 1
 WS_ADAPT = 2
+WS_STAGES = 3
+WS_ADJOINT_STORED = 4
 RED_SUMSQ, RED_SUM, RED_MAXSQ, RED_SUMSQDIFF, RED_DOT = 0, 1, 2, 3, 4
 OPT_TBLOCK = 1
 OPT_TILE = 3
@@ -108,6 +110,12 @@ _SIGS = {
     "frkc2_step_adjoint": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, ctypes.c_double,
                                           ctypes.c_int, ctypes.c_double, _VP, _VP, _VP, _VP,
                                           ctypes.c_size_t, _VP]),
+    "frkc2_step_store": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, _VP, ctypes.c_double,
+                                        ctypes.c_int, ctypes.c_double, _VP, ctypes.c_size_t, _VP,
+                                        ctypes.c_size_t, _VP]),
+    "frkc2_step_adjoint_stored": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, ctypes.c_size_t, _VP,
+                                                 ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                                 _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "frkc2_batched_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.POINTER(Grid),
                                                         ctypes.POINTER(ctypes.c_int)]),
     "frkc2_step_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Grid),
@@ -483,6 +491,50 @@ def frkc2_step_adjoint(grid, w_n, D, T, s, lam_next, lam_n, grad_logD=None, nu=0
                                          float(nu), _ptr(lam_next), _ptr(lam_n), _ptr(grad_logD),
                                          ctypes.c_void_p(buf.data_ptr()), buf.numel(),
                                          _stream_ptr(stream)))
+
+
+def _store_ptr(t):
+    """Pointer and byte size of a contiguous device buffer (the stage store)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or not t.is_contiguous():
+        raise TypeError("expected a contiguous GPU tensor for the stage store")
+    return ctypes.c_void_p(t.data_ptr()), t.numel() * t.element_size()
+
+
+def stage_store(grid, s, device=None):
+    """A new device buffer for one superstep's stage store (frkc2_step_store)."""
+    torch = _torch()
+    need = frkc2_workspace_bytes(grid, s, WS_STAGES)
+    if need == 0:
+        _check(-1)
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    return torch.empty(need, dtype=torch.uint8, device=dev)
+
+
+def frkc2_step_store(grid, w, D, T, s, stages, nu=0.01, stream=None, ws=None):
+    """One superstep in place on w that keeps its s stage states in stages."""
+    lib = load()
+    g = make_grid(grid)
+    buf = ws if ws is not None else workspace(64 * 1024)
+    sp, sb = _store_ptr(stages)
+    return _check(lib.frkc2_step_store(ctypes.byref(g), _ptr(w), _ptr(D), float(T), int(s),
+                                       float(nu), sp, sb, ctypes.c_void_p(buf.data_ptr()),
+                                       buf.numel(), _stream_ptr(stream)))
+
+
+def frkc2_step_adjoint_stored(grid, stages, D, T, s, lam_next, lam_n, grad_logD=None, nu=0.01,
+                              stream=None, ws=None):
+    lib = load()
+    g = make_grid(grid)
+    need = lib.frkc2_workspace_bytes(ctypes.byref(g), int(s), WS_ADJOINT_STORED)
+    if need == 0:
+        _check(-1)
+    buf = ws if ws is not None else workspace(need, key="adjoint_stored")
+    sp, sb = _store_ptr(stages)
+    return _check(lib.frkc2_step_adjoint_stored(ctypes.byref(g), sp, sb, _ptr(D), float(T), int(s),
+                                                float(nu), _ptr(lam_next), _ptr(lam_n),
+                                                _ptr(grad_logD), ctypes.c_void_p(buf.data_ptr()),
+                                                buf.numel(), _stream_ptr(stream)))
 
 
 def frkc2_batched_workspace_bytes(grids, s_list) -> int:

@@ -111,6 +111,62 @@ def test_step_validation(kw, expect):
     assert F.frkc2_last_error()
 
 
+def test_stage_store_workspace_sizes():
+    """The stage store holds s complex states in 256-byte-rounded slots; the stored adjoint's
+    workspace two complex adjoint buffers, one real gradient buffer and scratch."""
+    lib = F.load()
+    g = grid(n=(70, 13, 11))
+    N = 70 * 13 * 11
+    slot = (16 * N + 255) // 256 * 256
+    for s in (2, 64, 514):
+        assert lib.frkc2_workspace_bytes(ctypes.byref(g), s, F.WS_STAGES) == s * slot
+    for s in (0, 7, 516):
+        assert lib.frkc2_workspace_bytes(ctypes.byref(g), s, F.WS_STAGES) == 0
+    adj = lib.frkc2_workspace_bytes(ctypes.byref(g), 64, F.WS_ADJOINT_STORED)
+    assert 2 * 16 * N + 8 * N <= adj < 2 * 16 * N + 8 * N + (1 << 20)
+    assert lib.frkc2_workspace_bytes(ctypes.byref(g), 64, F.WS_ADJOINT) == 64 * slot + adj
+
+
+def _store(g, w=1, D=1, T=1e-3, s=16, nu=0.01, st=1, st_bytes=1 << 40, ws=1, ws_bytes=1 << 40):
+    lib = F.load()
+    p = lambda v: ctypes.c_void_p(4096 * 16) if v else None  # never dereferenced: validation fails first
+    return lib.frkc2_step_store(ctypes.byref(g), p(w), p(D), T, s, nu, p(st), st_bytes, p(ws),
+                                ws_bytes, None)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(w=0), -1), (dict(D=0), -1), (dict(st=0), -1), (dict(s=7), -1), (dict(nu=1.5), -1),
+    (dict(T=0.0), -1), (dict(T=float("inf")), -1), (dict(st_bytes=1000), -2),
+    (dict(ws=0), -2), (dict(ws_bytes=1000), -2),
+])
+def test_step_store_validation(kw, expect):
+    assert _store(grid(), **kw) == expect
+    assert F.frkc2_last_error()
+
+
+def _stored_adj(g, st=1, st_bytes=1 << 40, D=1, T=1e-3, s=16, nu=0.01, ln=1, l0=1, ws=1,
+                ws_bytes=1 << 40):
+    lib = F.load()
+    p = lambda v: ctypes.c_void_p(4096 * 16) if v else None  # never dereferenced: validation fails first
+    return lib.frkc2_step_adjoint_stored(ctypes.byref(g), p(st), st_bytes, p(D), T, s, nu, p(ln),
+                                         p(l0), None, p(ws), ws_bytes, None)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(st=0), -1), (dict(D=0), -1), (dict(ln=0), -1), (dict(l0=0), -1), (dict(s=3), -1),
+    (dict(T=-1.0), -1), (dict(st_bytes=1000), -2), (dict(ws=0), -2), (dict(ws_bytes=1000), -2),
+])
+def test_step_adjoint_stored_validation(kw, expect):
+    assert _stored_adj(grid(), **kw) == expect
+    assert F.frkc2_last_error()
+
+
+def test_stage_store_rejects_nonlinear_operator():
+    for op in (2, 3, 4):
+        assert _store(grid(op=op)) == -1
+        assert _stored_adj(grid(op=op)) == -1
+
+
 def test_adjoint_rejects_nonlinear_operator():
     lib = F.load()
     g = grid(op=2)

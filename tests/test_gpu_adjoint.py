@@ -194,3 +194,97 @@ def test_autograd_matches_oracle_chain():
     assert rel(host(w), w2) <= 1e-12
     assert rel(host(u0.grad), lam) <= 1e-12
     assert rel(host(logD.grad), g) <= 1e-10
+
+
+def _stored_stage(st, l, slot, n):
+    """W^l of a stage store as (re, im) host arrays."""
+    v = host(st[l * slot:l * slot + 16 * n].view(torch.float64)).reshape(n, 2)
+    return v[:, 0], v[:, 1]
+
+
+@pytest.mark.parametrize("kind", ["3d-var-dir", "3d-var-per", "2d-var-dir", "3d-lap-dir"])
+@pytest.mark.parametrize("s", [2, 6, 16, 64, 514])   # 3D: forward passes of three, two and one
+def test_stage_store_and_stored_adjoint(kind, s):
+    """frkc2_step_store gives the oracle's w^{n+1} bit for bit and leaves the oracle's stage
+    states W^l in the store; frkc2_step_adjoint_stored on that store gives the oracle's adjoint
+    bit for bit (lam_n and the accumulated D dJ/dD)."""
+    p = _prob(kind)
+    c = frkc2_coeffs(s, 0.01)
+    T = 0.9 * c.beta_bar / stage.rho_bound(p)
+    tr, ti = T * c.a_re, T * c.a_im
+    D = dev(p.D) if p.D is not None else None
+    w = dev(p.w0)
+    st = F.stage_store(p, s)
+    F.frkc2_step_store(p, w, D, T, s, st)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(w), stage.superstep(p, p.w0, tr, ti).reshape(-1))
+    n = p.npoints
+    slot = F.frkc2_workspace_bytes(p, s, F.WS_STAGES) // s
+    for l in sorted({0, 1, 2, 3, 4, s // 2, s - 2, s - 1}):
+        if l >= s:
+            continue
+        wr = p.w0.reshape(-1).astype(np.float64).copy()
+        wi = np.zeros_like(wr)
+        if l > 0:
+            stage.superstep_complex(p, wr, wi, tr[:l].copy(), ti[:l].copy())
+        gr, gi = _stored_stage(st, l, slot, n)
+        assert np.array_equal(gr, wr), "stage %d (real part)" % l
+        assert np.array_equal(gi, wi), "stage %d (imaginary part)" % l
+    lam_next = wl.random_state(p.shape, 9).reshape(-1)
+    g0 = wl.random_state(p.shape, 10).reshape(-1)
+    ref_lam, ref_g = stage.adjoint(p, p.w0, lam_next, tr, ti,
+                                   grad_logD=g0.copy() if p.D is not None else None)
+    lam_n = torch.empty(n, dtype=torch.float64, device="cuda")
+    g = dev(g0) if p.D is not None else None
+    F.frkc2_step_adjoint_stored(p, st, D, T, s, dev(lam_next), lam_n, g)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(lam_n), ref_lam)
+    if p.D is not None:
+        assert np.array_equal(host(g), ref_g)
+
+
+def test_stored_adjoint_aliased_lambda_and_pairs():
+    """lam_n may alias lam_next, and two reverse stages per pass (on request) read the store
+    as the one-stage passes do: both give the oracle's bits."""
+    p = _prob("3d-var-dir")
+    s = 16
+    c = frkc2_coeffs(s, 0.01)
+    T = 0.9 * c.beta_bar / stage.rho_bound(p)
+    tr, ti = T * c.a_re, T * c.a_im
+    D = dev(p.D)
+    st = F.stage_store(p, s)
+    F.frkc2_step_store(p, dev(p.w0), D, T, s, st)
+    lam_next = wl.random_state(p.shape, 11).reshape(-1)
+    ref_lam, ref_g = stage.adjoint(p, p.w0, lam_next, tr, ti, grad_logD=np.zeros(p.npoints))
+    try:
+        for stages in (1, 2):
+            assert F.frkc2_set_option(F.OPT_ADJ_STAGES, stages) == 0
+            lam = dev(lam_next)
+            g = torch.zeros(p.npoints, dtype=torch.float64, device="cuda")
+            F.frkc2_step_adjoint_stored(p, st, D, T, s, lam, lam, g)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(lam), ref_lam), "stages per pass %d" % stages
+            assert np.array_equal(host(g), ref_g), "stages per pass %d" % stages
+    finally:
+        F.frkc2_set_option(F.OPT_ADJ_STAGES, 0)
+
+
+def test_autograd_stage_store_matches_checkpoints():
+    """The autograd function with the stage store and with per-superstep checkpoints gives the
+    same w and the same gradients, bit for bit."""
+    from paper_1702_03818_amd.autograd import superstep_fn
+    p = _prob("3d-var-per")
+    s, nsteps = 16, 3
+    c = frkc2_coeffs(s, 0.01)
+    T = 0.9 * c.beta_bar / stage.rho_bound(p)
+    tgt = dev(wl.random_state(p.shape, 4))
+    res = []
+    for store in (False, True, None):
+        u = dev(p.w0).requires_grad_(True)
+        ld = dev(np.log(p.D)).requires_grad_(True)
+        w = superstep_fn(u, ld, p, T, s, nsteps, store_stages=store)
+        ((w - tgt) ** 2).sum().backward()
+        res.append((host(w), host(u.grad), host(ld.grad)))
+    for other in res[1:]:
+        for a, b in zip(res[0], other):
+            assert np.array_equal(a, b)
