@@ -22,9 +22,11 @@
 // in-kernel wait between workgroups could only get by writing back and
 // invalidating the L2 caches around every dependency.
 //
-// A work item is one tile of a problem. The items of a level are split into
-// eight contiguous ranges, one per XCD (workgroup b runs on XCD b % 8), so
-// neighbouring tiles share an L2; an item's problem descriptor is moved to
+// A work item is one tile of a problem. A fused item is one workgroup, the
+// block index remapped so that each XCD (workgroup b runs on XCD b % 8) takes
+// a contiguous range of items; the single-stage items of a level are split
+// into eight contiguous ranges, one per XCD, that the workgroups walk. Either
+// way neighbouring tiles share an L2. An item's problem descriptor is moved to
 // scalar registers, since the whole workgroup works on one problem.
 //
 // The per-point arithmetic is the one of the plain stage kernels (faces
@@ -113,7 +115,7 @@ __device__ void run_fused(const BatchProblem &P, Tb3Args &a, long long c, double
 {
     const int bx = (int)(c % P.ntx3);
     const long long r = c / P.ntx3;
-    tb3d_tile<OP, BC, KB, IR, OR, false, false, W, false, true>(a, bx, (int)(r % P.nty3),
+    tb3d_tile<OP, BC, KB, IR, OR, false, false, W, true, true>(a, bx, (int)(r % P.nty3),
                                                                  (int)(r / P.nty3), sL, sD);
 }
 
@@ -136,112 +138,127 @@ __device__ void row_io(const TbArgs &a, int bx, int bz, bool ir, bool orl, doubl
 }
 
 // One pass level of the 3D problems. FUSED: each active problem's pass of
-// KB stages (stages KB*level ..), as tb3d_tile items; otherwise its
-// single-stage pass (the stages left after the fused ones), as 64 x 16
-// plane-march items. A problem's first pass reads w, its last writes w, the
-// passes between ping-pong the workspace buffers.
+// KB stages (stages KB*level ..), as tb3d_tile items with the diffusivity
+// faces in registers, one item per workgroup (a loop over items around the
+// tile keeps more registers live than the face ring leaves, and spills);
+// otherwise its single-stage pass (the stages left after the fused ones), as
+// 64 x 16 plane-march items, each workgroup a range of items. A problem's
+// first pass reads w, its last writes w, the passes between ping-pong the
+// workspace buffers.
+template <bool FUSED, int W, int KB>
+__device__ __forceinline__ void pass3_item(const Pass3Args &t, long long g, double2 *sL, double *sD)
+{
+    const int L = t.level;
+    int a = 0, b = t.nprob - 1;
+    while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (t.item_prefix[mid] <= g) a = mid;
+        else b = mid - 1;
+    }
+    a = uni(a);
+    BatchProblem P = t.probs[a];
+    P.w = uni(P.w);
+    P.D = uni(P.D);
+    P.bufA = uni(P.bufA);
+    P.bufB = uni(P.bufB);
+    P.tau = uni(P.tau);
+    P.nx = uni(P.nx);
+    P.ny = uni(P.ny);
+    P.nz = uni(P.nz);
+    P.bc = uni(P.bc);
+    P.op = uni(P.op);
+    P.zchunk = uni(P.zchunk);
+    P.ntx = uni(P.ntx);
+    P.nty = uni(P.nty);
+    P.nfull = uni(P.nfull);
+    P.npass = uni(P.npass);
+    P.zc3 = uni(P.zc3);
+    P.ntx3 = uni(P.ntx3);
+    P.nty3 = uni(P.nty3);
+    P.inv_h2 = uni(P.inv_h2);
+    P.d_const = uni(P.d_const);
+    const long long c = uni(g - t.item_prefix[a]);
+    const bool ir = (L == 0), orl = (L == P.npass - 1);
+    const double *in_c = (L & 1) ? P.bufA : P.bufB;   // pass L-1 wrote buffer (L-1) & 1
+    double *out_c = (L & 1) ? P.bufB : P.bufA;
+    const bool per = (P.bc == PER), var = (P.op == VAR);
+    if (FUSED) {
+        Tb3Args ta{};
+        ta.in_re = P.w;
+        ta.in_c = reinterpret_cast<const double2 *>(in_c);
+        ta.out_re = P.w;
+        ta.out_c = reinterpret_cast<double2 *>(out_c);
+        ta.D = P.D;
+        ta.nx = P.nx;
+        ta.ny = P.ny;
+        ta.nz = P.nz;
+        ta.zchunk = P.zc3;
+        ta.ntx = P.ntx3;
+        ta.nty = P.nty3;
+        ta.inv_h2 = P.inv_h2;
+        ta.d_const = P.d_const;
+        for (int k = 0; k < 6; ++k) ta.fc[k] = P.d_const;
+        const int l0 = KB * L;
+#pragma unroll
+        for (int i = 0; i < KB; ++i) {
+            ta.tr[i] = uni(P.tau[2 * (l0 + i)]);
+            ta.ti[i] = uni(P.tau[2 * (l0 + i) + 1]);
+        }
+        if (var) {
+            if (per) fused_io_w<VAR, PER, W, KB>(P, ta, c, ir, orl, sL, sD);
+            else fused_io_w<VAR, DIR, W, KB>(P, ta, c, ir, orl, sL, sD);
+        } else {
+            if (per) fused_io_w<LAP, PER, W, KB>(P, ta, c, ir, orl, sL, sD);
+            else fused_io_w<LAP, DIR, W, KB>(P, ta, c, ir, orl, sL, sD);
+        }
+    } else {
+        const int l = KB * P.nfull + (L - P.nfull);
+        PlaneArgs pa{};
+        pa.in_re = P.w;
+        pa.in_c = reinterpret_cast<const double2 *>(in_c);
+        pa.out_re = P.w;
+        pa.out_c = reinterpret_cast<double2 *>(out_c);
+        pa.D = P.D;
+        pa.nx = P.nx;
+        pa.ny = P.ny;
+        pa.nz = P.nz;
+        pa.zchunk = P.zchunk;
+        pa.ntx = P.ntx;
+        pa.nty = P.nty;
+        pa.inv_h2 = P.inv_h2;
+        pa.d_const = P.d_const;
+        for (int k = 0; k < 6; ++k) pa.fc[k] = P.d_const;
+        pa.tr = uni(P.tau[2 * l]);
+        pa.ti = uni(P.tau[2 * l + 1]);
+        if (var) {
+            if (per) run_io<3, kPBX, kPBY, VAR, PER>(P, pa, c, ir, orl, sL, sD);
+            else run_io<3, kPBX, kPBY, VAR, DIR>(P, pa, c, ir, orl, sL, sD);
+        } else {
+            if (per) run_io<3, kPBX, kPBY, LAP, PER>(P, pa, c, ir, orl, sL, sD);
+            else run_io<3, kPBX, kPBY, LAP, DIR>(P, pa, c, ir, orl, sL, sD);
+        }
+    }
+}
+
 template <bool FUSED, int W, int KB>
 __global__ __launch_bounds__(1024) void batched_pass3(Pass3Args t)
 {
     using S1 = TileShape<VAR, DIR, 3, kPBX, kPBY>;
-    constexpr int NL = FUSED ? Tb3Lds<VAR, KB, W, true>::L : S1::LDS_W;
-    constexpr int ND = FUSED ? Tb3Lds<VAR, KB, W, true>::D : S1::LDS_D;
+    constexpr int NL = FUSED ? Tb3Lds<VAR, KB, W>::L : S1::LDS_W;
+    constexpr int ND = FUSED ? Tb3Lds<VAR, KB, W>::D : S1::LDS_D;
     __shared__ double2 sL[NL];
     __shared__ double sD[ND];
-    long long first, hi, step;
-    xcd_range(t.items, first, hi, step);
-    const int L = t.level;
-    for (long long g = first; g < hi; g += step) {
-        int a = 0, b = t.nprob - 1;
-        while (a < b) {
-            const int mid = (a + b + 1) >> 1;
-            if (t.item_prefix[mid] <= g) a = mid;
-            else b = mid - 1;
+    if constexpr (FUSED) {
+        // consecutive items (neighbouring tiles of a problem) on one XCD
+        const int g = xcd_remap(blockIdx.x, gridDim.x);
+        if (g < t.items) pass3_item<FUSED, W, KB>(t, g, sL, sD);
+    } else {
+        long long first, hi, step;
+        xcd_range(t.items, first, hi, step);
+        for (long long g = first; g < hi; g += step) {
+            pass3_item<FUSED, W, KB>(t, g, sL, sD);
+            __syncthreads();   // the next item reuses the LDS
         }
-        a = uni(a);
-        BatchProblem P = t.probs[a];
-        P.w = uni(P.w);
-        P.D = uni(P.D);
-        P.bufA = uni(P.bufA);
-        P.bufB = uni(P.bufB);
-        P.tau = uni(P.tau);
-        P.nx = uni(P.nx);
-        P.ny = uni(P.ny);
-        P.nz = uni(P.nz);
-        P.bc = uni(P.bc);
-        P.op = uni(P.op);
-        P.zchunk = uni(P.zchunk);
-        P.ntx = uni(P.ntx);
-        P.nty = uni(P.nty);
-        P.nfull = uni(P.nfull);
-        P.npass = uni(P.npass);
-        P.zc3 = uni(P.zc3);
-        P.ntx3 = uni(P.ntx3);
-        P.nty3 = uni(P.nty3);
-        P.inv_h2 = uni(P.inv_h2);
-        P.d_const = uni(P.d_const);
-        const long long c = uni(g - t.item_prefix[a]);
-        const bool ir = (L == 0), orl = (L == P.npass - 1);
-        const double *in_c = (L & 1) ? P.bufA : P.bufB;   // pass L-1 wrote buffer (L-1) & 1
-        double *out_c = (L & 1) ? P.bufB : P.bufA;
-        const bool per = (P.bc == PER), var = (P.op == VAR);
-        if (FUSED) {
-            Tb3Args ta{};
-            ta.in_re = P.w;
-            ta.in_c = reinterpret_cast<const double2 *>(in_c);
-            ta.out_re = P.w;
-            ta.out_c = reinterpret_cast<double2 *>(out_c);
-            ta.D = P.D;
-            ta.nx = P.nx;
-            ta.ny = P.ny;
-            ta.nz = P.nz;
-            ta.zchunk = P.zc3;
-            ta.ntx = P.ntx3;
-            ta.nty = P.nty3;
-            ta.inv_h2 = P.inv_h2;
-            ta.d_const = P.d_const;
-            for (int k = 0; k < 6; ++k) ta.fc[k] = P.d_const;
-            const int l0 = KB * L;
-#pragma unroll
-            for (int i = 0; i < KB; ++i) {
-                ta.tr[i] = uni(P.tau[2 * (l0 + i)]);
-                ta.ti[i] = uni(P.tau[2 * (l0 + i) + 1]);
-            }
-            if (var) {
-                if (per) fused_io_w<VAR, PER, W, KB>(P, ta, c, ir, orl, sL, sD);
-                else fused_io_w<VAR, DIR, W, KB>(P, ta, c, ir, orl, sL, sD);
-            } else {
-                if (per) fused_io_w<LAP, PER, W, KB>(P, ta, c, ir, orl, sL, sD);
-                else fused_io_w<LAP, DIR, W, KB>(P, ta, c, ir, orl, sL, sD);
-            }
-        } else {
-            const int l = KB * P.nfull + (L - P.nfull);
-            PlaneArgs pa{};
-            pa.in_re = P.w;
-            pa.in_c = reinterpret_cast<const double2 *>(in_c);
-            pa.out_re = P.w;
-            pa.out_c = reinterpret_cast<double2 *>(out_c);
-            pa.D = P.D;
-            pa.nx = P.nx;
-            pa.ny = P.ny;
-            pa.nz = P.nz;
-            pa.zchunk = P.zchunk;
-            pa.ntx = P.ntx;
-            pa.nty = P.nty;
-            pa.inv_h2 = P.inv_h2;
-            pa.d_const = P.d_const;
-            for (int k = 0; k < 6; ++k) pa.fc[k] = P.d_const;
-            pa.tr = uni(P.tau[2 * l]);
-            pa.ti = uni(P.tau[2 * l + 1]);
-            if (var) {
-                if (per) run_io<3, kPBX, kPBY, VAR, PER>(P, pa, c, ir, orl, sL, sD);
-                else run_io<3, kPBX, kPBY, VAR, DIR>(P, pa, c, ir, orl, sL, sD);
-            } else {
-                if (per) run_io<3, kPBX, kPBY, LAP, PER>(P, pa, c, ir, orl, sL, sD);
-                else run_io<3, kPBX, kPBY, LAP, DIR>(P, pa, c, ir, orl, sL, sD);
-            }
-        }
-        __syncthreads();   // the next item reuses the LDS
     }
 }
 

@@ -490,10 +490,17 @@ int build_graph(GraphEntry &E, const Batch &B, const Layout &L, const BatchCfg &
                 const size_t row = (size_t)(g * 2 * E.levels3 + 2 * lv + kind) * (n3 + 1);
                 const long long items = E.pass3[row + n3];
                 if (items == 0) continue;
+                // fused items: one workgroup each; single-stage items: a
+                // grid that fills the GPU, each workgroup a range of items
+                if (kind == 0 && items > 0x7fffffffLL) {
+                    lrc = (int)hipErrorInvalidValue;
+                    break;
+                }
                 lrc = launch_batched_pass3(
                     kind == 0, E.gcols[g], c.k3,
                     reinterpret_cast<const BatchProblem *>(base + L.probs[0]), pass3_dev + row,
-                    items, n3, lv, grid_for(0, items), g == 0 ? g_capture : g_group[g]);
+                    items, n3, lv, kind == 0 ? (int)items : grid_for(0, items),
+                    g == 0 ? g_capture : g_group[g]);
             }
         }
     const long long *pass2_dev = reinterpret_cast<const long long *>(base + L.pass2);
