@@ -280,6 +280,8 @@ def pass_schedule(s, k, supported=(2, 3)):
     out, l = [], 0
     while l < s:
         kk = k if (k >= 2 and s - l >= k) else 1
+        if kk >= 3 and s - l - kk == 1 and (kk - 1) in supported:
+            kk -= 1
         if kk == 1 and k > 2 and s - l >= 2 and (s - l) in supported:
             kk = s - l
         if l == 0 and kk == s:

@@ -324,6 +324,9 @@ int run_superstep(const KGrid &kg, const PassCfg &cfg, double *w, const double *
         // passes of k stages; a remainder of r >= 2 stages as one pass of
         // depth r where the tile supports it
         int kk = (k >= 2 && s - l >= k) ? k : 1;
+        // a pass that would leave one stage leaves two: a lone stage is a
+        // whole-grid pass of its own, about twice the time of a fused stage
+        if (kk >= 3 && s - l - kk == 1 && tblock_supported(kg, kk - 1)) kk -= 1;
         if (kk == 1 && k > 2 && s - l >= 2 && tblock_supported(kg, s - l)) kk = s - l;
         // A fused pass reads its input around each tile and chunk (halo), so it
         // must not write into the array it reads: the pass that starts from w
@@ -758,6 +761,9 @@ int run_flow_c(const KGrid &kg, const PassCfg &cfg, double *Z, double Tn, const 
     const double *in = Z;
     while (l < s) {
         int kk = (k >= 2 && s - l >= k) ? k : 1;
+        // a pass that would leave one stage leaves two: a lone stage is a
+        // whole-grid pass of its own, about twice the time of a fused stage
+        if (kk >= 3 && s - l - kk == 1 && tblock_supported(kg, kk - 1)) kk -= 1;
         if (kk == 1 && k > 2 && s - l >= 2 && tblock_supported(kg, s - l)) kk = s - l;
         if (l == 0 && kk == s && s > 1) {
             kk = s - 1;

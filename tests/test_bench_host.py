@@ -32,11 +32,14 @@ def test_pass_schedule_invariants(s, k):
         assert sched[0] != s          # the first pass reads w, the last writes it
     if k == 1:
         assert sched == [1] * s
+    if k == 3 and s >= 4:
+        assert 1 not in sched         # no lone single-stage pass
 
 
 def test_pass_schedule_examples():
-    assert bench.pass_schedule(100, 3) == [3] * 33 + [1]
+    assert bench.pass_schedule(100, 3) == [3] * 32 + [2, 2]
     assert bench.pass_schedule(98, 3) == [3] * 32 + [2]
     assert bench.pass_schedule(100, 2) == [2] * 50
     assert bench.pass_schedule(2, 3) == [1, 1]
-    assert bench.pass_schedule(3 + 1, 3) == [3, 1]
+    assert bench.pass_schedule(3 + 1, 3) == [2, 2]
+    assert bench.pass_schedule(64, 3) == [3] * 20 + [2, 2]
