@@ -554,7 +554,7 @@ def adaptive_leg(F, wl, torch, prob, D, rho, info):
 
 def brusselator_throughput(F, wl, torch):
     """2048^2 Brusselator supersteps (s = 100, T = 0.9 betabar / rho of the current state), the
-    default passes of 4 fused stages and one stage per pass."""
+    default passes of 4 fused stages and one stage per pass: 10 timed after 20 warm-up ones."""
     big = wl.brusselator(2048)
     n = big.npoints
 
@@ -562,17 +562,19 @@ def brusselator_throughput(F, wl, torch):
         F.frkc2_set_option(F.OPT_TBLOCK, depth)
         try:
             w = torch.tensor(big.w0.reshape(-1), dtype=torch.float64, device="cuda")
-            F.frkc2_step(big, w, None, cfl=CFL, s=S_STAGES, nsteps=1)
+            # warm-up long enough for the clocks to settle after the host-side set-up (the
+            # first few supersteps after an idle gap run up to 20 % slower)
+            F.frkc2_step(big, w, None, cfl=CFL, s=S_STAGES, nsteps=20)
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
-            F.frkc2_step(big, w, None, cfl=CFL, s=S_STAGES, nsteps=5)
+            F.frkc2_step(big, w, None, cfl=CFL, s=S_STAGES, nsteps=10)
             e1.record()
             torch.cuda.synchronize()
         finally:
             F.frkc2_set_option(F.OPT_TBLOCK, 0)
-        return e0.elapsed_time(e1) / 5
+        return e0.elapsed_time(e1) / 10
 
     ms = superstep_ms(0)        # the default: passes of 4 fused stages
     ms1 = superstep_ms(1)       # one stage per pass, for comparison
@@ -586,7 +588,7 @@ def brusselator_throughput(F, wl, torch):
 
 
 def brusselator_leg(F, wl, torch):
-    """The paper's two-species Brusselator (Sec. 3.1). Throughput: 5 supersteps (s = 100,
+    """The paper's two-species Brusselator (Sec. 3.1). Throughput: 10 supersteps (s = 100,
     T = 0.9 betabar / rho of the current state) on a 2048^2 grid. Accuracy: error-controlled
     runs on the paper's 200^2 grid from its initial data to t = 1 at several tolerances, with
     the accepted steps, the stages and the max error against a tol = 1e-8 run (the paper's
