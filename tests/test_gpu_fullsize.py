@@ -149,6 +149,33 @@ def test_adjoint_128_superstep():
     assert np.linalg.norm(gg - ref_g) <= 1e-12 * np.linalg.norm(ref_g)
 
 
+def test_adjoint_128_stage_store():
+    """128^3 adjoint configuration (s = 64) through the stage store, as the autograd function
+    runs it there: the forward superstep equals the oracle's, and the reverse stages on the
+    store equal the oracle's adjoint."""
+    p, target = wl.adjoint3d()
+    s = 64
+    c = frkc2_coeffs(s, 0.01)
+    T = 0.9 * c.beta_bar / stage.rho_bound(p)
+    w = dev(p.w0)
+    D = dev(p.D)
+    st = F.stage_store(p, s)
+    F.frkc2_step_store(p, w, D, T, s, st)
+    torch.cuda.synchronize()
+    ref_w = stage.superstep(p, p.w0, T * c.a_re, T * c.a_im).reshape(-1)
+    check(w.cpu().numpy(), ref_w, "stage-store forward 128^3")
+    lam_next = 2.0 * (ref_w - target.reshape(-1))
+    ref_lam, ref_g = stage.adjoint(p, p.w0, lam_next, T * c.a_re, T * c.a_im)
+    lam_n = torch.empty(p.npoints, dtype=torch.float64, device="cuda")
+    g = torch.zeros(p.npoints, dtype=torch.float64, device="cuda")
+    F.frkc2_step_adjoint_stored(p, st, D, T, s, dev(lam_next), lam_n, g)
+    torch.cuda.synchronize()
+    check(lam_n.cpu().numpy(), ref_lam, "stored adjoint lambda 128^3")
+    gg = g.cpu().numpy()
+    assert np.linalg.norm(gg - ref_g) <= 1e-12 * np.linalg.norm(ref_g)
+    del st
+
+
 def test_integrate_256(c2_reference):
     """Error-controlled integration on the benchmark grid (fused embedded passes, default
     configuration) over three superstep lengths: every attempt and the state equal the
