@@ -430,7 +430,7 @@ def batched_leg(F, wl, torch, reps=5):
         s_list.append(s)
         grids.append(p)
     work = sum(p.npoints * s for p, s in probs)
-    # the built-in launch configuration (the timing autotuner is switched off in this build)
+    # the built-in launch configuration (the library's timing autotuner is switched off)
     k3, cols3, k2 = F.frkc2_batched_config(grids, s_list)
     log("batched configuration: k3=%d cols=%d k2=%d (built-in)" % (k3, cols3, k2))
     args = F.BatchedArgs(grids, ws_list, D_list, T_list, s_list)

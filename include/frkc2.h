@@ -51,7 +51,7 @@ typedef enum {
     FRKC2_EUNSTABLE = -4,   /* T * rho > betabar: the superstep would leave the stability interval */
     FRKC2_ENONFINITE = -5,  /* a norm or bound came out NaN or infinite */
     FRKC2_ETIMEOUT = -6,    /* frkc2_integrate: attempt limit reached before the end time */
-    FRKC2_EDISABLED = -7    /* the call is switched off in this build (its block says why) */
+    FRKC2_EDISABLED = -7    /* the call is switched off in this version (its block says why) */
 } frkc2_status;
 
 typedef enum { FRKC2_BC_PERIODIC = 0, FRKC2_BC_DIRICHLET0 = 1 } frkc2_bc;
@@ -380,7 +380,7 @@ int frkc2_batched_release(void *ws);                  /* frees the graph cached 
  * gives the same bits. Synchronises st; drops the graph cached for ws.
  * Errors: FRKC2_EINVAL (arguments), FRKC2_EUNSTABLE, FRKC2_ENONFINITE,
  * FRKC2_ENOMEM (workspace), FRKC2_EHIP.
- * SWITCHED OFF in this build: after validating its arguments the call returns
+ * SWITCHED OFF in this version: after validating its arguments the call returns
  * FRKC2_EDISABLED without touching the GPU. Two test runs that rebuilt the
  * batch graph for every candidate ended in a host heap corruption detected
  * inside this call (glibc "free(): invalid pointer"), and its cause was not

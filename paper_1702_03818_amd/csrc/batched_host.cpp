@@ -651,7 +651,7 @@ extern "C" int frkc2_batched_autotune(int nprob, const frkc2_grid *grids, double
         return FRKC2_ENOMEM;
     }
     if (!g_autotune_enabled) {
-        set_error("batched autotune: switched off in this build (runs that rebuilt the batch "
+        set_error("batched autotune: switched off in this version (runs that rebuilt the batch "
                   "graph per candidate ended in a host heap corruption inside this call, cause "
                   "not found); frkc2_step_batched uses the options or the built-in "
                   "configuration");
