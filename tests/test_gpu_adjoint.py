@@ -203,7 +203,7 @@ def _stored_stage(st, l, slot, n):
 
 
 @pytest.mark.parametrize("kind", ["3d-var-dir", "3d-var-per", "2d-var-dir", "3d-lap-dir"])
-@pytest.mark.parametrize("s", [2, 6, 16, 64, 514])   # 3D: forward passes of three, two and one
+@pytest.mark.parametrize("s", [2, 6, 8, 16, 64, 514])   # 3D: forward passes of three, two and one
 def test_stage_store_and_stored_adjoint(kind, s):
     """frkc2_step_store gives the oracle's w^{n+1} bit for bit and leaves the oracle's stage
     states W^l in the store; frkc2_step_adjoint_stored on that store gives the oracle's adjoint
