@@ -890,16 +890,15 @@ extern "C" int frkc4s_step(const frkc2_grid *g, double *w, double T, int s, int 
 namespace {
 
 // Argument checks shared by the adjoint entry points (no HIP call).
-int adjoint_validate(const frkc2_grid *g, const double *D, double T, int s, double nu,
-                     const double *lam_next, double *lam_n, KGrid &kg)
+int adjoint_validate(const frkc2_grid *g, const double *D, double T, int s, double nu, KGrid &kg)
 {
     if (!make_kgrid(g, kg)) return FRKC2_EINVAL;
     if (nonlinear(kg) || kg.op == FRKC2_OP_ADVDIFF) {
         set_error("the adjoint supports the symmetric operators (LAPLACE, VARCOEF)");
         return FRKC2_EINVAL;
     }
-    if ((lam_next == nullptr) != (lam_n == nullptr) || (kg.op == FRKC2_OP_VARCOEF && !D)) {
-        set_error("lam_next and lam_n (and D for VARCOEF) must be non-NULL");
+    if (kg.op == FRKC2_OP_VARCOEF && !D) {
+        set_error("VARCOEF needs D");
         return FRKC2_EINVAL;
     }
     if (!check_s_nu(s, nu)) return FRKC2_EINVAL;
@@ -993,10 +992,10 @@ extern "C" int frkc2_step_adjoint(const frkc2_grid *g, const double *w_n, const 
                                   hipStream_t st)
 {
     KGrid kg;
-    const int vrc = adjoint_validate(g, D, T, s, nu, lam_next, lam_n, kg);
+    const int vrc = adjoint_validate(g, D, T, s, nu, kg);
     if (vrc < 0) return vrc;
-    if (!w_n || !lam_next) {
-        set_error("w_n, lam_next, lam_n (and D for VARCOEF) must be non-NULL");
+    if (!w_n || !lam_next || !lam_n) {
+        set_error("w_n, lam_next and lam_n must be non-NULL");
         return FRKC2_EINVAL;
     }
     const long long N = kg.npts();
@@ -1027,10 +1026,10 @@ extern "C" int frkc2_step_store(const frkc2_grid *g, double *w, const double *D,
                                 size_t ws_bytes, hipStream_t st)
 {
     KGrid kg;
-    const int vrc = adjoint_validate(g, D, T, s, nu, nullptr, nullptr, kg);
+    const int vrc = adjoint_validate(g, D, T, s, nu, kg);
     if (vrc < 0) return vrc;
     if (!w || !stages) {
-        set_error("w and stages (and D for VARCOEF) must be non-NULL");
+        set_error("w and stages must be non-NULL");
         return FRKC2_EINVAL;
     }
     const long long N = kg.npts();
@@ -1078,10 +1077,10 @@ extern "C" int frkc2_step_adjoint_stored(const frkc2_grid *g, const double *stag
                                          hipStream_t st)
 {
     KGrid kg;
-    const int vrc = adjoint_validate(g, D, T, s, nu, lam_next, lam_n, kg);
+    const int vrc = adjoint_validate(g, D, T, s, nu, kg);
     if (vrc < 0) return vrc;
-    if (!stages || !lam_next) {
-        set_error("stages, lam_next, lam_n (and D for VARCOEF) must be non-NULL");
+    if (!stages || !lam_next || !lam_n) {
+        set_error("stages, lam_next and lam_n must be non-NULL");
         return FRKC2_EINVAL;
     }
     const long long N = kg.npts();
