@@ -72,6 +72,10 @@ bool validate(int nprob, const frkc2_grid *grids, const int *s, std::vector<KGri
             set_error("batched: problem %d has invalid s = %d", i, s[i]);
             return false;
         }
+        if (kg[i].ndim == 3 && !tb3d_plane_ok(kg[i])) {
+            set_error("batched: problem %d has planes of 2^27 points or more", i);
+            return false;
+        }
     }
     return true;
 }

@@ -100,7 +100,7 @@ int launch_tblock(const KGrid &g, const PassArgs &p, int shape, hipStream_t st);
 // 3D passes with 64-column output tiles and halo wavefronts (tb3d.hip), k = 2, 3.
 int launch_tb3d(const KGrid &g, const PassArgs &p, hipStream_t st);
 // The full-width 3D tile addresses a plane with 32-bit byte offsets: planes
-// of at most 2^27 points (other grids take the other 3D tiles).
+// of fewer than 2^27 points (other grids take the other 3D tiles).
 bool tb3d_plane_ok(const KGrid &g);
 // Output columns (64 or 32) of the fused 3D tile with the lower predicted
 // pass time on this grid (rounds of workgroups x steps x step cost).

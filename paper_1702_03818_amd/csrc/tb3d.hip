@@ -180,7 +180,7 @@ double tb3d_cost(const KGrid &g)
 
 }  // namespace
 
-bool tb3d_plane_ok(const KGrid &g) { return (long long)g.nx * g.ny <= (1LL << 27); }
+bool tb3d_plane_ok(const KGrid &g) { return (long long)g.nx * g.ny < (1LL << 27); }
 
 int launch_tb3d(const KGrid &g, const PassArgs &p, hipStream_t st)
 {

@@ -156,7 +156,7 @@ __device__ __forceinline__ void tb3d_tile(const Tb3Args &a, int bx, int by, int 
     // registers) starts at the plane and spans its bytes, plus the lane's
     // column offset in bytes (clamped into the grid for Dirichlet, wrapped for
     // periodic) in one 32-bit vector register, so no lane holds a 64-bit
-    // pointer. The host sends planes of more than 2^27 points elsewhere, so
+    // pointer. The host sends planes of 2^27 points or more elsewhere, so
     // every offset and extent fits 31 bits.
     // (Without BUF: a 64-bit pointer per lane to its column plus a uniform
     // plane offset.)

@@ -478,6 +478,18 @@ def test_frkc4s_needs_brusselator():
     assert F.load().frkc4s_workspace_bytes(ctypes.byref(g)) == 0
 
 
+def test_batched_refuses_oversized_planes():
+    """A 3D batch problem whose planes reach 2^27 points is refused before any HIP call (the
+    fused tiles address a plane with 32-bit byte offsets); one point fewer is accepted."""
+    lib = F.load()
+    s = (ctypes.c_int * 1)(16)
+    big = grid(n=(1 << 14, 1 << 13, 2))
+    assert lib.frkc2_batched_workspace_bytes(1, ctypes.byref(big), s) == 0
+    assert b"2^27" in lib.frkc2_last_error()
+    ok = grid(n=(1 << 14, (1 << 13) - 1, 2))
+    assert lib.frkc2_batched_workspace_bytes(1, ctypes.byref(ok), s) > 0
+
+
 def test_batched_shapes_match_the_batch():
     """batched_shapes draws the same grids and stage counts as batched (first 6 problems)."""
     full = wl.batched(count=6)
