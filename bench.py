@@ -526,7 +526,8 @@ def porous2d_leg(F, wl, torch, nsup=5):
             "ms_per_superstep": ms, "value": p.npoints * s / (ms * 1e-3),
             "unit": "grid-point-stage updates/s", "stages_per_pass": tune["tblock"],
             "tile": tune["tile"], "bytes_per_point_per_pass": 32, "achieved_gbs": gbs,
-            "frac": gbs / HBM_PEAK_GBS}
+            "frac": gbs / HBM_PEAK_GBS,
+            "bound": "valu (FP64 issue; frac is the HBM fraction, not this pass's roofline)"}
 
 
 def adaptive_leg(F, wl, torch, prob, D, rho, info):
